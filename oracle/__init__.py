@@ -1,0 +1,322 @@
+"""Python access to the plain-C FP64 oracle (``sdsl_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use this package; the solver library never does.  It shares
+no code with the GPU path; both only read the seeded inputs of
+``ipm_inputs``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sdsl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, INVALID, STRUCTURE, BREAKDOWN, NOT_CONVERGED = 0, 1, 2, 4, 5
+PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT = 0, 1, 2
+FILTER_NONE, FILTER_MIN, FILTER_GEOMEAN = 0, 1, 2
+DIAG_DELTA, DIAG_DROPSUM = 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                               _SRC, "-lm", "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        _lib = C.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+P = C.c_void_p
+I64 = C.c_int64
+I32 = C.c_int32
+D = C.c_double
+
+
+def _declare(L):
+    L.or_spmv.argtypes = [I64, P, P, P, P, P]
+    L.or_lowrank_add.argtypes = [I64, I32, P, P, P, P, P, P]
+    L.or_residual.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P]
+    L.or_residual.restype = D
+    L.or_filter.argtypes = [I64, P, P, P, I32, P, I32, D, C.c_uint32, D, P, P, P, P]
+    L.or_filter.restype = I64
+    L.or_ilu0.argtypes = [I64, P, P, P, I32, I32, P, P, P]
+    L.or_ilu0.restype = C.c_int
+    L.or_bj_factor.argtypes = [I64, P, P, P, I32, P, I32, I32, D, P, P, P, P, P]
+    L.or_bj_factor.restype = C.c_int
+    L.or_lu_solve.argtypes = [I64, I64, P, P, P, P, P, P]
+    L.or_bj_apply.argtypes = [I64, P, P, P, P, P, P]
+    L.or_dense_lu.argtypes = [I64, P, P]
+    L.or_dense_lu.restype = C.c_int
+    L.or_dense_lu_solve.argtypes = [I64, P, P, P]
+    L.or_bbd_setup.argtypes = [I64, P, P, P, I32, P, I64, I32, D, C.c_uint32, D, I32, P, P]
+    L.or_bbd_setup.restype = P
+    L.or_bbd_free.argtypes = [P]
+    L.or_bbd_apply.argtypes = [P, P, P]
+    L.or_bbd_get.argtypes = [P, P, P, P, P, P, P]
+    L.or_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, D, I32, P, P, P]
+    L.or_pcg_bj.restype = C.c_int
+    L.or_gmres_bj.argtypes = [I64, P, P, P, P, P, P, P, P, P, D, I32, I32, P, P, P]
+    L.or_gmres_bj.restype = C.c_int
+    L.or_gmres_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
+    L.or_gmres_bbd.restype = C.c_int
+    L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P]
+    L.or_ir_pcg_bj.restype = C.c_int
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _csr(rp, ci, v):
+    return (np.ascontiguousarray(rp, dtype=np.int64), np.ascontiguousarray(ci, dtype=np.int32),
+            np.ascontiguousarray(v, dtype=np.float64))
+
+
+def spmv(rp, ci, v, x, lowrank=None):
+    rp, ci, v = _csr(rp, ci, v)
+    n = rp.shape[0] - 1
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(n)
+    lib().or_spmv(n, _p(rp), _p(ci), _p(v), _p(x), _p(y))
+    if lowrank is not None:
+        U, c = lowrank
+        urp, uci, uv = _csr(U.indptr, U.indices, U.data)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        lib().or_lowrank_add(n, U.shape[1], _p(urp), _p(uci), _p(uv), _p(c), _p(x), _p(y))
+    return y
+
+
+def residual(rp, ci, v, x, b, lowrank=None):
+    """Compensated true residual r = b - M x; returns (r, ||r||_2)."""
+    rp, ci, v = _csr(rp, ci, v)
+    n = rp.shape[0] - 1
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    r = np.empty(n)
+    if lowrank is not None:
+        U, c = lowrank
+        urp, uci, uv = _csr(U.indptr, U.indices, U.data)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        nr = lib().or_residual(n, _p(rp), _p(ci), _p(v), U.shape[1], _p(urp), _p(uci), _p(uv),
+                               _p(c), _p(x), _p(b), _p(r))
+    else:
+        nr = lib().or_residual(n, _p(rp), _p(ci), _p(v), 0, None, None, None, None, _p(x),
+                               _p(b), _p(r))
+    return r, nr
+
+
+def relres(sys_, x):
+    _, nr = residual(sys_.row_ptr, sys_.col, sys_.val, x, sys_.b, sys_.lowrank)
+    return nr / float(np.linalg.norm(sys_.b))
+
+
+def filter_correct(rp, ci, v, block_ptr, mode=FILTER_NONE, tau=0.0, flags=0, delta=0.0, n_int=None):
+    """Filtered + corrected block-diagonal matrix P_hat.  Returns
+    (p_rp, p_ci, p_v, dropsum)."""
+    rp, ci, v = _csr(rp, ci, v)
+    bp = np.ascontiguousarray(block_ptr, dtype=np.int32)
+    n_int = int(bp[-1]) if n_int is None else n_int
+    nnz = int(rp[n_int])
+    orp = np.zeros(n_int + 1, dtype=np.int64)
+    oci = np.empty(max(nnz, 1), dtype=np.int32)
+    ov = np.empty(max(nnz, 1), dtype=np.float64)
+    ds = np.empty(max(n_int, 1), dtype=np.float64)
+    kept = lib().or_filter(n_int, _p(rp), _p(ci), _p(v), bp.shape[0] - 1, _p(bp), mode, tau, flags,
+                           delta, _p(orp), _p(oci), _p(ov), _p(ds))
+    if kept < 0:
+        raise ValueError("row without a stored diagonal")
+    return orp, oci[:kept].copy(), ov[:kept].copy(), ds[:n_int].copy()
+
+
+def ilu0(rp, ci, v, spd=False, pivot_fix=False):
+    """In-place IKJ ILU(0) on a copy.  Returns (values, diag_pos, status,
+    pivot fixes, bad row)."""
+    rp, ci, v = _csr(rp, ci, v)
+    v = v.copy()
+    n = rp.shape[0] - 1
+    dp = np.empty(max(n, 1), dtype=np.int64)
+    nfix = C.c_int32(0)
+    bad = C.c_int64(-1)
+    st = lib().or_ilu0(n, _p(rp), _p(ci), _p(v), int(spd), int(pivot_fix), _p(dp), C.byref(nfix),
+                       C.byref(bad))
+    return v, dp[:n].copy(), st, nfix.value, bad.value
+
+
+def lu_solve(rp, ci, v, dp, r):
+    rp, ci, v = _csr(rp, ci, v)
+    n = rp.shape[0] - 1
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.empty(n)
+    dp = np.ascontiguousarray(dp, dtype=np.int64)
+    lib().or_bj_apply(n, _p(rp), _p(ci), _p(v), _p(dp), _p(r), _p(z))
+    return z
+
+
+class BJ:
+    """Block-Jacobi preconditioner of paper Sec. 2.3 with the filter and
+    correction of Sec. 3.2-3.3: filtered, corrected, ILU(0)-factored blocks.
+    ``policy`` handles ILU(0) breakdown (fail / replace the pivot / shift the
+    block's diagonal by a relative amount starting at ``shift0``)."""
+
+    def __init__(self, sys_, mode=FILTER_NONE, tau=0.0, flags=0, delta=0.0, spd=True,
+                 policy=PIVOT_SHIFT, shift0=1e-2):
+        self.rp, self.ci, v0, self.dropsum = filter_correct(sys_.row_ptr, sys_.col, sys_.val,
+                                                            sys_.block_ptr, mode, tau, flags, delta)
+        self.corrected = v0
+        n = self.rp.shape[0] - 1
+        bp = np.ascontiguousarray(sys_.block_ptr, dtype=np.int32)
+        self.v = np.empty_like(v0)
+        self.dp = np.empty(max(n, 1), dtype=np.int64)
+        self.shifts = np.zeros(bp.shape[0] - 1)
+        nfix = C.c_int32(0)
+        bad = C.c_int64(-1)
+        self.status = lib().or_bj_factor(n, _p(self.rp), _p(self.ci), _p(v0), bp.shape[0] - 1, _p(bp),
+                                         int(spd), policy, shift0, _p(self.v), _p(self.dp),
+                                         _p(self.shifts), C.byref(nfix), C.byref(bad))
+        self.dp = self.dp[:n]
+        self.nfix, self.bad_row = nfix.value, bad.value
+
+    def apply(self, r):
+        return lu_solve(self.rp, self.ci, self.v, self.dp, r)
+
+
+def _lr_args(lowrank):
+    if lowrank is None:
+        return 0, None, None, None, None, ()
+    U, c = lowrank
+    urp, uci, uv = _csr(U.indptr, U.indices, U.data)
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    return U.shape[1], urp, uci, uv, c, (urp, uci, uv, c)
+
+
+def pcg_bj(sys_, P: BJ, tol=1e-8, maxit=10_000, hist=False):
+    """PCG with the block-Jacobi preconditioner.  Returns (x, iters, relres,
+    status, history)."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
+    x = np.zeros(n)
+    its = C.c_int32(0)
+    rr = C.c_double(0.0)
+    h = np.zeros(maxit) if hist else None
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
+                         _p(P.ci), _p(P.v), _p(P.dp), _p(b), _p(x), tol, maxit, C.byref(its),
+                         C.byref(rr), _p(h))
+    return x, its.value, rr.value, st, (h[:its.value] if hist else None)
+
+
+def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000):
+    """FP32-inner PCG inside FP64 iterative refinement.  Returns (x, outer,
+    inner total, fp64 fallbacks, relres, status)."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
+    x = np.zeros(n)
+    out = np.zeros(3, dtype=np.int32)
+    rr = C.c_double(0.0)
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_ir_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
+                            _p(P.ci), _p(P.v), _p(P.dp), _p(b), _p(x), tol, inner_tol, max_outer,
+                            maxit, _p(out), C.byref(rr))
+    return x, int(out[0]), int(out[1]), int(out[2]), rr.value, st
+
+
+def gmres_bj(sys_, P: BJ, tol=1e-8, m=30, maxit=10_000, hist=False):
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    x = np.zeros(n)
+    its = C.c_int32(0)
+    rr = C.c_double(0.0)
+    h = np.zeros(maxit) if hist else None
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_gmres_bj(n, _p(rp), _p(ci), _p(v), _p(P.rp), _p(P.ci), _p(P.v), _p(P.dp), _p(b),
+                           _p(x), tol, m, maxit, C.byref(its), C.byref(rr), _p(h))
+    return x, its.value, rr.value, st, (h[:its.value] if hist else None)
+
+
+class BBD:
+    """Bordered-block-diagonal preconditioner of paper Sec. 2.4."""
+
+    def __init__(self, sys_, mode=FILTER_NONE, tau=0.0, flags=0, delta=0.0, pivot_fix=False):
+        self.rp, self.ci, self.v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+        self.bp = np.ascontiguousarray(sys_.block_ptr, dtype=np.int32)
+        self.n = sys_.n
+        self.n_border = sys_.n_border
+        st = C.c_int32(0)
+        info = np.zeros(3, dtype=np.int64)
+        self.ctx = lib().or_bbd_setup(self.n, _p(self.rp), _p(self.ci), _p(self.v),
+                                      self.bp.shape[0] - 1, _p(self.bp), self.n_border, mode, tau,
+                                      flags, delta, int(pivot_fix), C.byref(st), _p(info))
+        self.status = st.value
+        self.kept, self.nfix, self.bad_row = (int(t) for t in info)
+
+    def apply(self, r):
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.empty(self.n)
+        lib().or_bbd_apply(self.ctx, _p(r), _p(z))
+        return z
+
+    def parts(self):
+        nb = self.bp.shape[0] - 1
+        n_int = self.n - self.n_border
+        tail = np.empty(nb, dtype=np.int64)
+        lrp = np.empty(n_int + 1, dtype=np.int64)
+        lib().or_bbd_get(self.ctx, _p(tail), _p(lrp), None, None, None, None)
+        lci = np.empty(int(lrp[-1]), dtype=np.int32)
+        lv = np.empty(int(lrp[-1]))
+        S = np.empty((self.n_border, self.n_border))
+        piv = np.empty(self.n_border, dtype=np.int32)
+        lib().or_bbd_get(self.ctx, None, None, _p(lci), _p(lv), _p(S), _p(piv))
+        return dict(tail=tail, lrp=lrp, lci=lci, lv=lv, S=S, piv=piv)
+
+    def __del__(self):
+        if getattr(self, "ctx", None):
+            lib().or_bbd_free(self.ctx)
+            self.ctx = None
+
+
+def gmres_bbd(sys_, P: BBD, tol=1e-8, m=30, maxit=10_000, hist=False):
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    x = np.zeros(n)
+    its = C.c_int32(0)
+    rr = C.c_double(0.0)
+    h = np.zeros(maxit) if hist else None
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_gmres_bbd(n, _p(rp), _p(ci), _p(v), P.ctx, _p(b), _p(x), tol, m, maxit,
+                            C.byref(its), C.byref(rr), _p(h))
+    return x, its.value, rr.value, st, (h[:its.value] if hist else None)
+
+
+def dense_lu(a):
+    a = np.ascontiguousarray(a, dtype=np.float64).copy()
+    n = a.shape[0]
+    piv = np.empty(n, dtype=np.int32)
+    st = lib().or_dense_lu(n, _p(a), _p(piv))
+    return a, piv, st
+
+
+def dense_lu_solve(lu, piv, b):
+    b = np.ascontiguousarray(b, dtype=np.float64).copy()
+    lib().or_dense_lu_solve(lu.shape[0], _p(np.ascontiguousarray(lu)), _p(piv), _p(b))
+    return b

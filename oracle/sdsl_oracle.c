@@ -1,0 +1,915 @@
+/*
+ * CPU oracle for the preconditioned Krylov solve of IPM linear systems.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, sequential FP64
+ * statement of what the GPU path computes.  Only the test suite, the smoke
+ * check and the CPU-baseline leg of the benchmark load it.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * Paper: "SDSL-Solver: Scalable Distributed Sparse Linear Solvers for
+ * Large-Scale Interior Point Methods" (arXiv 2604.23979).  Each function names
+ * the passage it follows.  Readings of silent or ambiguous points:
+ *   - filter: strict '<' (ties keep the entry); the GEOMEAN variant drops
+ *     m_ij when m_ij*m_ij < (tau*tau)*(|m_ii|*|m_jj|), which is Eq. (filter)
+ *     after symmetric scaling to a unit diagonal; diagonals come from the
+ *     unfiltered matrix; only entries inside the row's own block are
+ *     filtered (entries outside it are not part of the block preconditioner).
+ *   - correction: sign(0) = +1; delta is absolute; the DROPSUM variant adds
+ *     the row's dropped magnitude (summed in ascending column order).
+ *   - ILU(0) is the IKJ variant on the (filtered) pattern with fma updates;
+ *     breakdown when a pivot is not positive (SPD mode) or when
+ *     |u_ii| < 1e-14 |p_ii| (general mode); with pivot_fix the pivot is
+ *     replaced by the corrected diagonal and counted.
+ *   - Krylov stopping rule: ||b - Mx||_2 <= tol ||b||_2 with x0 = 0; when the
+ *     recurrence residual meets it but the true one does not, the method
+ *     restarts from the true residual.
+ * Every function below is "parity pinned" by tests that compare it against
+ * dense linear algebra, closed forms or brute force on small inputs.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared sdsl_oracle.c -lm
+ * (-ffp-contract=off keeps every a*b+c as two roundings unless fma() is
+ * written out, so the arithmetic is exactly what is written here.)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_BREAKDOWN 4
+#define OR_NOT_CONVERGED 5
+#define OR_INVALID 1
+#define OR_STRUCTURE 2
+
+/* ------------------------------------------------------------------ */
+/* basic vector ops (plain sequential sums)                            */
+/* ------------------------------------------------------------------ */
+static double dot(int64_t n, const double* a, const double* b) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+static double nrm2(int64_t n, const double* a) { return sqrt(dot(n, a, a)); }
+
+/* y = M x for M in CSR (paper Sec. 2.3, the local product of the SpMV). */
+void or_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+             const double* x, double* y) {
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += v[p] * x[ci[p]];
+        y[i] = s;
+    }
+}
+
+/* y += U diag(c) U^T x with U an n x k CSR matrix: the dense columns of the
+ * constraint matrix kept as a bordered low-rank term (paper Sec. 2.1). */
+void or_lowrank_add(int64_t n, int32_t k, const int64_t* urp, const int32_t* uci,
+                    const double* uv, const double* c, const double* x, double* y) {
+    if (k <= 0) return;
+    double* t = (double*)calloc((size_t)k, sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = urp[i]; p < urp[i + 1]; ++p) t[uci[p]] += uv[p] * x[i];
+    for (int32_t j = 0; j < k; ++j) t[j] *= c[j];
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t p = urp[i]; p < urp[i + 1]; ++p) s += uv[p] * t[uci[p]];
+        y[i] += s;
+    }
+    free(t);
+}
+
+/* Error-free transformations (Ogita, Rump, Oishi, "Accurate sum and dot
+ * product", SIAM J. Sci. Comput. 26(6), 2005): TwoSum and TwoProduct. */
+static void two_sum(double a, double b, double* s, double* e) {
+    double x = a + b;
+    double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+static void two_prod(double a, double b, double* p, double* e) {
+    double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
+}
+
+/* r = b - (M + U diag(c) U^T) x with every row computed as a compensated
+ * (Dot2) sum; returns ||r||_2.  Used as the true residual for stopping and
+ * for checking results. */
+double or_residual(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                   int32_t k, const int64_t* urp, const int32_t* uci, const double* uv,
+                   const double* c, const double* x, const double* b, double* r) {
+    double* t = NULL;
+    if (k > 0) {
+        /* the k projections U^T x, each as a compensated sum */
+        t = (double*)calloc((size_t)k, sizeof(double));
+        double* te = (double*)calloc((size_t)k, sizeof(double));
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = urp[i]; p < urp[i + 1]; ++p) {
+                double pr, pe, s, se;
+                two_prod(uv[p], x[i], &pr, &pe);
+                two_sum(t[uci[p]], pr, &s, &se);
+                t[uci[p]] = s;
+                te[uci[p]] += pe + se;
+            }
+        for (int32_t j = 0; j < k; ++j) t[j] = (t[j] + te[j]) * c[j];
+        free(te);
+    }
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = b[i], e = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            double pr, pe, s2, se;
+            two_prod(-v[p], x[ci[p]], &pr, &pe);
+            two_sum(s, pr, &s2, &se);
+            s = s2;
+            e += pe + se;
+        }
+        if (k > 0)
+            for (int64_t p = urp[i]; p < urp[i + 1]; ++p) {
+                double pr, pe, s2, se;
+                two_prod(-uv[p], t[uci[p]], &pr, &pe);
+                two_sum(s, pr, &s2, &se);
+                s = s2;
+                e += pe + se;
+            }
+        r[i] = s + e;
+        ss += r[i] * r[i];
+    }
+    free(t);
+    return sqrt(ss);
+}
+
+/* ------------------------------------------------------------------ */
+/* Filter + diagonal correction (paper Sec. 3.2 Eq. (filter), Alg. 2;   */
+/* Sec. 3.3 Eq. (diagcorr), Alg. 3 steps 2-3)                          */
+/* ------------------------------------------------------------------ */
+#define OR_FILTER_NONE 0
+#define OR_FILTER_MIN 1
+#define OR_FILTER_GEOMEAN 2
+#define OR_DIAG_DELTA 1u
+#define OR_DIAG_DROPSUM 2u
+
+/* Builds the block-diagonal preconditioner matrix P_hat from M: for rows in
+ * [0, n_int) with blocks given by bp[0..nblocks], keeps the in-block entries
+ * that survive the filter, then corrects the diagonal.  Output arrays must
+ * hold nnz(M) entries.  Returns the number of kept entries, or -1 if a row of
+ * [0, n_int) has no stored diagonal. */
+int64_t or_filter(int64_t n_int, const int64_t* rp, const int32_t* ci, const double* v,
+                  int32_t nblocks, const int32_t* bp, int32_t mode, double tau,
+                  uint32_t flags, double delta, int64_t* out_rp, int32_t* out_ci,
+                  double* out_v, double* dropsum) {
+    double* dg = (double*)malloc((size_t)(n_int > 0 ? n_int : 1) * sizeof(double));
+    for (int64_t i = 0; i < n_int; ++i) {
+        dg[i] = 0.0;
+        int found = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] == i) { dg[i] = v[p]; found = 1; }
+        if (!found) { free(dg); return -1; }
+    }
+    int64_t w = 0;
+    out_rp[0] = 0;
+    for (int32_t blk = 0; blk < nblocks; ++blk) {
+        int64_t lo = bp[blk], hi = bp[blk + 1];
+        for (int64_t i = lo; i < hi; ++i) {
+            double ds = 0.0;
+            int64_t dpos = -1;
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                int64_t j = ci[p];
+                if (j < lo || j >= hi) continue;          /* outside the block */
+                int drop = 0;
+                if (j != i) {
+                    double a = v[p];
+                    if (mode == OR_FILTER_MIN) {
+                        drop = (fabs(a) < tau * fabs(dg[i])) && (fabs(a) < tau * fabs(dg[j]));
+                    } else if (mode == OR_FILTER_GEOMEAN) {
+                        double lhs = a * a;
+                        double rhs = (tau * tau) * (fabs(dg[i]) * fabs(dg[j]));
+                        drop = lhs < rhs;
+                    }
+                }
+                if (drop) { ds += fabs(v[p]); continue; }
+                if (j == i) dpos = w;
+                out_ci[w] = (int32_t)j;
+                out_v[w] = v[p];
+                ++w;
+            }
+            double corr = 0.0;
+            if (flags & OR_DIAG_DELTA) corr = delta;
+            if (flags & OR_DIAG_DROPSUM) corr = corr + ds;
+            if (flags & (OR_DIAG_DELTA | OR_DIAG_DROPSUM))
+                out_v[dpos] = (out_v[dpos] >= 0.0) ? out_v[dpos] + corr : out_v[dpos] - corr;
+            dropsum[i] = ds;
+            out_rp[i + 1] = w;
+        }
+    }
+    free(dg);
+    return w;
+}
+
+/* ------------------------------------------------------------------ */
+/* ILU(0), IKJ form (paper Sec. 2.3 "ILU(0) or IC(0)", Sec. 3.1).        */
+/* For row i ascending and each k < i in its pattern, ascending:          */
+/*   l_ik = p_ik / u_kk;  p_ij -= l_ik u_kj for j > k in both patterns.   */
+/* In place: strict lower part holds L (unit diagonal implied), the rest  */
+/* holds U.  diag_pos[i] receives the position of the diagonal.           */
+/* Returns OR_OK or OR_BREAKDOWN (bad_row set).                           */
+/* ------------------------------------------------------------------ */
+/* IKJ ILU(0) over rows [lo, hi) whose entries stay inside [lo, hi). */
+static int ilu0_rows(int64_t lo, int64_t hi, const int64_t* rp, const int32_t* ci, double* v,
+                     int64_t* diag_pos, int32_t spd, int32_t replace, int32_t* nfix,
+                     int64_t* bad_row) {
+    for (int64_t i = lo; i < hi; ++i) {
+        diag_pos[i] = -1;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] == i) diag_pos[i] = p;
+        if (diag_pos[i] < 0) { *bad_row = i; return OR_STRUCTURE; }
+    }
+    for (int64_t i = lo; i < hi; ++i) {
+        double orig = v[diag_pos[i]];
+        for (int64_t p = rp[i]; p < rp[i + 1] && ci[p] < i; ++p) {
+            int64_t k = ci[p];
+            double l = v[p] / v[diag_pos[k]];
+            v[p] = l;
+            /* merge row i (after p) with the upper part of row k */
+            int64_t q = diag_pos[k] + 1, s = p + 1;
+            while (q < rp[k + 1] && s < rp[i + 1]) {
+                if (ci[q] < ci[s]) ++q;
+                else if (ci[q] > ci[s]) ++s;
+                else { v[s] = fma(-l, v[q], v[s]); ++q; ++s; }
+            }
+        }
+        double u = v[diag_pos[i]];
+        int bad = spd ? !(u > 0.0) : !(fabs(u) >= 1e-14 * fabs(orig));
+        if (bad) {
+            if (!replace) { *bad_row = i; return OR_BREAKDOWN; }
+            v[diag_pos[i]] = orig;
+            ++*nfix;
+        }
+    }
+    return OR_OK;
+}
+
+int or_ilu0(int64_t n, const int64_t* rp, const int32_t* ci, double* v, int32_t spd,
+            int32_t pivot_fix, int64_t* diag_pos, int32_t* nfix, int64_t* bad_row) {
+    *nfix = 0;
+    *bad_row = -1;
+    return ilu0_rows(0, n, rp, ci, v, diag_pos, spd, pivot_fix, nfix, bad_row);
+}
+
+#define OR_PIVOT_FAIL 0
+#define OR_PIVOT_REPLACE 1
+#define OR_PIVOT_SHIFT 2
+#define OR_SHIFT_TRIES 48
+
+/* Block-Jacobi factorisation: ILU(0) of each diagonal block of the corrected
+ * matrix P_hat (given by pv), written to out_v.  On a breakdown in a block
+ * the policy decides:
+ *   FAIL    - return OR_BREAKDOWN;
+ *   REPLACE - a failed pivot is replaced by its corrected diagonal (counted);
+ *   SHIFT   - the block is refactored with every diagonal strengthened to
+ *             d + a*d, a = shift0, 2*shift0, 4*shift0, ...: the correction of
+ *             Eq. (diagcorr) taken in the unit-diagonal (MC64-scaled) frame,
+ *             where it is the relative increase a of each diagonal.
+ * shifts[b] receives the a used for block b (0 if none). */
+int or_bj_factor(int64_t n, const int64_t* rp, const int32_t* ci, const double* pv,
+                 int32_t nblocks, const int32_t* bp, int32_t spd, int32_t policy, double shift0,
+                 double* out_v, int64_t* diag_pos, double* shifts, int32_t* nfix, int64_t* bad_row) {
+    *nfix = 0;
+    *bad_row = -1;
+    memcpy(out_v, pv, (size_t)rp[n] * sizeof(double));
+    for (int32_t b = 0; b < nblocks; ++b) {
+        int64_t lo = bp[b], hi = bp[b + 1];
+        double a = 0.0;
+        shifts[b] = 0.0;
+        for (int tries = 0;; ++tries) {
+            int32_t fixes = 0;
+            int st = ilu0_rows(lo, hi, rp, ci, out_v, diag_pos, spd, policy == OR_PIVOT_REPLACE,
+                               &fixes, bad_row);
+            if (st == OR_STRUCTURE) return st;
+            if (st == OR_OK) { *nfix += fixes; shifts[b] = a; break; }
+            if (policy != OR_PIVOT_SHIFT || tries >= OR_SHIFT_TRIES) return OR_BREAKDOWN;
+            a = (a == 0.0) ? shift0 : 2.0 * a;
+            memcpy(out_v + rp[lo], pv + rp[lo], (size_t)(rp[hi] - rp[lo]) * sizeof(double));
+            for (int64_t i = lo; i < hi; ++i) {
+                double d = out_v[diag_pos[i]];
+                out_v[diag_pos[i]] = d + a * d;
+            }
+        }
+        *bad_row = -1;
+    }
+    return OR_OK;
+}
+
+/* z = U^{-1} L^{-1} r by forward then backward substitution (paper Sec. 2.3,
+ * "solve the precondition system").  Works on any set of rows [lo, hi)
+ * whose entries stay inside [lo, hi) (one block) or on a whole block
+ * diagonal matrix. */
+void or_lu_solve(int64_t lo, int64_t hi, const int64_t* rp, const int32_t* ci, const double* v,
+                 const int64_t* diag_pos, const double* r, double* z) {
+    for (int64_t i = lo; i < hi; ++i) {
+        double s = r[i];
+        for (int64_t p = rp[i]; p < diag_pos[i]; ++p) s -= v[p] * z[ci[p]];
+        z[i] = s;
+    }
+    for (int64_t i = hi - 1; i >= lo; --i) {
+        double s = z[i];
+        for (int64_t p = diag_pos[i] + 1; p < rp[i + 1]; ++p) s -= v[p] * z[ci[p]];
+        z[i] = s / v[diag_pos[i]];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Operators and preconditioners as callbacks for the Krylov methods     */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    const int64_t* rp; const int32_t* ci; const double* v;
+    int32_t k; const int64_t* urp; const int32_t* uci; const double* uv; const double* c;
+} or_op;
+
+static void op_apply(const or_op* A, const double* x, double* y) {
+    or_spmv(A->n, A->rp, A->ci, A->v, x, y);
+    or_lowrank_add(A->n, A->k, A->urp, A->uci, A->uv, A->c, x, y);
+}
+static double op_true_res(const or_op* A, const double* x, const double* b, double* r) {
+    return or_residual(A->n, A->rp, A->ci, A->v, A->k, A->urp, A->uci, A->uv, A->c, x, b, r);
+}
+
+typedef void (*or_prec_fn)(void* ctx, const double* r, double* z);
+
+/* block Jacobi: the factored block-diagonal matrix (Sec. 2.3) */
+typedef struct {
+    int64_t n; const int64_t* rp; const int32_t* ci; const double* v; const int64_t* dp;
+} or_bj;
+static void bj_apply(void* ctx, const double* r, double* z) {
+    const or_bj* P = (const or_bj*)ctx;
+    or_lu_solve(0, P->n, P->rp, P->ci, P->v, P->dp, r, z);
+}
+void or_bj_apply(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                 const int64_t* dp, const double* r, double* z) {
+    or_lu_solve(0, n, rp, ci, v, dp, r, z);
+}
+
+/* ------------------------------------------------------------------ */
+/* PCG (Hestenes-Stiefel; paper Sec. 2.2 lists CG; tolerance Sec. 4.2)   */
+/* ------------------------------------------------------------------ */
+static int pcg_run(const or_op* A, or_prec_fn prec, void* pctx, const double* b, double* x,
+                   double tol, int32_t maxit, int32_t* iters, double* relres, double* hist) {
+    int64_t n = A->n;
+    double *r = calloc(n, 8), *z = calloc(n, 8), *p = calloc(n, 8), *q = calloc(n, 8);
+    double nb = nrm2(n, b);
+    int st = OR_NOT_CONVERGED;
+    int it = 0;
+    memset(x, 0, (size_t)n * 8);
+    if (nb == 0.0) { *iters = 0; *relres = 0.0; free(r); free(z); free(p); free(q); return OR_OK; }
+    memcpy(r, b, (size_t)n * 8);
+    prec(pctx, r, z);
+    memcpy(p, z, (size_t)n * 8);
+    double rz = dot(n, r, z);
+    while (it < maxit) {
+        op_apply(A, p, q);
+        double pq = dot(n, p, q);
+        if (!(pq > 0.0)) { st = OR_BREAKDOWN; break; }
+        double alpha = rz / pq;
+        for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        ++it;
+        double rr = nrm2(n, r);
+        if (hist) hist[it - 1] = rr / nb;
+        if (rr <= tol * nb) {
+            double tr = op_true_res(A, x, b, r);
+            if (tr <= tol * nb) { st = OR_OK; break; }
+            /* restart from the true residual */
+            prec(pctx, r, z);
+            memcpy(p, z, (size_t)n * 8);
+            rz = dot(n, r, z);
+            continue;
+        }
+        prec(pctx, r, z);
+        double rz2 = dot(n, r, z);
+        double beta = rz2 / rz;
+        rz = rz2;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    }
+    *iters = it;
+    *relres = op_true_res(A, x, b, r) / nb;
+    free(r); free(z); free(p); free(q);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and */
+/* Givens rotations (paper Sec. 2.2: GMRES, right preconditioning).      */
+/* ------------------------------------------------------------------ */
+static int gmres_run(const or_op* A, or_prec_fn prec, void* pctx, const double* b, double* x,
+                     double tol, int32_t m, int32_t maxit, int32_t* iters, double* relres,
+                     double* hist) {
+    int64_t n = A->n;
+    double nb = nrm2(n, b);
+    memset(x, 0, (size_t)n * 8);
+    if (nb == 0.0) { *iters = 0; *relres = 0.0; return OR_OK; }
+    double* V = (double*)calloc((size_t)n * (m + 1), 8);
+    double* H = (double*)calloc((size_t)(m + 1) * m, 8);  /* H[i*m + j] */
+    double *cs = calloc(m, 8), *sn = calloc(m, 8), *g = calloc(m + 1, 8), *y = calloc(m, 8);
+    double *w = calloc(n, 8), *zt = calloc(n, 8), *r = calloc(n, 8);
+    int it = 0, st = OR_NOT_CONVERGED;
+    double beta = op_true_res(A, x, b, r);
+    while (it < maxit) {
+        if (beta <= tol * nb) { st = OR_OK; break; }
+        for (int64_t i = 0; i < n; ++i) V[i] = r[i] / beta;
+        memset(g, 0, (size_t)(m + 1) * 8);
+        g[0] = beta;
+        int j, jdone = 0;
+        for (j = 0; j < m && it < maxit; ++j) {
+            prec(pctx, V + (int64_t)j * n, zt);
+            op_apply(A, zt, w);
+            for (int i = 0; i <= j; ++i) {
+                double h = dot(n, w, V + (int64_t)i * n);
+                H[i * m + j] = h;
+                for (int64_t t = 0; t < n; ++t) w[t] -= h * V[(int64_t)i * n + t];
+            }
+            double hn = nrm2(n, w);
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * m + j], bb = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            double a = H[j * m + j], bb = H[(j + 1) * m + j];
+            double den = sqrt(a * a + bb * bb);
+            cs[j] = (den == 0.0) ? 1.0 : a / den;
+            sn[j] = (den == 0.0) ? 0.0 : bb / den;
+            H[j * m + j] = cs[j] * a + sn[j] * bb;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            if (hist) hist[it - 1] = fabs(g[j + 1]) / nb;
+            jdone = j + 1;
+            if (hn == 0.0 || fabs(g[j + 1]) <= tol * nb) break;
+            for (int64_t t = 0; t < n; ++t) V[(int64_t)(j + 1) * n + t] = w[t] / hn;
+        }
+        /* y = H^{-1} g (upper triangular jdone x jdone) */
+        for (int i = jdone - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < jdone; ++k) s -= H[i * m + k] * y[k];
+            y[i] = s / H[i * m + i];
+        }
+        /* x += P^{-1} (V y) */
+        memset(w, 0, (size_t)n * 8);
+        for (int k = 0; k < jdone; ++k)
+            for (int64_t t = 0; t < n; ++t) w[t] += y[k] * V[(int64_t)k * n + t];
+        prec(pctx, w, zt);
+        for (int64_t t = 0; t < n; ++t) x[t] += zt[t];
+        beta = op_true_res(A, x, b, r);
+    }
+    if (it >= maxit && beta <= tol * nb) st = OR_OK;
+    *iters = it;
+    *relres = beta / nb;
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(w); free(zt); free(r);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* BBD preconditioner (paper Sec. 2.4): interior blocks, tail sets,       */
+/* dense Schur complement with LU and partial pivoting, block LU apply.   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t n, n_int, nb_border;
+    int32_t nblocks;
+    int32_t* bp;          /* block boundaries (nblocks+1)                 */
+    int64_t* tail;        /* first row of each block's tail               */
+    /* ILU(0) factors of the interior block diagonal (CSR, global cols)   */
+    int64_t* lrp; int32_t* lci; double* lv; int64_t* ldp;
+    /* E: interior rows -> border columns; F: border rows -> interior cols */
+    int64_t* erp; int32_t* eci; double* ev;   /* rows 0..n_int, cols in [0,nb) */
+    int64_t* frp; int32_t* fci; double* fv;   /* rows 0..nb, cols interior   */
+    double* S;            /* dense LU of the Schur complement, row-major  */
+    int32_t* piv;
+    double *w, *g;
+} or_bbd;
+
+/* Dense LU with partial pivoting (row-major, in place), pivot = first
+ * maximum |a_ik| over rows k..n-1, as in LAPACK getrf. */
+int or_dense_lu(int64_t n, double* a, int32_t* piv) {
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t pr = k;
+        double best = fabs(a[k * n + k]);
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(a[i * n + k]) > best) { best = fabs(a[i * n + k]); pr = i; }
+        piv[k] = (int32_t)pr;
+        if (pr != k)
+            for (int64_t j = 0; j < n; ++j) { double t = a[k * n + j]; a[k * n + j] = a[pr * n + j]; a[pr * n + j] = t; }
+        if (a[k * n + k] == 0.0) return OR_BREAKDOWN;
+        double inv_piv = a[k * n + k];
+        for (int64_t i = k + 1; i < n; ++i) {
+            double l = a[i * n + k] / inv_piv;
+            a[i * n + k] = l;
+            if (l != 0.0)
+                for (int64_t j = k + 1; j < n; ++j) a[i * n + j] -= l * a[k * n + j];
+        }
+    }
+    return OR_OK;
+}
+
+/* x = A^{-1} b from or_dense_lu factors (b overwritten by x) */
+void or_dense_lu_solve(int64_t n, const double* a, const int32_t* piv, double* b) {
+    for (int64_t k = 0; k < n; ++k)
+        if (piv[k] != k) { double t = b[k]; b[k] = b[piv[k]]; b[piv[k]] = t; }
+    for (int64_t i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int64_t j = 0; j < i; ++j) s -= a[i * n + j] * b[j];
+        b[i] = s;
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int64_t j = i + 1; j < n; ++j) s -= a[i * n + j] * b[j];
+        b[i] = s / a[i * n + i];
+    }
+}
+
+static void bbd_apply(void* ctx, const double* r, double* z) {
+    or_bbd* B = (or_bbd*)ctx;
+    int64_t ni = B->n_int, nbd = B->nb_border;
+    double* w = B->w;
+    double* g = B->g;
+    /* w = L^{-1} r_I per block (forward substitution) */
+    for (int64_t i = 0; i < ni; ++i) {
+        double s = r[i];
+        for (int64_t p = B->lrp[i]; p < B->ldp[i]; ++p) s -= B->lv[p] * w[B->lci[p]];
+        w[i] = s;
+    }
+    /* g = r_G - sum_b F_{b,T} U_{b,TT}^{-1} w_{b,T}: the tail part of
+     * U^{-1} w only needs tail rows, solved backward inside each tail */
+    for (int32_t b = 0; b < B->nblocks; ++b) {
+        int64_t t0 = B->tail[b], hi = B->bp[b + 1];
+        for (int64_t i = hi - 1; i >= t0; --i) {
+            double s = w[i];
+            for (int64_t p = B->ldp[i] + 1; p < B->lrp[i + 1]; ++p) s -= B->lv[p] * z[B->lci[p]];
+            z[i] = s / B->lv[B->ldp[i]];
+        }
+    }
+    for (int64_t i = 0; i < nbd; ++i) {
+        double s = r[ni + i];
+        for (int64_t p = B->frp[i]; p < B->frp[i + 1]; ++p) s -= B->fv[p] * z[B->fci[p]];
+        g[i] = s;
+    }
+    /* x_G = S^{-1} g */
+    or_dense_lu_solve(nbd, B->S, B->piv, g);
+    for (int64_t i = 0; i < nbd; ++i) z[ni + i] = g[i];
+    /* w_T -= L_TT^{-1} (E_T x_G), then x_I = U^{-1} w per block */
+    for (int32_t b = 0; b < B->nblocks; ++b) {
+        int64_t t0 = B->tail[b], hi = B->bp[b + 1];
+        /* v = L_TT^{-1} (E_T x_G) by forward substitution inside the tail
+         * (the entries of L left of the tail multiply zeros); v is kept in z */
+        for (int64_t i = t0; i < hi; ++i) {
+            double s = 0.0;
+            for (int64_t p = B->erp[i]; p < B->erp[i + 1]; ++p) s += B->ev[p] * g[B->eci[p]];
+            for (int64_t p = B->lrp[i]; p < B->ldp[i]; ++p)
+                if (B->lci[p] >= t0) s -= B->lv[p] * z[B->lci[p]];
+            z[i] = s;
+        }
+        for (int64_t i = t0; i < hi; ++i) w[i] -= z[i];
+        int64_t lo = B->bp[b];
+        for (int64_t i = hi - 1; i >= lo; --i) {
+            double s = w[i];
+            for (int64_t p = B->ldp[i] + 1; p < B->lrp[i + 1]; ++p) s -= B->lv[p] * z[B->lci[p]];
+            z[i] = s / B->lv[B->ldp[i]];
+        }
+    }
+}
+
+static int64_t* tail_starts(int64_t n_int, const int64_t* rp, const int32_t* ci, int32_t nblocks,
+                            const int32_t* bp, int64_t n_border, int* bad) {
+    /* first local index of each block that couples to the border: rows with
+     * border-column entries (E) and columns referenced by border rows (F) */
+    int64_t* tail = (int64_t*)malloc((size_t)nblocks * sizeof(int64_t));
+    *bad = 0;
+    for (int32_t b = 0; b < nblocks; ++b) tail[b] = bp[b + 1];
+    for (int32_t b = 0; b < nblocks; ++b)
+        for (int64_t i = bp[b]; i < bp[b + 1]; ++i)
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+                int64_t j = ci[p];
+                if (j >= n_int) { if (i < tail[b]) tail[b] = i; }
+                else if (j < bp[b] || j >= bp[b + 1]) *bad = 1;   /* block-to-block coupling */
+            }
+    for (int64_t i = n_int; i < n_int + n_border; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            int64_t j = ci[p];
+            if (j >= n_int) continue;
+            /* block of column j */
+            int32_t lo = 0, hi = nblocks;
+            while (hi - lo > 1) { int32_t mid = (lo + hi) / 2; if (bp[mid] <= j) lo = mid; else hi = mid; }
+            if (j < tail[lo]) tail[lo] = j;
+        }
+    return tail;
+}
+
+/* Builds the BBD preconditioner of paper Sec. 2.4: the interior block
+ * diagonal (optionally filtered/corrected as in Sec. 3.2-3.3) is ILU(0)
+ * factored per block, and the dense Schur complement
+ *   S = C - sum_b F_{b,T} U_{b,TT}^{-1} L_{b,TT}^{-1} E_{b,T}
+ * is assembled column by column and LU factored with partial pivoting.
+ * status: OR_OK, OR_STRUCTURE (not in bordered block diagonal form, or a
+ * row without diagonal), OR_BREAKDOWN (ILU or Schur pivot).
+ * info[0] = kept entries, info[1] = pivot fixes, info[2] = bad row. */
+void* or_bbd_setup(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                   int32_t nblocks, const int32_t* bp, int64_t n_border, int32_t mode, double tau,
+                   uint32_t flags, double delta, int32_t pivot_fix, int32_t* status, int64_t* info) {
+    int64_t n_int = n - n_border;
+    *status = OR_OK;
+    if (bp[0] != 0 || bp[nblocks] != n_int) { *status = OR_STRUCTURE; return NULL; }
+    int bad = 0;
+    int64_t* tail = tail_starts(n_int, rp, ci, nblocks, bp, n_border, &bad);
+    if (bad) { free(tail); *status = OR_STRUCTURE; return NULL; }
+    or_bbd* B = (or_bbd*)calloc(1, sizeof(or_bbd));
+    B->n = n; B->n_int = n_int; B->nb_border = n_border; B->nblocks = nblocks;
+    B->bp = (int32_t*)malloc((size_t)(nblocks + 1) * 4);
+    memcpy(B->bp, bp, (size_t)(nblocks + 1) * 4);
+    B->tail = tail;
+    int64_t nnz = rp[n];
+    B->lrp = malloc((size_t)(n_int + 1) * 8); B->lci = malloc((size_t)nnz * 4 + 4);
+    B->lv = malloc((size_t)nnz * 8 + 8); B->ldp = malloc((size_t)(n_int + 1) * 8);
+    double* ds = malloc((size_t)(n_int + 1) * 8);
+    int64_t kept = or_filter(n_int, rp, ci, v, nblocks, bp, mode, tau, flags, delta,
+                             B->lrp, B->lci, B->lv, ds);
+    free(ds);
+    info[0] = kept;
+    if (kept < 0) { *status = OR_STRUCTURE; return B; }
+    int32_t nfix = 0; int64_t brow = -1;
+    int st = or_ilu0(n_int, B->lrp, B->lci, B->lv, 0, pivot_fix, B->ldp, &nfix, &brow);
+    info[1] = nfix; info[2] = brow;
+    if (st != OR_OK) { *status = st; return B; }
+    /* E (interior rows -> border cols) and F (border rows -> interior cols) */
+    B->erp = calloc((size_t)n_int + 1, 8);
+    for (int64_t i = 0; i < n_int; ++i) {
+        int64_t c = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) c += (ci[p] >= n_int);
+        B->erp[i + 1] = B->erp[i] + c;
+    }
+    B->eci = malloc((size_t)B->erp[n_int] * 4 + 4); B->ev = malloc((size_t)B->erp[n_int] * 8 + 8);
+    for (int64_t i = 0, w = 0; i < n_int; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] >= n_int) { B->eci[w] = (int32_t)(ci[p] - n_int); B->ev[w] = v[p]; ++w; }
+    B->frp = calloc((size_t)n_border + 1, 8);
+    for (int64_t i = 0; i < n_border; ++i) {
+        int64_t c = 0;
+        for (int64_t p = rp[n_int + i]; p < rp[n_int + i + 1]; ++p) c += (ci[p] < n_int);
+        B->frp[i + 1] = B->frp[i] + c;
+    }
+    B->fci = malloc((size_t)B->frp[n_border] * 4 + 4); B->fv = malloc((size_t)B->frp[n_border] * 8 + 8);
+    B->S = calloc((size_t)(n_border * n_border) + 1, 8);
+    for (int64_t i = 0, w = 0; i < n_border; ++i)
+        for (int64_t p = rp[n_int + i]; p < rp[n_int + i + 1]; ++p) {
+            if (ci[p] < n_int) { B->fci[w] = ci[p]; B->fv[w] = v[p]; ++w; }
+            else B->S[i * n_border + (ci[p] - n_int)] = v[p];      /* C */
+        }
+    /* F^T in CSC form over interior columns, to scatter S updates */
+    int64_t* fcp = calloc((size_t)n_int + 1, 8);
+    for (int64_t p = 0; p < B->frp[n_border]; ++p) fcp[B->fci[p] + 1]++;
+    for (int64_t j = 0; j < n_int; ++j) fcp[j + 1] += fcp[j];
+    int64_t* fpos = malloc((size_t)n_int * 8 + 8);
+    memcpy(fpos, fcp, (size_t)n_int * 8);
+    int32_t* frow = malloc((size_t)B->frp[n_border] * 4 + 4);
+    double* fval = malloc((size_t)B->frp[n_border] * 8 + 8);
+    for (int64_t i = 0; i < n_border; ++i)
+        for (int64_t p = B->frp[i]; p < B->frp[i + 1]; ++p) {
+            int64_t j = B->fci[p];
+            frow[fpos[j]] = (int32_t)i; fval[fpos[j]] = B->fv[p]; fpos[j]++;
+        }
+    free(fpos);
+    /* S -= F_T U_TT^{-1} L_TT^{-1} E_T, one border column at a time */
+    double* u = calloc((size_t)n_int + 1, 8);
+    char* seen = calloc((size_t)n_border + 1, 1);
+    for (int32_t b = 0; b < nblocks; ++b) {
+        int64_t t0 = tail[b], hi = bp[b + 1];
+        memset(seen, 0, (size_t)n_border);
+        for (int64_t i = t0; i < hi; ++i)
+            for (int64_t p = B->erp[i]; p < B->erp[i + 1]; ++p) {
+                int32_t c = B->eci[p];
+                if (seen[c]) continue;
+                seen[c] = 1;
+                /* e = E_T[:, c]; y = L_TT^{-1} e */
+                for (int64_t r = t0; r < hi; ++r) {
+                    double s = 0.0;
+                    for (int64_t q = B->erp[r]; q < B->erp[r + 1]; ++q)
+                        if (B->eci[q] == c) s += B->ev[q];
+                    for (int64_t q = B->lrp[r]; q < B->ldp[r]; ++q)
+                        if (B->lci[q] >= t0) s -= B->lv[q] * u[B->lci[q]];
+                    u[r] = s;
+                }
+                /* u = U_TT^{-1} y */
+                for (int64_t r = hi - 1; r >= t0; --r) {
+                    double s = u[r];
+                    for (int64_t q = B->ldp[r] + 1; q < B->lrp[r + 1]; ++q) s -= B->lv[q] * u[B->lci[q]];
+                    u[r] = s / B->lv[B->ldp[r]];
+                }
+                /* S[:, c] -= F_T u */
+                for (int64_t j = t0; j < hi; ++j) {
+                    if (u[j] == 0.0) continue;
+                    for (int64_t q = fcp[j]; q < fcp[j + 1]; ++q)
+                        B->S[(int64_t)frow[q] * n_border + c] -= fval[q] * u[j];
+                }
+            }
+    }
+    free(u); free(seen); free(fcp); free(frow); free(fval);
+    B->piv = malloc((size_t)n_border * 4 + 4);
+    st = or_dense_lu(n_border, B->S, B->piv);
+    if (st != OR_OK) *status = st;
+    B->w = malloc((size_t)n_int * 8 + 8);
+    B->g = malloc((size_t)n_border * 8 + 8);
+    return B;
+}
+
+void or_bbd_free(void* ctx) {
+    or_bbd* B = (or_bbd*)ctx;
+    if (!B) return;
+    free(B->bp); free(B->tail); free(B->lrp); free(B->lci); free(B->lv); free(B->ldp);
+    free(B->erp); free(B->eci); free(B->ev); free(B->frp); free(B->fci); free(B->fv);
+    free(B->S); free(B->piv); free(B->w); free(B->g); free(B);
+}
+
+void or_bbd_apply(void* ctx, const double* r, double* z) { bbd_apply(ctx, r, z); }
+
+/* exports of the BBD state for comparisons: tails, factors, Schur LU */
+void or_bbd_get(void* ctx, int64_t* tail, int64_t* lrp, int32_t* lci, double* lv, double* S,
+                int32_t* piv) {
+    or_bbd* B = (or_bbd*)ctx;
+    if (tail) memcpy(tail, B->tail, (size_t)B->nblocks * 8);
+    if (lrp) memcpy(lrp, B->lrp, (size_t)(B->n_int + 1) * 8);
+    if (lci) memcpy(lci, B->lci, (size_t)B->lrp[B->n_int] * 4);
+    if (lv) memcpy(lv, B->lv, (size_t)B->lrp[B->n_int] * 8);
+    if (S) memcpy(S, B->S, (size_t)(B->nb_border * B->nb_border) * 8);
+    if (piv) memcpy(piv, B->piv, (size_t)B->nb_border * 4);
+}
+
+/* ------------------------------------------------------------------ */
+/* Krylov entry points                                                 */
+/* ------------------------------------------------------------------ */
+int or_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+              int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
+              const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
+              const double* b, double* x, double tol, int32_t maxit, int32_t* iters,
+              double* relres, double* hist) {
+    or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
+    or_bj P = {n, prp, pci, pv, pdp};
+    return pcg_run(&A, bj_apply, &P, b, x, tol, maxit, iters, relres, hist);
+}
+
+int or_gmres_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
+                const double* b, double* x, double tol, int32_t m, int32_t maxit, int32_t* iters,
+                double* relres, double* hist) {
+    or_op A = {n, rp, ci, v, 0, NULL, NULL, NULL, NULL};
+    or_bj P = {n, prp, pci, pv, pdp};
+    return gmres_run(&A, bj_apply, &P, b, x, tol, m, maxit, iters, relres, hist);
+}
+
+int or_gmres_bbd(int64_t n, const int64_t* rp, const int32_t* ci, const double* v, void* bbd,
+                 const double* b, double* x, double tol, int32_t m, int32_t maxit, int32_t* iters,
+                 double* relres, double* hist) {
+    or_op A = {n, rp, ci, v, 0, NULL, NULL, NULL, NULL};
+    return gmres_run(&A, bbd_apply, bbd, b, x, tol, m, maxit, iters, relres, hist);
+}
+
+/* ------------------------------------------------------------------ */
+/* FP32-inner PCG with FP64 iterative refinement.  The paper states no   */
+/* precision; this mixed form is the served variant: the inner PCG keeps */
+/* FP32 vectors, FP32 operator values and FP32 factors (rounded from the  */
+/* FP64 ones), computes the product and the triangular solves in FP32,    */
+/* accumulates dot products in FP64 and rounds alpha/beta to FP32 for the */
+/* vector updates.  The outer loop forms the true residual in FP64.       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    const int64_t* rp; const int32_t* ci; float* v;
+    int32_t k; const int64_t* urp; const int32_t* uci; float* uv; float* c;
+    const int64_t* prp; const int32_t* pci; float* pv; const int64_t* pdp;
+} or_f32sys;
+
+static void spmv32(const or_f32sys* S, const float* x, float* y) {
+    for (int64_t i = 0; i < S->n; ++i) {
+        float s = 0.0f;
+        for (int64_t p = S->rp[i]; p < S->rp[i + 1]; ++p) s += S->v[p] * x[S->ci[p]];
+        y[i] = s;
+    }
+    if (S->k > 0) {
+        float* t = calloc((size_t)S->k, 4);
+        for (int64_t i = 0; i < S->n; ++i)
+            for (int64_t p = S->urp[i]; p < S->urp[i + 1]; ++p) t[S->uci[p]] += S->uv[p] * x[i];
+        for (int32_t j = 0; j < S->k; ++j) t[j] *= S->c[j];
+        for (int64_t i = 0; i < S->n; ++i) {
+            float s = 0.0f;
+            for (int64_t p = S->urp[i]; p < S->urp[i + 1]; ++p) s += S->uv[p] * t[S->uci[p]];
+            y[i] += s;
+        }
+        free(t);
+    }
+}
+static void lusolve32(const or_f32sys* S, const float* r, float* z) {
+    for (int64_t i = 0; i < S->n; ++i) {
+        float s = r[i];
+        for (int64_t p = S->prp[i]; p < S->pdp[i]; ++p) s -= S->pv[p] * z[S->pci[p]];
+        z[i] = s;
+    }
+    for (int64_t i = S->n - 1; i >= 0; --i) {
+        float s = z[i];
+        for (int64_t p = S->pdp[i] + 1; p < S->prp[i + 1]; ++p) s -= S->pv[p] * z[S->pci[p]];
+        z[i] = s / S->pv[S->pdp[i]];
+    }
+}
+static double dot32(int64_t n, const float* a, const float* b) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (double)a[i] * (double)b[i];
+    return s;
+}
+/* inner PCG in FP32, x0 = 0, stop when ||r|| <= itol ||b|| (recurrence) */
+static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int32_t maxit,
+                 int32_t* iters) {
+    int64_t n = S->n;
+    float *r = calloc(n, 4), *z = calloc(n, 4), *p = calloc(n, 4), *q = calloc(n, 4);
+    double nb = sqrt(dot32(n, b, b));
+    int it = 0, st = OR_NOT_CONVERGED;
+    memset(x, 0, (size_t)n * 4);
+    memcpy(r, b, (size_t)n * 4);
+    lusolve32(S, r, z);
+    memcpy(p, z, (size_t)n * 4);
+    double rz = dot32(n, r, z);
+    while (it < maxit) {
+        spmv32(S, p, q);
+        double pq = dot32(n, p, q);
+        if (!(pq > 0.0)) { st = OR_BREAKDOWN; break; }
+        float a = (float)(rz / pq);
+        for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + a * p[i]; r[i] = r[i] - a * q[i]; }
+        ++it;
+        if (sqrt(dot32(n, r, r)) <= itol * nb) { st = OR_OK; break; }
+        lusolve32(S, r, z);
+        double rz2 = dot32(n, r, z);
+        float be = (float)(rz2 / rz);
+        rz = rz2;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
+    }
+    *iters = it;
+    free(r); free(z); free(p); free(q);
+    return st;
+}
+
+/* out[0] = outer steps, out[1] = inner iterations (sum), out[2] = FP64
+ * fallbacks.  Stagnation (the true residual shrinking by less than 2x on two
+ * consecutive outer steps) switches to an FP64 PCG on the remaining
+ * correction. */
+int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                 int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
+                 const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
+                 const double* b, double* x, double tol, double inner_tol, int32_t max_outer,
+                 int32_t maxit, int32_t* out, double* relres) {
+    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp};
+    int64_t nnz = rp[n], pnnz = prp[n], unnz = k > 0 ? urp[n] : 0;
+    S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
+    for (int64_t p = 0; p < nnz; ++p) S.v[p] = (float)v[p];
+    for (int64_t p = 0; p < pnnz; ++p) S.pv[p] = (float)pv[p];
+    if (k > 0) {
+        S.uv = malloc((size_t)unnz * 4 + 4); S.c = malloc((size_t)k * 4);
+        for (int64_t p = 0; p < unnz; ++p) S.uv[p] = (float)uv[p];
+        for (int32_t j = 0; j < k; ++j) S.c[j] = (float)c[j];
+    }
+    or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
+    or_bj P = {n, prp, pci, pv, pdp};
+    double *r = calloc(n, 8);
+    float *rs = calloc(n, 4), *d = calloc(n, 4);
+    double nb = nrm2(n, b);
+    memset(x, 0, (size_t)n * 8);
+    out[0] = out[1] = out[2] = 0;
+    int st = OR_NOT_CONVERGED;
+    if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
+    double nr = op_true_res(&A, x, b, r), prev = nr;
+    int slow = 0;
+    while (out[0] < max_outer) {
+        if (nr <= tol * nb) { st = OR_OK; break; }
+        if (slow >= 2) {
+            /* FP64 fallback: PCG on M d = r to the remaining tolerance */
+            double* dd = calloc(n, 8);
+            int32_t its = 0; double rr = 0.0;
+            pcg_run(&A, bj_apply, &P, r, dd, tol * nb / nr, maxit, &its, &rr, NULL);
+            for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
+            free(dd);
+            out[1] += its; out[2] += 1; out[0] += 1;
+            nr = op_true_res(&A, x, b, r);
+            slow = 0; prev = nr;
+            continue;
+        }
+        for (int64_t i = 0; i < n; ++i) rs[i] = (float)(r[i] / nr);
+        int32_t its = 0;
+        pcg32(&S, rs, d, inner_tol, maxit, &its);
+        for (int64_t i = 0; i < n; ++i) x[i] += nr * (double)d[i];
+        out[0] += 1; out[1] += its;
+        nr = op_true_res(&A, x, b, r);
+        slow = (nr > 0.5 * prev) ? slow + 1 : 0;
+        prev = nr;
+    }
+    if (nr <= tol * nb) st = OR_OK;
+    *relres = nr / nb;
+done:
+    free(r); free(rs); free(d); free(S.v); free(S.pv);
+    if (k > 0) { free(S.uv); free(S.c); }
+    return st;
+}

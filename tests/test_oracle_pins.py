@@ -1,0 +1,524 @@
+"""Pins of the CPU oracle against things other than itself: hand-worked
+fixtures, dense linear algebra, closed forms, invariants and brute force on
+tiny inputs.  A plausible slip anywhere in the oracle (a dropped term, a wrong
+sign or index, a transposed operand, a wrong tie rule) fails one of these."""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+import scipy.sparse as sp
+
+import oracle as O
+from ipm_inputs import gen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def csr_of(a):
+    m = sp.csr_matrix(np.asarray(a, dtype=np.float64))
+    m.sort_indices()
+    return m
+
+
+def with_diag(m):
+    """CSR with an explicit diagonal entry in every row."""
+    m = sp.csr_matrix(m)
+    d = m.diagonal()
+    m = m + sp.diags(np.where(d == 0, 1.0, 0.0))
+    m = sp.csr_matrix(m)
+    m.sort_indices()
+    return m
+
+
+def rand_sparse(n, density, rng, sym=False, dd=1.5):
+    a = sp.random(n, n, density=density, random_state=rng, data_rvs=rng.standard_normal).toarray()
+    if sym:
+        a = np.triu(a, 1)
+        a = a + a.T
+    np.fill_diagonal(a, 0.0)
+    np.fill_diagonal(a, dd * np.abs(a).sum(axis=1) + 1.0)
+    return a
+
+
+def unpack_lu(rp, ci, v, n):
+    L = np.eye(n)
+    U = np.zeros((n, n))
+    for i in range(n):
+        for p in range(rp[i], rp[i + 1]):
+            j = ci[p]
+            if j < i:
+                L[i, j] = v[p]
+            else:
+                U[i, j] = v[p]
+    return L, U
+
+
+# --------------------------------------------------------------- SpMV / residual
+
+def test_spmv_matches_scipy():
+    rng = np.random.default_rng(1)
+    a = csr_of(rand_sparse(300, 0.05, rng))
+    x = rng.standard_normal(300)
+    y = O.spmv(a.indptr, a.indices, a.data, x)
+    ref = a @ x
+    assert np.max(np.abs(y - ref) / (np.abs(a) @ np.abs(x))) < 4e-16 * 20
+
+
+def test_lowrank_reading_equals_explicit_ada():
+    """M_s + U diag(D_d) U^T equals the explicit A D A^T with the dense columns
+    kept inside A (the dense-column reading of paper Sec. 2.1)."""
+    s = gen.ada_system(200, 500, 3, -2.0, 2.0, 4, model="loc", dense_cols=2, dense_p=0.3, seed=3)
+    r_pat, r_val, r_d, _, _, _ = gen.streams(3)
+    col_ptr, rows = gen.a_pattern(r_pat, 200, 500, 3, "loc")
+    vals = r_val.standard_normal(rows.shape[0])
+    d_all = gen.log_uniform(r_d, 502, -2.0, 2.0)
+    A = sp.csc_matrix((vals, rows, col_ptr), shape=(200, 500)).toarray()
+    mask = r_pat.random((200, 2)) < 0.3
+    ri, ci = np.nonzero(mask)
+    Ud = np.zeros((200, 2))
+    Ud[ri, ci] = r_val.standard_normal(ri.shape[0])
+    Afull = np.hstack([A, Ud])
+    Mexp = Afull @ np.diag(d_all) @ Afull.T + 1e-8 * np.eye(200)
+    x = np.random.default_rng(0).standard_normal(200)
+    y = O.spmv(s.row_ptr, s.col, s.val, x, lowrank=s.lowrank)
+    assert np.allclose(y, Mexp @ x, rtol=1e-12, atol=1e-12 * np.abs(Mexp).max())
+
+
+def test_compensated_residual_is_exact_to_rounding():
+    """The Dot2 residual equals the exactly rounded rational residual to
+    within a couple of ulps even under heavy cancellation."""
+    rng = np.random.default_rng(2)
+    n = 40
+    a = rand_sparse(n, 0.2, rng)
+    x = rng.standard_normal(n)
+    b = a @ x  # residual is pure cancellation
+    b = b + 1e-10 * rng.standard_normal(n)
+    m = csr_of(a)
+    r, _ = O.residual(m.indptr, m.indices, m.data, x, b)
+    for i in range(n):
+        exact = Fraction(b[i])
+        for p in range(m.indptr[i], m.indptr[i + 1]):
+            exact -= Fraction(m.data[p]) * Fraction(x[m.indices[p]])
+        ex = float(exact)
+        assert abs(r[i] - ex) <= 4 * np.finfo(float).eps * abs(ex) + 1e-300
+
+
+# --------------------------------------------------------------- filter / correction
+
+def _golden_filter(mode, kept_key, ds_key, diag_key):
+    g = json.load(open(os.path.join(GOLD, "filter_4x4.json")))
+    m = csr_of(g["matrix"])
+    bp = np.array([0, 4], dtype=np.int32)
+    rp, ci, v, ds = O.filter_correct(m.indptr, m.indices, m.data, bp, mode, g["tau"], 0, 0.0)
+    kept = sorted((i, int(ci[p])) for i in range(4) for p in range(rp[i], rp[i + 1]))
+    assert kept == sorted(tuple(t) for t in g[kept_key])
+    assert np.allclose(ds, g[ds_key], rtol=1e-15, atol=0)
+    rp2, ci2, v2, _ = O.filter_correct(m.indptr, m.indices, m.data, bp, mode, g["tau"], O.DIAG_DROPSUM, 0.0)
+    dg = [v2[p] for i in range(4) for p in range(rp2[i], rp2[i + 1]) if ci2[p] == i]
+    assert np.allclose(dg, g[diag_key], rtol=1e-15, atol=0)
+
+
+def test_filter_min_hand_example():
+    _golden_filter(O.FILTER_MIN, "kept_min", "dropsum_min", "diag_dropsum_min")
+
+
+def test_filter_geomean_hand_example():
+    _golden_filter(O.FILTER_GEOMEAN, "kept_geomean", "dropsum_geomean", "diag_dropsum_geomean")
+
+
+def test_filter_tie_keeps_entry():
+    """Strict '<' in Eq. (filter): |a_ij| == tau |a_ii| keeps the entry."""
+    a = np.array([[4.0, 1.0], [1.0, 4.0]])  # tau = 0.25: 1 == 0.25 * 4
+    m = csr_of(a)
+    for mode in (O.FILTER_MIN, O.FILTER_GEOMEAN):
+        rp, ci, v, ds = O.filter_correct(m.indptr, m.indices, m.data, np.array([0, 2]), mode, 0.25)
+        assert rp[-1] == 4 and np.all(ds == 0)
+
+
+def test_filter_extremes_and_blocks():
+    rng = np.random.default_rng(4)
+    a = csr_of(rand_sparse(120, 0.1, rng, sym=True))
+    bp = gen.contiguous_blocks(120, 5)
+    for mode in (O.FILTER_MIN, O.FILTER_GEOMEAN):
+        # tau = 0: nothing dropped, the pattern is exactly the in-block pattern
+        rp, ci, v, ds = O.filter_correct(a.indptr, a.indices, a.data, bp, mode, 0.0)
+        dense = a.toarray()
+        blk = np.searchsorted(bp, np.arange(120), side="right") - 1
+        inblock = (blk[:, None] == blk[None, :]) & (dense != 0)
+        assert rp[-1] == inblock.sum() and np.all(ds == 0)
+        # tau = inf: only the diagonal remains; DROPSUM gives l1-Jacobi on the block
+        rp, ci, v, ds = O.filter_correct(a.indptr, a.indices, a.data, bp, mode, np.inf, O.DIAG_DROPSUM)
+        assert rp[-1] == 120 and np.all(ci == np.arange(120))
+        l1 = np.abs(np.where(inblock, dense, 0.0)).sum(axis=1)
+        assert np.allclose(v, l1, rtol=1e-14)
+    # monotone in tau
+    prev = None
+    for tau in (1e-3, 1e-2, 1e-1, 0.5):
+        rp, ci, _, _ = O.filter_correct(a.indptr, a.indices, a.data, bp, O.FILTER_MIN, tau)
+        cur = {(i, int(ci[p])) for i in range(120) for p in range(rp[i], rp[i + 1])}
+        if prev is not None:
+            assert cur <= prev
+        prev = cur
+
+
+def test_geomean_is_min_rule_on_unit_diagonal_scaling():
+    """GEOMEAN on M equals Eq. (filter) on D^-1/2 M D^-1/2 (unit diagonal)."""
+    rng = np.random.default_rng(5)
+    a = rand_sparse(150, 0.08, rng, sym=True)
+    a = a * np.exp(rng.uniform(-6, 6, 150))[:, None]
+    a = (a + a.T) / 2
+    np.fill_diagonal(a, np.abs(a).sum(axis=1))
+    d = np.sqrt(np.diag(a))
+    s = a / d[:, None] / d[None, :]
+    bp = np.array([0, 75, 150], dtype=np.int32)
+    m1, m2 = csr_of(a), csr_of(s)
+    for tau in (1e-3, 3e-2, 0.2):
+        rp1, ci1, _, _ = O.filter_correct(m1.indptr, m1.indices, m1.data, bp, O.FILTER_GEOMEAN, tau)
+        rp2, ci2, _, _ = O.filter_correct(m2.indptr, m2.indices, m2.data, bp, O.FILTER_MIN, tau)
+        assert np.array_equal(rp1, rp2) and np.array_equal(ci1, ci2)
+
+
+def test_dropsum_correction_dominates_block():
+    """With DROPSUM the corrected matrix minus the in-block part of M is
+    diag(dropsum) - E: symmetric, weakly diagonally dominant with a
+    non-negative diagonal, hence positive semidefinite."""
+    s = gen.c2(0.004, dense_cols=0)
+    rp, ci, v, ds = O.filter_correct(s.row_ptr, s.col, s.val, s.block_ptr, O.FILTER_GEOMEAN, 1e-2,
+                                     O.DIAG_DROPSUM)
+    n = s.n
+    Phat = sp.csr_matrix((v, ci, rp), shape=(n, n)).toarray()
+    M = s.scipy().toarray()
+    blk = np.searchsorted(s.block_ptr, np.arange(n), side="right") - 1
+    Mb = np.where(blk[:, None] == blk[None, :], M, 0.0)
+    diff = Phat - Mb
+    assert np.allclose(diff, diff.T, rtol=0, atol=1e-12 * np.abs(M).max())
+    lam = np.linalg.eigvalsh((diff + diff.T) / 2)
+    assert lam.min() >= -1e-12 * np.abs(M).max()
+
+
+def test_delta_correction_sign_rule():
+    a = np.array([[-3.0, 0.1], [0.1, 0.0 + 2.0]])
+    a[1, 1] = 0.0
+    m = sp.csr_matrix(a)
+    m = sp.csr_matrix((np.array([-3.0, 0.1, 0.1, 0.0]), np.array([0, 1, 0, 1]), np.array([0, 2, 4])))
+    rp, ci, v, _ = O.filter_correct(m.indptr, m.indices, m.data, np.array([0, 2]), O.FILTER_NONE, 0.0,
+                                    O.DIAG_DELTA, 1e-12)
+    dg = {i: v[p] for i in range(2) for p in range(rp[i], rp[i + 1]) if ci[p] == i}
+    assert dg[0] == -3.0 - 1e-12  # sign(-3) = -1
+    assert dg[1] == 1e-12         # sign(0) = +1 (reading)
+
+
+# --------------------------------------------------------------- ILU(0)
+
+def test_ilu0_hand_example_tridiagonal():
+    g = json.load(open(os.path.join(GOLD, "ilu0_tridiag_3x3.json")))
+    m = csr_of(g["matrix"])
+    v, dp, st, _, _ = O.ilu0(m.indptr, m.indices, m.data)
+    assert st == O.OK
+    L, U = unpack_lu(m.indptr, m.indices, v, 3)
+    assert np.allclose(L, g["L"], rtol=1e-15) and np.allclose(U, g["U"], rtol=1e-15)
+
+
+def test_ilu0_pattern_identity():
+    """(LU)_ij = p_ij on every pattern position (the defining property of
+    ILU(0)), up to rounding."""
+    rng = np.random.default_rng(6)
+    for sym in (False, True):
+        a = rand_sparse(200, 0.04, rng, sym=sym, dd=0.6)
+        m = csr_of(a)
+        v, dp, st, _, _ = O.ilu0(m.indptr, m.indices, m.data)
+        assert st == O.OK
+        L, U = unpack_lu(m.indptr, m.indices, v, 200)
+        LU = L @ U
+        mask = a != 0
+        err = np.abs(LU - a)[mask] / (np.abs(L) @ np.abs(U))[mask]
+        assert err.max() < 1e-13
+        if sym:
+            # symmetric input: u_ij = u_ii l_ji
+            for i in range(200):
+                for j in range(i + 1, 200):
+                    if mask[i, j]:
+                        assert abs(U[i, j] - U[i, i] * L[j, i]) <= 1e-12 * abs(U[i, j]) + 1e-300
+
+
+def test_ilu0_tridiagonal_and_dense_equal_exact_lu():
+    rng = np.random.default_rng(7)
+    for kind in ("tri", "dense"):
+        n = 60
+        if kind == "tri":
+            a = np.diag(rng.uniform(4, 5, n)) + np.diag(rng.standard_normal(n - 1), 1) + np.diag(rng.standard_normal(n - 1), -1)
+        else:
+            a = rng.standard_normal((n, n))
+            np.fill_diagonal(a, np.abs(a).sum(axis=1) + 1)
+        m = csr_of(a)
+        v, dp, st, _, _ = O.ilu0(m.indptr, m.indices, m.data)
+        L, U = unpack_lu(m.indptr, m.indices, v, n)
+        P, Ls, Us = sl.lu(a)  # diagonally dominant -> no row exchanges
+        assert np.array_equal(P, np.eye(n))
+        assert np.allclose(L, Ls, rtol=1e-12, atol=1e-14) and np.allclose(U, Us, rtol=1e-12, atol=1e-12)
+
+
+def test_ilu0_breakdown_policies():
+    """An SPD matrix whose ILU(0) meets a non-positive pivot: FAIL reports
+    it, SHIFT refactors the block with a strengthened diagonal (d + a d) and
+    the result is the ILU(0) of that shifted block."""
+    # SPD (lambda_min ~ 0.146) with a zero (1,4) entry: the fill that
+    # eliminating row 0 would put there is dropped, and the last pivot of
+    # ILU(0) goes negative (exact LU pivots stay positive).
+    a = np.array([[1.0, -0.6, 0.1, 0.2, -0.6],
+                  [-0.6, 1.0, 0.0, 0.4, 0.0],
+                  [0.1, 0.0, 1.0, -0.1, 0.0],
+                  [0.2, 0.4, -0.1, 1.0, -0.7],
+                  [-0.6, 0.0, 0.0, -0.7, 1.0]])
+    assert np.linalg.eigvalsh(a).min() > 0.1
+    assert np.all(np.diag(sl.lu(a)[2]) > 0)
+    s = gen.System("t", *(lambda m: (m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data))(csr_of(a)),
+                   b=np.ones(5), block_ptr=np.array([0, 5], dtype=np.int32))
+    fail = O.BJ(s, policy=O.PIVOT_FAIL)
+    assert fail.status == O.BREAKDOWN
+    sh = O.BJ(s, policy=O.PIVOT_SHIFT, shift0=0.01)
+    assert sh.status == O.OK and sh.shifts[0] > 0
+    a2 = a + np.diag(sh.shifts[0] * np.diag(a))
+    m2 = csr_of(a2)
+    v, dp, st, _, _ = O.ilu0(m2.indptr, m2.indices, m2.data, spd=True)
+    assert st == O.OK and np.allclose(v, sh.v, rtol=1e-14)
+    # the smaller shift a/2 still breaks down (first success of the doubling)
+    a3 = a + np.diag(sh.shifts[0] / 2 * np.diag(a))
+    m3 = csr_of(a3)
+    assert sh.shifts[0] == 0.01 or O.ilu0(m3.indptr, m3.indices, m3.data, spd=True)[2] == O.BREAKDOWN
+
+
+# --------------------------------------------------------------- BJ apply
+
+def test_bj_apply_equals_dense_block_solve():
+    s = gen.c2(0.004, dense_cols=0)
+    P = O.BJ(s, O.FILTER_GEOMEAN, 1e-2, O.DIAG_DROPSUM)
+    assert P.status == O.OK
+    n = s.n
+    L, U = unpack_lu(P.rp, P.ci, P.v, n)
+    r = np.random.default_rng(8).standard_normal(n)
+    z = P.apply(r)
+    zz = sl.solve_triangular(U, sl.solve_triangular(L, r, lower=True, unit_diagonal=True))
+    assert np.allclose(z, zz, rtol=1e-9, atol=1e-12 * np.abs(zz).max())
+    # block structure: L U is block diagonal
+    blk = np.searchsorted(s.block_ptr, np.arange(n), side="right") - 1
+    LU = L @ U
+    assert np.all(LU[blk[:, None] != blk[None, :]] == 0)
+
+
+def test_bj_with_one_row_blocks_is_jacobi():
+    rng = np.random.default_rng(9)
+    a = csr_of(rand_sparse(50, 0.1, rng, sym=True))
+    s = gen.System("j", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data, np.ones(50),
+                   np.arange(51, dtype=np.int32))
+    P = O.BJ(s)
+    r = rng.standard_normal(50)
+    assert np.allclose(P.apply(r), r / a.diagonal(), rtol=1e-15)
+
+
+# --------------------------------------------------------------- PCG
+
+def _small_spd(n, seed):
+    rng = np.random.default_rng(seed)
+    a = rand_sparse(n, 0.15, rng, sym=True, dd=0.3)
+    a = a + a.T
+    w = np.linalg.eigvalsh(a)
+    a = a + (1e-2 - min(w.min(), 0)) * np.eye(n) * (w.min() < 1e-2)
+    m = csr_of(a)
+    b = rng.standard_normal(n)
+    return gen.System("spd", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, b,
+                      gen.contiguous_blocks(n, 3)), a
+
+
+def test_pcg_iterates_are_krylov_minimisers_and_monotone():
+    """x_k minimises the M-norm error over K_k(P^-1 M, P^-1 b) (x0 = 0), and
+    that error never increases (paper Sec. 2.2, CG)."""
+    s, a = _small_spd(40, 10)
+    P = O.BJ(s, policy=O.PIVOT_FAIL, spd=True)
+    assert P.status == O.OK
+    n = s.n
+    L, U = unpack_lu(P.rp, P.ci, P.v, n)
+    Pm = L @ U
+    Pinv = np.linalg.inv(Pm)
+    xs = np.linalg.solve(a, s.b)
+    errs = []
+    for k in range(1, 9):
+        x, its, rr, st, _ = O.pcg_bj(s, P, tol=1e-30, maxit=k)
+        assert its == k
+        K = [Pinv @ s.b]
+        for _ in range(k - 1):
+            K.append(Pinv @ (a @ K[-1]))
+        Q, _ = np.linalg.qr(np.array(K).T)
+        y = np.linalg.solve(Q.T @ a @ Q, Q.T @ s.b)
+        xb = Q @ y
+        assert np.linalg.norm(x - xb) <= 1e-7 * np.linalg.norm(xb)
+        e = x - xs
+        errs.append(np.sqrt(e @ a @ e))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-12) for i in range(len(errs) - 1))
+
+
+def test_pcg_exact_preconditioner_converges_in_one_step():
+    """Tridiagonal SPD matrix in one block: ILU(0) is the exact LU, so PCG
+    converges in one iteration."""
+    n = 300
+    rng = np.random.default_rng(11)
+    off = rng.standard_normal(n - 1)
+    a = np.diag(np.abs(np.r_[off, 0]) + np.abs(np.r_[0, off]) + 0.5) + np.diag(off, 1) + np.diag(off, -1)
+    m = csr_of(a)
+    s = gen.System("tri", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                   rng.standard_normal(n), np.array([0, n], dtype=np.int32))
+    P = O.BJ(s)
+    x, its, rr, st, _ = O.pcg_bj(s, P, tol=1e-12)
+    assert st == O.OK and its == 1 and rr <= 1e-12
+
+
+def test_pcg_c1_true_residual():
+    s = gen.c1()
+    P = O.BJ(s)
+    x, its, rr, st, _ = O.pcg_bj(s, P)
+    assert st == O.OK and rr <= 1e-8
+    # true residual recomputed independently with scipy
+    M = s.scipy()
+    assert np.linalg.norm(s.b - M @ x) / np.linalg.norm(s.b) <= 1.5e-8
+    # against a direct solve: ||x - x*||_M / ||x*||_M is bounded by kappa * relres
+    xs = sp.linalg.spsolve(M.tocsc(), s.b)
+    e = x - xs
+    assert np.sqrt(e @ (M @ e)) / np.sqrt(xs @ (M @ xs)) < 1e-4
+
+
+# --------------------------------------------------------------- GMRES
+
+def test_gmres_iterates_minimise_residual():
+    rng = np.random.default_rng(12)
+    n = 50
+    a = rand_sparse(n, 0.15, rng, dd=0.4)
+    m = csr_of(a)
+    s = gen.System("ns", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                   rng.standard_normal(n), gen.contiguous_blocks(n, 4))
+    P = O.BJ(s, spd=False, policy=O.PIVOT_FAIL)
+    L, U = unpack_lu(P.rp, P.ci, P.v, n)
+    Pinv = np.linalg.inv(L @ U)
+    prev = np.inf
+    for k in range(1, 10):
+        x, its, rr, st, hist = O.gmres_bj(s, P, tol=1e-30, m=30, maxit=k, hist=True)
+        # brute force: min ||b - M P^-1 y|| over y in K_k(M P^-1, b)
+        K = [s.b]
+        for _ in range(k - 1):
+            K.append(a @ (Pinv @ K[-1]))
+        Q, _ = np.linalg.qr(np.array(K).T)
+        B = a @ Pinv @ Q
+        c, *_ = np.linalg.lstsq(B, s.b, rcond=None)
+        xb = Pinv @ (Q @ c)
+        assert np.linalg.norm(x - xb) <= 1e-8 * max(1.0, np.linalg.norm(xb))
+        assert rr <= prev * (1 + 1e-12)
+        prev = rr
+
+
+def test_gmres_full_dimension_converges():
+    rng = np.random.default_rng(13)
+    n = 25
+    a = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    m = csr_of(a)
+    s = gen.System("g", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                   rng.standard_normal(n), np.arange(n + 1, dtype=np.int32))
+    P = O.BJ(s, spd=False, policy=O.PIVOT_FAIL)
+    x, its, rr, st, _ = O.gmres_bj(s, P, tol=1e-10, m=30)
+    assert st == O.OK and its <= n
+
+
+# --------------------------------------------------------------- BBD
+
+def _bbd_dense_parts(s, P):
+    n, nb = s.n, s.n_border
+    ni = n - nb
+    M = s.scipy().toarray()
+    parts = P.parts()
+    L, U = unpack_lu(parts["lrp"], parts["lci"], parts["lv"], ni)
+    E, F, Cc = M[:ni, ni:], M[ni:, :ni], M[ni:, ni:]
+    return M, L, U, E, F, Cc, parts
+
+
+def test_bbd_schur_and_apply_match_dense():
+    s = gen.bbd_system(nblocks=3, block_rows=60, n_border=12, nnz_off=4, half_band=10, tail_frac=0.2,
+                       border_c=2, seed=14, name="bbd-tiny")
+    P = O.BBD(s)
+    assert P.status == O.OK
+    M, L, U, E, F, Cc, parts = _bbd_dense_parts(s, P)
+    S = Cc - F @ np.linalg.solve(L @ U, E)
+    # oracle LU of S with its pivots reproduces S
+    lu, piv = parts["S"], parts["piv"]
+    nb = s.n_border
+    Ls = np.tril(lu, -1) + np.eye(nb)
+    Us = np.triu(lu)
+    Sp = S.copy()
+    for k in range(nb):
+        Sp[[k, piv[k]]] = Sp[[piv[k], k]]
+    assert np.linalg.norm(Sp - Ls @ Us) <= 1e-12 * np.linalg.norm(S) * nb
+    # pivots are LAPACK's (first maximum)
+    lu_ref, piv_ref = sl.lu_factor(S)
+    assert np.array_equal(piv, piv_ref)
+    # apply = solve with the assembled M_BBD
+    Mbbd = np.block([[L @ U, E], [F, Cc]])
+    r = np.random.default_rng(15).standard_normal(s.n)
+    z = P.apply(r)
+    zz = np.linalg.solve(Mbbd, r)
+    assert np.allclose(z, zz, rtol=1e-9, atol=1e-11 * np.abs(zz).max())
+    # tail = first local index coupled to the border
+    ni = s.n - nb
+    for b in range(3):
+        lo, hi = s.block_ptr[b], s.block_ptr[b + 1]
+        rows_e = np.nonzero(np.any(E[lo:hi] != 0, axis=1))[0]
+        cols_f = np.nonzero(np.any(F[:, lo:hi] != 0, axis=0))[0]
+        assert parts["tail"][b] == lo + min(rows_e.min(), cols_f.min())
+
+
+def test_bbd_exact_blocks_gmres_one_step():
+    """Tridiagonal interior blocks: ILU(0) is exact, M_BBD = M, and
+    right-preconditioned GMRES converges in one step."""
+    s = gen.bbd_system(nblocks=4, block_rows=80, n_border=16, nnz_off=1, half_band=1, tail_frac=0.1,
+                       border_c=2, seed=16, name="bbd-tri")
+    P = O.BBD(s)
+    assert P.status == O.OK
+    x, its, rr, st, _ = O.gmres_bbd(s, P, tol=1e-10)
+    assert st == O.OK and its == 1 and rr <= 1e-10
+
+
+def test_bbd_rejects_block_coupling():
+    s = gen.bbd_system(nblocks=2, block_rows=30, n_border=6, nnz_off=2, half_band=4, tail_frac=0.2,
+                       border_c=1, seed=17)
+    M = s.scipy().tolil()
+    M[0, 45] = 1.0  # block 0 row -> block 1 column
+    M = M.tocsr()
+    M.sort_indices()
+    s2 = gen.System("bad", M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data, s.b,
+                    s.block_ptr, n_border=s.n_border)
+    assert O.BBD(s2).status == O.STRUCTURE
+
+
+def test_dense_lu_matches_lapack():
+    rng = np.random.default_rng(18)
+    a = rng.standard_normal((70, 70))
+    lu, piv, st = O.dense_lu(a)
+    lu_ref, piv_ref = sl.lu_factor(a)
+    assert st == O.OK and np.array_equal(piv, piv_ref)
+    assert np.allclose(lu, lu_ref, rtol=1e-12, atol=1e-13)
+    b = rng.standard_normal(70)
+    assert np.allclose(O.dense_lu_solve(lu, piv, b), np.linalg.solve(a, b), rtol=1e-10)
+
+
+# --------------------------------------------------------------- IR
+
+def test_ir_reaches_tolerance_and_matches_fp64_solution():
+    s = gen.c2(0.004, dense_cols=0)
+    P = O.BJ(s, O.FILTER_GEOMEAN, 1e-3, O.DIAG_DROPSUM)
+    x, outer, inner, fb, rr, st = O.ir_pcg_bj(s, P, tol=1e-8)
+    assert st == O.OK and rr <= 1e-8 and outer >= 2
+    M = s.scipy()
+    assert np.linalg.norm(s.b - M @ x) / np.linalg.norm(s.b) <= 1.5e-8
+    x64, its, rr64, st64, _ = O.pcg_bj(s, P, tol=1e-8)
+    e = x - x64
+    den = np.sqrt(x64 @ (M @ x64))
+    assert np.sqrt(e @ (M @ e)) / den < 1e-3
