@@ -1,0 +1,228 @@
+/*
+ * sdsl.h - C ABI of the MI355X (gfx950) preconditioned Krylov solver for
+ * interior-point-method linear systems.
+ *
+ * The method is that of "SDSL-Solver: Scalable Distributed Sparse Linear
+ * Solvers for Large-Scale Interior Point Methods" (arXiv 2604.23979): at every
+ * IPM iteration a sparse system M x = b (Sec. 2.1, Eq. (schur); Alg. 1 takes
+ * "Ax = b at each interior-point iteration" as its input) is solved by a
+ * preconditioned Krylov method (Sec. 2.2, right preconditioning) with either
+ *   - a block-Jacobi preconditioner (Sec. 2.3): contiguous row blocks, each
+ *     diagonal block filtered (Sec. 3.2, Eq. (filter)), diagonally corrected
+ *     (Sec. 3.3, Eq. (diagcorr)) and ILU(0) factored; or
+ *   - a bordered-block-diagonal (BBD) preconditioner (Sec. 2.4): factored
+ *     interior blocks coupled through a dense Schur complement of the border.
+ * Preconditioners stay resident between calls so that consecutive IPM systems
+ * reuse them (Sec. 3.4).
+ *
+ * All arrays named "device" live in GPU memory of the current HIP device;
+ * "host" arrays live in CPU memory.  Every call returns an sdsl_status and
+ * never aborts or throws; sdsl_last_error() gives a readable reason.  A handle
+ * stays usable after any error except SDSL_E_DEVICE.  Handles are not
+ * thread-safe; distinct handles may be used from distinct threads.
+ * Int32 indices are used internally: n and nnz must be below 2^31.
+ */
+#ifndef SDSL_H
+#define SDSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDSL_ABI_VERSION 1
+
+typedef struct sdsl_ctx* sdsl_handle;
+
+typedef enum {
+    SDSL_OK = 0,
+    SDSL_E_INVALID = 1,       /* bad argument: NaN/Inf, unsorted or duplicate
+                                 columns, missing diagonal, bad partition     */
+    SDSL_E_STRUCTURE = 2,     /* BBD: matrix not in bordered block form        */
+    SDSL_E_NOMEM = 3,         /* device allocation failed                      */
+    SDSL_E_BREAKDOWN = 4,     /* factorisation pivot or Krylov breakdown       */
+    SDSL_E_NOT_CONVERGED = 5, /* tolerance not reached within the limits      */
+    SDSL_E_DEVICE = 6,        /* HIP runtime error; the handle is unusable     */
+    SDSL_E_STATE = 7          /* call not valid in the handle's state          */
+} sdsl_status;
+
+typedef enum { SDSL_BJ = 0, SDSL_BBD = 1 } sdsl_method;           /* Sec. 2.3 / 2.4 */
+
+/* Sparse filter of Sec. 3.2.  MIN is Eq. (filter): drop a_ij (i != j) iff
+ * |a_ij| < tau |a_ii| and |a_ij| < tau |a_jj|.  GEOMEAN drops iff
+ * a_ij^2 < tau^2 |a_ii a_jj|, which is Eq. (filter) after symmetric scaling
+ * to a unit diagonal.  Diagonals are always kept; the diagonals used in the
+ * test are those of the unfiltered matrix. */
+typedef enum { SDSL_FILTER_NONE = 0, SDSL_FILTER_MIN = 1, SDSL_FILTER_GEOMEAN = 2 } sdsl_filter;
+
+/* Diagonal correction of Sec. 3.3 (bit flags, applied to the preconditioner
+ * only).  DELTA is Eq. (diagcorr): p_ii += delta * sign(p_ii), sign(0) = +1.
+ * DROPSUM adds sign(p_ii) * (sum of |a_ij| dropped by the filter in row i).
+ * Both together add sign(p_ii) * (delta + dropsum_i). */
+enum { SDSL_DIAG_DELTA = 1u, SDSL_DIAG_DROPSUM = 2u };
+
+/* What to do when ILU(0) meets a bad pivot (non-positive in SPD mode,
+ * |u_ii| < 1e-14 |p_ii| otherwise).  FAIL returns SDSL_E_BREAKDOWN; REPLACE
+ * replaces the pivot by its corrected diagonal; SHIFT refactors the block
+ * with every diagonal raised to d + a*d for a = shift0, 2*shift0, ... (the
+ * correction of Eq. (diagcorr) taken relative to the diagonal). */
+typedef enum { SDSL_PIVOT_FAIL = 0, SDSL_PIVOT_REPLACE = 1, SDSL_PIVOT_SHIFT = 2 } sdsl_pivot;
+
+typedef enum { SDSL_PCG = 0, SDSL_GMRES = 1 } sdsl_krylov;          /* Sec. 2.2 */
+
+/* FP64: every step in FP64.  FP32_IR: FP64 iterative refinement around an
+ * inner solve whose operator values, factors and vectors are FP32 (products
+ * and triangular solves accumulate in FP32, dot products in FP64). */
+typedef enum { SDSL_FP64 = 0, SDSL_FP32_IR = 1 } sdsl_precision;
+
+typedef enum { SDSL_MEM_DEVICE = 0, SDSL_MEM_HOST = 1 } sdsl_mem;
+
+/* Square sparse matrix in CSR: row_ptr[n+1] (int64), col[nnz] (int32,
+ * strictly increasing within a row, diagonal present), val[nnz] (double).
+ * `mem` says where the three arrays live. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+    sdsl_mem mem;
+} sdsl_csr;
+
+/* Contiguous row blocks (Sec. 2.3 "partition"): block_ptr is a HOST array of
+ * nblocks+1 increasing row indices with block_ptr[0] = 0 and
+ * block_ptr[nblocks] = n - n_border.  For BBD the n_border trailing rows are
+ * the border (Sec. 2.4); for BJ n_border must be 0. */
+typedef struct {
+    int32_t nblocks;
+    const int32_t* block_ptr;
+    int32_t n_border;
+} sdsl_partition;
+
+/* Optional low-rank operator term: the operator becomes M + U diag(c) U^T
+ * with U an n x k CSR matrix (dense columns of the constraint matrix kept
+ * apart, Sec. 2.1).  The preconditioner is built from M alone.  Arrays live
+ * where U.mem says; c has k entries in the same memory. */
+typedef struct {
+    int32_t k;
+    sdsl_csr U;          /* n x k: U.n = n rows, columns 0..k-1             */
+    const double* c;
+} sdsl_lowrank;
+
+typedef struct {
+    sdsl_method method;
+    sdsl_filter filter;
+    double tau;            /* filter threshold (Sec. 3.2; 1e-3 typical)      */
+    uint32_t diag_flags;   /* SDSL_DIAG_* bits                               */
+    double delta;          /* Eq. (diagcorr) delta (paper: 1e-12 typical)    */
+    sdsl_pivot pivot;      /* ILU(0) breakdown policy                        */
+    double shift0;         /* first relative shift of SDSL_PIVOT_SHIFT       */
+    int32_t spd;           /* 1: symmetric positive definite mode            */
+    sdsl_krylov krylov;
+    int32_t restart;       /* GMRES(m) restart length                        */
+    int32_t max_iter;      /* Krylov iterations (all inner iterations)       */
+    sdsl_precision precision;
+    double inner_tol;      /* FP32_IR: relative tolerance of each inner solve */
+    int32_t max_outer;     /* FP32_IR: refinement steps                       */
+    int32_t check_every;   /* iterations launched between convergence checks */
+} sdsl_options;
+
+typedef struct {
+    int64_t nnz_kept;       /* entries of the filtered block preconditioner  */
+    int64_t nnz_dropped;    /* in-block entries dropped by the filter        */
+    int32_t pivot_fixes;    /* REPLACE policy: replaced pivots               */
+    int32_t shifted_blocks; /* SHIFT policy: blocks refactored with a shift  */
+    double max_shift;       /* SHIFT policy: largest relative shift used     */
+    int32_t outer_iters;    /* FP32_IR refinement steps of the last solve    */
+    int32_t inner_iters;    /* Krylov iterations of the last solve (total)   */
+    int32_t fp64_fallbacks; /* FP32_IR: inner solves redone in FP64          */
+    int32_t restarts;       /* restarts from the true residual               */
+    double setup_ms;        /* last setup / refactor time                    */
+    double solve_ms;        /* last solve time                               */
+    double relres;          /* last true relative residual                   */
+    int64_t bytes_per_iter; /* algorithmic bytes of one Krylov iteration     */
+    int64_t device_bytes;   /* device memory held by the handle              */
+} sdsl_info;
+
+/* Fills *o with defaults: BJ, no filter, no correction, SHIFT(1e-2), SPD,
+ * PCG, restart 30, max_iter 100000, FP64, inner_tol 1e-4, max_outer 30,
+ * check_every 16. */
+void sdsl_default_options(sdsl_options* o);
+
+/* Device bytes a handle for this problem will hold (for admission control).
+ * Returns 0 on invalid arguments. */
+size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o,
+                            const sdsl_lowrank* lr);
+
+/* Creates a handle: validates A and the partition, copies A (and the
+ * low-rank term, may be NULL) into handle-owned device memory, builds and
+ * factors the preconditioner (filter Eq. (filter), correction Eq. (diagcorr),
+ * ILU(0) of every block in one launch; for BBD also the dense Schur
+ * complement and its LU).  `hip_stream` (a hipStream_t, NULL = default
+ * stream) orders every later call of the handle.  The caller's arrays may be
+ * freed when the call returns.  On error *out is NULL. */
+sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o,
+                       const sdsl_lowrank* lr, void* hip_stream, sdsl_handle* out);
+
+/* New values for the same pattern (Sec. 3.4, "reuse the symbolic ... and
+ * perform only the numerical factorization"): new_val (DEVICE, nnz doubles in
+ * the CSR order given at setup) replaces the operator values, and the filter,
+ * correction and factorisation are redone.  Stream-ordered; returns after the
+ * factorisation finished. */
+sdsl_status sdsl_refactor(sdsl_handle h, const double* new_val);
+
+/* New operator values only; the preconditioner is kept (Sec. 3.4, the
+ * aggressive mode that reuses the numerical factorisation). */
+sdsl_status sdsl_update_values(sdsl_handle h, const double* new_val);
+
+/* Solves M x = b to ||b - Mx||_2 <= tol ||b||_2 with x0 = 0.  b and x are
+ * DEVICE arrays of n doubles (x is overwritten).  On return *iters holds the
+ * Krylov iterations (inner iterations summed for FP32_IR) and *relres the
+ * true relative residual recomputed in compensated FP64.  Returns
+ * SDSL_E_NOT_CONVERGED (x = last iterate) or SDSL_E_BREAKDOWN on failure. */
+sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, int32_t* iters,
+                       double* relres);
+
+/* Solves k independent systems, one per handle, with their launches
+ * interleaved on the handles' streams so that they overlap on the device.
+ * Each result equals that of sdsl_solve on the same handle.  iters/relres
+ * are HOST arrays of k entries.  Returns the first non-OK status. */
+sdsl_status sdsl_solve_batch(int32_t k, const sdsl_handle* hs, const double* const* b,
+                             double* const* x, double tol, int32_t* iters, double* relres);
+
+sdsl_status sdsl_get_info(sdsl_handle h, sdsl_info* out);
+
+/* Last error message of h (or of the calling thread when h is NULL). */
+const char* sdsl_last_error(sdsl_handle h);
+
+void sdsl_destroy(sdsl_handle h);
+
+/* ---- single-step entry points (kernel-level checks) -------------------- */
+
+/* y = M x (+ U diag(c) U^T x).  prec: SDSL_FP64 uses the FP64 values and
+ * vectors; SDSL_FP32_IR uses the FP32 values with FP32 x and y (x, y point to
+ * n floats).  DEVICE arrays; stream-ordered, returns after completion. */
+sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y);
+
+/* z = P^{-1} r with the handle's preconditioner (BJ: forward then backward
+ * substitution per block, Sec. 2.3; BBD: the Schur-coupled solve, Sec. 2.4).
+ * prec as for sdsl_spmv.  DEVICE arrays. */
+sdsl_status sdsl_precond_apply(sdsl_handle h, int32_t prec, const void* r, void* z);
+
+/* r = b - M x in compensated FP64; *norm receives ||r||_2.  DEVICE arrays. */
+sdsl_status sdsl_residual(sdsl_handle h, const double* b, const double* x, double* r, double* norm);
+
+/* Copies the filtered preconditioner pattern and its factors to HOST arrays
+ * (any pointer may be NULL): row_ptr[n_int+1] (int64), col[nnz_kept],
+ * corrected[nnz_kept] (filtered + corrected values before factorisation),
+ * lu[nnz_kept] (ILU(0) factors in place: strict lower = L, rest = U),
+ * shifts[nblocks] (relative shift used per block). */
+sdsl_status sdsl_get_factors(sdsl_handle h, int64_t* row_ptr, int32_t* col, double* corrected,
+                             double* lu, double* shifts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SDSL_H */

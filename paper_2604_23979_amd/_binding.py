@@ -1,0 +1,296 @@
+"""ctypes binding of libsdsl.so (the C ABI declared in include/sdsl.h).
+
+Argument marshalling only: every numerical step runs in the library's gfx950
+kernels.  Device memory and streams come from PyTorch.  There is no fallback:
+if the library is missing, importing the solver raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdsl.so")
+
+OK, E_INVALID, E_STRUCTURE, E_NOMEM, E_BREAKDOWN, E_NOT_CONVERGED, E_DEVICE, E_STATE = range(8)
+STATUS_NAMES = ["OK", "E_INVALID", "E_STRUCTURE", "E_NOMEM", "E_BREAKDOWN", "E_NOT_CONVERGED", "E_DEVICE",
+                "E_STATE"]
+BJ, BBD = 0, 1
+FILTER_NONE, FILTER_MIN, FILTER_GEOMEAN = 0, 1, 2
+DIAG_DELTA, DIAG_DROPSUM = 1, 2
+PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT = 0, 1, 2
+PCG, GMRES = 0, 1
+FP64, FP32_IR = 0, 1
+MEM_DEVICE, MEM_HOST = 0, 1
+
+
+class SdslError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        self.status = status
+
+
+class CSR(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p), ("mem", C.c_int)]
+
+
+class Partition(C.Structure):
+    _fields_ = [("nblocks", C.c_int32), ("block_ptr", C.c_void_p), ("n_border", C.c_int32)]
+
+
+class LowRank(C.Structure):
+    _fields_ = [("k", C.c_int32), ("U", CSR), ("c", C.c_void_p)]
+
+
+class COptions(C.Structure):
+    _fields_ = [("method", C.c_int), ("filter", C.c_int), ("tau", C.c_double), ("diag_flags", C.c_uint32),
+                ("delta", C.c_double), ("pivot", C.c_int), ("shift0", C.c_double), ("spd", C.c_int32),
+                ("krylov", C.c_int), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32)]
+
+
+class CInfo(C.Structure):
+    _fields_ = [("nnz_kept", C.c_int64), ("nnz_dropped", C.c_int64), ("pivot_fixes", C.c_int32),
+                ("shifted_blocks", C.c_int32), ("max_shift", C.c_double), ("outer_iters", C.c_int32),
+                ("inner_iters", C.c_int32), ("fp64_fallbacks", C.c_int32), ("restarts", C.c_int32),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("relres", C.c_double),
+                ("bytes_per_iter", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+# every symbol the header declares, with its ctypes signature
+H = C.c_void_p
+P = C.c_void_p
+SIGNATURES = {
+    "sdsl_default_options": (None, [C.POINTER(COptions)]),
+    "sdsl_footprint_bytes": (C.c_size_t, [C.POINTER(CSR), C.POINTER(Partition), C.POINTER(COptions),
+                                          C.POINTER(LowRank)]),
+    "sdsl_setup": (C.c_int, [C.POINTER(CSR), C.POINTER(Partition), C.POINTER(COptions), C.POINTER(LowRank), P,
+                             C.POINTER(H)]),
+    "sdsl_refactor": (C.c_int, [H, P]),
+    "sdsl_update_values": (C.c_int, [H, P]),
+    "sdsl_solve": (C.c_int, [H, P, P, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "sdsl_solve_batch": (C.c_int, [C.c_int32, P, P, P, C.c_double, P, P]),
+    "sdsl_get_info": (C.c_int, [H, C.POINTER(CInfo)]),
+    "sdsl_last_error": (C.c_char_p, [H]),
+    "sdsl_destroy": (None, [H]),
+    "sdsl_spmv": (C.c_int, [H, C.c_int32, P, P]),
+    "sdsl_precond_apply": (C.c_int, [H, C.c_int32, P, P]),
+    "sdsl_residual": (C.c_int, [H, P, P, P, C.POINTER(C.c_double)]),
+    "sdsl_get_factors": (C.c_int, [H, P, P, P, P, P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsdsl.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2604_23979_amd.build` first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+@dataclasses.dataclass
+class Options:
+    method: int = BJ
+    filter: int = FILTER_NONE
+    tau: float = 0.0
+    diag_flags: int = 0
+    delta: float = 0.0
+    pivot: int = PIVOT_SHIFT
+    shift0: float = 1e-2
+    spd: bool = True
+    krylov: int = PCG
+    restart: int = 30
+    max_iter: int = 100000
+    precision: int = FP64
+    inner_tol: float = 1e-4
+    max_outer: int = 30
+    check_every: int = 16
+
+    def c(self) -> COptions:
+        o = COptions()
+        for f in dataclasses.fields(self):
+            setattr(o, f.name, int(getattr(self, f.name)) if isinstance(getattr(self, f.name), bool)
+                    else getattr(self, f.name))
+        return o
+
+
+def _check(h, st):
+    if st != OK:
+        msg = lib().sdsl_last_error(h)
+        raise SdslError(st, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """A resident preconditioned solver for one sparsity pattern.
+
+    ``row_ptr``/``col``/``val`` are numpy arrays (copied from host memory) or
+    torch CUDA tensors (int64 / int32 / float64, copied device to device).
+    ``block_ptr`` is a host int array of contiguous row blocks."""
+
+    def __init__(self, row_ptr, col, val, block_ptr, n_border: int = 0, lowrank=None,
+                 options: Optional[Options] = None, stream=None):
+        import torch
+        self.options = options or Options()
+        self._keep = []
+        on_dev = isinstance(val, torch.Tensor)
+        if on_dev:
+            row_ptr = row_ptr.to(torch.int64).contiguous()
+            col = col.to(torch.int32).contiguous()
+            val = val.to(torch.float64).contiguous()
+            ptrs = [C.c_void_p(t.data_ptr()) for t in (row_ptr, col, val)]
+            n = row_ptr.numel() - 1
+            nnz = col.numel()
+            self._keep += [row_ptr, col, val]
+        else:
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            val = np.ascontiguousarray(val, dtype=np.float64)
+            ptrs = [a.ctypes.data_as(C.c_void_p) for a in (row_ptr, col, val)]
+            n = row_ptr.shape[0] - 1
+            nnz = col.shape[0]
+            self._keep += [row_ptr, col, val]
+        A = CSR(n, nnz, ptrs[0], ptrs[1], ptrs[2], MEM_DEVICE if on_dev else MEM_HOST)
+        bp = np.ascontiguousarray(block_ptr, dtype=np.int32)
+        self._keep.append(bp)
+        part = Partition(bp.shape[0] - 1, bp.ctypes.data_as(C.c_void_p), int(n_border))
+        lrp = None
+        if lowrank is not None:
+            U, cvec = lowrank
+            urp = np.ascontiguousarray(U.indptr, dtype=np.int64)
+            uci = np.ascontiguousarray(U.indices, dtype=np.int32)
+            uv = np.ascontiguousarray(U.data, dtype=np.float64)
+            cc = np.ascontiguousarray(cvec, dtype=np.float64)
+            self._keep += [urp, uci, uv, cc]
+            lrp = LowRank(U.shape[1], CSR(n, uv.shape[0], urp.ctypes.data_as(C.c_void_p),
+                                          uci.ctypes.data_as(C.c_void_p), uv.ctypes.data_as(C.c_void_p),
+                                          MEM_HOST), cc.ctypes.data_as(C.c_void_p))
+        self.n, self.nnz, self.nblocks = n, nnz, bp.shape[0] - 1
+        self.stream = stream
+        self._opts = self.options.c()
+        h = C.c_void_p()
+        st = lib().sdsl_setup(C.byref(A), C.byref(part), C.byref(self._opts),
+                              C.byref(lrp) if lrp is not None else None, _stream_ptr(stream), C.byref(h))
+        self._keep = []
+        if st != OK:
+            msg = lib().sdsl_last_error(None)
+            raise SdslError(st, msg.decode() if msg else "")
+        self.h = h
+
+    # -- solves
+    def solve(self, b, x=None, tol: float = 1e-8, check: bool = True):
+        """Solve M x = b (b: CUDA float64 tensor).  Returns (x, iters, relres, status)."""
+        import torch
+        assert b.is_cuda and b.dtype == torch.float64 and b.numel() == self.n
+        b = b.contiguous()
+        self._order()
+        if x is None:
+            x = torch.empty_like(b)
+        its = C.c_int32(0)
+        rr = C.c_double(0.0)
+        st = lib().sdsl_solve(self.h, _dptr(b), _dptr(x), tol, C.byref(its), C.byref(rr))
+        if check and st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN):
+            _check(self.h, st)
+        return x, its.value, rr.value, st
+
+    def _order(self):
+        """Work on torch's current stream must be finished before a handle
+        on another stream reads it."""
+        if self.stream is not None:
+            import torch
+            torch.cuda.current_stream().synchronize()
+
+    def refactor(self, vals):
+        self._order()
+        _check(self.h, lib().sdsl_refactor(self.h, _dptr(vals.contiguous())))
+
+    def update_values(self, vals):
+        self._order()
+        _check(self.h, lib().sdsl_update_values(self.h, _dptr(vals.contiguous())))
+
+    # -- single steps
+    def spmv(self, x, fp32: bool = False):
+        import torch
+        y = torch.empty_like(x)
+        _check(self.h, lib().sdsl_spmv(self.h, FP32_IR if fp32 else FP64, _dptr(x), _dptr(y)))
+        return y
+
+    def precond_apply(self, r, fp32: bool = False):
+        import torch
+        z = torch.empty_like(r)
+        _check(self.h, lib().sdsl_precond_apply(self.h, FP32_IR if fp32 else FP64, _dptr(r), _dptr(z)))
+        return z
+
+    def residual(self, b, x):
+        import torch
+        r = torch.empty_like(b)
+        nr = C.c_double(0.0)
+        _check(self.h, lib().sdsl_residual(self.h, _dptr(b), _dptr(x), _dptr(r), C.byref(nr)))
+        return r, nr.value
+
+    def factors(self):
+        info = self.info()
+        n_int = None
+        kept = int(info["nnz_kept"])
+        # row_ptr length is n - n_border + 1; ask for it through nnz_kept's rows
+        rp = np.zeros(self.n + 1, dtype=np.int64)
+        ci = np.zeros(max(kept, 1), dtype=np.int32)
+        corr = np.zeros(max(kept, 1))
+        lu = np.zeros(max(kept, 1))
+        sh = np.zeros(self.nblocks)
+        _check(self.h, lib().sdsl_get_factors(self.h, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                                              corr.ctypes.data_as(C.c_void_p), lu.ctypes.data_as(C.c_void_p),
+                                              sh.ctypes.data_as(C.c_void_p)))
+        del n_int
+        return dict(row_ptr=rp, col=ci[:kept], corrected=corr[:kept], lu=lu[:kept], shifts=sh)
+
+    def info(self) -> dict:
+        inf = CInfo()
+        _check(self.h, lib().sdsl_get_info(self.h, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in CInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sdsl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(solvers, bs, xs, tol: float = 1e-8):
+    """Solve several systems with interleaved launches (one per solver)."""
+    k = len(solvers)
+    hs = (C.c_void_p * k)(*[s.h for s in solvers])
+    bp = (C.c_void_p * k)(*[b.data_ptr() for b in bs])
+    xp = (C.c_void_p * k)(*[x.data_ptr() for x in xs])
+    its = np.zeros(k, dtype=np.int32)
+    rr = np.zeros(k)
+    st = lib().sdsl_solve_batch(k, hs, bp, xp, tol, its.ctypes.data_as(C.c_void_p), rr.ctypes.data_as(C.c_void_p))
+    return its, rr, st

@@ -1,0 +1,193 @@
+// Internal declarations shared by the gfx950 kernels and the host runtime.
+// Every kernel is hand-written HIP for CDNA4 (64-wide wavefronts).  The files
+// are compiled with -ffp-contract=off: every fused multiply-add is written as
+// fma(), so the arithmetic is exactly what the source says.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sdsl.h"
+
+namespace sdsl {
+
+constexpr int kWave = 64;
+
+// -------------------------------------------------------------- device state
+// Per-solve scalars that the iteration kernels read and write on the device,
+// so that no Krylov scalar round-trips through the host.
+struct KrylovState {
+    int done;        // set once converged / broken down: later kernels exit at entry
+    int conv;        // 1: recurrence residual met the tolerance
+    int breakdown;   // 1: (p, Mp) <= 0 or a non-finite scalar
+    int iters;       // iteration count at the moment `done` was set
+    int spin_err;    // a bounded in-workgroup wait gave up (never expected)
+    int pad[3];
+    double bb;       // ||b||^2 of the current (inner) right-hand side
+    double tol2;     // tol^2 for the squared-residual test
+};
+
+// -------------------------------------------------------------- reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum over aligned groups of G lanes (G a power of two <= 64).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Deterministic block sum: per-wave shuffle tree, then wave 0 sums the wave
+// results in wave order.  `scratch` holds >= blockDim.x / 64 doubles.  The
+// result is valid in every thread.  Must be reached by all threads.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (l == 0) scratch[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (w == 0) {
+        s = (l < nw) ? scratch[l] : 0.0;
+        s = wave_sum(s);
+        if (l == 0) scratch[0] = s;
+    }
+    __syncthreads();
+    s = scratch[0];
+    __syncthreads();
+    return s;
+}
+
+// Sum of a[0..m) in a fixed order (strided per thread, then block_sum), the
+// same in every workgroup that calls it.
+__device__ __forceinline__ double block_sum_array(const double* a, int m, double* scratch) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) s += a[i];
+    return block_sum(s, scratch);
+}
+
+// -------------------------------------------------------------- sentinels
+// A solution slot that is not yet written holds a signalling-NaN pattern
+// that no arithmetic produces (arithmetic NaNs are quiet), so the value
+// itself says whether it is ready.
+template <typename T> struct Sentinel;
+template <> struct Sentinel<double> {
+    using Bits = unsigned long long;
+    static constexpr Bits bits = 0x7FF40000DEADBEEFull;
+};
+template <> struct Sentinel<float> {
+    using Bits = unsigned int;
+    static constexpr Bits bits = 0x7FA0BEEFu;
+};
+
+// -------------------------------------------------------------- launchers
+// Setup kernels (kernels_setup.hip).
+struct ValidateOut {
+    int bad_rows;        // rows with unsorted/duplicate/out-of-range columns
+    int missing_diag;    // rows without a stored diagonal
+    int nonfinite;       // non-finite values
+    int bad_rowptr;      // decreasing row pointers
+    int first_bad;       // smallest offending row (or INT_MAX)
+};
+
+void launch_validate(int n, const int64_t* rp64, const int* ci, const double* v, ValidateOut* out,
+                     hipStream_t s);
+void launch_count_nonfinite(int64_t m, const double* v, ValidateOut* out, hipStream_t s);
+void launch_rowptr32(int n, const int64_t* rp64, int* rp32, hipStream_t s);
+void launch_cast_f32(int64_t m, const double* a, float* b, hipStream_t s);
+void launch_diag(int n, const int* rp, const int* ci, const double* v, double* diag, hipStream_t s);
+void launch_filter_count(int n_int, const int* rp, const int* ci, const double* v, const double* diag,
+                         const int* bp, int nblocks, int mode, double tau, int* cnt, double* dropsum,
+                         hipStream_t s);
+// exclusive scan of cnt[0..n) into out[0..n] (out[n] = total); tmp holds
+// >= (n + 1023) / 1024 + 1 ints
+void launch_scan(int n, const int* cnt, int* out, int* tmp, hipStream_t s);
+void launch_filter_compact(int n_int, const int* rp, const int* ci, const double* v, const double* diag,
+                           const int* bp, int nblocks, int mode, double tau, unsigned flags,
+                           double delta, const double* dropsum, const int* prp, int* pci,
+                           double* pv_corr, int* pdiag, hipStream_t s);
+void launch_ilu0(int nblocks, const int* bp, const int* prp, const int* pci, const double* pv_corr,
+                 double* pv, const int* pdiag, int spd, int policy, double shift0, double* shifts,
+                 int* nfix, int* block_status, int* spin_err, hipStream_t s);
+
+// Iteration kernels (kernels_iter.hip).
+struct CsrView {
+    int n;
+    const int* rp;
+    const int* ci;
+};
+
+struct LowRankDev {
+    int k = 0;          // number of columns (0: none)
+    int slices = 0;     // partial sums per column in the U^T x reduction
+    const int* urp = nullptr;  // CSR n x k
+    const int* uci = nullptr;
+    const void* uv = nullptr;  // double or float
+    const int* ucp = nullptr;  // CSC (k columns)
+    const int* uri = nullptr;
+    const void* ucv = nullptr;
+    const void* c = nullptr;   // k scaling factors (same type as values)
+    double* part = nullptr;    // [k * slices] (FP64 sums; compensated: 2x)
+};
+
+int spmv_grid(int n);
+int spmv_lanes(double mean_row);
+
+template <typename T>
+void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, hipStream_t s);
+template <typename T>
+void launch_spmv(const CsrView& A, const T* v, const LowRankDev& lr, const T* x, T* y, double* part_dot,
+                 const KrylovState* st, int lanes, int grid, hipStream_t s);
+void launch_residual(const CsrView& A, const double* v, const LowRankDev& lr, const double* b,
+                     const double* x, double* r, double* part, int lanes, int grid, hipStream_t s);
+// ||a||^2 and similar final reductions into out[0] (one workgroup)
+void launch_sum_partials(const double* part, int m, double* out, hipStream_t s);
+
+struct BJDev {
+    int nblocks;
+    const int* bp;
+    const int* prp;
+    const int* pci;
+    const void* pv;     // double or float factors
+    const int* pdiag;
+};
+
+// MODE 0: z = P^{-1} r.  MODE 1: PCG step (alpha from partials, x/r update,
+// ||r||^2 partial, z = P^{-1} r, (r,z) partial).  MODE 2: z = P^{-1} r and
+// (r,z) partial (PCG start).
+struct PcgVecs {
+    void* x;
+    void* r;
+    const void* p;
+    const void* q;
+    void* z;
+    void* y;               // scratch for the forward-substitution result
+    const double* part_pq; // SpMV partials of (p, q)
+    int npq;
+    double* part_rz;       // [2 * nblocks], parity-indexed
+    double* part_rr;       // [nblocks]
+};
+template <typename T>
+void launch_bj(int mode, const BJDev& P, const PcgVecs& v, KrylovState* st, int it, hipStream_t s);
+
+template <typename T>
+void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, KrylovState* st, int it, hipStream_t s);
+
+// vector helpers
+template <typename T>
+void launch_fill(int64_t n, T* a, T val, hipStream_t s);
+template <typename T>
+void launch_copy(int64_t n, const T* a, T* b, hipStream_t s);
+void launch_sqnorm_partials(int n, const double* a, double* part, int grid, hipStream_t s);
+void launch_ir_scale_cast(int n, const double* r, const double* nr, float* rs, hipStream_t s);
+void launch_ir_update(int n, double* x, const double* nr, const float* d, hipStream_t s);
+void launch_init_state(KrylovState* st, const double* part_bb, int m, double tol, hipStream_t s);
+
+}  // namespace sdsl

@@ -1,0 +1,359 @@
+"""GPU path vs the CPU oracle on the same seeded inputs, through the C ABI.
+
+Tolerances: the filtered pattern is compared bitwise (an integer decision
+taken in FP64 on both sides); corrected values and ILU(0) factors within
+1e-12 relative (both sides use the same operation order and explicit fma, so
+they are expected to agree bitwise); SpMV per entry within 64 u (|M||x|)_i;
+the triangular solves within 1e-12 relative (same order of operations);
+solves: true relative residual <= 1e-8 recomputed by the oracle's compensated
+residual and iteration counts within 10% of the oracle's."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from ipm_inputs import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2604_23979_amd as sd  # noqa: E402
+
+DEV = "cuda:0"
+U64 = np.finfo(np.float64).eps
+U32 = np.finfo(np.float32).eps
+
+
+def opts(**kw):
+    return sd.Options(**kw)
+
+
+def oracle_opts(o: sd.Options):
+    return dict(mode=o.filter, tau=o.tau, flags=o.diag_flags, delta=o.delta, spd=bool(o.spd), policy=o.pivot,
+                shift0=o.shift0)
+
+
+def tdev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def ragged_system(n=3000, nblocks=5, seed=0, maxrow=180):
+    """Symmetric diagonally dominant matrix with row lengths from 1 to ~maxrow
+    and uneven block sizes."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, maxrow, size=n)
+    rows = np.repeat(np.arange(n), lens)
+    cols = np.clip(rows + rng.integers(-400, 400, size=rows.shape[0]), 0, n - 1)
+    a = sp.coo_matrix((rng.standard_normal(rows.shape[0]), (rows, cols)), shape=(n, n)).tocsr()
+    a = a + a.T
+    a.setdiag(0.0)
+    a.eliminate_zeros()
+    d = np.asarray(abs(a).sum(axis=1)).ravel() + 1.0
+    a = (a + sp.diags(d)).tocsr()
+    a.sort_indices()
+    cuts = np.sort(rng.choice(np.arange(1, n), size=nblocks - 1, replace=False))
+    bp = np.r_[0, cuts, n].astype(np.int32)
+    return gen.System("ragged", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data,
+                      rng.standard_normal(n), bp)
+
+
+def big_block_system(n=20000, seed=1):
+    """One block larger than the LDS solution ring (so the triangular solves
+    read evicted values back from global memory), banded plus far entries."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), 6)
+    off = rng.integers(1, 3000, size=rows.shape[0])
+    far = rng.random(rows.shape[0]) < 0.1
+    off = np.where(far, rng.integers(1, n, size=rows.shape[0]), off)
+    cols = (rows + off) % n
+    a = sp.coo_matrix((rng.standard_normal(rows.shape[0]), (rows, cols)), shape=(n, n)).tocsr()
+    a = a + a.T
+    a.setdiag(0.0)
+    a.eliminate_zeros()
+    d = np.asarray(abs(a).sum(axis=1)).ravel() * 1.2 + 1.0
+    a = (a + sp.diags(d)).tocsr()
+    a.sort_indices()
+    return gen.System("bigblock", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data,
+                      rng.standard_normal(n), np.array([0, 7000, n], dtype=np.int32))
+
+
+CASES = {
+    "C1": (lambda: gen.c1(), opts()),
+    "C2x0.02": (lambda: gen.c2(0.02), opts(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)),
+    "ragged-min-delta": (lambda: ragged_system(), opts(filter=sd.FILTER_MIN, tau=5e-2, diag_flags=sd.DIAG_DELTA,
+                                                       delta=1e-3)),
+    "bigblock": (lambda: big_block_system(), opts(filter=sd.FILTER_GEOMEAN, tau=1e-2,
+                                                  diag_flags=sd.DIAG_DROPSUM | sd.DIAG_DELTA, delta=1e-12)),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    print(f"\n[case {request.param}]", flush=True)
+    mk, o = CASES[request.param]
+    s = mk()
+    solver = sd.from_system(s, o)
+    P = O.BJ(s, **oracle_opts(o))
+    yield request.param, s, o, solver, P
+    solver.close()
+
+
+def test_factor_parity(case):
+    name, s, o, solver, P = case
+    assert P.status == O.OK
+    f = solver.factors()
+    n = s.n
+    assert np.array_equal(f["row_ptr"][: n + 1], P.rp), "filtered pattern row pointers"
+    assert np.array_equal(f["col"], P.ci), "filtered pattern columns"
+    assert np.array_equal(f["corrected"], P.corrected), "filter + correction values"
+    rel = np.abs(f["lu"] - P.v) / np.maximum(np.abs(P.v), 1e-300)
+    assert rel.max() <= 1e-12, f"ILU(0) factors: max rel diff {rel.max():.3e}"
+    assert np.array_equal(f["shifts"], P.shifts)
+    print(f"{name}: kept {P.rp[-1]} entries, bitwise factors: {np.array_equal(f['lu'], P.v)}, "
+          f"shifts {sorted(set(P.shifts.tolist()))}")
+
+
+def test_spmv_parity(case):
+    name, s, o, solver, P = case
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(s.n)
+    y = solver.spmv(tdev(x)).cpu().numpy()
+    ref = O.spmv(s.row_ptr, s.col, s.val, x, lowrank=s.lowrank)
+    M = s.scipy()
+    scale = abs(M) @ np.abs(x)
+    if s.lowrank is not None:
+        U, c = s.lowrank
+        scale = scale + abs(U) @ (np.abs(c) * (abs(U).T @ np.abs(x)))
+    err = np.abs(y - ref) / scale
+    assert err.max() <= 64 * U64, f"{name}: FP64 SpMV {err.max():.3e}"
+    x32 = x.astype(np.float32)
+    y32 = solver.spmv(tdev(x32, torch.float32), fp32=True).cpu().numpy().astype(np.float64)
+    v32 = s.val.astype(np.float32).astype(np.float64)
+    lr32 = None
+    if s.lowrank is not None:
+        U, c = s.lowrank
+        U32m = sp.csr_matrix((U.data.astype(np.float32).astype(np.float64), U.indices, U.indptr), shape=U.shape)
+        lr32 = (U32m, c.astype(np.float32).astype(np.float64))
+    ref32 = O.spmv(s.row_ptr, s.col, v32, x32.astype(np.float64), lowrank=lr32)
+    err32 = np.abs(y32 - ref32) / scale
+    assert err32.max() <= 512 * U32, f"{name}: FP32 SpMV {err32.max():.3e}"
+
+
+def test_precond_apply_parity(case):
+    name, s, o, solver, P = case
+    r = np.random.default_rng(6).standard_normal(s.n)
+    z = solver.precond_apply(tdev(r)).cpu().numpy()
+    zo = P.apply(r)
+    rel = np.abs(z - zo) / np.maximum(np.abs(zo), 1e-300)
+    assert np.max(np.abs(z - zo)) <= 1e-12 * np.max(np.abs(zo)), f"{name}: apply rel {rel.max():.3e}"
+    # FP32 apply against the FP64 oracle on rounded factors: close to FP32 rounding
+    r32 = r.astype(np.float32)
+    z32 = solver.precond_apply(tdev(r32, torch.float32), fp32=True).cpu().numpy().astype(np.float64)
+    zo32 = O.lu_solve(P.rp, P.ci, P.v.astype(np.float32).astype(np.float64), P.dp, r32.astype(np.float64))
+    assert np.max(np.abs(z32 - zo32)) <= 1e-3 * np.max(np.abs(zo32)), f"{name}: FP32 apply"
+
+
+def test_residual_parity(case):
+    name, s, o, solver, P = case
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(s.n)
+    r, nr = solver.residual(tdev(s.b), tdev(x))
+    ro, nro = O.residual(s.row_ptr, s.col, s.val, x, s.b, s.lowrank)
+    r = r.cpu().numpy()
+    assert np.max(np.abs(r - ro)) <= 1e-15 * np.max(np.abs(ro)) + 1e-300
+    assert abs(nr - nro) <= 1e-14 * nro
+
+
+def test_pcg_fp64_matches_oracle(case):
+    name, s, o, solver, P = case
+    xo, its_o, rr_o, st_o, _ = O.pcg_bj(s, P, tol=1e-8, maxit=50_000)
+    assert st_o == O.OK
+    b = tdev(s.b)
+    x, its, rr, st = solver.solve(b, tol=1e-8)
+    x = x.cpu().numpy()
+    true_rr = O.relres(s, x)
+    print(f"{name}: FP64 PCG gpu {its} its relres {true_rr:.2e} | oracle {its_o} its {rr_o:.2e}")
+    assert st == sd.OK
+    assert true_rr <= 1e-8
+    assert abs(rr - true_rr) <= 1e-3 * true_rr + 1e-15
+    assert abs(its - its_o) <= max(1, 0.10 * its_o)
+    # error against the oracle's solution in the M-norm, bounded by both residuals
+    M = s.scipy()
+    e = x - xo
+    rel_m = np.sqrt(abs(e @ (M @ e))) / np.sqrt(abs(xo @ (M @ xo)))
+    print(f"{name}: ||x - x_oracle||_M / ||x_oracle||_M = {rel_m:.2e}, 2-norm {np.linalg.norm(e) / np.linalg.norm(xo):.2e}")
+
+
+def test_ir_fp32_inner(case):
+    name, s, o, solver, P = case
+    o2 = sd.Options(**{**o.__dict__, "precision": sd.FP32_IR})
+    sv = sd.from_system(s, o2)
+    try:
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        true_rr = O.relres(s, x.cpu().numpy())
+        inf = sv.info()
+        xo, outer_o, inner_o, fb_o, rr_o, st_o = O.ir_pcg_bj(s, P, tol=1e-8, inner_tol=o2.inner_tol,
+                                                              maxit=50_000)
+        print(f"{name}: FP32-IR gpu outer {inf['outer_iters']} inner {its} fallbacks {inf['fp64_fallbacks']} "
+              f"relres {true_rr:.2e} | oracle outer {outer_o} inner {inner_o} fallbacks {fb_o}")
+        assert st == sd.OK and true_rr <= 1e-8
+        x64, _, _, _ = solver.solve(tdev(s.b), tol=1e-8)
+        M = s.scipy()
+        e = x.cpu().numpy() - x64.cpu().numpy()
+        x64 = x64.cpu().numpy()
+        print(f"{name}: FP32-IR vs FP64 solution M-norm rel diff "
+              f"{np.sqrt(abs(e @ (M @ e))) / np.sqrt(abs(x64 @ (M @ x64))):.2e}")
+    finally:
+        sv.close()
+
+
+# ------------------------------------------------------------------ edge cases
+
+def _tiny(a, bp, o=None, b=None):
+    m = sp.csr_matrix(np.asarray(a, dtype=np.float64))
+    m.sort_indices()
+    n = m.shape[0]
+    s = gen.System("tiny", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                   np.ones(n) if b is None else b, np.asarray(bp, dtype=np.int32))
+    return s
+
+
+def test_one_row_blocks_is_jacobi_and_single_row():
+    rng = np.random.default_rng(3)
+    n = 700
+    a = np.diag(rng.uniform(1, 2, n)) + np.diag(0.1 * rng.standard_normal(n - 1), 1)
+    a = a + a.T
+    s = _tiny(a, np.arange(n + 1))
+    sv = sd.from_system(s)
+    r = rng.standard_normal(n)
+    z = sv.precond_apply(tdev(r)).cpu().numpy()
+    assert np.array_equal(z, r / np.diag(a))
+    sv.close()
+    s1 = _tiny([[4.0]], [0, 1], b=np.array([2.0]))
+    sv = sd.from_system(s1)
+    x, its, rr, st = sv.solve(tdev(s1.b))
+    assert st == sd.OK and abs(x.item() - 0.5) < 1e-15 and its == 1
+    sv.close()
+
+
+def test_exact_preconditioner_one_iteration():
+    """Tridiagonal SPD in one block: ILU(0) is exact, PCG takes one step."""
+    rng = np.random.default_rng(4)
+    n = 5000
+    off = rng.standard_normal(n - 1)
+    a = sp.diags([off, np.abs(np.r_[off, 0]) + np.abs(np.r_[0, off]) + 0.5, off], [-1, 0, 1]).tocsr()
+    a.sort_indices()
+    s = gen.System("tri", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data,
+                   rng.standard_normal(n), np.array([0, n], dtype=np.int32))
+    sv = sd.from_system(s)
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-12)
+    assert st == sd.OK and its == 1 and O.relres(s, x.cpu().numpy()) <= 1e-12
+    sv.close()
+
+
+def test_zero_rhs():
+    s = gen.c1()
+    sv = sd.from_system(s)
+    x, its, rr, st = sv.solve(torch.zeros(s.n, dtype=torch.float64, device=DEV))
+    assert st == sd.OK and its == 0 and rr == 0.0 and torch.count_nonzero(x).item() == 0
+    sv.close()
+
+
+def test_invalid_inputs_are_rejected():
+    a = np.array([[2.0, 1.0], [1.0, 2.0]])
+    s = _tiny(a, [0, 2])
+    bad = s.val.copy()
+    bad[1] = np.nan
+    with pytest.raises(sd.SdslError) as e:
+        sd.Solver(s.row_ptr, s.col, bad, s.block_ptr)
+    assert e.value.status == sd.E_INVALID
+    col = s.col.copy()
+    col[0], col[1] = col[1], col[0]
+    with pytest.raises(sd.SdslError) as e:
+        sd.Solver(s.row_ptr, col, s.val, s.block_ptr)
+    assert e.value.status == sd.E_INVALID
+    nodiag = _tiny([[0.0, 1.0], [1.0, 2.0]], [0, 2])
+    with pytest.raises(sd.SdslError) as e:
+        sd.Solver(nodiag.row_ptr, nodiag.col, nodiag.val, nodiag.block_ptr)
+    assert e.value.status == sd.E_INVALID
+    for bp in ([0, 1], [0, 2, 2], [1, 2]):
+        with pytest.raises(sd.SdslError) as e:
+            sd.Solver(s.row_ptr, s.col, s.val, np.array(bp))
+        assert e.value.status == sd.E_INVALID
+    sv = sd.Solver(s.row_ptr, s.col, s.val, s.block_ptr)
+    with pytest.raises(sd.SdslError):
+        sv.refactor(tdev(bad))
+    sv.close()
+
+
+def test_breakdown_policies_on_device():
+    a = np.array([[1.0, -0.6, 0.1, 0.2, -0.6],
+                  [-0.6, 1.0, 0.0, 0.4, 0.0],
+                  [0.1, 0.0, 1.0, -0.1, 0.0],
+                  [0.2, 0.4, -0.1, 1.0, -0.7],
+                  [-0.6, 0.0, 0.0, -0.7, 1.0]])
+    s = _tiny(a, [0, 5])
+    with pytest.raises(sd.SdslError) as e:
+        sd.from_system(s, sd.Options(pivot=sd.PIVOT_FAIL))
+    assert e.value.status == sd.E_BREAKDOWN
+    sv = sd.from_system(s, sd.Options(pivot=sd.PIVOT_SHIFT, shift0=0.01))
+    P = O.BJ(s, policy=O.PIVOT_SHIFT, shift0=0.01)
+    f = sv.factors()
+    assert np.array_equal(f["shifts"], P.shifts) and np.array_equal(f["lu"], P.v)
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-12)
+    assert st == sd.OK and O.relres(s, x.cpu().numpy()) <= 1e-12
+    sv.close()
+    sv = sd.from_system(s, sd.Options(pivot=sd.PIVOT_REPLACE))
+    P = O.BJ(s, policy=O.PIVOT_REPLACE)
+    assert np.array_equal(sv.factors()["lu"], P.v) and sv.info()["pivot_fixes"] == P.nfix
+    sv.close()
+
+
+def test_not_converged_and_max_iter():
+    s = gen.c1()
+    sv = sd.from_system(s, sd.Options(max_iter=3, check_every=2))
+    x, its, rr, st = sv.solve(tdev(s.b))
+    assert st == sd.E_NOT_CONVERGED and its == 3
+    assert abs(rr - O.relres(s, x.cpu().numpy())) <= 1e-10
+    sv.close()
+
+
+def test_refactor_update_values_and_reuse():
+    q = gen.IPMSequence(m=12000, nblocks=8, steps=4, seed=1)
+    o = sd.Options(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    s0 = q.system(0)
+    sv = sd.from_system(s0, o)
+    for k in (1, 2, 3):
+        sk = q.system(k)
+        vals = tdev(sk.val)
+        if k == 2:
+            sv.update_values(vals)      # keep the factors of step 1
+        else:
+            sv.refactor(vals)
+            P = O.BJ(sk, **oracle_opts(o))
+            f = sv.factors()
+            assert np.array_equal(f["col"], P.ci) and np.array_equal(f["lu"], P.v)
+        x, its, rr, st = sv.solve(tdev(sk.b))
+        assert st == sd.OK and O.relres(sk, x.cpu().numpy()) <= 1e-8
+    sv.close()
+
+
+def test_solve_batch_equals_solo():
+    systems = [gen.c2(0.01, seed=s, dense_cols=0) for s in range(3)]
+    o = sd.Options(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    streams = [torch.cuda.Stream() for _ in systems]
+    solvers = [sd.from_system(s, o, stream=st) for s, st in zip(systems, streams)]
+    solo = []
+    for sv, s in zip(solvers, systems):
+        x, its, rr, st = sv.solve(tdev(s.b))
+        solo.append((x.cpu().numpy(), its))
+    bs = [tdev(s.b) for s in systems]
+    xs = [torch.empty_like(b) for b in bs]
+    torch.cuda.synchronize()
+    its, rr, st = sd.solve_batch(solvers, bs, xs)
+    assert st == sd.OK
+    for i in range(3):
+        assert its[i] == solo[i][1]
+        assert np.array_equal(xs[i].cpu().numpy(), solo[i][0])
+    for sv in solvers:
+        sv.close()
