@@ -72,10 +72,18 @@ typedef enum { SDSL_PIVOT_FAIL = 0, SDSL_PIVOT_REPLACE = 1, SDSL_PIVOT_SHIFT = 2
 
 typedef enum { SDSL_PCG = 0, SDSL_GMRES = 1 } sdsl_krylov;          /* Sec. 2.2 */
 
-/* FP64: every step in FP64.  FP32_IR: FP64 iterative refinement around an
- * inner solve whose operator values, factors and vectors are FP32 (products
- * and triangular solves accumulate in FP32, dot products in FP64). */
-typedef enum { SDSL_FP64 = 0, SDSL_FP32_IR = 1 } sdsl_precision;
+/* FP64: every step in FP64.
+ * FP32_IR: the SpMV and the preconditioner apply run in FP32 (FP32 operator
+ * values and factors, products accumulated in FP32) inside an FP64
+ * refinement loop: the recurrence vectors, the solution update, the low-rank
+ * term and its border correction stay FP64, and at each refinement point
+ * (the recurrence residual fell by refine_delta, met the tolerance, or
+ * refine_every iterations passed) the true residual is formed in FP64 and
+ * replaces the recurrence one, which continues with its search direction
+ * (reliable updating).
+ * FP32_IR_RESTART: classical refinement; every step restarts the inner PCG
+ * on the current residual and stops it at inner_tol. */
+typedef enum { SDSL_FP64 = 0, SDSL_FP32_IR = 1, SDSL_FP32_IR_RESTART = 2 } sdsl_precision;
 
 typedef enum { SDSL_MEM_DEVICE = 0, SDSL_MEM_HOST = 1 } sdsl_mem;
 
@@ -127,6 +135,17 @@ typedef struct {
     double inner_tol;      /* FP32_IR: relative tolerance of each inner solve */
     int32_t max_outer;     /* FP32_IR: refinement steps                       */
     int32_t check_every;   /* iterations launched between convergence checks */
+    int32_t kernel_timing; /* 1: time the SpMV and block-Jacobi launches of
+                              every solve with HIP events (sdsl_info)        */
+    int32_t border;        /* 1: with a low-rank term, the preconditioner
+                              also eliminates its columns as a border:
+                              (P + U C U^T)^{-1} through the k x k Schur
+                              complement K = C^{-1} + U^T P^{-1} U (Sec. 2.1
+                              bordered dense columns, Sec. 2.4 Schur coupling) */
+    double refine_delta;   /* FP32_IR: residual reduction between refinement
+                              points (0.1 typical)                           */
+    int32_t refine_every;  /* FP32_IR: iterations after which a refinement
+                              point is taken regardless of the reduction     */
 } sdsl_options;
 
 typedef struct {
@@ -135,7 +154,7 @@ typedef struct {
     int32_t pivot_fixes;    /* REPLACE policy: replaced pivots               */
     int32_t shifted_blocks; /* SHIFT policy: blocks refactored with a shift  */
     double max_shift;       /* SHIFT policy: largest relative shift used     */
-    int32_t outer_iters;    /* FP32_IR refinement steps of the last solve    */
+    int32_t outer_iters;    /* FP32_IR refinement points of the last solve   */
     int32_t inner_iters;    /* Krylov iterations of the last solve (total)   */
     int32_t fp64_fallbacks; /* FP32_IR: inner solves redone in FP64          */
     int32_t restarts;       /* restarts from the true residual               */
@@ -144,11 +163,21 @@ typedef struct {
     double relres;          /* last true relative residual                   */
     int64_t bytes_per_iter; /* algorithmic bytes of one Krylov iteration     */
     int64_t device_bytes;   /* device memory held by the handle              */
+    /* kernel_timing: summed durations and counts of the launches made by the
+     * last solve before it converged (no-op launches after it are excluded);
+     * index 0 = FP64 kernels, 1 = FP32 kernels */
+    double spmv_ms[2];
+    int64_t spmv_launches[2];
+    double bj_ms[2];
+    int64_t bj_launches[2];
+    int64_t spmv_bytes[2];  /* algorithmic bytes of one SpMV launch          */
+    int64_t bj_bytes[2];    /* algorithmic bytes of one fused PCG/BJ launch  */
 } sdsl_info;
 
 /* Fills *o with defaults: BJ, no filter, no correction, SHIFT(1e-2), SPD,
  * PCG, restart 30, max_iter 100000, FP64, inner_tol 1e-4, max_outer 30,
- * check_every 16. */
+ * check_every 16, kernel_timing 0, border 1, refine_delta 0.1,
+ * refine_every 500. */
 void sdsl_default_options(sdsl_options* o);
 
 /* Device bytes a handle for this problem will hold (for admission control).

@@ -21,8 +21,10 @@ Two pattern models:
 
 * ``uni``: each column's ``c`` distinct rows are uniform over ``[0, m)``.
 * ``loc``: column ``j`` has a home row ``floor((j + 0.5) m / n_A)``; each of its
-  nonzeros lands uniformly in ``[home - 1024, home + 1024)`` (clipped) with
-  probability 0.9 and uniformly over ``[0, m)`` otherwise; rows are distinct.
+  nonzeros lands uniformly in the 2048-row window ``[home - 1024, home + 1024)``
+  (shifted, not clipped, to stay inside ``[0, m)`` near the ends, so no row
+  collects the overflow) with probability 0.9 and uniformly over ``[0, m)``
+  otherwise; rows are distinct.
 """
 from __future__ import annotations
 
@@ -93,8 +95,10 @@ def _draw_rows(rng, m, n_cols, c, model, home):
     if model == "uni":
         return rng.integers(0, m, size=(n_cols, c), dtype=np.int64)
     local = rng.random((n_cols, c)) < P_LOCAL
-    off = rng.integers(-HALF_WINDOW, HALF_WINDOW, size=(n_cols, c), dtype=np.int64)
-    near = np.clip(home[:, None] + off, 0, m - 1)
+    width = min(2 * HALF_WINDOW, m)
+    lo = np.clip(home - HALF_WINDOW, 0, m - width)
+    off = rng.integers(0, width, size=(n_cols, c), dtype=np.int64)
+    near = lo[:, None] + off
     far = rng.integers(0, m, size=(n_cols, c), dtype=np.int64)
     return np.where(local, near, far)
 

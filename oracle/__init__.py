@@ -72,14 +72,22 @@ def _declare(L):
     L.or_bbd_free.argtypes = [P]
     L.or_bbd_apply.argtypes = [P, P, P]
     L.or_bbd_get.argtypes = [P, P, P, P, P, P, P]
-    L.or_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, D, I32, P, P, P]
+    L.or_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, I32, P, P, P]
     L.or_pcg_bj.restype = C.c_int
     L.or_gmres_bj.argtypes = [I64, P, P, P, P, P, P, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bj.restype = C.c_int
     L.or_gmres_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bbd.restype = C.c_int
-    L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P]
+    L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P]
     L.or_ir_pcg_bj.restype = C.c_int
+    L.or_ru_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, P, P]
+    L.or_mx_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P]
+    L.or_mx_pcg_bj.restype = C.c_int
+    L.or_border_setup.argtypes = [I64, P, P, P, P, I32, P, P, P, P, P]
+    L.or_border_setup.restype = P
+    L.or_border_free.argtypes = [P]
+    L.or_border_apply.argtypes = [P, P, P]
+    L.or_ru_pcg_bj.restype = C.c_int
 
 
 def _p(a):
@@ -178,7 +186,7 @@ class BJ:
     block's diagonal by a relative amount starting at ``shift0``)."""
 
     def __init__(self, sys_, mode=FILTER_NONE, tau=0.0, flags=0, delta=0.0, spd=True,
-                 policy=PIVOT_SHIFT, shift0=1e-2):
+                 policy=PIVOT_SHIFT, shift0=1e-2, border=False):
         self.rp, self.ci, v0, self.dropsum = filter_correct(sys_.row_ptr, sys_.col, sys_.val,
                                                             sys_.block_ptr, mode, tau, flags, delta)
         self.corrected = v0
@@ -194,9 +202,28 @@ class BJ:
                                          _p(self.shifts), C.byref(nfix), C.byref(bad))
         self.dp = self.dp[:n]
         self.nfix, self.bad_row = nfix.value, bad.value
+        self.border = None
+        if border and sys_.lowrank is not None and self.status == OK:
+            U, c = sys_.lowrank
+            self._bk = _csr(U.indptr, U.indices, U.data) + (np.ascontiguousarray(c, dtype=np.float64),)
+            urp, uci, uv, cc = self._bk
+            st = C.c_int32(0)
+            self.border = lib().or_border_setup(n, _p(self.rp), _p(self.ci), _p(self.v), _p(self.dp),
+                                                U.shape[1], _p(urp), _p(uci), _p(uv), _p(cc), C.byref(st))
+            self.border_status = st.value
 
     def apply(self, r):
+        if self.border:
+            r = np.ascontiguousarray(r, dtype=np.float64)
+            z = np.empty(r.shape[0])
+            lib().or_border_apply(self.border, _p(r), _p(z))
+            return z
         return lu_solve(self.rp, self.ci, self.v, self.dp, r)
+
+    def __del__(self):
+        if getattr(self, "border", None):
+            lib().or_border_free(self.border)
+            self.border = None
 
 
 def _lr_args(lowrank):
@@ -220,7 +247,7 @@ def pcg_bj(sys_, P: BJ, tol=1e-8, maxit=10_000, hist=False):
     h = np.zeros(maxit) if hist else None
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
     st = lib().or_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
-                         _p(P.ci), _p(P.v), _p(P.dp), _p(b), _p(x), tol, maxit, C.byref(its),
+                         _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, maxit, C.byref(its),
                          C.byref(rr), _p(h))
     return x, its.value, rr.value, st, (h[:its.value] if hist else None)
 
@@ -236,8 +263,40 @@ def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000)
     rr = C.c_double(0.0)
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
     st = lib().or_ir_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
-                            _p(P.ci), _p(P.v), _p(P.dp), _p(b), _p(x), tol, inner_tol, max_outer,
+                            _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, inner_tol, max_outer,
                             maxit, _p(out), C.byref(rr))
+    return x, int(out[0]), int(out[1]), int(out[2]), rr.value, st
+
+
+def ru_pcg_bj(sys_, P: BJ, tol=1e-8, delta=0.1, maxit=100_000):
+    """FP32 PCG with FP64 reliable updates.  Returns (x, refinement points,
+    iterations, fp64 fallbacks, relres, status)."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
+    x = np.zeros(n)
+    out = np.zeros(3, dtype=np.int32)
+    rr = C.c_double(0.0)
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_ru_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
+                            _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, delta, maxit, _p(out),
+                            C.byref(rr))
+    return x, int(out[0]), int(out[1]), int(out[2]), rr.value, st
+
+
+def mx_pcg_bj(sys_, P: BJ, tol=1e-8, delta=0.1, every=500, maxit=100_000):
+    """PCG with FP32 SpMV / preconditioner apply inside FP64 refinement.
+    Returns (x, refinement points, iterations, fp64 fallbacks, relres, status)."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
+    x = np.zeros(n)
+    out = np.zeros(3, dtype=np.int32)
+    rr = C.c_double(0.0)
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_mx_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
+                            _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, delta, every, maxit,
+                            _p(out), C.byref(rr))
     return x, int(out[0]), int(out[1]), int(out[2]), rr.value, st
 
 

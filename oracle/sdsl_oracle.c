@@ -351,6 +351,83 @@ void or_bj_apply(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
 }
 
 /* ------------------------------------------------------------------ */
+/* Border correction for dense columns kept as a low-rank term.  The     */
+/* dense columns form a border of the system (paper Sec. 2.1: they are   */
+/* relocated to a bordered structure); eliminating that border with the  */
+/* block preconditioner P gives the Schur complement                      */
+/*   K = C^{-1} + U^T P^{-1} U     (k x k, dense)                         */
+/* and the preconditioner (P + U C U^T)^{-1} r = z - W K^{-1} U^T z with  */
+/* z = P^{-1} r and W = P^{-1} U (the Sherman-Morrison-Woodbury form of   */
+/* the bordered block elimination, Sec. 2.4).                             */
+/* ------------------------------------------------------------------ */
+int or_dense_lu(int64_t n, double* a, int32_t* piv);
+void or_dense_lu_solve(int64_t n, const double* a, const int32_t* piv, double* b);
+
+typedef struct {
+    or_bj bj;
+    int32_t k;
+    const int64_t* urp; const int32_t* uci; const double* uv;
+    double* W;      /* n x k row-major */
+    double* K;      /* LU of K */
+    int32_t* piv;
+    double* t;
+    float* W32;
+} or_bjb;
+
+void* or_border_setup(int64_t n, const int64_t* prp, const int32_t* pci, const double* pv,
+                      const int64_t* pdp, int32_t k, const int64_t* urp, const int32_t* uci,
+                      const double* uv, const double* c, int32_t* status) {
+    or_bjb* B = (or_bjb*)calloc(1, sizeof(or_bjb));
+    B->bj.n = n; B->bj.rp = prp; B->bj.ci = pci; B->bj.v = pv; B->bj.dp = pdp;
+    B->k = k; B->urp = urp; B->uci = uci; B->uv = uv;
+    B->W = calloc((size_t)(n * k) + 1, 8);
+    B->W32 = calloc((size_t)(n * k) + 1, 4);
+    B->K = calloc((size_t)(k * k) + 1, 8);
+    B->piv = calloc((size_t)k + 1, 4);
+    B->t = calloc((size_t)k + 1, 8);
+    double *e = calloc(n, 8), *w = calloc(n, 8);
+    for (int32_t j = 0; j < k; ++j) {
+        memset(e, 0, (size_t)n * 8);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = urp[i]; p < urp[i + 1]; ++p)
+                if (uci[p] == j) e[i] = uv[p];
+        bj_apply(&B->bj, e, w);
+        for (int64_t i = 0; i < n; ++i) B->W[i * k + j] = w[i];
+    }
+    for (int64_t i = 0; i < n * k; ++i) B->W32[i] = (float)B->W[i];
+    for (int32_t a = 0; a < k; ++a) B->K[a * k + a] = 1.0 / c[a];
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = urp[i]; p < urp[i + 1]; ++p)
+            for (int32_t bb = 0; bb < k; ++bb) B->K[(int64_t)uci[p] * k + bb] += uv[p] * B->W[i * k + bb];
+    free(e); free(w);
+    *status = or_dense_lu(k, B->K, B->piv);
+    return B;
+}
+
+void or_border_free(void* ctx) {
+    or_bjb* B = (or_bjb*)ctx;
+    if (!B) return;
+    free(B->W); free(B->W32); free(B->K); free(B->piv); free(B->t); free(B);
+}
+
+static void bjb_apply(void* ctx, const double* r, double* z) {
+    or_bjb* B = (or_bjb*)ctx;
+    int32_t k = B->k;
+    bj_apply(&B->bj, r, z);
+    for (int32_t j = 0; j < k; ++j) B->t[j] = 0.0;
+    for (int64_t i = 0; i < B->bj.n; ++i)
+        for (int64_t p = B->urp[i]; p < B->urp[i + 1]; ++p) B->t[B->uci[p]] += B->uv[p] * z[i];
+    or_dense_lu_solve(k, B->K, B->piv, B->t);
+    for (int64_t i = 0; i < B->bj.n; ++i) {
+        double s = 0.0;
+        for (int32_t j = 0; j < k; ++j) s += B->W[i * k + j] * B->t[j];
+        z[i] -= s;
+    }
+}
+
+void or_border_apply(void* ctx, const double* r, double* z) { bjb_apply(ctx, r, z); }
+
+/* ------------------------------------------------------------------ */
 /* PCG (Hestenes-Stiefel; paper Sec. 2.2 lists CG; tolerance Sec. 4.2)   */
 /* ------------------------------------------------------------------ */
 static int pcg_run(const or_op* A, or_prec_fn prec, void* pctx, const double* b, double* x,
@@ -748,10 +825,11 @@ void or_bbd_get(void* ctx, int64_t* tail, int64_t* lrp, int32_t* lci, double* lv
 int or_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
               int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
               const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
-              const double* b, double* x, double tol, int32_t maxit, int32_t* iters,
+              void* border, const double* b, double* x, double tol, int32_t maxit, int32_t* iters,
               double* relres, double* hist) {
     or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
     or_bj P = {n, prp, pci, pv, pdp};
+    if (border) return pcg_run(&A, bjb_apply, border, b, x, tol, maxit, iters, relres, hist);
     return pcg_run(&A, bj_apply, &P, b, x, tol, maxit, iters, relres, hist);
 }
 
@@ -784,6 +862,8 @@ typedef struct {
     const int64_t* rp; const int32_t* ci; float* v;
     int32_t k; const int64_t* urp; const int32_t* uci; float* uv; float* c;
     const int64_t* prp; const int32_t* pci; float* pv; const int64_t* pdp;
+    /* optional border correction of the preconditioner (see or_bjb) */
+    int32_t bk; float* W; const double* K; const int32_t* Kpiv; double* t;
 } or_f32sys;
 
 static void spmv32(const or_f32sys* S, const float* x, float* y) {
@@ -803,6 +883,23 @@ static void spmv32(const or_f32sys* S, const float* x, float* y) {
             y[i] += s;
         }
         free(t);
+    }
+}
+static void lusolve32(const or_f32sys* S, const float* r, float* z);
+/* FP32 preconditioner: block solve, then the border correction
+ * z <- z - W K^{-1} U^T z with the projections and K in FP64 */
+static void prec32(const or_f32sys* S, const float* r, float* z) {
+    lusolve32(S, r, z);
+    if (S->bk <= 0) return;
+    int32_t k = S->bk;
+    for (int32_t j = 0; j < k; ++j) S->t[j] = 0.0;
+    for (int64_t i = 0; i < S->n; ++i)
+        for (int64_t p = S->urp[i]; p < S->urp[i + 1]; ++p) S->t[S->uci[p]] += (double)S->uv[p] * (double)z[i];
+    or_dense_lu_solve(k, S->K, S->Kpiv, S->t);
+    for (int64_t i = 0; i < S->n; ++i) {
+        double s = 0.0;
+        for (int32_t j = 0; j < k; ++j) s += (double)S->W[i * k + j] * S->t[j];
+        z[i] = (float)((double)z[i] - s);
     }
 }
 static void lusolve32(const or_f32sys* S, const float* r, float* z) {
@@ -831,7 +928,7 @@ static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int3
     int it = 0, st = OR_NOT_CONVERGED;
     memset(x, 0, (size_t)n * 4);
     memcpy(r, b, (size_t)n * 4);
-    lusolve32(S, r, z);
+    prec32(S, r, z);
     memcpy(p, z, (size_t)n * 4);
     double rz = dot32(n, r, z);
     while (it < maxit) {
@@ -842,7 +939,7 @@ static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int3
         for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + a * p[i]; r[i] = r[i] - a * q[i]; }
         ++it;
         if (sqrt(dot32(n, r, r)) <= itol * nb) { st = OR_OK; break; }
-        lusolve32(S, r, z);
+        prec32(S, r, z);
         double rz2 = dot32(n, r, z);
         float be = (float)(rz2 / rz);
         rz = rz2;
@@ -860,9 +957,9 @@ static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int3
 int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                  int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
                  const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
-                 const double* b, double* x, double tol, double inner_tol, int32_t max_outer,
+                 void* border, const double* b, double* x, double tol, double inner_tol, int32_t max_outer,
                  int32_t maxit, int32_t* out, double* relres) {
-    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp};
+    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
     int64_t nnz = rp[n], pnnz = prp[n], unnz = k > 0 ? urp[n] : 0;
     S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
     for (int64_t p = 0; p < nnz; ++p) S.v[p] = (float)v[p];
@@ -874,6 +971,12 @@ int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     }
     or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
     or_bj P = {n, prp, pci, pv, pdp};
+    or_prec_fn pf = border ? bjb_apply : bj_apply;
+    void* pc = border ? border : (void*)&P;
+    if (border) {
+        or_bjb* B = (or_bjb*)border;
+        S.bk = B->k; S.W = B->W32; S.K = B->K; S.Kpiv = B->piv; S.t = B->t;
+    }
     double *r = calloc(n, 8);
     float *rs = calloc(n, 4), *d = calloc(n, 4);
     double nb = nrm2(n, b);
@@ -889,7 +992,7 @@ int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
             /* FP64 fallback: PCG on M d = r to the remaining tolerance */
             double* dd = calloc(n, 8);
             int32_t its = 0; double rr = 0.0;
-            pcg_run(&A, bj_apply, &P, r, dd, tol * nb / nr, maxit, &its, &rr, NULL);
+            pcg_run(&A, pf, pc, r, dd, tol * nb / nr, maxit, &its, &rr, NULL);
             for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
             free(dd);
             out[1] += its; out[2] += 1; out[0] += 1;
@@ -911,5 +1014,218 @@ int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
 done:
     free(r); free(rs); free(d); free(S.v); free(S.pv);
     if (k > 0) { free(S.uv); free(S.c); }
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* FP32 PCG with FP64 reliable updates (refinement without restart).     */
+/* The inner recurrence (FP32 vectors, FP32 operator and factors, FP64    */
+/* dot products) solves M y = b / ||b||; whenever its residual norm has   */
+/* fallen below delta times its value at the last refinement point (or    */
+/* meets the tolerance), the FP32 correction is folded into the FP64      */
+/* solution, the FP64 true residual is formed and rounded back into the   */
+/* FP32 recurrence, which then continues with its search direction kept   */
+/* (reliable updating: Sleijpen and van der Vorst, Computing 56 (1996);   */
+/* mixed precision: Clark et al., Comput. Phys. Commun. 181 (2010)).       */
+/* out[0] = refinement points, out[1] = iterations, out[2] = FP64          */
+/* fallbacks (taken when two consecutive refinement points shrink the true */
+/* residual by less than 2x).                                             */
+/* ------------------------------------------------------------------ */
+int or_ru_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                 int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
+                 const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
+                 void* border, const double* b, double* x, double tol, double delta, int32_t maxit, int32_t* out,
+                 double* relres) {
+    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
+    int64_t nnz = rp[n], pnnz = prp[n], unnz = k > 0 ? urp[n] : 0;
+    S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
+    for (int64_t p = 0; p < nnz; ++p) S.v[p] = (float)v[p];
+    for (int64_t p = 0; p < pnnz; ++p) S.pv[p] = (float)pv[p];
+    if (k > 0) {
+        S.uv = malloc((size_t)unnz * 4 + 4); S.c = malloc((size_t)k * 4);
+        for (int64_t p = 0; p < unnz; ++p) S.uv[p] = (float)uv[p];
+        for (int32_t j = 0; j < k; ++j) S.c[j] = (float)c[j];
+    }
+    or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
+    or_bj P = {n, prp, pci, pv, pdp};
+    or_prec_fn pf = border ? bjb_apply : bj_apply;
+    void* pc = border ? border : (void*)&P;
+    if (border) {
+        or_bjb* B = (or_bjb*)border;
+        S.bk = B->k; S.W = B->W32; S.K = B->K; S.Kpiv = B->piv; S.t = B->t;
+    }
+    double* rh = calloc(n, 8);
+    float *xl = calloc(n, 4), *r = calloc(n, 4), *z = calloc(n, 4), *p = calloc(n, 4), *q = calloc(n, 4);
+    double nb = nrm2(n, b);
+    int st = OR_NOT_CONVERGED, it = 0;
+    out[0] = out[1] = out[2] = 0;
+    memset(x, 0, (size_t)n * 8);
+    double nr = nb;
+    if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
+    for (int64_t i = 0; i < n; ++i) r[i] = (float)(b[i] / nb);
+    double rr0 = dot32(n, r, r), prev = nb;
+    int slow = 0;
+    prec32(&S, r, z);
+    memcpy(p, z, (size_t)n * 4);
+    double rz = dot32(n, r, z);
+    while (it < maxit) {
+        spmv32(&S, p, q);
+        double pq = dot32(n, p, q);
+        if (!(pq > 0.0)) { st = OR_BREAKDOWN; break; }
+        float a = (float)(rz / pq);
+        for (int64_t i = 0; i < n; ++i) { xl[i] = xl[i] + a * p[i]; r[i] = r[i] - a * q[i]; }
+        ++it;
+        double rr = dot32(n, r, r);
+        if (rr <= tol * tol * 1.0 || rr < delta * delta * rr0) {
+            /* refinement point: x += ||b|| xl in FP64, true residual */
+            for (int64_t i = 0; i < n; ++i) { x[i] += nb * (double)xl[i]; xl[i] = 0.0f; }
+            nr = op_true_res(&A, x, b, rh);
+            out[0] += 1;
+            if (nr <= tol * nb) { st = OR_OK; break; }
+            slow = (nr > 0.5 * prev) ? slow + 1 : 0;
+            prev = nr;
+            if (slow >= 2) {
+                /* FP64 fallback on M d = r for the rest of the tolerance */
+                double* dd = calloc(n, 8);
+                int32_t its = 0; double r2 = 0.0;
+                st = pcg_run(&A, pf, pc, rh, dd, tol * nb / nr, maxit - it, &its, &r2, NULL);
+                for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
+                free(dd);
+                it += its; out[2] += 1;
+                nr = op_true_res(&A, x, b, rh);
+                st = (nr <= tol * nb) ? OR_OK : (st == OR_BREAKDOWN ? OR_BREAKDOWN : OR_NOT_CONVERGED);
+                break;
+            }
+            for (int64_t i = 0; i < n; ++i) r[i] = (float)(rh[i] / nb);
+            rr0 = dot32(n, r, r);
+        }
+        prec32(&S, r, z);
+        double rz2 = dot32(n, r, z);
+        float be = (float)(rz2 / rz);
+        rz = rz2;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
+    }
+    if (st == OR_NOT_CONVERGED) {
+        for (int64_t i = 0; i < n; ++i) x[i] += nb * (double)xl[i];
+        nr = op_true_res(&A, x, b, rh);
+        if (nr <= tol * nb) st = OR_OK;
+    }
+    *relres = nr / nb;
+    out[1] = it;
+done:
+    free(rh); free(xl); free(r); free(z); free(p); free(q); free(S.v); free(S.pv);
+    if (k > 0) { free(S.uv); free(S.c); }
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* PCG with FP32 SpMV and FP32 preconditioner apply inside FP64          */
+/* refinement.  The recurrence vectors (x, r, z, p, q) are FP64; the       */
+/* product of the sparse part and the triangular solves round their inputs */
+/* to FP32, use FP32 values/factors and accumulate in FP32; the low-rank   */
+/* term and the border correction are FP64.  At a refinement point (the    */
+/* recurrence residual fell below delta times its value at the last point, */
+/* met the tolerance, or `every` iterations passed) the compensated FP64   */
+/* true residual replaces r; z, (r,z), beta and p are then recomputed and  */
+/* the recurrence continues (reliable updating).  Three consecutive points */
+/* that shrink the true residual by less than 2x switch to FP64 PCG on the */
+/* remaining correction.                                                   */
+/* out[0] = refinement points, out[1] = iterations, out[2] = fallbacks.    */
+/* ------------------------------------------------------------------ */
+static void mx_spmv(const or_f32sys* S, const or_op* A, const double* x, float* xs, double* y) {
+    for (int64_t i = 0; i < S->n; ++i) xs[i] = (float)x[i];
+    for (int64_t i = 0; i < S->n; ++i) {
+        float s = 0.0f;
+        for (int64_t p = S->rp[i]; p < S->rp[i + 1]; ++p) s += S->v[p] * xs[S->ci[p]];
+        y[i] = (double)s;
+    }
+    or_lowrank_add(A->n, A->k, A->urp, A->uci, A->uv, A->c, x, y);
+}
+static void mx_prec(const or_f32sys* S, void* border, const double* r, float* rs, float* zs, double* z) {
+    for (int64_t i = 0; i < S->n; ++i) rs[i] = (float)r[i];
+    lusolve32(S, rs, zs);
+    for (int64_t i = 0; i < S->n; ++i) z[i] = (double)zs[i];
+    if (!border) return;
+    or_bjb* B = (or_bjb*)border;
+    int32_t k = B->k;
+    for (int32_t j = 0; j < k; ++j) B->t[j] = 0.0;
+    for (int64_t i = 0; i < S->n; ++i)
+        for (int64_t p = B->urp[i]; p < B->urp[i + 1]; ++p) B->t[B->uci[p]] += B->uv[p] * z[i];
+    or_dense_lu_solve(k, B->K, B->piv, B->t);
+    for (int64_t i = 0; i < S->n; ++i) {
+        double s = 0.0;
+        for (int32_t j = 0; j < k; ++j) s += B->W[i * k + j] * B->t[j];
+        z[i] -= s;
+    }
+}
+
+int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                 int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
+                 const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
+                 void* border, const double* b, double* x, double tol, double delta, int32_t every,
+                 int32_t maxit, int32_t* out, double* relres) {
+    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
+    int64_t nnz = rp[n], pnnz = prp[n];
+    S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
+    for (int64_t p = 0; p < nnz; ++p) S.v[p] = (float)v[p];
+    for (int64_t p = 0; p < pnnz; ++p) S.pv[p] = (float)pv[p];
+    or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
+    or_bj P = {n, prp, pci, pv, pdp};
+    or_prec_fn pf = border ? bjb_apply : bj_apply;
+    void* pc = border ? border : (void*)&P;
+    double *r = calloc(n, 8), *z = calloc(n, 8), *p = calloc(n, 8), *q = calloc(n, 8);
+    float *xs = calloc(n, 4), *zs = calloc(n, 4);
+    double nb = nrm2(n, b);
+    int st = OR_NOT_CONVERGED, it = 0, slow = 0, last = 0;
+    out[0] = out[1] = out[2] = 0;
+    memset(x, 0, (size_t)n * 8);
+    double nr = nb, prev = nb;
+    if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
+    memcpy(r, b, (size_t)n * 8);
+    double rr0 = dot(n, r, r);
+    mx_prec(&S, border, r, xs, zs, z);
+    memcpy(p, z, (size_t)n * 8);
+    double rz = dot(n, r, z);
+    while (it < maxit) {
+        mx_spmv(&S, &A, p, xs, q);
+        double pq = dot(n, p, q);
+        double alpha = rz / pq;
+        if (!(pq > 0.0) || !isfinite(alpha)) { st = OR_BREAKDOWN; break; }
+        for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
+        ++it;
+        double rr = dot(n, r, r);
+        int conv = rr <= tol * tol * (nb * nb);
+        int upd = rr < delta * delta * rr0 || (every > 0 && it - last >= every);
+        if (conv || upd) {
+            out[0] += 1;
+            prev = nr;
+            nr = op_true_res(&A, x, b, r);
+            if (nr <= tol * nb) { st = OR_OK; break; }
+            slow = (nr > 0.5 * prev) ? slow + 1 : 0;
+            if (slow >= 3) {
+                double* dd = calloc(n, 8);
+                int32_t its = 0; double r2 = 0.0;
+                st = pcg_run(&A, pf, pc, r, dd, tol * nb / nr, maxit - it, &its, &r2, NULL);
+                for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
+                free(dd);
+                it += its; out[2] += 1;
+                nr = op_true_res(&A, x, b, r);
+                st = (nr <= tol * nb) ? OR_OK : (st == OR_BREAKDOWN ? OR_BREAKDOWN : OR_NOT_CONVERGED);
+                break;
+            }
+            rr0 = dot(n, r, r);
+            last = it;
+        }
+        mx_prec(&S, border, r, xs, zs, z);
+        double rz2 = dot(n, r, z);
+        double beta = rz2 / rz;
+        rz = rz2;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    }
+    if (st == OR_NOT_CONVERGED) nr = op_true_res(&A, x, b, r);
+    *relres = nr / nb;
+    out[1] = it;
+done:
+    free(r); free(z); free(p); free(q); free(xs); free(zs); free(S.v); free(S.pv);
     return st;
 }

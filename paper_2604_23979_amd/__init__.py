@@ -4,6 +4,7 @@ preconditioned CG in FP64 or FP32-inner / FP64-refined form, behind the C ABI
 of include/sdsl.h.  This package is the binding of that library."""
 from ._binding import (BBD, BJ, DIAG_DELTA, DIAG_DROPSUM, E_BREAKDOWN, E_DEVICE, E_INVALID, E_NOMEM,
                        E_NOT_CONVERGED, E_STATE, E_STRUCTURE, FILTER_GEOMEAN, FILTER_MIN, FILTER_NONE, FP32_IR,
+                       FP32_IR_RESTART,
                        FP64, GMRES, OK, PCG, PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT, SIGNATURES, LIB_PATH, Options,
                        SdslError, Solver, lib, solve_batch)
 

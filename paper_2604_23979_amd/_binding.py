@@ -24,7 +24,7 @@ FILTER_NONE, FILTER_MIN, FILTER_GEOMEAN = 0, 1, 2
 DIAG_DELTA, DIAG_DROPSUM = 1, 2
 PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT = 0, 1, 2
 PCG, GMRES = 0, 1
-FP64, FP32_IR = 0, 1
+FP64, FP32_IR, FP32_IR_RESTART = 0, 1, 2
 MEM_DEVICE, MEM_HOST = 0, 1
 
 
@@ -51,7 +51,9 @@ class COptions(C.Structure):
     _fields_ = [("method", C.c_int), ("filter", C.c_int), ("tau", C.c_double), ("diag_flags", C.c_uint32),
                 ("delta", C.c_double), ("pivot", C.c_int), ("shift0", C.c_double), ("spd", C.c_int32),
                 ("krylov", C.c_int), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
+                ("kernel_timing", C.c_int32), ("border", C.c_int32), ("refine_delta", C.c_double),
+                ("refine_every", C.c_int32)]
 
 
 class CInfo(C.Structure):
@@ -59,7 +61,9 @@ class CInfo(C.Structure):
                 ("shifted_blocks", C.c_int32), ("max_shift", C.c_double), ("outer_iters", C.c_int32),
                 ("inner_iters", C.c_int32), ("fp64_fallbacks", C.c_int32), ("restarts", C.c_int32),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("relres", C.c_double),
-                ("bytes_per_iter", C.c_int64), ("device_bytes", C.c_int64)]
+                ("bytes_per_iter", C.c_int64), ("device_bytes", C.c_int64), ("spmv_ms", C.c_double * 2),
+                ("spmv_launches", C.c_int64 * 2), ("bj_ms", C.c_double * 2), ("bj_launches", C.c_int64 * 2),
+                ("spmv_bytes", C.c_int64 * 2), ("bj_bytes", C.c_int64 * 2)]
 
 
 # every symbol the header declares, with its ctypes signature
@@ -119,6 +123,10 @@ class Options:
     inner_tol: float = 1e-4
     max_outer: int = 30
     check_every: int = 16
+    kernel_timing: bool = False
+    border: bool = True
+    refine_delta: float = 0.1
+    refine_every: int = 500
 
     def c(self) -> COptions:
         o = COptions()
@@ -270,7 +278,11 @@ class Solver:
     def info(self) -> dict:
         inf = CInfo()
         _check(self.h, lib().sdsl_get_info(self.h, C.byref(inf)))
-        return {f: getattr(inf, f) for f, _ in CInfo._fields_}
+        out = {}
+        for f, _ in CInfo._fields_:
+            v = getattr(inf, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
 
     def close(self):
         if getattr(self, "h", None):

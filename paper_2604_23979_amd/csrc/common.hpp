@@ -22,9 +22,15 @@ struct KrylovState {
     int breakdown;   // 1: (p, Mp) <= 0 or a non-finite scalar
     int iters;       // iteration count at the moment `done` was set
     int spin_err;    // a bounded in-workgroup wait gave up (never expected)
-    int pad[3];
+    int update;      // 1: a refinement point is due (residual fell below delta
+                     //    times its last refined value, or refine_every passed)
+    int it_refine;   // iteration index of the last refinement point
+    int refine_every;
     double bb;       // ||b||^2 of the current (inner) right-hand side
     double tol2;     // tol^2 for the squared-residual test
+    double rr0;      // ||r||^2 at the last refinement point
+    double delta2;   // refinement trigger (0: never)
+    double rzs[2];   // (r, z) of the last two iterations, parity-indexed
 };
 
 // -------------------------------------------------------------- reductions
@@ -113,6 +119,11 @@ void launch_filter_compact(int n_int, const int* rp, const int* ci, const double
                            const int* bp, int nblocks, int mode, double tau, unsigned flags,
                            double delta, const double* dropsum, const int* prp, int* pci,
                            double* pv_corr, int* pdiag, hipStream_t s);
+// split the in-place factors into L (strict lower) and U (strict upper +
+// diagonal) arrays; lrp/urp must hold the exclusive scans of the counts
+void launch_lu_counts(int n_int, const int* prp, const int* pdiag, int* lcnt, int* ucnt, hipStream_t s);
+void launch_lu_split(int n_int, const int* prp, const int* pci, const double* pv, const int* pdiag, const int* lrp,
+                     int* lci, double* lval, const int* urp, int* uci, double* uval, double* udiag, hipStream_t s);
 void launch_ilu0(int nblocks, const int* bp, const int* prp, const int* pci, const double* pv_corr,
                  double* pv, const int* pdiag, int spd, int policy, double shift0, double* shifts,
                  int* nfix, int* block_status, int* spin_err, hipStream_t s);
@@ -142,21 +153,26 @@ int spmv_lanes(double mean_row);
 
 template <typename T>
 void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, hipStream_t s);
-template <typename T>
-void launch_spmv(const CsrView& A, const T* v, const LowRankDev& lr, const T* x, T* y, double* part_dot,
+template <typename V, typename F>
+void launch_spmv(const CsrView& A, const F* v, const LowRankDev& lr, const V* x, V* y, double* part_dot,
                  const KrylovState* st, int lanes, int grid, hipStream_t s);
 void launch_residual(const CsrView& A, const double* v, const LowRankDev& lr, const double* b,
                      const double* x, double* r, double* part, int lanes, int grid, hipStream_t s);
 // ||a||^2 and similar final reductions into out[0] (one workgroup)
 void launch_sum_partials(const double* part, int m, double* out, hipStream_t s);
 
+// Block factors split for the sweeps: strict lower part (unit L) and strict
+// upper part of U in CSR, and the diagonal of U; values double or float.
 struct BJDev {
     int nblocks;
     const int* bp;
-    const int* prp;
-    const int* pci;
-    const void* pv;     // double or float factors
-    const int* pdiag;
+    const int* lrp;
+    const int* lci;
+    const void* lval;
+    const int* urp;
+    const int* uci;
+    const void* uval;
+    const void* udiag;
 };
 
 // MODE 0: z = P^{-1} r.  MODE 1: PCG step (alpha from partials, x/r update,
@@ -174,11 +190,33 @@ struct PcgVecs {
     double* part_rz;       // [2 * nblocks], parity-indexed
     double* part_rr;       // [nblocks]
 };
-template <typename T>
+
+// Border correction of a low-rank term in the preconditioner:
+// z <- z - W s with s = Kinv t, t = U^T z (partials of the U^T x kernel).
+struct BorderDev {
+    int k = 0;                  // 0: no border
+    int slices = 0;
+    const double* part = nullptr;  // U^T z partials [k * slices]
+    const double* W = nullptr;     // n x k, column-major
+    const double* Kinv = nullptr;  // k x k, row-major
+};
+
+// pupdate modes
+enum { PUPD_STEP = 0, PUPD_START = 1, PUPD_REAPPLY = 2 };
+template <typename V, typename F>
 void launch_bj(int mode, const BJDev& P, const PcgVecs& v, KrylovState* st, int it, hipStream_t s);
 
 template <typename T>
-void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, KrylovState* st, int it, hipStream_t s);
+void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, const BorderDev& bd, KrylovState* st, int it,
+                        int mode, hipStream_t s);
+template <typename T>
+void launch_border_fix(int n, T* z, const BorderDev& bd, hipStream_t s);
+// border setup: dense column j of U (CSC) into e; K = diag(1/c) + U^T W; Kinv
+void launch_scatter_column(int n, const int* ucp, const int* uri, const double* ucv, int j, double* e,
+                           hipStream_t s);
+void launch_border_k(int n, int k, const int* ucp, const int* uri, const double* ucv, const double* c,
+                     const double* W, double* K, hipStream_t s);
+void launch_small_inverse(int k, const double* K, double* Kinv, int* status, hipStream_t s);
 
 // vector helpers
 template <typename T>
@@ -188,6 +226,11 @@ void launch_copy(int64_t n, const T* a, T* b, hipStream_t s);
 void launch_sqnorm_partials(int n, const double* a, double* part, int grid, hipStream_t s);
 void launch_ir_scale_cast(int n, const double* r, const double* nr, float* rs, hipStream_t s);
 void launch_ir_update(int n, double* x, const double* nr, const float* d, hipStream_t s);
-void launch_init_state(KrylovState* st, const double* part_bb, int m, double tol, hipStream_t s);
+void launch_init_state(KrylovState* st, const double* part_bb, int m, double tol, double delta,
+                       hipStream_t s);
+// after a refinement point at iteration `it`: rr0 = sum(part), clear
+// done/conv/update (keep rzs), next forced refinement after `every` more
+void launch_refine_state(KrylovState* st, const double* part, int m, int it, int every, hipStream_t s);
+void launch_sqnorm_f32_partials(int n, const float* a, double* part, int grid, hipStream_t s);
 
 }  // namespace sdsl

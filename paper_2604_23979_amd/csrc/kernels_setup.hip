@@ -374,6 +374,36 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu0(const int* __restrict__ bp
     }
 }
 
+__global__ void k_lu_counts(int n, const int* __restrict__ prp, const int* __restrict__ pdiag, int* __restrict__ lc,
+                            int* __restrict__ uc) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        lc[i] = pdiag[i] - prp[i];
+        uc[i] = prp[i + 1] - pdiag[i] - 1;
+    }
+}
+void launch_lu_counts(int n_int, const int* prp, const int* pdiag, int* lcnt, int* ucnt, hipStream_t s) {
+    const int g = (n_int + 255) / 256 < 4096 ? (n_int + 255) / 256 : 4096;
+    if (n_int > 0) k_lu_counts<<<g, 256, 0, s>>>(n_int, prp, pdiag, lcnt, ucnt);
+}
+__global__ void k_lu_split(int n, const int* __restrict__ prp, const int* __restrict__ pci,
+                           const double* __restrict__ pv, const int* __restrict__ pdiag, const int* __restrict__ lrp,
+                           int* __restrict__ lci, double* __restrict__ lval, const int* __restrict__ urp,
+                           int* __restrict__ uci, double* __restrict__ uval, double* __restrict__ udiag) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int a = prp[i], d = pdiag[i], e = prp[i + 1];
+        int w = lrp[i];
+        for (int p = a; p < d; ++p, ++w) { lci[w] = pci[p]; lval[w] = pv[p]; }
+        w = urp[i];
+        for (int p = d + 1; p < e; ++p, ++w) { uci[w] = pci[p]; uval[w] = pv[p]; }
+        udiag[i] = pv[d];
+    }
+}
+void launch_lu_split(int n_int, const int* prp, const int* pci, const double* pv, const int* pdiag, const int* lrp,
+                     int* lci, double* lval, const int* urp, int* uci, double* uval, double* udiag, hipStream_t s) {
+    const int g = (n_int + 255) / 256 < 4096 ? (n_int + 255) / 256 : 4096;
+    if (n_int > 0) k_lu_split<<<g, 256, 0, s>>>(n_int, prp, pci, pv, pdiag, lrp, lci, lval, urp, uci, uval, udiag);
+}
+
 void launch_ilu0(int nblocks, const int* bp, const int* prp, const int* pci, const double* pv_corr,
                  double* pv, const int* pdiag, int spd, int policy, double shift0, double* shifts,
                  int* nfix, int* block_status, int* spin_err, hipStream_t s) {

@@ -1,7 +1,8 @@
 // Host runtime and C ABI of the solver: the handle, preconditioner setup and
-// refactorisation, and the Krylov drivers (PCG in FP64, FP32-inner PCG inside
-// FP64 iterative refinement).  Every numerical step runs in the gfx950
-// kernels; the host only sequences launches and reads a few scalars.
+// refactorisation, and the Krylov drivers (PCG in FP64; PCG over FP32
+// operator values and factors inside FP64 refinement; classical FP32 inner
+// refinement).  Every numerical step runs in the gfx950 kernels; the host only
+// sequences launches and reads a few scalars.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -55,26 +56,39 @@ struct sdsl_ctx {
     float* v32 = nullptr;
     double* diag = nullptr;
     int lanes = 4, grid = 8;
-    // low-rank term
-    LowRankDev lr64{}, lr32{};
-    // block-Jacobi preconditioner
+    // low-rank term (kept in FP64 in every mode)
+    LowRankDev lr{};
+    int64_t lr_nnz = 0;
+    // block-Jacobi preconditioner: filtered + corrected values, in-place
+    // ILU(0) factors, and the split copies the sweeps read
     int *prp = nullptr, *pci = nullptr, *pdiag = nullptr, *cnt = nullptr, *scan_tmp = nullptr;
     double *pv_corr = nullptr, *pv = nullptr, *dropsum = nullptr, *shifts = nullptr;
-    float* pv32 = nullptr;
     int *nfix = nullptr, *bstatus = nullptr, *spin_err = nullptr;
+    int *lrp = nullptr, *lci = nullptr, *urp = nullptr, *uci = nullptr, *ucnt = nullptr;
+    double *lval = nullptr, *uval = nullptr, *udiag = nullptr;
+    float *lval32 = nullptr, *uval32 = nullptr, *udiag32 = nullptr;
     int p_nnz = 0;
+    // border correction of the low-rank term (W = P^{-1} U, K^{-1})
+    double* W64 = nullptr;
+    double *Kmat = nullptr, *Kinv = nullptr;
+    int* kstat = nullptr;
+    BorderDev bd{};
     // Krylov workspace
-    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *y = nullptr, *d = nullptr;
-    double* rf = nullptr;  // right-hand side of an FP64 fallback solve
-    float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *y32 = nullptr;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *d = nullptr, *rf = nullptr;
+    double* y = nullptr;     // forward-sweep scratch of the FP64 solve
+    float* y32 = nullptr;    // forward-sweep scratch of FP32 solves
+    float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_b = nullptr, *part_res = nullptr;
-    double* scal = nullptr;  // [0] = ||r||^2 of the latest residual, [1] = ||b||^2
+    double* scal = nullptr;  // [0] = ||r||^2 of the latest true residual, [1] = ||b||^2
     KrylovState* st = nullptr;
     KrylovState* st_h = nullptr;  // pinned
     double* scal_h = nullptr;     // pinned
     ValidateOut* vout = nullptr;
     ValidateOut* vout_h = nullptr;
     sdsl_info info{};
+    // kernel timing: three events per iteration (SpMV start, SpMV end = BJ
+    // start, BJ end), reused across batches
+    std::vector<hipEvent_t> ev;
 
     template <typename T>
     T* alloc(size_t count) {
@@ -88,12 +102,21 @@ struct sdsl_ctx {
         bytes += b;
         return (T*)ptr;
     }
+    void release(void* ptr, size_t b) {
+        auto it = std::find(allocs.begin(), allocs.end(), ptr);
+        if (it != allocs.end()) {
+            allocs.erase(it);
+            (void)hipFree(ptr);
+            bytes -= b;
+        }
+    }
     ~sdsl_ctx() {
         if (s) (void)hipStreamSynchronize(s);
         for (void* a : allocs) (void)hipFree(a);
         if (st_h) (void)hipHostFree(st_h);
         if (scal_h) (void)hipHostFree(scal_h);
         if (vout_h) (void)hipHostFree(vout_h);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
     void sync() { hip_check(hipStreamSynchronize(s), "stream synchronize"); }
     void check_launch() { hip_check(hipGetLastError(), "kernel launch"); }
@@ -127,6 +150,51 @@ void check_values(sdsl_ctx* h, const double* vals) {
     if (h->vout_h->nonfinite) fail(SDSL_E_INVALID, "non-finite matrix values");
 }
 
+BJDev bj_dev(sdsl_ctx* h, bool fp32) {
+    BJDev P;
+    P.nblocks = h->nb;
+    P.bp = h->bp;
+    P.lrp = h->lrp;
+    P.lci = h->lci;
+    P.urp = h->urp;
+    P.uci = h->uci;
+    P.lval = fp32 ? (const void*)h->lval32 : (const void*)h->lval;
+    P.uval = fp32 ? (const void*)h->uval32 : (const void*)h->uval;
+    P.udiag = fp32 ? (const void*)h->udiag32 : (const void*)h->udiag;
+    return P;
+}
+
+// W = P^{-1} U column by column (block-Jacobi applies), K = C^{-1} + U^T W
+// and its inverse; rebuilt with every factorisation.
+void build_border(sdsl_ctx* h) {
+    h->bd = BorderDev{};
+    if (!h->o.border || h->lr.k <= 0) return;
+    const int k = h->lr.k, n = h->n;
+    if (!h->W64) {
+        h->W64 = h->alloc<double>((size_t)k * n);
+        h->Kmat = h->alloc<double>((size_t)k * k);
+        h->Kinv = h->alloc<double>((size_t)k * k);
+        h->kstat = h->alloc<int>(1);
+    }
+    PcgVecs V{};
+    for (int j = 0; j < k; ++j) {
+        launch_scatter_column(n, h->lr.ucp, h->lr.uri, (const double*)h->lr.ucv, j, h->d, h->s);
+        V.r = h->d;
+        V.z = h->W64 + (size_t)j * n;
+        V.y = h->y;
+        launch_bj<double, double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
+    }
+    launch_border_k(n, k, h->lr.ucp, h->lr.uri, (const double*)h->lr.ucv, (const double*)h->lr.c, h->W64, h->Kmat,
+                    h->s);
+    launch_small_inverse(k, h->Kmat, h->Kinv, h->kstat, h->s);
+    h->check_launch();
+    int bad = 0;
+    hip_check(hipMemcpyAsync(&bad, h->kstat, sizeof(int), hipMemcpyDeviceToHost, h->s), "copy");
+    h->sync();
+    if (bad) fail(SDSL_E_BREAKDOWN, "border Schur complement K = C^-1 + U^T P^-1 U is singular");
+    h->bd = BorderDev{k, h->lr.slices, h->lr.part, h->W64, h->Kinv};
+}
+
 void build_precond(sdsl_ctx* h) {
     const double t0 = now_ms();
     hipStream_t s = h->s;
@@ -140,9 +208,17 @@ void build_precond(sdsl_ctx* h) {
     hip_check(hipMemsetAsync(h->spin_err, 0, sizeof(int), s), "memset");
     launch_ilu0(h->nb, h->bp, h->prp, h->pci, h->pv_corr, h->pv, h->pdiag, h->o.spd, h->o.pivot, h->o.shift0,
                 h->shifts, h->nfix, h->bstatus, h->spin_err, s);
+    // split copies for the sweeps (and their FP32 roundings)
+    launch_lu_counts(h->n_int, h->prp, h->pdiag, h->cnt, h->ucnt, s);
+    launch_scan(h->n_int, h->cnt, h->lrp, h->scan_tmp, s);
+    launch_scan(h->n_int, h->ucnt, h->urp, h->scan_tmp, s);
+    launch_lu_split(h->n_int, h->prp, h->pci, h->pv, h->pdiag, h->lrp, h->lci, h->lval, h->urp, h->uci, h->uval,
+                    h->udiag, s);
     h->check_launch();
-    int kept = 0, nfix = 0, spin = 0;
+    int kept = 0, nfix = 0, spin = 0, nl = 0, nu = 0;
     hip_check(hipMemcpyAsync(&kept, h->prp + h->n_int, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    hip_check(hipMemcpyAsync(&nl, h->lrp + h->n_int, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    hip_check(hipMemcpyAsync(&nu, h->urp + h->n_int, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     hip_check(hipMemcpyAsync(&nfix, h->nfix, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     hip_check(hipMemcpyAsync(&spin, h->spin_err, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     std::vector<int> bst(h->nb);
@@ -151,11 +227,11 @@ void build_precond(sdsl_ctx* h) {
     hip_check(hipMemcpyAsync(sh.data(), h->shifts, h->nb * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
     h->sync();
     h->p_nnz = kept;
-    launch_cast_f32(kept, h->pv, h->pv32, s);
+    launch_cast_f32(nl, h->lval, h->lval32, s);
+    launch_cast_f32(nu, h->uval, h->uval32, s);
+    launch_cast_f32(h->n_int, h->udiag, h->udiag32, s);
     h->check_launch();
     h->info.nnz_kept = kept;
-    int64_t in_block = 0;
-    (void)in_block;
     h->info.pivot_fixes = nfix;
     h->info.shifted_blocks = 0;
     h->info.max_shift = 0.0;
@@ -168,10 +244,18 @@ void build_precond(sdsl_ctx* h) {
             fail(SDSL_E_BREAKDOWN, "ILU(0) breakdown in block " + std::to_string(b) + " (pivot policy " +
                                        std::to_string((int)h->o.pivot) + ")");
     h->sync();
+    build_border(h);
     h->info.setup_ms = now_ms() - t0;
-    // algorithmic bytes of one FP64 PCG iteration (SpMV + BJ apply + vectors)
-    const int64_t n = h->n;
-    h->info.bytes_per_iter = (8 + 4) * h->nnz + (4 + 16) * n + (8 + 4) * (int64_t)kept + (8 + 32) * n + 72 * n;
+    // algorithmic bytes: every array a launch must touch, once.  Index 0: FP64
+    // values and vectors; index 1: FP32 values/factors with FP64 vectors.
+    const int64_t n = h->n, ni = h->n_int, off = (int64_t)kept - ni;
+    for (int p = 0; p < 2; ++p) {
+        const int64_t f = p ? 4 : 8;
+        h->info.spmv_bytes[p] = (f + 4) * h->nnz + 4 * (n + 1) + 2 * 8 * n;
+        if (h->lr_nnz > 0) h->info.spmv_bytes[p] += 12 * h->lr_nnz + 4 * (n + 1);
+        h->info.bj_bytes[p] = (f + 4) * off + f * ni + 8 * (ni + 1) + 2 * f * n + 7 * 8 * n;
+    }
+    h->info.bytes_per_iter = h->info.spmv_bytes[0] + h->info.bj_bytes[0] + 3 * 8 * n;
 }
 
 void setup_lowrank(sdsl_ctx* h, const sdsl_lowrank* lr) {
@@ -198,7 +282,7 @@ void setup_lowrank(sdsl_ctx* h, const sdsl_lowrank* lr) {
             if (uci[p] < 0 || uci[p] >= k || !std::isfinite(uv[p])) fail(SDSL_E_INVALID, "bad low-rank entry");
     }
     for (double cj : c)
-        if (!std::isfinite(cj)) fail(SDSL_E_INVALID, "non-finite low-rank scale");
+        if (!std::isfinite(cj) || cj == 0.0) fail(SDSL_E_INVALID, "low-rank scales must be finite and non-zero");
     // CSC copy for U^T x
     std::vector<int> cp(k + 1, 0), ri(U.nnz);
     std::vector<double> cv(U.nnz);
@@ -214,99 +298,98 @@ void setup_lowrank(sdsl_ctx* h, const sdsl_lowrank* lr) {
     std::vector<int> urp32(n + 1);
     for (int i = 0; i <= n; ++i) urp32[i] = (int)urp[i];
     const int64_t m = U.nnz;
+    h->lr_nnz = m;
     int* d_urp = h->alloc<int>(n + 1);
     int* d_uci = h->alloc<int>(m);
     double* d_uv = h->alloc<double>(m);
-    float* d_uv32 = h->alloc<float>(m);
     int* d_ucp = h->alloc<int>(k + 1);
     int* d_uri = h->alloc<int>(m);
     double* d_ucv = h->alloc<double>(m);
-    float* d_ucv32 = h->alloc<float>(m);
     double* d_c = h->alloc<double>(k);
-    float* d_c32 = h->alloc<float>(k);
     const int slices = 32;
     double* part = h->alloc<double>(2 * k * slices);
-    std::vector<float> f(m);
     hip_check(hipMemcpy(d_urp, urp32.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_uci, uci.data(), m * sizeof(int), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_uv, uv.data(), m * sizeof(double), hipMemcpyHostToDevice), "copy");
-    for (int64_t p = 0; p < m; ++p) f[p] = (float)uv[p];
-    hip_check(hipMemcpy(d_uv32, f.data(), m * sizeof(float), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_ucp, cp.data(), (k + 1) * sizeof(int), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_uri, ri.data(), m * sizeof(int), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_ucv, cv.data(), m * sizeof(double), hipMemcpyHostToDevice), "copy");
-    for (int64_t p = 0; p < m; ++p) f[p] = (float)cv[p];
-    hip_check(hipMemcpy(d_ucv32, f.data(), m * sizeof(float), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_c, c.data(), k * sizeof(double), hipMemcpyHostToDevice), "copy");
-    std::vector<float> c32(k);
-    for (int j = 0; j < k; ++j) c32[j] = (float)c[j];
-    hip_check(hipMemcpy(d_c32, c32.data(), k * sizeof(float), hipMemcpyHostToDevice), "copy");
-    LowRankDev base;
-    base.k = k;
-    base.slices = slices;
-    base.urp = d_urp;
-    base.uci = d_uci;
-    base.ucp = d_ucp;
-    base.uri = d_uri;
-    base.part = part;
-    h->lr64 = base;
-    h->lr64.uv = d_uv;
-    h->lr64.ucv = d_ucv;
-    h->lr64.c = d_c;
-    h->lr32 = base;
-    h->lr32.uv = d_uv32;
-    h->lr32.ucv = d_ucv32;
-    h->lr32.c = d_c32;
-}
-
-BJDev bj_dev(sdsl_ctx* h, bool fp32) {
-    BJDev P;
-    P.nblocks = h->nb;
-    P.bp = h->bp;
-    P.prp = h->prp;
-    P.pci = h->pci;
-    P.pv = fp32 ? (const void*)h->pv32 : (const void*)h->pv;
-    P.pdiag = h->pdiag;
-    return P;
+    LowRankDev L;
+    L.k = k;
+    L.slices = slices;
+    L.urp = d_urp;
+    L.uci = d_uci;
+    L.uv = d_uv;
+    L.ucp = d_ucp;
+    L.uri = d_uri;
+    L.ucv = d_ucv;
+    L.c = d_c;
+    L.part = part;
+    h->lr = L;
 }
 
 // ------------------------------------------------------------- PCG engine
-// One PCG run on the device.  The right-hand side is already in r and x is
-// zero; `issue` launches up to `count` iterations (kernels become no-ops once
-// the device state says done); `poll` synchronises and reads that state.
-template <typename T>
+// One PCG recurrence on the device with vectors of type V and operator
+// values / factors of type F.  `start` forms z = P^{-1} r and p = z for the
+// residual in r; `issue` launches up to `count` iterations (kernels become
+// no-ops once the device state says done); `reapply` resumes after a
+// refinement point replaced r; `poll` synchronises and reads the state.
+template <typename V, typename F>
 struct Pcg {
     sdsl_ctx* h;
-    T *x, *r, *z, *p, *q, *y;
-    const T* v;
-    const LowRankDev* lr;
+    V *x, *r, *z, *p, *q;
+    F* y;
+    const F* v;
     BJDev P;
-    PcgVecs V;
-    int it = 0;      // next iteration index
-    int done_its = 0;
+    PcgVecs Vv;
+    int it = 0;  // next iteration index
+    int batch_start = 0, batch_count = 0;
+    static constexpr int kPrec = sizeof(F) == 4 ? 1 : 0;
 
-    void init(bool fp32) {
-        P = bj_dev(h, fp32);
-        V.x = x; V.r = r; V.p = p; V.q = q; V.z = z; V.y = y;
-        V.part_pq = h->part_pq;
-        V.npq = h->grid;
-        V.part_rz = h->part_rz;
-        V.part_rr = h->part_rr;
+    void init() {
+        P = bj_dev(h, sizeof(F) == 4);
+        Vv.x = x; Vv.r = r; Vv.p = p; Vv.q = q; Vv.z = z; Vv.y = y;
+        Vv.part_pq = h->part_pq;
+        Vv.npq = h->grid;
+        Vv.part_rz = h->part_rz;
+        Vv.part_rr = h->part_rr;
     }
-    // z = P^{-1} r, p = z, (r,z) into the parity slot of iteration it-1
-    void start() {
-        launch_bj<T>(2, P, V, h->st, it - 1, h->s);
-        launch_copy<T>(h->n, z, p, h->s);
-        if (lr->k > 0) launch_lowrank_tdot<T>(*lr, p, h->st, h->s);
+    void set_x(V* xx) { x = xx; Vv.x = xx; }
+    void precondition(int j, int mode) {
+        launch_bj<V, F>(2, P, Vv, h->st, j, h->s);
+        if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, nullptr, h->s);
+        launch_pcg_pupdate<V>(h->n, Vv, h->nb, h->bd, h->st, j, mode, h->s);
+        if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, h->s);
         h->check_launch();
+    }
+    void start(int it0) {
+        precondition(it0 - 1, PUPD_START);
+        it = it0;
+    }
+    void reapply(int j) {
+        precondition(j, PUPD_REAPPLY);
+        it = j + 1;
     }
     void issue(int count) {
         const CsrView A{h->n, h->rp, h->ci};
+        const bool timing = h->o.kernel_timing != 0;
+        if (timing && (int)h->ev.size() < 3 * count) {
+            const size_t old = h->ev.size();
+            h->ev.resize(3 * count);
+            for (size_t i = old; i < h->ev.size(); ++i) hip_check(hipEventCreate(&h->ev[i]), "event create");
+        }
+        batch_start = it;
+        batch_count = count;
         for (int k = 0; k < count; ++k, ++it) {
-            launch_spmv<T>(A, v, *lr, p, q, h->part_pq, h->st, h->lanes, h->grid, h->s);
-            launch_bj<T>(1, P, V, h->st, it, h->s);
-            launch_pcg_pupdate<T>(h->n, V, h->nb, h->st, it, h->s);
-            if (lr->k > 0) launch_lowrank_tdot<T>(*lr, p, h->st, h->s);
+            if (timing) hip_check(hipEventRecord(h->ev[3 * k], h->s), "event record");
+            launch_spmv<V, F>(A, v, h->lr, p, q, h->part_pq, h->st, h->lanes, h->grid, h->s);
+            if (timing) hip_check(hipEventRecord(h->ev[3 * k + 1], h->s), "event record");
+            launch_bj<V, F>(1, P, Vv, h->st, it, h->s);
+            if (timing) hip_check(hipEventRecord(h->ev[3 * k + 2], h->s), "event record");
+            if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, h->st, h->s);
+            launch_pcg_pupdate<V>(h->n, Vv, h->nb, h->bd, h->st, it, PUPD_STEP, h->s);
+            if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, h->s);
         }
         h->check_launch();
     }
@@ -314,6 +397,21 @@ struct Pcg {
         hip_check(hipMemcpyAsync(h->st_h, h->st, sizeof(KrylovState), hipMemcpyDeviceToHost, h->s), "copy");
         h->sync();
         if (h->st_h->spin_err) fail(SDSL_E_DEVICE, "triangular solve in-workgroup wait limit exceeded");
+        if (h->o.kernel_timing && batch_count > 0) {
+            // only launches made before the state said done did work
+            int live = batch_count;
+            if (h->st_h->done) live = std::max(0, std::min(batch_count, h->st_h->iters - batch_start));
+            for (int k = 0; k < live; ++k) {
+                float a = 0.f, b = 0.f;
+                hip_check(hipEventElapsedTime(&a, h->ev[3 * k], h->ev[3 * k + 1]), "event time");
+                hip_check(hipEventElapsedTime(&b, h->ev[3 * k + 1], h->ev[3 * k + 2]), "event time");
+                h->info.spmv_ms[kPrec] += a;
+                h->info.bj_ms[kPrec] += b;
+            }
+            h->info.spmv_launches[kPrec] += live;
+            h->info.bj_launches[kPrec] += live;
+        }
+        batch_count = 0;
         return *h->st_h;
     }
 };
@@ -327,17 +425,22 @@ double reduce_to_host(sdsl_ctx* h, const double* part, int m, int idx) {
     return h->scal_h[idx];
 }
 
+// r = b - M x (compensated FP64); scal[0] = ||r||^2; returns ||r||
 double true_residual(sdsl_ctx* h, const double* b, const double* x, double* r) {
     const CsrView A{h->n, h->rp, h->ci};
-    launch_residual(A, h->v, h->lr64, b, x, r, h->part_res, h->lanes, h->grid, h->s);
+    launch_residual(A, h->v, h->lr, b, x, r, h->part_res, h->lanes, h->grid, h->s);
     h->check_launch();
     return std::sqrt(reduce_to_host(h, h->part_res, h->grid, 0));
 }
 
+__global__ void k_axpy1(int n, double* __restrict__ x, const double* __restrict__ d) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = x[i] + d[i];
+}
+
 // ------------------------------------------------------------- solve task
-// Resumable solve: `step()` issues the next stretch of device work and
-// returns; `wait()` synchronises on it.  sdsl_solve runs one task to the end;
-// sdsl_solve_batch interleaves several on their own streams.
+// Resumable solve: `step()` reads the state of the pending device work and
+// issues the next stretch; sdsl_solve runs one task to the end,
+// sdsl_solve_batch interleaves several tasks on their own streams.
 struct SolveTask {
     sdsl_ctx* h = nullptr;
     const double* b = nullptr;
@@ -350,52 +453,57 @@ struct SolveTask {
     bool finished = false;
     double t0 = 0.0;
 
-    enum Phase { P64_ITER, IR_ITER } phase = P64_ITER;
-    // FP64 PCG (also the IR fallback)
-    Pcg<double> pcg64{};
-    double* pcg_rhs = nullptr;   // b (plain solve) or the IR residual (fallback)
-    double* pcg_out = nullptr;   // x (plain) or d (fallback)
-    double pcg_tol = 0.0;
+    enum Phase { P64, PMIX, P32_RESTART } phase = P64;
+    Pcg<double, double> pcg64{};
+    Pcg<double, float> pcgmix{};
+    Pcg<float, float> pcg32{};
+    // FP64 PCG target (the solve itself, or an FP64 fallback of an FP32 mode)
+    const double* rhs64 = nullptr;
+    double* out64 = nullptr;
+    double tol64 = 0.0, nrhs64 = 0.0;
     bool fallback = false;
-    // FP32 inner PCG
-    Pcg<float> pcg32{};
+    int fb_base_its = 0;
+    // refinement bookkeeping
     double nr = 0.0, prev = 0.0;
     int slow = 0;
+
+    int max_iter() const { return h->o.max_iter; }
 
     void begin(sdsl_ctx* hh, const double* bb, double* xx, double tt) {
         h = hh; b = bb; xout = xx; tol = tt;
         t0 = now_ms();
+        for (int p = 0; p < 2; ++p) {
+            h->info.spmv_ms[p] = h->info.bj_ms[p] = 0.0;
+            h->info.spmv_launches[p] = h->info.bj_launches[p] = 0;
+        }
         launch_sqnorm_partials(h->n, b, h->part_b, h->grid, h->s);
         h->check_launch();
-        nb = std::sqrt(reduce_to_host(h, h->part_b, h->grid, 1));
+        nb = std::sqrt(reduce_to_host(h, h->part_b, h->grid, 1));  // scal[1] = ||b||^2
         launch_fill<double>(h->n, xout, 0.0, h->s);
         if (nb == 0.0) { finish(SDSL_OK, 0.0); return; }
-        pcg64 = Pcg<double>{h, h->x, h->r, h->z, h->p, h->q, h->y, h->v, &h->lr64};
-        pcg64.init(false);
-        pcg32 = Pcg<float>{h, h->x32, h->r32, h->z32, h->p32, h->q32, h->y32, h->v32, &h->lr32};
-        pcg32.init(true);
+        pcg64 = Pcg<double, double>{h, h->x, h->r, h->z, h->p, h->q, h->y, h->v};
+        pcg64.init();
+        pcgmix = Pcg<double, float>{h, xout, h->r, h->z, h->p, h->q, h->y32, h->v32};
+        pcgmix.init();
+        pcg32 = Pcg<float, float>{h, h->x32, h->r32, h->z32, h->p32, h->q32, h->y32, h->v32};
+        pcg32.init();
         if (h->o.precision == SDSL_FP64) {
-            start_pcg64(b, xout, tol);
+            start64(b, xout, tol, nb);
+        } else if (h->o.precision == SDSL_FP32_IR) {
+            // FP64 recurrence over the FP32 operator and factors; the true
+            // FP64 residual replaces the recurrence one at refinement points
+            phase = PMIX;
+            nr = prev = nb;
+            launch_copy<double>(h->n, b, h->r, h->s);
+            launch_init_state(h->st, h->part_b, h->grid, tol, h->o.refine_delta, h->s);
+            launch_refine_state(h->st, h->part_b, h->grid, 0, h->o.refine_every, h->s);
+            pcgmix.start(0);
+            pcgmix.issue(std::min(h->o.check_every, max_iter()));
         } else {
-            phase = IR_ITER;
-            ir_outer_check(true);
+            phase = P32_RESTART;
+            nr = true_residual(h, b, xout, h->r);
+            restart_inner();
         }
-    }
-    // plain FP64 PCG on M out = rhs (x0 = 0) to ||rhs - M out|| <= t ||rhs||
-    void start_pcg64(const double* rhs, double* out, double t) {
-        phase = P64_ITER;
-        pcg_rhs = const_cast<double*>(rhs);
-        pcg_out = out;
-        pcg_tol = t;
-        pcg64.x = out;
-        pcg64.V.x = out;
-        pcg64.it = 0;
-        launch_fill<double>(h->n, out, 0.0, h->s);
-        launch_copy<double>(h->n, rhs, h->r, h->s);
-        launch_sqnorm_partials(h->n, rhs, h->part_res, h->grid, h->s);
-        launch_init_state(h->st, h->part_res, h->grid, t, h->s);
-        pcg64.start();
-        pcg64.issue(std::min(h->o.check_every, h->o.max_iter - total_its));
     }
     void finish(sdsl_status s, double rr) {
         status = s;
@@ -408,149 +516,127 @@ struct SolveTask {
         h->info.fp64_fallbacks = fallbacks;
         h->info.restarts = restarts;
     }
-    // IR: residual of the current x; decide to stop, fall back or run an inner solve
-    void ir_outer_check(bool first) {
-        if (first) {
-            nr = true_residual(h, b, xout, h->r);
-        }
+    // FP64 PCG on M out = rhs, x0 = 0, to ||rhs - M out|| <= t * nrhs
+    void start64(const double* rhs, double* out, double t, double nrhs) {
+        phase = P64;
+        rhs64 = rhs;
+        out64 = out;
+        tol64 = t;
+        nrhs64 = nrhs;
+        pcg64.set_x(out);
+        launch_fill<double>(h->n, out, 0.0, h->s);
+        launch_copy<double>(h->n, rhs, h->r, h->s);
+        launch_sqnorm_partials(h->n, rhs, h->part_res, h->grid, h->s);
+        launch_init_state(h->st, h->part_res, h->grid, t, 0.0, h->s);
+        pcg64.start(0);
+        pcg64.issue(std::min(h->o.check_every, std::max(1, max_iter() - total_its)));
+    }
+    // FP64 fallback of the FP32 modes: solve M d = r (the current residual)
+    void start_fallback() {
+        fallback = true;
+        fallbacks++;
+        fb_base_its = total_its;
+        launch_copy<double>(h->n, h->r, h->rf, h->s);
+        start64(h->rf, h->d, tol * nb / nr, nr);
+    }
+    void restart_inner() {
+        // classical refinement: inner FP32 PCG on M d = r / ||r|| to inner_tol
         if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
-        if (outer >= h->o.max_outer || total_its >= h->o.max_iter) {
-            finish(SDSL_E_NOT_CONVERGED, nr / nb);
-            return;
-        }
-        if (slow >= 2) {
-            // FP64 fallback on M d = r for the rest of the tolerance
-            fallback = true;
-            fallbacks++;
-            outer++;
-            launch_copy<double>(h->n, h->r, h->rf, h->s);
-            start_pcg64(h->rf, h->d, tol * nb / nr);
-            return;
-        }
-        // inner FP32 solve of M d = r / ||r||
+        if (outer >= h->o.max_outer || total_its >= max_iter()) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
+        if (slow >= 2) { start_fallback(); return; }
         launch_ir_scale_cast(h->n, h->r, h->scal + 0, h->r32, h->s);
         launch_fill<float>(h->n, h->x32, 0.0f, h->s);
-        // ||rs||^2 accumulated in FP64 from the FP32 values
-        launch_inner_bb();
-        launch_init_state(h->st, h->part_res, h->grid, h->o.inner_tol, h->s);
-        pcg32.it = 0;
-        pcg32.start();
-        pcg32.issue(std::min(h->o.check_every, h->o.max_iter - total_its));
+        launch_sqnorm_f32_partials(h->n, h->r32, h->part_res, h->grid, h->s);
+        launch_init_state(h->st, h->part_res, h->grid, h->o.inner_tol, 0.0, h->s);
+        pcg32.start(0);
+        pcg32.issue(std::min(h->o.check_every, max_iter() - total_its));
     }
-    void launch_inner_bb();
+    void after_fallback(sdsl_status st64) {
+        const int g = std::min(4096, (h->n + 255) / 256);
+        k_axpy1<<<std::max(g, 1), 256, 0, h->s>>>(h->n, xout, h->d);  // x += d
+        h->check_launch();
+        nr = true_residual(h, b, xout, h->r);
+        fallback = false;
+        finish(nr <= tol * nb ? SDSL_OK : (st64 == SDSL_E_BREAKDOWN ? SDSL_E_BREAKDOWN : SDSL_E_NOT_CONVERGED),
+               nr / nb);
+    }
 
-    // advance after the pending work finished; returns false once finished
     void step() {
         if (finished) return;
-        if (phase == P64_ITER) {
-            const KrylovState& s = pcg64.poll();
-            if (!s.done) {
-                const int used = pcg64.it;
-                if (total_its + used >= h->o.max_iter) {
-                    total_its += used;
-                    double rr = true_residual(h, pcg_rhs, pcg_out, h->r);
-                    end_pcg64(SDSL_E_NOT_CONVERGED, rr);
-                    return;
-                }
-                pcg64.issue(std::min(h->o.check_every, h->o.max_iter - total_its - used));
-                return;
-            }
-            const int its = s.iters;
-            if (s.breakdown) {
-                total_its += its;
-                double rr = true_residual(h, pcg_rhs, pcg_out, h->r);
-                end_pcg64(SDSL_E_BREAKDOWN, rr);
-                return;
-            }
-            // converged on the recurrence: check the true residual
-            const double rr = true_residual(h, pcg_rhs, pcg_out, h->r);
-            const double nrhs = fallback ? nr : nb;
-            if (rr <= pcg_tol * nrhs || total_its + its >= h->o.max_iter) {
-                total_its += its;
-                end_pcg64(rr <= pcg_tol * nrhs ? SDSL_OK : SDSL_E_NOT_CONVERGED, rr);
-                return;
-            }
-            // restart from the true residual (now in r); x keeps accumulating
-            restarts++;
-            total_its += its;
-            pcg64.it = 0;
-            if (fallback) {
-                // bb is ||rhs||^2 of the fallback system
-                launch_sqnorm_partials(h->n, pcg_rhs, h->part_res, h->grid, h->s);
-                launch_init_state(h->st, h->part_res, h->grid, pcg_tol, h->s);
-            } else {
-                launch_init_state(h->st, h->part_b, h->grid, pcg_tol, h->s);
-            }
-            pcg64.start();
-            pcg64.issue(std::min(h->o.check_every, h->o.max_iter - total_its));
-            return;
-        }
-        // IR inner FP32 PCG
+        if (phase == P64) { step64(); return; }
+        if (phase == PMIX) { step_mixed(); return; }
+        // classical refinement: wait for the inner solve to stop
         const KrylovState& s = pcg32.poll();
-        if (!s.done && total_its + pcg32.it < h->o.max_iter) {
-            pcg32.issue(std::min(h->o.check_every, h->o.max_iter - total_its - pcg32.it));
+        if (!s.done && total_its + pcg32.it < max_iter()) {
+            pcg32.issue(std::min(h->o.check_every, max_iter() - total_its - pcg32.it));
             return;
         }
         total_its += s.done ? s.iters : pcg32.it;
-        if (s.done && s.breakdown && s.iters == 0) {
-            // no progress possible in FP32: force the FP64 fallback
-            slow = 2;
-        }
-        // x += ||r|| d
-        launch_ir_update(h->n, xout, h->scal + 0, h->x32, h->s);
+        if (s.done && s.breakdown && s.iters <= 1) slow = 2;
+        launch_ir_update(h->n, xout, h->scal + 0, h->x32, h->s);   // x += ||r|| d
         h->check_launch();
         outer++;
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
         slow = (nr > 0.5 * prev) ? slow + 1 : (slow >= 2 ? slow : 0);
-        ir_outer_check(false);
+        restart_inner();
     }
-    void end_pcg64(sdsl_status st, double rr) {
-        if (!fallback) {
-            finish(st, rr / nb);
+    void step_mixed() {
+        const KrylovState& s = pcgmix.poll();
+        const bool at_limit = pcgmix.it >= max_iter();
+        if (!s.done && !at_limit) {
+            pcgmix.issue(std::min(h->o.check_every, max_iter() - pcgmix.it));
             return;
         }
-        // fallback finished: x += d, back to the refinement loop
-        fallback = false;
-        phase = IR_ITER;
-        launch_axpy_x();
+        // refinement point: the true residual of the FP64 solution
+        const int its = s.done ? s.iters : pcgmix.it;
+        total_its = its;
+        outer++;
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
-        slow = 0;
-        if (st == SDSL_E_BREAKDOWN) { finish(st, nr / nb); return; }
-        ir_outer_check(false);
+        if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
+        slow = (nr > 0.5 * prev) ? slow + 1 : 0;
+        if (slow >= 3 || (s.done && s.breakdown)) { start_fallback(); return; }
+        if (at_limit || (!s.conv && !s.update)) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
+        // the true residual (now in r) replaces the recurrence one; the
+        // recurrence continues with its search direction
+        launch_refine_state(h->st, h->part_res, h->grid, its, h->o.refine_every, h->s);
+        pcgmix.reapply(its - 1);
+        pcgmix.issue(std::min(h->o.check_every, max_iter() - pcgmix.it));
     }
-    void launch_axpy_x();
+    void step64() {
+        const KrylovState& s = pcg64.poll();
+        const int used = pcg64.it;
+        const int base = fallback ? fb_base_its : 0;
+        if (!s.done) {
+            if (base + used >= max_iter()) {
+                total_its = base + used;
+                end64(SDSL_E_NOT_CONVERGED);
+                return;
+            }
+            pcg64.issue(std::min(h->o.check_every, max_iter() - base - used));
+            return;
+        }
+        total_its = base + s.iters;
+        if (s.breakdown) { end64(SDSL_E_BREAKDOWN); return; }
+        // converged on the recurrence: check the true residual
+        const double rr = true_residual(h, rhs64, out64, h->r);
+        if (rr <= tol64 * nrhs64) { end64(SDSL_OK, rr); return; }
+        if (total_its >= max_iter()) { end64(SDSL_E_NOT_CONVERGED, rr); return; }
+        // restart from the true residual (now in r); the solution keeps accumulating
+        restarts++;
+        launch_sqnorm_partials(h->n, rhs64, h->part_res, h->grid, h->s);
+        launch_init_state(h->st, h->part_res, h->grid, tol64, 0.0, h->s);
+        pcg64.start(s.iters);
+        pcg64.issue(std::min(h->o.check_every, max_iter() - base - s.iters));
+    }
+    void end64(sdsl_status st, double rr = -1.0) {
+        if (fallback) { after_fallback(st); return; }
+        if (rr < 0) rr = true_residual(h, rhs64, out64, h->r);
+        finish(st, rr / nb);
+    }
 };
 
-}  // namespace
-
-// small device helpers used by the task (defined here to keep them local)
-__global__ void k_axpy1(int n, double* __restrict__ x, const double* __restrict__ d) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = x[i] + d[i];
-}
-__global__ __launch_bounds__(256) void k_sqnorm_f32(int n, const float* __restrict__ a, double* __restrict__ part) {
-    __shared__ double red[8];
-    const int g = gridDim.x;
-    const int per = (n + g - 1) / g;
-    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
-    double s = 0.0;
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) s += (double)a[i] * (double)a[i];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-void SolveTask::launch_axpy_x() {
-    const int g = std::min(4096, (h->n + 255) / 256);
-    k_axpy1<<<std::max(g, 1), 256, 0, h->s>>>(h->n, xout, h->d);
-    h->check_launch();
-}
-void SolveTask::launch_inner_bb() {
-    k_sqnorm_f32<<<h->grid, 256, 0, h->s>>>(h->n, h->r32, h->part_res);
-    h->check_launch();
-}
-
-namespace {
 sdsl_status guard(sdsl_ctx* h, const std::function<void()>& fn) {
     try {
         fn();
@@ -582,9 +668,11 @@ void check_options(const sdsl_options* o) {
         fail(SDSL_E_INVALID, "shift0 must be positive");
     if (o->krylov != SDSL_PCG) fail(SDSL_E_INVALID, "only PCG is available in this library");
     if (o->max_iter < 1 || o->check_every < 1) fail(SDSL_E_INVALID, "max_iter and check_every must be >= 1");
-    if (o->precision != SDSL_FP64 && o->precision != SDSL_FP32_IR) fail(SDSL_E_INVALID, "unknown precision");
-    if (o->precision == SDSL_FP32_IR && (!(o->inner_tol > 0.0 && o->inner_tol < 1.0) || o->max_outer < 1))
+    if (o->precision < SDSL_FP64 || o->precision > SDSL_FP32_IR_RESTART) fail(SDSL_E_INVALID, "unknown precision");
+    if (o->precision == SDSL_FP32_IR_RESTART && (!(o->inner_tol > 0.0 && o->inner_tol < 1.0) || o->max_outer < 1))
         fail(SDSL_E_INVALID, "inner_tol must be in (0,1) and max_outer >= 1");
+    if (o->precision == SDSL_FP32_IR && (!(o->refine_delta > 0.0 && o->refine_delta < 1.0) || o->refine_every < 1))
+        fail(SDSL_E_INVALID, "refine_delta must be in (0,1) and refine_every >= 1");
 }
 
 void check_partition(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o) {
@@ -626,6 +714,10 @@ void sdsl_default_options(sdsl_options* o) {
     o->inner_tol = 1e-4;
     o->max_outer = 30;
     o->check_every = 16;
+    o->kernel_timing = 0;
+    o->border = 1;
+    o->refine_delta = 0.1;
+    o->refine_every = 500;
 }
 
 size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o,
@@ -633,11 +725,12 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
     if (!A || !p || !o || A->n <= 0 || A->nnz < 0) return 0;
     const size_t n = (size_t)A->n, nnz = (size_t)A->nnz, nb = (size_t)std::max(p->nblocks, 1);
     size_t b = 0;
-    b += (n + 1) * 4 + nnz * (4 + 8 + 4) + n * 8;           // operator + FP32 copy + diag
-    b += (n + 1) * 4 + nnz * (4 + 8 + 8 + 4) + n * (4 + 4 + 8);  // preconditioner capacity
-    b += n * (7 * 8 + 6 * 4);                                  // Krylov vectors
+    b += (n + 1) * 4 + nnz * (4 + 8 + 4) + n * 8;                  // operator + FP32 copy + diag
+    b += (n + 1) * 4 + nnz * (4 + 8 + 8) + n * (4 + 4 + 4 + 8);     // filtered pattern, values, factors
+    b += nnz * (4 + 8 + 4) + 2 * (n + 1) * 4 + n * (8 + 4);         // split factors + FP32 copies
+    b += n * (8 * 8 + 6 * 4);                                       // Krylov vectors
     b += (nb + 1) * 4 + nb * (8 + 4) + 2048 * 8 * 4 + nb * 8 * 3;
-    if (lr && lr->k > 0) b += (size_t)lr->U.nnz * 2 * (4 + 8 + 4) + (n + 1) * 4;
+    if (lr && lr->k > 0) b += (size_t)lr->U.nnz * 2 * (4 + 8) + (n + 1) * 4 + (size_t)lr->k * n * 8;
     b += (n + 1023) / 1024 * 4 + 4096;
     return b;
 }
@@ -699,19 +792,30 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->grid = spmv_grid(n);
         setup_lowrank(h, lr);
         // preconditioner buffers (capacity: every entry of M)
-        h->prp = h->alloc<int>(h->n_int + 1);
+        const int ni = h->n_int;
+        h->prp = h->alloc<int>(ni + 1);
         h->pci = h->alloc<int>(nnz);
         h->pv_corr = h->alloc<double>(nnz);
         h->pv = h->alloc<double>(nnz);
-        h->pv32 = h->alloc<float>(nnz);
-        h->pdiag = h->alloc<int>(h->n_int);
-        h->cnt = h->alloc<int>(h->n_int);
-        h->dropsum = h->alloc<double>(h->n_int);
-        h->scan_tmp = h->alloc<int>((h->n_int + 1023) / 1024 + 2);
+        h->pdiag = h->alloc<int>(ni);
+        h->cnt = h->alloc<int>(ni);
+        h->ucnt = h->alloc<int>(ni);
+        h->dropsum = h->alloc<double>(ni);
+        h->scan_tmp = h->alloc<int>((ni + 1023) / 1024 + 2);
         h->shifts = h->alloc<double>(h->nb);
         h->nfix = h->alloc<int>(1);
         h->bstatus = h->alloc<int>(h->nb);
         h->spin_err = h->alloc<int>(1);
+        h->lrp = h->alloc<int>(ni + 1);
+        h->urp = h->alloc<int>(ni + 1);
+        h->lci = h->alloc<int>(nnz);
+        h->uci = h->alloc<int>(nnz);
+        h->lval = h->alloc<double>(nnz);
+        h->uval = h->alloc<double>(nnz);
+        h->udiag = h->alloc<double>(ni);
+        h->lval32 = h->alloc<float>(nnz);
+        h->uval32 = h->alloc<float>(nnz);
+        h->udiag32 = h->alloc<float>(ni);
         // Krylov workspace
         h->x = h->alloc<double>(n);
         h->r = h->alloc<double>(n);
@@ -736,9 +840,7 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->st = h->alloc<KrylovState>(1);
         build_precond(h);
         h->sync();
-        hip_check(hipFree(rp64), "free");
-        h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), (void*)rp64));
-        h->bytes -= (size_t)(n + 1) * sizeof(int64_t);
+        h->release(rp64, (size_t)(n + 1) * sizeof(int64_t));
         h->info.device_bytes = (int64_t)h->bytes;
         h->info.nnz_dropped = 0;
         h->info.setup_ms = now_ms() - t0;
@@ -785,9 +887,9 @@ sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, in
         if (iters) *iters = t.total_its;
         if (relres) *relres = t.relres;
         result = t.status;
-        if (result != SDSL_OK)
-            h->err = result == SDSL_E_BREAKDOWN ? "Krylov breakdown" : "tolerance not reached";
     });
+    if (st == SDSL_OK && result != SDSL_OK)
+        h->err = result == SDSL_E_BREAKDOWN ? "Krylov breakdown" : "tolerance not reached";
     return st != SDSL_OK ? st : result;
 }
 
@@ -801,6 +903,7 @@ sdsl_status sdsl_solve_batch(int32_t k, const sdsl_handle* hs, const double* con
         if (!hs[i]) { res[i] = SDSL_E_INVALID; continue; }
         res[i] = guard(hs[i], [&] {
             if (!b[i] || !x[i]) fail(SDSL_E_INVALID, "null vector");
+            if (!(tol > 0.0)) fail(SDSL_E_INVALID, "tol must be positive");
             tasks[i].begin(hs[i], b[i], x[i], tol);
         });
         live[i] = res[i] == SDSL_OK;
@@ -843,13 +946,13 @@ sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y) {
         if (!x || !y) fail(SDSL_E_INVALID, "null vector");
         const CsrView A{h->n, h->rp, h->ci};
         if (prec == SDSL_FP64) {
-            if (h->lr64.k > 0) launch_lowrank_tdot<double>(h->lr64, (const double*)x, nullptr, h->s);
-            launch_spmv<double>(A, h->v, h->lr64, (const double*)x, (double*)y, nullptr, nullptr, h->lanes, h->grid,
-                                h->s);
+            if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, (const double*)x, nullptr, h->s);
+            launch_spmv<double, double>(A, h->v, h->lr, (const double*)x, (double*)y, nullptr, nullptr, h->lanes,
+                                        h->grid, h->s);
         } else {
-            if (h->lr32.k > 0) launch_lowrank_tdot<float>(h->lr32, (const float*)x, nullptr, h->s);
-            launch_spmv<float>(A, h->v32, h->lr32, (const float*)x, (float*)y, nullptr, nullptr, h->lanes, h->grid,
-                               h->s);
+            if (h->lr.k > 0) launch_lowrank_tdot<float>(h->lr, (const float*)x, nullptr, h->s);
+            launch_spmv<float, float>(A, h->v32, h->lr, (const float*)x, (float*)y, nullptr, nullptr, h->lanes,
+                                      h->grid, h->s);
         }
         h->check_launch();
         h->sync();
@@ -866,10 +969,18 @@ sdsl_status sdsl_precond_apply(sdsl_handle h, int32_t prec, const void* r, void*
         hip_check(hipMemsetAsync(h->spin_err, 0, sizeof(int), h->s), "memset");
         if (prec == SDSL_FP64) {
             V.y = h->y;
-            launch_bj<double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
+            launch_bj<double, double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
+            if (h->bd.k > 0) {
+                launch_lowrank_tdot<double>(h->lr, (const double*)z, nullptr, h->s);
+                launch_border_fix<double>(h->n, (double*)z, h->bd, h->s);
+            }
         } else {
             V.y = h->y32;
-            launch_bj<float>(0, bj_dev(h, true), V, nullptr, 0, h->s);
+            launch_bj<float, float>(0, bj_dev(h, true), V, nullptr, 0, h->s);
+            if (h->bd.k > 0) {
+                launch_lowrank_tdot<float>(h->lr, (const float*)z, nullptr, h->s);
+                launch_border_fix<float>(h->n, (float*)z, h->bd, h->s);
+            }
         }
         h->check_launch();
         h->sync();

@@ -522,3 +522,62 @@ def test_ir_reaches_tolerance_and_matches_fp64_solution():
     e = x - x64
     den = np.sqrt(x64 @ (M @ x64))
     assert np.sqrt(e @ (M @ e)) / den < 1e-3
+
+
+# --------------------------------------------------------------- border, reliable updates
+
+def test_border_correction_is_exact_inverse_of_bordered_preconditioner():
+    """With the dense columns as a border, the preconditioner applies
+    (P + U C U^T)^{-1} exactly (Sherman-Morrison-Woodbury of the bordered
+    block elimination)."""
+    s = gen.c2(0.004)
+    P = O.BJ(s, O.FILTER_GEOMEAN, 1e-3, O.DIAG_DROPSUM, border=True)
+    assert P.status == O.OK and P.border_status == O.OK
+    n = s.n
+    L, Uf = unpack_lu(P.rp, P.ci, P.v, n)
+    U, c = s.lowrank
+    Ud = U.toarray()
+    Pfull = L @ Uf + Ud @ np.diag(c) @ Ud.T
+    r = np.random.default_rng(30).standard_normal(n)
+    z = P.apply(r)
+    zz = np.linalg.solve(Pfull, r)
+    assert np.linalg.norm(z - zz) <= 1e-8 * np.linalg.norm(zz)
+
+
+def test_border_removes_low_rank_outliers():
+    """The border preconditioner needs fewer PCG iterations than the block
+    preconditioner that ignores the low-rank term (no more than the system
+    without the dense columns needs, plus a few)."""
+    s = gen.c2(0.004)
+    s0 = gen.c2(0.004, dense_cols=0)
+    its = {}
+    for key, sys_, border in (("plain", s, False), ("border", s, True), ("nodense", s0, False)):
+        P = O.BJ(sys_, O.FILTER_GEOMEAN, 1e-3, O.DIAG_DROPSUM, border=border)
+        x, it, rr, st, _ = O.pcg_bj(sys_, P, tol=1e-8, maxit=50_000)
+        assert st == O.OK and rr <= 1e-8
+        its[key] = it
+    assert its["border"] < its["plain"]
+    assert its["border"] <= 1.5 * its["nodense"] + 20
+
+
+def test_reliable_update_fp32_reaches_tolerance_near_fp64_count():
+    s = gen.c2(0.01, dense_cols=0)
+    P = O.BJ(s, O.FILTER_GEOMEAN, 1e-3, O.DIAG_DROPSUM)
+    x64, it64, rr64, st64, _ = O.pcg_bj(s, P, tol=1e-8)
+    x, pts, it, fb, rr, st = O.ru_pcg_bj(s, P, tol=1e-8, delta=0.1)
+    assert st == O.OK and rr <= 1e-8 and fb == 0 and pts >= 2
+    assert it <= 2.0 * it64  # FP32 recurrences lose some conjugacy: 1.05-1.75x observed
+    M = s.scipy()
+    assert np.linalg.norm(s.b - M @ x) / np.linalg.norm(s.b) <= 1.5e-8
+    # a tridiagonal system in one block: the FP32 recurrence is exact up to
+    # FP32 rounding, so refinement ends after one or two points
+    n = 400
+    rng = np.random.default_rng(31)
+    off = rng.standard_normal(n - 1)
+    a = np.diag(np.abs(np.r_[off, 0]) + np.abs(np.r_[0, off]) + 1.0) + np.diag(off, 1) + np.diag(off, -1)
+    m = csr_of(a)
+    t = gen.System("tri", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, rng.standard_normal(n),
+                   np.array([0, n], dtype=np.int32))
+    Pt = O.BJ(t)
+    x, pts, it, fb, rr, st = O.ru_pcg_bj(t, Pt, tol=1e-12, delta=0.1)
+    assert st == O.OK and rr <= 1e-12 and it <= 4
