@@ -303,7 +303,9 @@ int or_bj_factor(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
 /* z = U^{-1} L^{-1} r by forward then backward substitution (paper Sec. 2.3,
  * "solve the precondition system").  Works on any set of rows [lo, hi)
  * whose entries stay inside [lo, hi) (one block) or on a whole block
- * diagonal matrix. */
+ * diagonal matrix.  The paper does not fix the order of the sums; each
+ * substitution subtracts its terms in the order in which their unknowns
+ * were solved: ascending columns going forward, descending going back. */
 void or_lu_solve(int64_t lo, int64_t hi, const int64_t* rp, const int32_t* ci, const double* v,
                  const int64_t* diag_pos, const double* r, double* z) {
     for (int64_t i = lo; i < hi; ++i) {
@@ -313,7 +315,7 @@ void or_lu_solve(int64_t lo, int64_t hi, const int64_t* rp, const int32_t* ci, c
     }
     for (int64_t i = hi - 1; i >= lo; --i) {
         double s = z[i];
-        for (int64_t p = diag_pos[i] + 1; p < rp[i + 1]; ++p) s -= v[p] * z[ci[p]];
+        for (int64_t p = rp[i + 1] - 1; p > diag_pos[i]; --p) s -= v[p] * z[ci[p]];
         z[i] = s / v[diag_pos[i]];
     }
 }

@@ -146,13 +146,22 @@ struct LowRankDev {
     const void* ucv = nullptr;
     const void* c = nullptr;   // k scaling factors (same type as values)
     double* part = nullptr;    // [k * slices] (FP64 sums; compensated: 2x)
+    double* fold = nullptr;    // [2 * kMaxRank] folded coefficients (see LrFold)
+    unsigned* counter = nullptr;  // arrival count of the folding reduction (self-resetting)
 };
+
+// What the last workgroup of a U^T x reduction leaves in fold[]:
+// LR_SCALED: fold[j] = c_j (U^T x)_j (the operator's low-rank term);
+// LR_BORDER: fold[j] = t_j = (U^T x)_j and fold[kMaxRank + j] = (K^{-1} t)_j.
+enum LrFold { LR_NONE = 0, LR_SCALED = 1, LR_BORDER = 2 };
+constexpr int kMaxRank = 64;
 
 int spmv_grid(int n);
 int spmv_lanes(double mean_row);
 
 template <typename T>
-void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, hipStream_t s);
+void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, int fold, const double* Kinv,
+                         hipStream_t s);
 template <typename V, typename F>
 void launch_spmv(const CsrView& A, const F* v, const LowRankDev& lr, const V* x, V* y, double* part_dot,
                  const KrylovState* st, int lanes, int grid, hipStream_t s);
@@ -173,6 +182,12 @@ struct BJDev {
     const int* uci;
     const void* uval;
     const void* udiag;
+    const int2* lch;  // forward chunk table (k_bj_chunks layout)
+    const int2* uch;  // backward chunk table
+    const int* llev;  // per-row level inside its forward chunk
+    const int* ulev;  // per-row level inside its backward chunk
+    const int* lnl;   // levels per forward chunk (chunk-table indexing)
+    const int* unl;   // levels per backward chunk
 };
 
 // MODE 0: z = P^{-1} r.  MODE 1: PCG step (alpha from partials, x/r update,
@@ -196,7 +211,7 @@ struct PcgVecs {
 struct BorderDev {
     int k = 0;                  // 0: no border
     int slices = 0;
-    const double* part = nullptr;  // U^T z partials [k * slices]
+    const double* fold = nullptr;  // t = U^T z and K^{-1} t (LR_BORDER layout)
     const double* W = nullptr;     // n x k, column-major
     const double* Kinv = nullptr;  // k x k, row-major
 };
@@ -205,6 +220,10 @@ struct BorderDev {
 enum { PUPD_STEP = 0, PUPD_START = 1, PUPD_REAPPLY = 2 };
 template <typename V, typename F>
 void launch_bj(int mode, const BJDev& P, const PcgVecs& v, KrylovState* st, int it, hipStream_t s);
+void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp, int2* lch, int2* uch,
+                      hipStream_t s);
+void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci, const int* urp, const int* uci,
+                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, hipStream_t s);
 
 template <typename T>
 void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, const BorderDev& bd, KrylovState* st, int it,

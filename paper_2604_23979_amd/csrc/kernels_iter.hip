@@ -6,7 +6,6 @@
 
 namespace sdsl {
 
-constexpr int kSpinLimitIter = 1 << 24;
 
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ bool krylov_done(const KrylovState* st) {
@@ -35,9 +34,10 @@ __device__ __forceinline__ int xcd_swizzle(int w, int g) {
 }
 
 int spmv_grid(int n) {
-    // 8 workgroups of 256 threads per CU over 256 CUs at most; a multiple of 8
-    int g = (n + 63) / 64;
-    if (g > 2048) g = 2048;
+    // one 64-row batch per wave (4 waves of 64 lanes per workgroup) up to
+    // 4096 workgroups; a multiple of 8 so the XCD swizzle is a permutation
+    int g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
     g = (g + 7) / 8 * 8;
     return g < 8 ? 8 : g;
 }
@@ -54,30 +54,52 @@ int spmv_lanes(double mean_row) {
 // ------------------------------------------------------------------ low rank
 // part[j * slices + s] = sum over slice s of column j of U^T x (FP64).  With
 // COMP the slice sums are compensated and their error terms go to
-// part[k * slices + j * slices + s].
-template <typename T, bool COMP>
-__global__ __launch_bounds__(256) void k_lowrank_tdot(int k, int slices, const int* __restrict__ ucp,
-                                                      const int* __restrict__ uri, const double* __restrict__ ucv,
-                                                      const T* __restrict__ x, double* __restrict__ part,
-                                                      const KrylovState* st) {
+// part[k * slices + j * slices + s].  With FOLD the last workgroup to finish
+// sums the slices of every column in slice order and writes the coefficients
+// that the consumers need into lr.fold (LrFold), so that they read k values
+// instead of k * slices.
+template <typename T, bool COMP, int FOLD>
+__global__ __launch_bounds__(256) void k_lowrank_tdot(LowRankDev lr, const T* __restrict__ x,
+                                                      const double* __restrict__ Kinv, const KrylovState* st) {
     __shared__ double red[8];
     __shared__ int shd;
     if (block_done(st, &shd)) return;
+    const int k = lr.k, slices = lr.slices;
+    const int* __restrict__ uri = lr.uri;
+    const double* __restrict__ ucv = (const double*)lr.ucv;
+    double* part = lr.part;
     const int j = blockIdx.x / slices, s = blockIdx.x % slices;
-    const int a = ucp[j], e = ucp[j + 1];
+    const int a = lr.ucp[j], e = lr.ucp[j + 1];
     const int len = e - a;
     const int lo = a + (int)((int64_t)len * s / slices), hi = a + (int)((int64_t)len * (s + 1) / slices);
     double sum = 0.0, err = 0.0;
-    for (int p = lo + threadIdx.x; p < hi; p += blockDim.x) {
-        const double pr = (double)ucv[p] * (double)x[uri[p]];
-        if (COMP) {
-            const double pe = fma((double)ucv[p], (double)x[uri[p]], -pr);
-            const double t = sum + pr;
-            const double z = t - sum;
-            err += (sum - (t - z)) + (pr - z) + pe;
-            sum = t;
-        } else {
-            sum += pr;
+    // four strides of loads in flight per thread; each thread still adds its
+    // entries in ascending order
+    for (int p0 = lo + (int)threadIdx.x; p0 < hi; p0 += 4 * (int)blockDim.x) {
+        int id[4];
+        double uv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = p0 + u * (int)blockDim.x;
+            id[u] = p < hi ? uri[p] : 0;
+            uv[u] = p < hi ? ucv[p] : 0.0;
+        }
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = (p0 + u * (int)blockDim.x < hi) ? (double)x[id[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (p0 + u * (int)blockDim.x >= hi) break;
+            const double pr = uv[u] * xv[u];
+            if (COMP) {
+                const double pe = fma(uv[u], xv[u], -pr);
+                const double t = sum + pr;
+                const double z = t - sum;
+                err += (sum - (t - z)) + (pr - z) + pe;
+                sum = t;
+            } else {
+                sum += pr;
+            }
         }
     }
     if (COMP) {
@@ -94,16 +116,54 @@ __global__ __launch_bounds__(256) void k_lowrank_tdot(int k, int slices, const i
         const double tot = block_sum(sum, red);
         if (threadIdx.x == 0) part[j * slices + s] = tot;
     }
+    if (FOLD != LR_NONE) {
+        __shared__ double sp[kMaxRank * kMaxRank];
+        __shared__ double ts[kMaxRank];
+        __shared__ int last;
+        if (threadIdx.x == 0) {
+            __threadfence();  // publish this workgroup's partial
+            const unsigned prev = atomicInc(lr.counter, gridDim.x - 1);
+            last = prev == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (!last) return;
+        __threadfence();  // every partial is visible
+        const int m = k * slices;
+        for (int q = threadIdx.x; q < m; q += blockDim.x) sp[q] = part[q];
+        __syncthreads();
+        for (int jj = threadIdx.x; jj < k; jj += blockDim.x) {
+            double t = 0.0;
+            for (int q = 0; q < slices; ++q) t += sp[jj * slices + q];
+            ts[jj] = t;
+            if (FOLD == LR_SCALED) lr.fold[jj] = ((const double*)lr.c)[jj] * t;
+            else lr.fold[jj] = t;
+        }
+        if (FOLD == LR_BORDER) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < k * k; q += blockDim.x) sp[q] = Kinv[q];
+            __syncthreads();
+            for (int jj = threadIdx.x; jj < k; jj += blockDim.x) {
+                double t = 0.0;
+                for (int i = 0; i < k; ++i) t = fma(sp[jj * k + i], ts[i], t);
+                lr.fold[kMaxRank + jj] = t;
+            }
+        }
+    }
 }
 
 template <typename T>
-void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, hipStream_t s) {
+void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, int fold, const double* Kinv,
+                         hipStream_t s) {
     if (lr.k <= 0) return;
-    k_lowrank_tdot<T, false><<<lr.k * lr.slices, 256, 0, s>>>(lr.k, lr.slices, lr.ucp, lr.uri,
-                                                              (const double*)lr.ucv, x, lr.part, st);
+    const int g = lr.k * lr.slices;
+    if (fold == LR_SCALED) k_lowrank_tdot<T, false, LR_SCALED><<<g, 256, 0, s>>>(lr, x, Kinv, st);
+    else if (fold == LR_BORDER) k_lowrank_tdot<T, false, LR_BORDER><<<g, 256, 0, s>>>(lr, x, Kinv, st);
+    else k_lowrank_tdot<T, false, LR_NONE><<<g, 256, 0, s>>>(lr, x, Kinv, st);
 }
-template void launch_lowrank_tdot<double>(const LowRankDev&, const double*, const KrylovState*, hipStream_t);
-template void launch_lowrank_tdot<float>(const LowRankDev&, const float*, const KrylovState*, hipStream_t);
+template void launch_lowrank_tdot<double>(const LowRankDev&, const double*, const KrylovState*, int, const double*,
+                                          hipStream_t);
+template void launch_lowrank_tdot<float>(const LowRankDev&, const float*, const KrylovState*, int, const double*,
+                                         hipStream_t);
 
 // ------------------------------------------------------------------ SpMV
 // y = M x (+ U diag(c) U^T x) with G lanes per row.  Values (type F) and
@@ -128,12 +188,7 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
     __shared__ int shd;
     if (block_done(st, &shd)) return;
     if (LR) {
-        const double* c = (const double*)lr.c;
-        for (int j = threadIdx.x; j < lr.k; j += blockDim.x) {
-            double s = 0.0;
-            for (int q = 0; q < lr.slices; ++q) s += lr.part[j * lr.slices + q];
-            tk[j] = c[j] * s;
-        }
+        for (int j = threadIdx.x; j < lr.k; j += blockDim.x) tk[j] = lr.fold[j];
         __syncthreads();
     }
     constexpr int RPS = kWave / G;  // rows per step per wave
@@ -150,6 +205,8 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
         const int nrow = min(kWave, r1 - base);
         const int my_a = (lane < nrow) ? rp[base + lane] : 0;
         const int my_e = (lane < nrow) ? rp[base + lane + 1] : 0;
+        const int my_u0 = (LR && lane < nrow) ? lr.urp[base + lane] : 0;
+        const int my_u1 = (LR && lane < nrow) ? lr.urp[base + lane + 1] : 0;
         F res = F(0);
 #pragma unroll 1
         for (int j = 0; j < kWave; j += RPS) {
@@ -181,9 +238,22 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
             const int row = base + lane;
             V out = (V)res;
             if (LR) {
-                const double* uv = (const double*)lr.uv;
+                // low-rank term in FP64, entries in order, 8 loads in flight
+                const double* __restrict__ uv = (const double*)lr.uv;
+                const int* __restrict__ uci = lr.uci;
                 double t = (double)res;
-                for (int q = lr.urp[row]; q < lr.urp[row + 1]; ++q) t = fma(uv[q], tk[lr.uci[q]], t);
+                for (int q = my_u0; q < my_u1; q += 8) {
+                    int cc[8];
+                    double uu[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        cc[u] = q + u < my_u1 ? uci[q + u] : 0;
+                        uu[u] = q + u < my_u1 ? uv[q + u] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (q + u < my_u1) t = fma(uu[u], tk[cc[u]], t);
+                }
                 out = (V)t;
             }
             y[row] = out;
@@ -300,9 +370,7 @@ __global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__
 void launch_residual(const CsrView& A, const double* v, const LowRankDev& lr, const double* b,
                      const double* x, double* r, double* part, int lanes, int grid, hipStream_t s) {
     if (lr.k > 0)
-        k_lowrank_tdot<double, true><<<lr.k * lr.slices, 256, 0, s>>>(lr.k, lr.slices, lr.ucp, lr.uri,
-                                                                      (const double*)lr.ucv, x, lr.part,
-                                                                      nullptr);
+        k_lowrank_tdot<double, true, LR_NONE><<<lr.k * lr.slices, 256, 0, s>>>(lr, x, nullptr, nullptr);
 #define RES_CASE(G)                                                                                  \
     case G:                                                                                          \
         if (lr.k > 0) k_residual<G, true><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, v, b, x, r, part, lr); \
@@ -456,22 +524,28 @@ void launch_ir_update(int n, double* x, const double* nr2, const float* d, hipSt
 // ------------------------------------------------------------------ BJ apply
 // One workgroup per diagonal block (all blocks in one launch).  Forward
 // substitution y = L^{-1} r then backward substitution z = U^{-1} y, each
-// over chunks of kBjThreads consecutive rows with one row per thread.  A
-// chunk's factor entries are first staged in LDS with coalesced loads (up to
-// kCap entries; the rest of an unusually dense chunk is read from memory).
+// over chunks of at most kBjThreads consecutive rows, one row per thread.
+// The chunk partition and the level of every row inside its chunk are fixed
+// by the factor's pattern and built once per factorisation (k_bj_chunks,
+// k_bj_levels): a chunk is the longest run of rows whose factor entries fit
+// the LDS stage (kStage entries); a single row that does not fit is a chunk
+// of its own and reads its entries from memory.  While a chunk is solved,
+// the next chunk's entries and row data are already in flight into
+// registers, so each chunk costs about one memory round trip.
 // The block's most recent kRing solution values live in an LDS ring (slot =
-// local row mod kRing); a slot of the current chunk holds the sentinel until
-// its row is final, so a row waits on a same-chunk dependency by re-reading
-// the slot.  Dependencies in earlier chunks are final after the chunk barrier
-// and are read from the ring, or from global memory once evicted.  No lane
-// ever blocks: every pass lets each row consume its terms, in ascending
-// column order, up to the first one that is not ready, so the smallest
-// pending row always advances.  The solve runs in the factor type F (FP32
-// factors: FP32 arithmetic); vectors have type V.
+// local row mod kRing).  Per row, the terms on earlier chunks (final: in the
+// ring, or in memory once evicted) are taken in one straight pass at the
+// start of the chunk; the same-chunk terms wait for the row's level: levels
+// are separated by workgroup barriers, so at its level every term of a row
+// is final.  Terms are always subtracted in ascending column order with a
+// separate product and difference, the order of a plain substitution.  The
+// solve runs in the factor type F (FP32 factors: FP32 arithmetic); vectors
+// have type V.
 constexpr int kBjThreads = 512;
 constexpr int kRing = 4096;
-template <typename F> struct BjCap { static constexpr int value = 8192; };
-template <> struct BjCap<float> { static constexpr int value = 12288; };
+constexpr int kStage = 8192;
+constexpr int kPer = kStage / kBjThreads;
+constexpr int kTab = 128;  // chunk-table entries per sweep cached in LDS
 
 template <typename T>
 __device__ __forceinline__ T from_bits(typename Sentinel<T>::Bits b) {
@@ -486,39 +560,272 @@ __device__ __forceinline__ typename Sentinel<T>::Bits to_bits(T v) {
     return b;
 }
 
-// Value of solution entry j.  `cur` tells whether j lies in the current chunk
-// (may be pending); `in_ring` whether an earlier row is still in the ring.
-template <typename F, typename G>
-__device__ __forceinline__ bool fetch_sol(const typename Sentinel<F>::Bits* ring, const G* g, int j, int lo, bool cur,
-                                          bool in_ring, F& out) {
-    using Bits = typename Sentinel<F>::Bits;
-    if (cur) {
-        const Bits raw = __hip_atomic_load(&ring[(j - lo) & (kRing - 1)], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-        out = from_bits<F>(raw);
-        return raw != Sentinel<F>::bits;
+// Chunk tables of block b, both with room for hi - lo + 1 entries at offset
+// lo + b: lch[m] = {first row of forward chunk m, lrp[that row]} with
+// lch[nch] = {hi, lrp[hi]}; uch[m] = {end row of backward chunk m, urp[that
+// row]} from uch[0] = {hi, urp[hi]} down to {lo, urp[lo]}.
+__global__ __launch_bounds__(kBjThreads) void k_bj_chunks(const int* __restrict__ bp, const int* __restrict__ lrp,
+                                                          const int* __restrict__ urp, int2* __restrict__ lch,
+                                                          int2* __restrict__ uch) {
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int lo = bp[b], hi = bp[b + 1];
+    int2* L = lch + lo + b;
+    int2* U = uch + lo + b;
+    int m = 0;
+    for (int c0 = lo; c0 < hi; ++m) {
+        if (t == 0) L[m] = make_int2(c0, lrp[c0]);
+        const int ebase = lrp[c0];
+        const bool fits = (c0 + t < hi) && (lrp[c0 + t + 1] - ebase <= kStage);
+        const int nrows = __syncthreads_count(fits);
+        c0 += nrows > 0 ? nrows : 1;
     }
-    if (in_ring) {
-        out = from_bits<F>(ring[(j - lo) & (kRing - 1)]);
-        return true;
+    if (t == 0) L[m] = make_int2(hi, lrp[hi]);
+    m = 0;
+    for (int c_hi = hi; c_hi > lo; ++m) {
+        if (t == 0) U[m] = make_int2(c_hi, urp[c_hi]);
+        const int top = urp[c_hi];
+        const int rowt = c_hi - 1 - t;
+        const bool fits = (rowt >= lo) && (top - urp[rowt] <= kStage);
+        const int nrows = __syncthreads_count(fits);
+        c_hi -= nrows > 0 ? nrows : 1;
     }
-    out = (F)g[j];
-    return true;
+    if (t == 0) U[m] = make_int2(lo, urp[lo]);
+}
+void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp, int2* lch, int2* uch,
+                      hipStream_t s) {
+    if (nblocks > 0) k_bj_chunks<<<nblocks, kBjThreads, 0, s>>>(bp, lrp, urp, lch, uch);
+}
+
+// Local levels of the rows of every chunk: level(i) = 0 if row i has no
+// dependency inside its chunk, else 1 + the largest level among them, so a
+// chunk is solved level by level with a barrier in between and every term
+// a row takes is final.  llev/ulev hold the level per row, lnl/unl the
+// number of levels per chunk (same indexing as the chunk tables).  Computed
+// in rounds: a row gets its level once all its same-chunk dependencies have
+// one; a chain of r rows needs r rounds and at most nrows rounds are run.
+__global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict__ bp, const int* __restrict__ lrp,
+                                                          const int* __restrict__ lci, const int* __restrict__ urp,
+                                                          const int* __restrict__ uci, const int2* __restrict__ lch,
+                                                          const int2* __restrict__ uch, int* __restrict__ llev,
+                                                          int* __restrict__ ulev, int* __restrict__ lnl,
+                                                          int* __restrict__ unl) {
+    __shared__ int slev[kBjThreads];
+    __shared__ int smax;
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int lo = bp[b], hi = bp[b + 1];
+    const int2* L = lch + lo + b;
+    const int2* U = uch + lo + b;
+    for (int dir = 0; dir < 2; ++dir) {
+        const int2* T = dir == 0 ? L : U;
+        const int* rp = dir == 0 ? lrp : urp;
+        const int* ci = dir == 0 ? lci : uci;
+        int* lev = dir == 0 ? llev : ulev;
+        int* nl = (dir == 0 ? lnl : unl) + lo + b;
+        const int end = dir == 0 ? hi : lo;
+        for (int m = 0; T[m].x != end; ++m) {
+            // chunk rows: forward [a, e) with row a + t; backward [e, a) with row a - 1 - t
+            const int a = T[m].x, e = T[m + 1].x;
+            const int nrows = dir == 0 ? e - a : a - e;
+            const int i = dir == 0 ? a + t : a - 1 - t;
+            const bool live = t < nrows;
+            // same-chunk dependencies: the tail of the row in both directions
+            // (forward rows ascend, j >= a; backward rows descend, j < a)
+            int q0 = 0, q1 = 0;
+            if (live) {
+                q0 = rp[i];
+                q1 = rp[i + 1];
+                int f = q1;
+                if (dir == 0)
+                    while (f > q0 && ci[f - 1] >= a) --f;
+                else
+                    while (f > q0 && ci[f - 1] < a) --f;
+                q0 = f;
+            }
+            if (t < kBjThreads) slev[t] = -1;
+            if (t == 0) smax = 0;
+            __syncthreads();
+            int mine = live ? -1 : 0;
+            for (int round = 0; round <= nrows; ++round) {
+                if (mine < 0) {
+                    int mx = -1;
+                    bool ok = true;
+                    for (int q = q0; q < q1 && ok; ++q) {
+                        const int j = ci[q];
+                        const int pj = dir == 0 ? j - a : a - 1 - j;
+                        const int lj = __hip_atomic_load(&slev[pj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        ok = lj >= 0;
+                        mx = lj > mx ? lj : mx;
+                    }
+                    if (ok) {
+                        mine = mx + 1;
+                        __hip_atomic_store(&slev[t], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                if (__syncthreads_count(mine < 0) == 0) break;
+            }
+            if (live) {
+                lev[i] = mine;
+                atomicMax(&smax, mine + 1);
+            }
+            __syncthreads();
+            if (t == 0) nl[m] = smax;
+            __syncthreads();
+        }
+    }
+}
+void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci, const int* urp, const int* uci,
+                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, hipStream_t s) {
+    if (nblocks > 0)
+        k_bj_levels<<<nblocks, kBjThreads, 0, s>>>(bp, lrp, lci, urp, uci, lch, uch, llev, ulev, lnl, unl);
+}
+
+// Issue the loads of a chunk's entries [ebase, ebase + nst) into registers
+// (entry t + u * kBjThreads goes to slot u); commit writes them to LDS.
+template <typename F>
+__device__ __forceinline__ void stage_issue(int (&pc)[kPer], F (&pv)[kPer], const int* __restrict__ ci,
+                                            const F* __restrict__ val, int ebase, int nst, int t) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = t + u * kBjThreads;
+        if (e < nst) {
+            pc[u] = ci[ebase + e];
+            pv[u] = val[ebase + e];
+        }
+    }
+}
+template <typename F>
+__device__ __forceinline__ void stage_commit(const int (&pc)[kPer], const F (&pv)[kPer], int* scol, F* sval, int nst,
+                                             int t) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = t + u * kBjThreads;
+        if (e < nst) {
+            scol[e] = pc[u];
+            sval[e] = pv[u];
+        }
+    }
+}
+
+// Take the terms [pos, lim) of one row, four at a time, while their slots
+// hold final values; returns with pos at the first pending term (or lim).
+template <typename F, typename Bits>
+__device__ __forceinline__ void take_ready(int& pos, int lim, F& acc, const int* scol, const F* sval,
+                                           const Bits* ring, int lo) {
+    constexpr Bits SENT = Sentinel<F>::bits;
+    bool blocked = false;
+    while (pos < lim && !blocked) {
+        int jj[4];
+        F ww[4];
+        Bits raw[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(pos + u, lim - 1);
+            jj[u] = scol[e];
+            ww[u] = sval[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            raw[u] = __hip_atomic_load(&ring[(jj[u] - lo) & (kRing - 1)], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool take = !blocked && (pos < lim) && (raw[u] != SENT);
+            acc = take ? acc - ww[u] * from_bits<F>(raw[u]) : acc;
+            blocked = blocked || !take;
+            pos += take ? 1 : 0;
+        }
+    }
+}
+
+// Subtract the terms [q0, q1) of a row whose solution slots are final, in
+// order, four loads in flight; a slot still holding the sentinel means the
+// level table does not match the factor and sets `bad`.
+template <typename F, typename Bits>
+__device__ __forceinline__ F take_final(int q0, int q1, F acc, const int* scol, const F* sval, const Bits* ring,
+                                        int lo, int& bad) {
+    constexpr Bits SENT = Sentinel<F>::bits;
+    for (int q = q0; q < q1; q += 4) {
+        int jj[4];
+        F ww[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(q + u, q1 - 1);
+            jj[u] = scol[e];
+            ww[u] = sval[e];
+        }
+        Bits raw[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) raw[u] = ring[(jj[u] - lo) & (kRing - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (q + u < q1) {
+                bad |= raw[u] == SENT;
+                acc = acc - ww[u] * from_bits<F>(raw[u]);
+            }
+        }
+    }
+    return acc;
+}
+
+// The same-chunk terms of a row (the tail of its entries) are held in
+// registers, kHold of them, from the start of the chunk; at the row's level
+// their slots are read in one round.
+constexpr int kHold = 8;
+template <typename F>
+__device__ __forceinline__ void hold_terms(int (&cj)[kHold], F (&cw)[kHold], int pos, int lim, const int* scol,
+                                           const F* sval) {
+#pragma unroll
+    for (int u = 0; u < kHold; ++u) {
+        const int e = min(pos + u, lim - 1);
+        cj[u] = scol[e];
+        cw[u] = sval[e];
+    }
+}
+template <typename F, typename Bits>
+__device__ __forceinline__ F take_held(const int (&cj)[kHold], const F (&cw)[kHold], int n, F acc, const Bits* ring,
+                                       int lo, int& bad) {
+    constexpr Bits SENT = Sentinel<F>::bits;
+    Bits raw[kHold];
+#pragma unroll
+    for (int u = 0; u < kHold; ++u) raw[u] = ring[(cj[u] - lo) & (kRing - 1)];
+#pragma unroll
+    for (int u = 0; u < kHold; ++u) {
+        if (u < n) {
+            bad |= raw[u] == SENT;
+            acc = acc - cw[u] * from_bits<F>(raw[u]);
+        }
+    }
+    return acc;
 }
 
 template <typename V, typename F, int MODE>
 __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovState* st, int it) {
     using Bits = typename Sentinel<F>::Bits;
     constexpr Bits SENT = Sentinel<F>::bits;
-    constexpr int kCap = BjCap<F>::value;
     __shared__ Bits ring[kRing];
-    __shared__ int scol[kCap];
-    __shared__ F sval[kCap];
+    __shared__ int scol[kStage];
+    __shared__ F sval[kStage];
     __shared__ double red[16];
     __shared__ int shd;
+    __shared__ int2 ltab[kTab];
+    __shared__ int2 utab[kTab];
+    __shared__ int lnl[kTab];
+    __shared__ int unl[kTab];
     const int b = blockIdx.x, t = threadIdx.x;
     const int nb = P.nblocks;
     const int lo = P.bp[b], hi = P.bp[b + 1];
+    // The block's chunk tables (hi - lo + 1 entries each, of which the
+    // first nch + 1 are used) are cached in LDS up to kTab entries; a
+    // uniform branch reads any further entries from memory.
+    const int2* LT = P.lch + lo + b;
+    const int2* UT = P.uch + lo + b;
+    for (int q = t; q < kTab && q <= hi - lo; q += kBjThreads) {
+        ltab[q] = LT[q];
+        utab[q] = UT[q];
+        lnl[q] = P.lnl[lo + b + q];
+        unl[q] = P.unl[lo + b + q];
+    }
+    __syncthreads();
     const int* __restrict__ lrp = P.lrp;
     const int* __restrict__ lci = P.lci;
     const F* __restrict__ lval = (const F*)P.lval;
@@ -548,216 +855,229 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
         const V* p = (const V*)Vv.p;
         const V* q = (const V*)Vv.q;
         double rr = 0.0;
-        for (int i = lo + t; i < hi; i += kBjThreads) {
-            x[i] = x[i] + a * p[i];
-            const V ri = r[i] - a * q[i];
-            r[i] = ri;
-            rr += (double)ri * (double)ri;
+        // four rows per thread in flight; each thread adds its rows in order
+        for (int i0 = lo + t; i0 < hi; i0 += 4 * kBjThreads) {
+            V pv[4], qv[4], xv[4], rv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * kBjThreads;
+                if (i < hi) {
+                    pv[u] = p[i];
+                    qv[u] = q[i];
+                    xv[u] = x[i];
+                    rv[u] = r[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * kBjThreads;
+                if (i < hi) {
+                    x[i] = xv[u] + a * pv[u];
+                    const V ri = rv[u] - a * qv[u];
+                    r[i] = ri;
+                    rr += (double)ri * (double)ri;
+                }
+            }
         }
-        rr = block_sum(rr, red);
+        rr = block_sum(rr, red);  // also orders the r updates before the sweeps read them
         if (t == 0) Vv.part_rr[b] = rr;
     }
     const V* rin = r;
-    int spin_fail = 0;
+    int bad = 0;
+    int pc[kPer];
+    F pv[kPer];
 
-    // forward substitution: y_i = r_i - sum_{j<i} l_ij y_j.  A chunk is the
-    // longest run of at most kBjThreads rows whose entries fit the LDS stage
-    // (a single row that does not fit is a chunk of its own and reads its
-    // entries from memory; all its dependencies are in earlier chunks).
-    // Per row: entries older than the ring (final, in global y) first, then
-    // the pass loop, which touches LDS only.  Ascending column order.
-    for (int c0 = lo; c0 < hi;) {
-        const int ebase = lrp[c0];
-        const bool fits = (c0 + t < hi) && (lrp[c0 + t + 1] - ebase <= kCap);
-        int nrows = __syncthreads_count(fits);
-        const bool big = nrows == 0;
-        if (big) nrows = 1;
-        const int c1 = c0 + nrows;
-        const int nst = big ? 0 : lrp[c1] - ebase;
-        for (int e = t; e < nst; e += kBjThreads) {
-            scol[e] = lci[ebase + e];
-            sval[e] = lval[ebase + e];
-        }
-        const int i = c0 + t;
-        if (i < c1) ring[(i - lo) & (kRing - 1)] = SENT;
-        __syncthreads();
-        bool fin = i >= c1;
-        int pos = fin ? 0 : lrp[i] - ebase;
-        const int pend = fin ? 0 : lrp[i + 1] - ebase;
-        F acc = fin ? F(0) : (F)rin[i];
-        const int ring_lo = c1 - kRing;
-        if (!fin && big) {
-            // oversized row: every dependency lies in an earlier chunk
-            for (; pos < pend; ++pos) {
-                const int j = lci[ebase + pos];
-                const F yj = (j >= ring_lo) ? from_bits<F>(ring[(j - lo) & (kRing - 1)]) : y[j];
-                acc = acc - lval[ebase + pos] * yj;
-            }
-        }
-        if (!fin && ring_lo > lo) {
-            // dependencies evicted from the ring: final, read from memory
-            while (pos < pend) {
-                const int j = scol[pos];
-                if (j >= ring_lo) break;
-                acc = acc - sval[pos] * y[j];
-                ++pos;
-            }
-        }
-        if (!fin) {
-            // dependencies in earlier chunks: final, in the ring
-            while (pos < pend) {
-                const int j = scol[pos];
-                if (j >= c0) break;
-                acc = acc - sval[pos] * from_bits<F>(ring[(j - lo) & (kRing - 1)]);
-                ++pos;
-            }
-        }
-        int spins = 0;
+    // ---- forward substitution: y_i = r_i - sum_{j<i} l_ij y_j
+    if (lo < hi) {
+        auto T = [&](int q) { return q < kTab ? ltab[q] : LT[q]; };
+        auto NL = [&](int q) { return q < kTab ? lnl[q] : P.lnl[lo + b + q]; };
+        int m = 0;
+        int2 ta = T(0), tb = T(1);
+        int2 tn = T(tb.x < hi ? 2 : 1);
+        int nst = tb.y - ta.y;
+        bool big = nst > kStage;
+        stage_issue(pc, pv, lci, lval, ta.y, big ? 0 : nst, t);
+        int i = ta.x + t;
+        bool live = i < tb.x;
+        int rp0 = live ? lrp[i] : 0, rp1 = live ? lrp[i + 1] : 0;
+        V rv = live ? rin[i] : V(0);
+        int lvn = live ? P.llev[i] : 0;
         while (true) {
-            if (!fin) {
-                // same-chunk dependencies: consume in order up to the first
-                // one whose slot still holds the sentinel
-                bool blocked = false;
-                while (pos < pend && !blocked) {
-                    int jj[4];
-                    F ww[4];
-                    Bits raw[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int e = min(pos + u, pend - 1);
-                        jj[u] = scol[e];
-                        ww[u] = sval[e];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        raw[u] = __hip_atomic_load(&ring[(jj[u] - lo) & (kRing - 1)], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const bool take = !blocked && (pos < pend) && (raw[u] != SENT);
-                        const F yv = from_bits<F>(raw[u]);
-                        acc = take ? acc - ww[u] * yv : acc;
-                        blocked = blocked || !take;
-                        pos += take ? 1 : 0;
-                    }
+            // current chunk [c0, c1), entries from ebase
+            const int c1 = tb.x, ebase = ta.y;
+            const bool cbig = big;
+            stage_commit(pc, pv, scol, sval, cbig ? 0 : nst, t);
+            if (live) ring[(i - lo) & (kRing - 1)] = SENT;
+            __syncthreads();
+            const int row = i;
+            bool fin = !live;
+            int pos = rp0 - ebase;
+            const int pend = rp1 - ebase;
+            F acc = (F)rv;
+            const int clev = lvn, cnl = NL(m);
+            // prefetch the next chunk
+            ++m;
+            ta = tb;
+            tb = tn;
+            const bool more = ta.x < hi;
+            if (more) {
+                tn = T(tb.x < hi ? m + 2 : m + 1);
+                nst = tb.y - ta.y;
+                big = nst > kStage;
+                stage_issue(pc, pv, lci, lval, ta.y, big ? 0 : nst, t);
+                i = ta.x + t;
+                live = i < tb.x;
+                rp0 = live ? lrp[i] : 0;
+                rp1 = live ? lrp[i + 1] : 0;
+                rv = live ? rin[i] : V(0);
+                lvn = live ? P.llev[i] : 0;
+            } else {
+                // last forward chunk: the first backward chunk's entries do
+                // not depend on y, so they load while this chunk is solved
+                const int2 ua = utab[0], ub = utab[1];
+                const int un = ua.y - ub.y;
+                stage_issue(pc, pv, uci, uval, ub.y, un > kStage ? 0 : un, t);
+            }
+            // solve the current chunk
+            const int ring_lo = c1 - kRing;
+            if (!fin && cbig) {
+                // oversized row: every dependency lies in an earlier chunk
+                for (; pos < pend; ++pos) {
+                    const int j = lci[ebase + pos];
+                    const F yj = (j >= ring_lo) ? from_bits<F>(ring[(j - lo) & (kRing - 1)]) : y[j];
+                    acc = acc - lval[ebase + pos] * yj;
                 }
-                if (pos == pend) {
-                    __hip_atomic_store(&ring[(i - lo) & (kRing - 1)], to_bits<F>(acc), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            if (!fin && ring_lo > lo) {
+                // dependencies evicted from the ring: final, in memory
+                while (pos < pend) {
+                    const int j = scol[pos];
+                    if (j >= ring_lo) break;
+                    acc = acc - sval[pos] * y[j];
+                    ++pos;
+                }
+            }
+            // terms on earlier chunks (final, in the ring) in one straight
+            // pass; it stops at the first same-chunk term still pending
+            if (!fin) take_ready(pos, pend, acc, scol, sval, ring, lo);
+            // same-chunk terms, level by level: at its level every term a
+            // row has left is final
+            int cj[kHold];
+            F cw[kHold];
+            const int nh = fin ? 0 : min(pend - pos, kHold);
+            if (nh > 0) hold_terms(cj, cw, pos, pend, scol, sval);
+            for (int lv = 0; lv < cnl; ++lv) {
+                if (!fin && clev == lv) {
+                    if (nh > 0) acc = take_held(cj, cw, nh, acc, ring, lo, bad);
+                    acc = take_final(pos + nh, pend, acc, scol, sval, ring, lo, bad);
+                    ring[(row - lo) & (kRing - 1)] = to_bits<F>(acc);
                     fin = true;
                 }
+                __syncthreads();
             }
-            if (__all(fin)) break;
-            if (++spins > kSpinLimitIter && !fin) {
-                spin_fail = 1;
-                __hip_atomic_store(&ring[(i - lo) & (kRing - 1)], to_bits<F>(acc), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                fin = true;
-            }
+            if (row < c1) y[row] = from_bits<F>(ring[(row - lo) & (kRing - 1)]);
+            __syncthreads();
+            if (!more) break;
         }
-        __syncthreads();
-        if (i < c1) y[i] = from_bits<F>(ring[(i - lo) & (kRing - 1)]);
-        __syncthreads();
-        c0 = c1;
     }
-    // backward substitution: z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii over
-    // chunks from the bottom of the block up.  Per row: the pass loop (LDS
-    // only) for dependencies still in the ring, then the evicted ones.
-    for (int c_hi = hi; c_hi > lo;) {
-        const int ebase_hi = urp[c_hi];
-        const int rowt = c_hi - 1 - t;
-        const bool fits = (t < kBjThreads) && (rowt >= lo) && (ebase_hi - urp[rowt] <= kCap);
-        int nrows = __syncthreads_count(fits);
-        const bool big = nrows == 0;
-        if (big) nrows = 1;
-        const int c_lo = c_hi - nrows;
-        const int ebase = urp[c_lo];
-        const int nst = big ? 0 : ebase_hi - ebase;
-        for (int e = t; e < nst; e += kBjThreads) {
-            scol[e] = uci[ebase + e];
-            sval[e] = uval[ebase + e];
-        }
-        const int i = c_hi - 1 - t;
-        if (i >= c_lo) ring[(i - lo) & (kRing - 1)] = SENT;
-        __syncthreads();
-        bool fin = i < c_lo;
-        int pos = fin ? 0 : urp[i] - ebase;
-        const int pend = fin ? 0 : urp[i + 1] - ebase;
-        const F dgv = fin ? F(1) : udiag[i];
-        F acc = fin ? F(0) : y[i];
-        const int ring_hi = c_lo + kRing;
-        // same-chunk dependencies (j < c_hi) come first in the row; `lim`
-        // marks where the final ones (earlier chunks) start
-        int lim = pos;
-        if (!fin && !big)
-            while (lim < pend && scol[lim] < c_hi) ++lim;
-        if (!fin && big) {
-            // oversized row: every dependency lies in an earlier chunk
-            for (; pos < pend; ++pos) {
-                const int j = uci[ebase + pos];
-                const F zj = (j < ring_hi) ? from_bits<F>(ring[(j - lo) & (kRing - 1)]) : (F)z[j];
-                acc = acc - uval[ebase + pos] * zj;
-            }
-            lim = pend;
-        }
-        int spins = 0;
+
+    // ---- backward substitution: z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii,
+    // chunks from the bottom of the block up
+    double rz = 0.0;
+    if (lo < hi) {
+        auto T = [&](int q) { return q < kTab ? utab[q] : UT[q]; };
+        auto NL = [&](int q) { return q < kTab ? unl[q] : P.unl[lo + b + q]; };
+        int m = 0;
+        int2 ta = T(0), tb = T(1);  // chunk [tb.x, ta.x), entries [tb.y, ta.y)
+        int2 tn = T(tb.x > lo ? 2 : 1);
+        int nst = ta.y - tb.y;
+        bool big = nst > kStage;  // entries already in flight (last forward chunk)
+        int i = ta.x - 1 - t;
+        bool live = i >= tb.x;
+        int rp0 = live ? urp[i] : 0, rp1 = live ? urp[i + 1] : 0;
+        F yv = live ? y[i] : F(0);
+        F dv = live ? udiag[i] : F(1);
+        V rv = (MODE != 0 && live) ? rin[i] : V(0);
+        int lvn = live ? P.ulev[i] : 0;
         while (true) {
-            if (!fin) {
-                bool blocked = false;
-                while (pos < lim && !blocked) {
-                    int jj[4];
-                    F ww[4];
-                    Bits raw[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int e = min(pos + u, lim - 1);
-                        jj[u] = scol[e];
-                        ww[u] = sval[e];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        raw[u] = __hip_atomic_load(&ring[(jj[u] - lo) & (kRing - 1)], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const bool take = !blocked && (pos < lim) && (raw[u] != SENT);
-                        const F zv = from_bits<F>(raw[u]);
-                        acc = take ? acc - ww[u] * zv : acc;
-                        blocked = blocked || !take;
-                        pos += take ? 1 : 0;
-                    }
+            const int c_lo = tb.x, ebase = tb.y;
+            const bool cbig = big;
+            stage_commit(pc, pv, scol, sval, cbig ? 0 : nst, t);
+            if (live) ring[(i - lo) & (kRing - 1)] = SENT;
+            __syncthreads();
+            const int row = i;
+            bool fin = !live;
+            int pos = rp0 - ebase;
+            const int pend = rp1 - ebase;
+            const F dgv = dv;
+            F acc = yv;
+            const V rrow = rv;
+            const int clev = lvn, cnl = NL(m);
+            // prefetch the next chunk
+            ++m;
+            ta = tb;
+            tb = tn;
+            const bool more = ta.x > lo;
+            if (more) {
+                tn = T(tb.x > lo ? m + 2 : m + 1);
+                nst = ta.y - tb.y;
+                big = nst > kStage;
+                stage_issue(pc, pv, uci, uval, tb.y, big ? 0 : nst, t);
+                i = ta.x - 1 - t;
+                live = i >= tb.x;
+                rp0 = live ? urp[i] : 0;
+                rp1 = live ? urp[i + 1] : 0;
+                yv = live ? y[i] : F(0);
+                dv = live ? udiag[i] : F(1);
+                rv = (MODE != 0 && live) ? rin[i] : V(0);
+                lvn = live ? P.ulev[i] : 0;
+            }
+            // solve the current chunk.  Rows hold their entries in descending
+            // column order: terms evicted from the ring (in memory), then the
+            // other terms on earlier chunks (in the ring), then the same-chunk
+            // ones.
+            const int ring_hi = c_lo + kRing;
+            if (!fin && cbig) {
+                // oversized row: every dependency lies in an earlier chunk
+                for (; pos < pend; ++pos) {
+                    const int j = uci[ebase + pos];
+                    const F zj = (j < ring_hi) ? from_bits<F>(ring[(j - lo) & (kRing - 1)]) : (F)z[j];
+                    acc = acc - uval[ebase + pos] * zj;
                 }
-                if (pos == lim) {
-                    // final dependencies of earlier chunks, ascending: in the
-                    // ring, then (beyond it) in memory
-                    for (; pos < pend; ++pos) {
-                        const int j = scol[pos];
-                        const F zj = (j < ring_hi) ? from_bits<F>(ring[(j - lo) & (kRing - 1)]) : (F)z[j];
-                        acc = acc - sval[pos] * zj;
-                    }
-                    const F zi = acc / dgv;
-                    __hip_atomic_store(&ring[(i - lo) & (kRing - 1)], to_bits<F>(zi), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            if (!fin && ring_hi < hi) {
+                while (pos < pend) {
+                    const int j = scol[pos];
+                    if (j < ring_hi) break;
+                    acc = acc - sval[pos] * (F)z[j];
+                    ++pos;
+                }
+            }
+            if (!fin) take_ready(pos, pend, acc, scol, sval, ring, lo);
+            int cj[kHold];
+            F cw[kHold];
+            const int nh = fin ? 0 : min(pend - pos, kHold);
+            if (nh > 0) hold_terms(cj, cw, pos, pend, scol, sval);
+            for (int lv = 0; lv < cnl; ++lv) {
+                if (!fin && clev == lv) {
+                    if (nh > 0) acc = take_held(cj, cw, nh, acc, ring, lo, bad);
+                    acc = take_final(pos + nh, pend, acc, scol, sval, ring, lo, bad);
+                    ring[(row - lo) & (kRing - 1)] = to_bits<F>(acc / dgv);
                     fin = true;
                 }
+                __syncthreads();
             }
-            if (__all(fin)) break;
-            if (++spins > kSpinLimitIter && !fin) {
-                spin_fail = 1;
-                __hip_atomic_store(&ring[(i - lo) & (kRing - 1)], to_bits<F>(acc), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                fin = true;
+            if (row >= c_lo) {
+                const V zv = (V)from_bits<F>(ring[(row - lo) & (kRing - 1)]);
+                z[row] = zv;
+                if (MODE != 0) rz += (double)rrow * (double)zv;
             }
+            __syncthreads();
+            if (!more) break;
         }
-        __syncthreads();
-        if (i >= c_lo) z[i] = (V)from_bits<F>(ring[(i - lo) & (kRing - 1)]);
-        __syncthreads();
-        c_hi = c_lo;
     }
-    if (spin_fail && st) atomicExch(&st->spin_err, 1);
+    if (bad && st) atomicExch(&st->spin_err, 1);
     if (MODE != 0) {
-        double rz = 0.0;
-        for (int i = lo + t; i < hi; i += kBjThreads) rz += (double)rin[i] * (double)z[i];
         rz = block_sum(rz, red);
         if (t == 0) Vv.part_rz[(it & 1) * nb + b] = rz;
     }
@@ -811,15 +1131,8 @@ __global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, c
     if (BORDER) {
         const int k = bd.k;
         for (int j = threadIdx.x; j < k; j += blockDim.x) {
-            double s = 0.0;
-            for (int q = 0; q < bd.slices; ++q) s += bd.part[j * bd.slices + q];
-            ts[j] = s;
-        }
-        __syncthreads();
-        for (int j = threadIdx.x; j < k; j += blockDim.x) {
-            double s = 0.0;
-            for (int i = 0; i < k; ++i) s = fma(bd.Kinv[j * k + i], ts[i], s);
-            ss[j] = s;
+            ts[j] = bd.fold[j];
+            ss[j] = bd.fold[kMaxRank + j];
         }
         __syncthreads();
         double ts_dot = 0.0;
@@ -875,20 +1188,9 @@ template void launch_pcg_pupdate<float>(int, const PcgVecs&, int, const BorderDe
 // on its own (the solve loop fuses it into the direction update)
 template <typename T>
 __global__ __launch_bounds__(256) void k_border_fix(int n, T* __restrict__ z, BorderDev bd) {
-    __shared__ double ts[64];
     __shared__ double ss[64];
     const int k = bd.k;
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
-        double s = 0.0;
-        for (int q = 0; q < bd.slices; ++q) s += bd.part[j * bd.slices + q];
-        ts[j] = s;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
-        double s = 0.0;
-        for (int i = 0; i < k; ++i) s = fma(bd.Kinv[j * k + i], ts[i], s);
-        ss[j] = s;
-    }
+    for (int j = threadIdx.x; j < k; j += blockDim.x) ss[j] = bd.fold[kMaxRank + j];
     __syncthreads();
     const double* W = bd.W;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {

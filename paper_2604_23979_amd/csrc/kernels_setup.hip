@@ -393,8 +393,10 @@ __global__ void k_lu_split(int n, const int* __restrict__ prp, const int* __rest
         const int a = prp[i], d = pdiag[i], e = prp[i + 1];
         int w = lrp[i];
         for (int p = a; p < d; ++p, ++w) { lci[w] = pci[p]; lval[w] = pv[p]; }
+        // U rows in descending column order: the backward substitution
+        // takes its terms in the order their unknowns are solved
         w = urp[i];
-        for (int p = d + 1; p < e; ++p, ++w) { uci[w] = pci[p]; uval[w] = pv[p]; }
+        for (int p = e - 1; p > d; --p, ++w) { uci[w] = pci[p]; uval[w] = pv[p]; }
         udiag[i] = pv[d];
     }
 }

@@ -65,6 +65,8 @@ struct sdsl_ctx {
     double *pv_corr = nullptr, *pv = nullptr, *dropsum = nullptr, *shifts = nullptr;
     int *nfix = nullptr, *bstatus = nullptr, *spin_err = nullptr;
     int *lrp = nullptr, *lci = nullptr, *urp = nullptr, *uci = nullptr, *ucnt = nullptr;
+    int2 *lch = nullptr, *uch = nullptr;  // sweep chunk tables
+    int *lnl = nullptr, *unl = nullptr, *llev = nullptr, *ulev = nullptr;  // chunk-local levels
     double *lval = nullptr, *uval = nullptr, *udiag = nullptr;
     float *lval32 = nullptr, *uval32 = nullptr, *udiag32 = nullptr;
     int p_nnz = 0;
@@ -161,6 +163,12 @@ BJDev bj_dev(sdsl_ctx* h, bool fp32) {
     P.lval = fp32 ? (const void*)h->lval32 : (const void*)h->lval;
     P.uval = fp32 ? (const void*)h->uval32 : (const void*)h->uval;
     P.udiag = fp32 ? (const void*)h->udiag32 : (const void*)h->udiag;
+    P.lch = h->lch;
+    P.uch = h->uch;
+    P.llev = h->llev;
+    P.ulev = h->ulev;
+    P.lnl = h->lnl;
+    P.unl = h->unl;
     return P;
 }
 
@@ -192,7 +200,7 @@ void build_border(sdsl_ctx* h) {
     hip_check(hipMemcpyAsync(&bad, h->kstat, sizeof(int), hipMemcpyDeviceToHost, h->s), "copy");
     h->sync();
     if (bad) fail(SDSL_E_BREAKDOWN, "border Schur complement K = C^-1 + U^T P^-1 U is singular");
-    h->bd = BorderDev{k, h->lr.slices, h->lr.part, h->W64, h->Kinv};
+    h->bd = BorderDev{k, h->lr.slices, h->lr.fold, h->W64, h->Kinv};
 }
 
 void build_precond(sdsl_ctx* h) {
@@ -214,6 +222,9 @@ void build_precond(sdsl_ctx* h) {
     launch_scan(h->n_int, h->ucnt, h->urp, h->scan_tmp, s);
     launch_lu_split(h->n_int, h->prp, h->pci, h->pv, h->pdiag, h->lrp, h->lci, h->lval, h->urp, h->uci, h->uval,
                     h->udiag, s);
+    launch_bj_chunks(h->nb, h->bp, h->lrp, h->urp, h->lch, h->uch, s);
+    launch_bj_levels(h->nb, h->bp, h->lrp, h->lci, h->urp, h->uci, h->lch, h->uch, h->llev, h->ulev, h->lnl, h->unl,
+                     s);
     h->check_launch();
     int kept = 0, nfix = 0, spin = 0, nl = 0, nu = 0;
     hip_check(hipMemcpyAsync(&kept, h->prp + h->n_int, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
@@ -261,7 +272,7 @@ void build_precond(sdsl_ctx* h) {
 void setup_lowrank(sdsl_ctx* h, const sdsl_lowrank* lr) {
     if (!lr || lr->k <= 0) return;
     const int k = lr->k, n = h->n;
-    if (k > 64) fail(SDSL_E_INVALID, "low-rank term limited to 64 columns");
+    if (k > kMaxRank) fail(SDSL_E_INVALID, "low-rank term limited to 64 columns");
     const sdsl_csr& U = lr->U;
     if (U.n != n || U.nnz < 0 || !U.row_ptr || (U.nnz > 0 && (!U.col || !U.val)) || !lr->c)
         fail(SDSL_E_INVALID, "bad low-rank term");
@@ -308,6 +319,9 @@ void setup_lowrank(sdsl_ctx* h, const sdsl_lowrank* lr) {
     double* d_c = h->alloc<double>(k);
     const int slices = 32;
     double* part = h->alloc<double>(2 * k * slices);
+    double* fold = h->alloc<double>(2 * kMaxRank);
+    unsigned* counter = h->alloc<unsigned>(1);
+    hip_check(hipMemset(counter, 0, sizeof(unsigned)), "memset");
     hip_check(hipMemcpy(d_urp, urp32.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_uci, uci.data(), m * sizeof(int), hipMemcpyHostToDevice), "copy");
     hip_check(hipMemcpy(d_uv, uv.data(), m * sizeof(double), hipMemcpyHostToDevice), "copy");
@@ -326,6 +340,8 @@ void setup_lowrank(sdsl_ctx* h, const sdsl_lowrank* lr) {
     L.ucv = d_ucv;
     L.c = d_c;
     L.part = part;
+    L.fold = fold;
+    L.counter = counter;
     h->lr = L;
 }
 
@@ -358,9 +374,9 @@ struct Pcg {
     void set_x(V* xx) { x = xx; Vv.x = xx; }
     void precondition(int j, int mode) {
         launch_bj<V, F>(2, P, Vv, h->st, j, h->s);
-        if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, nullptr, h->s);
+        if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
         launch_pcg_pupdate<V>(h->n, Vv, h->nb, h->bd, h->st, j, mode, h->s);
-        if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, h->s);
+        if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
         h->check_launch();
     }
     void start(int it0) {
@@ -387,16 +403,16 @@ struct Pcg {
             if (timing) hip_check(hipEventRecord(h->ev[3 * k + 1], h->s), "event record");
             launch_bj<V, F>(1, P, Vv, h->st, it, h->s);
             if (timing) hip_check(hipEventRecord(h->ev[3 * k + 2], h->s), "event record");
-            if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, h->st, h->s);
+            if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, h->st, LR_BORDER, h->bd.Kinv, h->s);
             launch_pcg_pupdate<V>(h->n, Vv, h->nb, h->bd, h->st, it, PUPD_STEP, h->s);
-            if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, h->s);
+            if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
         }
         h->check_launch();
     }
     const KrylovState& poll() {
         hip_check(hipMemcpyAsync(h->st_h, h->st, sizeof(KrylovState), hipMemcpyDeviceToHost, h->s), "copy");
         h->sync();
-        if (h->st_h->spin_err) fail(SDSL_E_DEVICE, "triangular solve in-workgroup wait limit exceeded");
+        if (h->st_h->spin_err) fail(SDSL_E_DEVICE, "triangular solve met a term not yet solved at its level (stale level tables)");
         if (h->o.kernel_timing && batch_count > 0) {
             // only launches made before the state said done did work
             int live = batch_count;
@@ -813,6 +829,12 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->lval = h->alloc<double>(nnz);
         h->uval = h->alloc<double>(nnz);
         h->udiag = h->alloc<double>(ni);
+        h->lch = h->alloc<int2>(ni + h->nb);
+        h->uch = h->alloc<int2>(ni + h->nb);
+        h->lnl = h->alloc<int>(ni + h->nb);
+        h->unl = h->alloc<int>(ni + h->nb);
+        h->llev = h->alloc<int>(ni);
+        h->ulev = h->alloc<int>(ni);
         h->lval32 = h->alloc<float>(nnz);
         h->uval32 = h->alloc<float>(nnz);
         h->udiag32 = h->alloc<float>(ni);
@@ -946,11 +968,11 @@ sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y) {
         if (!x || !y) fail(SDSL_E_INVALID, "null vector");
         const CsrView A{h->n, h->rp, h->ci};
         if (prec == SDSL_FP64) {
-            if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, (const double*)x, nullptr, h->s);
+            if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, (const double*)x, nullptr, LR_SCALED, nullptr, h->s);
             launch_spmv<double, double>(A, h->v, h->lr, (const double*)x, (double*)y, nullptr, nullptr, h->lanes,
                                         h->grid, h->s);
         } else {
-            if (h->lr.k > 0) launch_lowrank_tdot<float>(h->lr, (const float*)x, nullptr, h->s);
+            if (h->lr.k > 0) launch_lowrank_tdot<float>(h->lr, (const float*)x, nullptr, LR_SCALED, nullptr, h->s);
             launch_spmv<float, float>(A, h->v32, h->lr, (const float*)x, (float*)y, nullptr, nullptr, h->lanes,
                                       h->grid, h->s);
         }
@@ -971,14 +993,14 @@ sdsl_status sdsl_precond_apply(sdsl_handle h, int32_t prec, const void* r, void*
             V.y = h->y;
             launch_bj<double, double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
             if (h->bd.k > 0) {
-                launch_lowrank_tdot<double>(h->lr, (const double*)z, nullptr, h->s);
+                launch_lowrank_tdot<double>(h->lr, (const double*)z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
                 launch_border_fix<double>(h->n, (double*)z, h->bd, h->s);
             }
         } else {
             V.y = h->y32;
             launch_bj<float, float>(0, bj_dev(h, true), V, nullptr, 0, h->s);
             if (h->bd.k > 0) {
-                launch_lowrank_tdot<float>(h->lr, (const float*)z, nullptr, h->s);
+                launch_lowrank_tdot<float>(h->lr, (const float*)z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
                 launch_border_fix<float>(h->n, (float*)z, h->bd, h->s);
             }
         }
