@@ -133,6 +133,7 @@ struct CsrView {
     int n;
     const int* rp;
     const int* ci;
+    int halo = 0;  // SpMV near window: rows of a workgroup +- halo columns staged in LDS (0: none)
 };
 
 struct LowRankDev {
@@ -157,6 +158,9 @@ enum LrFold { LR_NONE = 0, LR_SCALED = 1, LR_BORDER = 2 };
 constexpr int kMaxRank = 64;
 
 int spmv_grid(int n);
+void launch_spmv_near(int n, int grid, const int* rp, const int* ci, int halo, unsigned long long* count,
+                      hipStream_t s);
+constexpr int kSpmvHalo = 2176;  // near-window halo (FP64 window: 36 KB of LDS)
 int spmv_lanes(double mean_row);
 
 template <typename T>

@@ -34,21 +34,19 @@ __device__ __forceinline__ int xcd_swizzle(int w, int g) {
 }
 
 int spmv_grid(int n) {
-    // one 64-row batch per wave (4 waves of 64 lanes per workgroup) up to
-    // 4096 workgroups; a multiple of 8 so the XCD swizzle is a permutation
+    // one workgroup per 256 rows (kSpmvRows), a multiple of 8 so that the
+    // XCD swizzle is a permutation (the extra workgroups have no rows)
     int g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
     g = (g + 7) / 8 * 8;
     return g < 8 ? 8 : g;
 }
 
-// lanes per row of the SpMV: enough that a typical row needs one round of
-// U loads per lane (U = 12 for 16 lanes, 8 otherwise)
+// lanes per row of the SpMV (4 loads per lane per round): the smallest
+// power of two from 4 to 64 whose round covers the mean row
 int spmv_lanes(double mean_row) {
-    if (mean_row >= 96) return 16;
-    if (mean_row >= 40) return 8;
-    if (mean_row >= 16) return 4;
-    return 2;
+    int g = 4;
+    while (g < 64 && 4 * g < mean_row) g *= 2;
+    return g;
 }
 
 // ------------------------------------------------------------------ low rank
@@ -170,94 +168,158 @@ template void launch_lowrank_tdot<float>(const LowRankDev&, const float*, const 
 // column indices are streamed with non-temporal loads so that the gathered x
 // (type V) stays in L2; the products and their sum are formed in F (FP32
 // values give an FP32 product, accumulated in FP32); the low-rank term is
-// added in FP64.  Each workgroup owns one contiguous row range
-// (XCD-swizzled).  With part_dot the workgroup's share of (x, y) is written
+// added in FP64.  With part_dot the workgroup's share of (x, y) is written
 // to part_dot[w].
+//
+// Layout of the launch: a workgroup of kSpmvThreads threads owns
+// kSpmvRows consecutive rows (XCD-swizzled); each of its waves takes
+// kSpmvRows / 16 of them, 64 / G rows per step with G lanes per row and U
+// loads per lane per round, and the loads of the next step are issued before
+// the current step gathers x.  Row sums use DPP lane exchanges (no LDS).
+//
+// Near window: with halo > 0 the workgroup first copies x[r0 - halo,
+// r1 + halo) (rounded to F) into LDS; entries whose column falls inside are
+// gathered from LDS, the others from memory.  Banded-plus-scattered
+// patterns keep most gathers off the L2.
+constexpr int kSpmvThreads = 1024;
+constexpr int kSpmvRows = 256;
+
+// v moved by DPP control CTRL within the enabled rows (others give 0)
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    int lo = (int)(b & 0xffffffff), hi = (int)(b >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWM, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWM, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ float dpp_move(float v) {
+    const int b = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWM, 0xF, false);
+    return __builtin_bit_cast(float, b);
+}
+// Sum over aligned groups of G lanes.  The total is valid in every lane of
+// the group for G <= 16, in lanes 16..31 of each 32-lane group for G = 32
+// and in lanes 48..63 for G = 64 (kSumLane<G> is the first such lane).
+template <int G, typename T>
+__device__ __forceinline__ T dpp_sum(T s) {
+    if (G >= 2) s += dpp_move<0xB1>(s);        // quad_perm [1,0,3,2]
+    if (G >= 4) s += dpp_move<0x4E>(s);        // quad_perm [2,3,0,1]
+    if (G >= 8) s += dpp_move<0x141>(s);       // row_half_mirror
+    if (G >= 16) s += dpp_move<0x140>(s);      // row_mirror
+    if (G >= 32) s += dpp_move<0x142, 0xA>(s); // row_bcast:15 into rows 1, 3
+    if (G >= 64) s += dpp_move<0x143, 0xC>(s); // row_bcast:31 into rows 2, 3
+    return s;
+}
+template <int G> struct SumLane { static constexpr int value = G <= 16 ? 0 : (G == 32 ? 16 : 48); };
+
 template <typename V, typename F, int G, int U, bool LR>
-__global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                              const F* __restrict__ v, const V* __restrict__ x,
-                                              V* __restrict__ y, double* __restrict__ part_dot,
-                                              const KrylovState* st, LowRankDev lr) {
-    // Each wave works on batches of 64 consecutive rows: the batch's row
-    // bounds are loaded once (coalesced) and broadcast, 64/G rows are in
-    // flight per step with G lanes each and U independent loads per lane per
-    // round trip (G*U entries per row per round), and the 64 results stay in
-    // their lanes until one coalesced store per batch.
-    __shared__ double red[8];
-    __shared__ double tk[64];
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, const F* __restrict__ v,
+                                                       const V* __restrict__ x, V* __restrict__ y,
+                                                       double* __restrict__ part_dot, const KrylovState* st,
+                                                       LowRankDev lr, int halo) {
+    extern __shared__ double xwin_lds[];
+    __shared__ double red[16];
+    __shared__ double tk[kMaxRank];
     __shared__ int shd;
     if (block_done(st, &shd)) return;
     if (LR) {
         for (int j = threadIdx.x; j < lr.k; j += blockDim.x) tk[j] = lr.fold[j];
-        __syncthreads();
     }
-    constexpr int RPS = kWave / G;  // rows per step per wave
     const int g = gridDim.x;
     const int lw = xcd_swizzle(blockIdx.x, g);
-    const int per = (n + g - 1) / g;
-    const int r0 = lw * per;
-    const int r1 = min(n, r0 + per);
+    const int r0 = min(n, lw * kSpmvRows), r1 = min(n, r0 + kSpmvRows);
+    F* xs = reinterpret_cast<F*>(xwin_lds);
+    const int wlo = halo > 0 ? max(0, r0 - halo) : 0;
+    const int whi = halo > 0 ? min(n, r1 + halo) - 1 : -1;  // empty window without halo
+    for (int c0 = wlo + (int)threadIdx.x; c0 <= whi; c0 += 4 * kSpmvThreads) {
+        V t4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kSpmvThreads;
+            t4[u] = c <= whi ? x[c] : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kSpmvThreads;
+            if (c <= whi) xs[c - wlo] = (F)t4[u];
+        }
+    }
+    __syncthreads();
+    auto gather = [&](int c) -> F { return (c >= wlo && c <= whi) ? xs[c - wlo] : (F)x[c]; };
+
+    constexpr int RPS = kWave / G;
+    constexpr int RW = kSpmvRows / (kSpmvThreads / kWave);  // rows per wave
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int nwaves = blockDim.x / kWave;
     const int grp = lane / G, gl = lane % G;
+    const int base = r0 + wave * RW;
+    const int nrow = max(0, min(RW, r1 - base));
     double dacc = 0.0;
-    for (int base = r0 + wave * kWave; base < r1; base += nwaves * kWave) {
-        const int nrow = min(kWave, r1 - base);
-        const int my_a = (lane < nrow) ? rp[base + lane] : 0;
-        const int my_e = (lane < nrow) ? rp[base + lane + 1] : 0;
-        const int my_u0 = (LR && lane < nrow) ? lr.urp[base + lane] : 0;
-        const int my_u1 = (LR && lane < nrow) ? lr.urp[base + lane + 1] : 0;
-        F res = F(0);
-#pragma unroll 1
-        for (int j = 0; j < kWave; j += RPS) {
-            if (j >= nrow) break;
-            const int a = __shfl(my_a, j + grp, kWave);
-            const int e = __shfl(my_e, j + grp, kWave);
+    if (nrow > 0) {
+        const int my_a = lane < nrow ? rp[base + lane] : 0;
+        const int my_e = lane < nrow ? rp[base + lane + 1] : 0;
+        int my_u0 = 0, my_u1 = 0;
+        if (LR) {
+            my_u0 = lane < nrow ? lr.urp[base + lane] : 0;
+            my_u1 = lane < nrow ? lr.urp[base + lane + 1] : 0;
+        }
+        F vv[U], nv[U];
+        int cc[U], nc[U];
+        int a = __shfl(my_a, grp, kWave), e = __shfl(my_e, grp, kWave);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = a + gl + u * G;
+            vv[u] = p < e ? __builtin_nontemporal_load(&v[p]) : F(0);
+            cc[u] = p < e ? __builtin_nontemporal_load(&ci[p]) : r0;
+        }
+        for (int j = 0; j < nrow; j += RPS) {
+            // next step's entries in flight while this one gathers
+            const int jn = j + RPS;
+            const int an = __shfl(my_a, min(jn + grp, kWave - 1), kWave);
+            const int en = __shfl(my_e, min(jn + grp, kWave - 1), kWave);
+            const bool more = jn < nrow;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = an + gl + u * G;
+                const bool ok = more && p < en;
+                nv[u] = ok ? __builtin_nontemporal_load(&v[p]) : F(0);
+                nc[u] = ok ? __builtin_nontemporal_load(&ci[p]) : r0;
+            }
             F s = F(0);
-            for (int p0 = a + gl; p0 < e; p0 += U * G) {
-                F vv[U];
-                int cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) s = fma(vv[u], gather(cc[u]), s);
+            // rows longer than one round
+            for (int p0 = a + gl + U * G; p0 < e; p0 += U * G) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int p = p0 + u * G;
-                    vv[u] = p < e ? __builtin_nontemporal_load(&v[p]) : F(0);
-                    cc[u] = p < e ? __builtin_nontemporal_load(&ci[p]) : 0;
+                    if (p < e) s = fma(v[p], gather(ci[p]), s);
                 }
-                F xv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) xv[u] = (p0 + u * G < e) ? (F)x[cc[u]] : F(0);
-#pragma unroll
-                for (int u = 0; u < U; ++u) s = fma(vv[u], xv[u], s);
             }
-            s = group_sum<G>(s);
-            // lane L of this step's rows takes the sum of group L - j
-            const F mine = __shfl(s, (lane - j) * G, kWave);
-            if (lane >= j && lane < j + RPS) res = mine;
-        }
-        if (lane < nrow) {
-            const int row = base + lane;
-            V out = (V)res;
+            // low-rank term of the step's rows, FP64, one entry per lane
+            double t = 0.0;
             if (LR) {
-                // low-rank term in FP64, entries in order, 8 loads in flight
-                const double* __restrict__ uv = (const double*)lr.uv;
-                const int* __restrict__ uci = lr.uci;
-                double t = (double)res;
-                for (int q = my_u0; q < my_u1; q += 8) {
-                    int cc[8];
-                    double uu[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        cc[u] = q + u < my_u1 ? uci[q + u] : 0;
-                        uu[u] = q + u < my_u1 ? uv[q + u] : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (q + u < my_u1) t = fma(uu[u], tk[cc[u]], t);
-                }
-                out = (V)t;
+                const int row_j = min(j + grp, nrow - 1);
+                const int ua = __shfl(my_u0, row_j, kWave), ue = __shfl(my_u1, row_j, kWave);
+                for (int q = ua + gl; q < ue; q += G)
+                    t = fma(((const double*)lr.uv)[q], tk[lr.uci[q]], t);
             }
-            y[row] = out;
-            if (part_dot) dacc += (double)x[row] * (double)out;
+            s = dpp_sum<G>(s);
+            if (LR) t = dpp_sum<G>(t);
+            const int row = j + grp;
+            if (gl == SumLane<G>::value && row < nrow) {
+                const V out = LR ? (V)((double)s + t) : (V)s;
+                y[base + row] = out;
+                if (part_dot) dacc += (double)x[base + row] * (double)out;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                vv[u] = nv[u];
+                cc[u] = nc[u];
+            }
+            a = an;
+            e = en;
         }
     }
     if (part_dot) {
@@ -266,14 +328,33 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int* __restrict__ rp,
     }
 }
 
+// Entries of the SpMV workgroups' rows whose column lies in the near window
+// [r0 - halo, r1 + halo): count[0] += their number.
+__global__ __launch_bounds__(256) void k_spmv_near(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   int halo, unsigned long long* count) {
+    const int w = blockIdx.x;
+    const int r0 = min(n, w * kSpmvRows), r1 = min(n, r0 + kSpmvRows);
+    const int lo = max(0, r0 - halo), hi = min(n, r1 + halo);
+    unsigned long long c = 0;
+    for (int p = rp[r0] + (int)threadIdx.x; p < rp[r1]; p += blockDim.x) c += (ci[p] >= lo && ci[p] < hi);
+    atomicAdd(count, c);
+}
+void launch_spmv_near(int n, int grid, const int* rp, const int* ci, int halo, unsigned long long* count,
+                      hipStream_t s) {
+    k_spmv_near<<<grid, 256, 0, s>>>(n, rp, ci, halo, count);
+}
+
 template <typename V, typename F, bool LR>
 static void spmv_dispatch(const CsrView& A, const F* v, const LowRankDev& lr, const V* x, V* y, double* pd,
                           const KrylovState* st, int lanes, int grid, hipStream_t s) {
+    const size_t shm = A.halo > 0 ? (size_t)(kSpmvRows + 2 * A.halo) * sizeof(F) : 0;
+    constexpr int T = kSpmvThreads;
     switch (lanes) {
-        case 16: k_spmv<V, F, 16, 12, LR><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr); break;
-        case 8: k_spmv<V, F, 8, 8, LR><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr); break;
-        case 4: k_spmv<V, F, 4, 8, LR><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr); break;
-        default: k_spmv<V, F, 2, 8, LR><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr); break;
+        case 64: k_spmv<V, F, 64, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
+        case 32: k_spmv<V, F, 32, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
+        case 16: k_spmv<V, F, 16, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
+        case 8: k_spmv<V, F, 8, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
+        default: k_spmv<V, F, 4, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
     }
 }
 

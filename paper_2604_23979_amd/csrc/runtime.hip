@@ -66,6 +66,7 @@ struct sdsl_ctx {
     int *nfix = nullptr, *bstatus = nullptr, *spin_err = nullptr;
     int *lrp = nullptr, *lci = nullptr, *urp = nullptr, *uci = nullptr, *ucnt = nullptr;
     int2 *lch = nullptr, *uch = nullptr;  // sweep chunk tables
+    int halo = 0;                          // SpMV near-window halo (0: gather from memory)
     int *lnl = nullptr, *unl = nullptr, *llev = nullptr, *ulev = nullptr;  // chunk-local levels
     double *lval = nullptr, *uval = nullptr, *udiag = nullptr;
     float *lval32 = nullptr, *uval32 = nullptr, *udiag32 = nullptr;
@@ -388,7 +389,7 @@ struct Pcg {
         it = j + 1;
     }
     void issue(int count) {
-        const CsrView A{h->n, h->rp, h->ci};
+        const CsrView A{h->n, h->rp, h->ci, h->halo};
         const bool timing = h->o.kernel_timing != 0;
         if (timing && (int)h->ev.size() < 3 * count) {
             const size_t old = h->ev.size();
@@ -443,7 +444,7 @@ double reduce_to_host(sdsl_ctx* h, const double* part, int m, int idx) {
 
 // r = b - M x (compensated FP64); scal[0] = ||r||^2; returns ||r||
 double true_residual(sdsl_ctx* h, const double* b, const double* x, double* r) {
-    const CsrView A{h->n, h->rp, h->ci};
+    const CsrView A{h->n, h->rp, h->ci, h->halo};
     launch_residual(A, h->v, h->lr, b, x, r, h->part_res, h->lanes, h->grid, h->s);
     h->check_launch();
     return std::sqrt(reduce_to_host(h, h->part_res, h->grid, 0));
@@ -806,6 +807,18 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->check_launch();
         h->lanes = spmv_lanes((double)nnz / n);
         h->grid = spmv_grid(n);
+        // near window of the SpMV: used when at least half of the entries
+        // fall inside it (fixed by the pattern)
+        {
+            unsigned long long* cnt = h->alloc<unsigned long long>(1);
+            hip_check(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), h->s), "memset");
+            launch_spmv_near(n, h->grid, h->rp, h->ci, kSpmvHalo, cnt, h->s);
+            h->check_launch();
+            unsigned long long near = 0;
+            hip_check(hipMemcpyAsync(&near, cnt, sizeof(near), hipMemcpyDeviceToHost, h->s), "copy");
+            h->sync();
+            h->halo = 2 * near >= (unsigned long long)nnz ? kSpmvHalo : 0;
+        }
         setup_lowrank(h, lr);
         // preconditioner buffers (capacity: every entry of M)
         const int ni = h->n_int;
@@ -966,7 +979,7 @@ sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y) {
     if (!h) return SDSL_E_INVALID;
     return guard(h, [&] {
         if (!x || !y) fail(SDSL_E_INVALID, "null vector");
-        const CsrView A{h->n, h->rp, h->ci};
+        const CsrView A{h->n, h->rp, h->ci, h->halo};
         if (prec == SDSL_FP64) {
             if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, (const double*)x, nullptr, LR_SCALED, nullptr, h->s);
             launch_spmv<double, double>(A, h->v, h->lr, (const double*)x, (double*)y, nullptr, nullptr, h->lanes,
