@@ -99,6 +99,25 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol):
     return res
 
 
+def measured_traffic(which, mode):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_k_{which}_c2_{mode}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as g:
+            h.update(g.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
 def cpu_baseline(system, gpu_iters, seconds, opts_o):
     """The oracle (single-threaded C) on a bounded sample of the same solve:
     the preconditioner build, then a fixed number of PCG iterations, scaled to
@@ -134,6 +153,10 @@ def main():
     ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing inside the solves")
     ap.add_argument("--max-iter", type=int, default=60_000)
     ap.add_argument("--refine-delta", type=float, default=0.3)
+    ap.add_argument("--profile-iters", type=int, default=0,
+                    help="profiling run: only this many iterations per mode, no JSON line")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="profiling run: first copy a buffer of this many bytes three times (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -147,6 +170,17 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
+    if args.copy_bytes > 0:
+        # a plain device copy of known size; its FETCH_SIZE / WRITE_SIZE
+        # counters scale those of the solver kernels to bytes
+        src = torch.empty(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_bytes} bytes three times")
+        del src, dst
     t0 = time.time()
     log("generating the workload ...")
     system = gen.c2(args.scale)
@@ -155,6 +189,17 @@ def main():
     common = dict(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM, pivot=sd.PIVOT_SHIFT,
                   shift0=1e-2, kernel_timing=bool(args.timing), max_iter=args.max_iter,
                   refine_delta=args.refine_delta, border=True)
+    if args.profile_iters > 0:
+        b_dev = torch.as_tensor(system.b, device="cuda:0")
+        for m in args.modes.split(","):
+            prec = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR, "fp32restart": sd.FP32_IR_RESTART}[m]
+            o = sd.Options(precision=prec, **dict(common, max_iter=args.profile_iters))
+            sv = sd.from_system(system, o)
+            _, its, rr, st = sv.solve(b_dev, torch.empty_like(b_dev), 1e-8)
+            torch.cuda.synchronize()
+            log(f"profile {m}: {its} iterations, status {st}, relres {rr:.2e}")
+            sv.close()
+        return
     modes = {}
     for m in args.modes.split(","):
         prec = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR, "fp32restart": sd.FP32_IR_RESTART}[m]
@@ -165,15 +210,23 @@ def main():
     best = max(modes, key=lambda k: modes[k]["solves_per_s"])
     r = modes[best]
     fp64_its = modes["fp64"]["iterations"][-1] if "fp64" in modes else r["iterations"][-1]
-    # roofline of the dominant kernel (the SpMV): algorithmic bytes of one
-    # launch over its average duration from HIP events inside the solves
+    # roofline of the dominant kernel (the larger share of the solve time
+    # between the SpMV and the fused block-Jacobi step): algorithmic bytes of
+    # one launch over its average duration from HIP events inside the solves
     roof = None
     if r.get("spmv_gbps"):
-        roof = {"bound": "hbm", "kernel": "k_spmv (FP64)" if best == "fp64" else "k_spmv (FP32)",
-                "achieved": round(r["spmv_gbps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(r["spmv_gbps"] / HBM_PEAK_GBPS, 4), "traffic": None,
-                "bytes_per_launch": r["spmv_bytes"], "avg_launch_us": round(r["spmv_avg_us"], 2),
-                "launches": r["spmv_launches"]}
+        sp_t = r["spmv_avg_us"] * r["spmv_launches"]
+        bj_t = r["bj_avg_us"] * r["bj_launches"]
+        which = "bj" if bj_t > sp_t else "spmv"
+        prec = "FP64" if best == "fp64" else "FP32"
+        name = {"bj": f"k_bj ({prec})", "spmv": f"k_spmv ({prec})"}[which]
+        gbps = r[f"{which}_gbps"]
+        roof = {"bound": "hbm", "kernel": name, "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                "traffic": measured_traffic(which, best),
+                "bytes_per_launch": r[f"{which}_bytes"], "avg_launch_us": round(r[f"{which}_avg_us"], 2),
+                "launches": r[f"{which}_launches"],
+                "share_of_solve": round(max(sp_t, bj_t) / args.steps / (1e3 * r["ms_per_solve"]), 3)}
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

@@ -473,6 +473,8 @@ struct SolveTask {
     enum Phase { P64, PMIX, P32_RESTART } phase = P64;
     Pcg<double, double> pcg64{};
     Pcg<double, float> pcgmix{};
+    Pcg<double, double> pcghand{};  // FP64 continuation of the pcgmix recurrence
+    bool handed = false;            // pcgmix stagnated: the recurrence runs on in FP64
     Pcg<float, float> pcg32{};
     // FP64 PCG target (the solve itself, or an FP64 fallback of an FP32 mode)
     const double* rhs64 = nullptr;
@@ -502,6 +504,8 @@ struct SolveTask {
         pcg64.init();
         pcgmix = Pcg<double, float>{h, xout, h->r, h->z, h->p, h->q, h->y32, h->v32};
         pcgmix.init();
+        pcghand = Pcg<double, double>{h, xout, h->r, h->z, h->p, h->q, h->y, h->v};
+        pcghand.init();
         pcg32 = Pcg<float, float>{h, h->x32, h->r32, h->z32, h->p32, h->q32, h->y32, h->v32};
         pcg32.init();
         if (h->o.precision == SDSL_FP64) {
@@ -554,7 +558,9 @@ struct SolveTask {
         fallbacks++;
         fb_base_its = total_its;
         launch_copy<double>(h->n, h->r, h->rf, h->s);
-        start64(h->rf, h->d, tol * nb / nr, nr);
+        // half the needed reduction, so that the rounding of x += d keeps
+        // the true residual below the tolerance
+        start64(h->rf, h->d, 0.5 * tol * nb / nr, nr);
     }
     void restart_inner() {
         // classical refinement: inner FP32 PCG on M d = r / ||r|| to inner_tol
@@ -574,6 +580,10 @@ struct SolveTask {
         h->check_launch();
         nr = true_residual(h, b, xout, h->r);
         fallback = false;
+        if (nr > tol * nb && st64 == SDSL_OK && fallbacks < 4 && total_its < max_iter()) {
+            start_fallback();  // the corrected solution is not there yet: once more
+            return;
+        }
         finish(nr <= tol * nb ? SDSL_OK : (st64 == SDSL_E_BREAKDOWN ? SDSL_E_BREAKDOWN : SDSL_E_NOT_CONVERGED),
                nr / nb);
     }
@@ -599,27 +609,43 @@ struct SolveTask {
         restart_inner();
     }
     void step_mixed() {
-        const KrylovState& s = pcgmix.poll();
-        const bool at_limit = pcgmix.it >= max_iter();
+        Pcg<double, double>& e64 = pcghand;
+        const KrylovState& s = handed ? e64.poll() : pcgmix.poll();
+        const int it_now = handed ? e64.it : pcgmix.it;
+        const bool at_limit = it_now >= max_iter();
+        auto issue = [&](int count) {
+            if (handed) e64.issue(count);
+            else pcgmix.issue(count);
+        };
         if (!s.done && !at_limit) {
-            pcgmix.issue(std::min(h->o.check_every, max_iter() - pcgmix.it));
+            issue(std::min(h->o.check_every, max_iter() - it_now));
             return;
         }
         // refinement point: the true residual of the FP64 solution
-        const int its = s.done ? s.iters : pcgmix.it;
+        const int its = s.done ? s.iters : it_now;
         total_its = its;
         outer++;
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
         if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
         slow = (nr > 0.5 * prev) ? slow + 1 : 0;
-        if (slow >= 3 || (s.done && s.breakdown)) { start_fallback(); return; }
-        if (at_limit || (!s.conv && !s.update)) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
+        if (at_limit) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
+        if ((slow >= 3 || (s.done && s.breakdown)) && !handed) {
+            // the FP32 operator or factors stall the recurrence: it continues
+            // with the FP64 ones from the same search direction
+            handed = true;
+            fallbacks++;
+            slow = 0;
+        } else if (slow >= 3 || (s.done && s.breakdown) || (!s.conv && !s.update)) {
+            start_fallback();
+            return;
+        }
         // the true residual (now in r) replaces the recurrence one; the
         // recurrence continues with its search direction
         launch_refine_state(h->st, h->part_res, h->grid, its, h->o.refine_every, h->s);
-        pcgmix.reapply(its - 1);
-        pcgmix.issue(std::min(h->o.check_every, max_iter() - pcgmix.it));
+        if (handed) e64.reapply(its - 1);
+        else pcgmix.reapply(its - 1);
+        issue(std::min(h->o.check_every, max_iter() - (its)));
     }
     void step64() {
         const KrylovState& s = pcg64.poll();
