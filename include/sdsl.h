@@ -251,6 +251,13 @@ sdsl_status sdsl_residual(sdsl_handle h, const double* b, const double* x, doubl
 sdsl_status sdsl_get_factors(sdsl_handle h, int64_t* row_ptr, int32_t* col, double* corrected,
                              double* lu, double* shifts);
 
+/* BBD only (Sec. 2.4): copies the dense border Schur complement's LU
+ * factors with partial pivoting (row-major n_border x n_border, strict
+ * lower = unit L, rest = U, after the row swaps), the pivot rows (piv[k] =
+ * row swapped with row k at step k, 0-based) and its inverse (row-major) to
+ * HOST arrays; any pointer may be NULL.  SDSL_E_STATE for a BJ handle. */
+sdsl_status sdsl_get_schur(sdsl_handle h, double* lu, int32_t* piv, double* inv);
+
 #ifdef __cplusplus
 }
 #endif

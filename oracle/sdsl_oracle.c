@@ -476,8 +476,8 @@ static int pcg_run(const or_op* A, or_prec_fn prec, void* pctx, const double* b,
 }
 
 /* ------------------------------------------------------------------ */
-/* Right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and */
-/* Givens rotations (paper Sec. 2.2: GMRES, right preconditioning).      */
+/* Right-preconditioned restarted GMRES(m): classical Gram-Schmidt applied  */
+/* twice, Givens rotations (paper Sec. 2.2: GMRES, right preconditioning). */
 /* ------------------------------------------------------------------ */
 static int gmres_run(const or_op* A, or_prec_fn prec, void* pctx, const double* b, double* x,
                      double tol, int32_t m, int32_t maxit, int32_t* iters, double* relres,
@@ -489,6 +489,7 @@ static int gmres_run(const or_op* A, or_prec_fn prec, void* pctx, const double* 
     double* V = (double*)calloc((size_t)n * (m + 1), 8);
     double* H = (double*)calloc((size_t)(m + 1) * m, 8);  /* H[i*m + j] */
     double *cs = calloc(m, 8), *sn = calloc(m, 8), *g = calloc(m + 1, 8), *y = calloc(m, 8);
+    double* hc = calloc(m + 1, 8);
     double *w = calloc(n, 8), *zt = calloc(n, 8), *r = calloc(n, 8);
     int it = 0, st = OR_NOT_CONVERGED;
     double beta = op_true_res(A, x, b, r);
@@ -501,10 +502,15 @@ static int gmres_run(const or_op* A, or_prec_fn prec, void* pctx, const double* 
         for (j = 0; j < m && it < maxit; ++j) {
             prec(pctx, V + (int64_t)j * n, zt);
             op_apply(A, zt, w);
-            for (int i = 0; i <= j; ++i) {
-                double h = dot(n, w, V + (int64_t)i * n);
-                H[i * m + j] = h;
-                for (int64_t t = 0; t < n; ++t) w[t] -= h * V[(int64_t)i * n + t];
+            /* classical Gram-Schmidt applied twice: all projections of a
+             * pass use the same w, and the second pass re-orthogonalises */
+            for (int i = 0; i <= j; ++i) H[i * m + j] = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) hc[i] = dot(n, w, V + (int64_t)i * n);
+                for (int i = 0; i <= j; ++i) {
+                    H[i * m + j] += hc[i];
+                    for (int64_t t = 0; t < n; ++t) w[t] -= hc[i] * V[(int64_t)i * n + t];
+                }
             }
             double hn = nrm2(n, w);
             H[(j + 1) * m + j] = hn;
@@ -544,7 +550,7 @@ static int gmres_run(const or_op* A, or_prec_fn prec, void* pctx, const double* 
     if (it >= maxit && beta <= tol * nb) st = OR_OK;
     *iters = it;
     *relres = beta / nb;
-    free(V); free(H); free(cs); free(sn); free(g); free(y); free(w); free(zt); free(r);
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(w); free(zt); free(r); free(hc);
     return st;
 }
 
@@ -623,7 +629,7 @@ static void bbd_apply(void* ctx, const double* r, double* z) {
         int64_t t0 = B->tail[b], hi = B->bp[b + 1];
         for (int64_t i = hi - 1; i >= t0; --i) {
             double s = w[i];
-            for (int64_t p = B->ldp[i] + 1; p < B->lrp[i + 1]; ++p) s -= B->lv[p] * z[B->lci[p]];
+            for (int64_t p = B->lrp[i + 1] - 1; p > B->ldp[i]; --p) s -= B->lv[p] * z[B->lci[p]];
             z[i] = s / B->lv[B->ldp[i]];
         }
     }
@@ -651,7 +657,7 @@ static void bbd_apply(void* ctx, const double* r, double* z) {
         int64_t lo = B->bp[b];
         for (int64_t i = hi - 1; i >= lo; --i) {
             double s = w[i];
-            for (int64_t p = B->ldp[i] + 1; p < B->lrp[i + 1]; ++p) s -= B->lv[p] * z[B->lci[p]];
+            for (int64_t p = B->lrp[i + 1] - 1; p > B->ldp[i]; --p) s -= B->lv[p] * z[B->lci[p]];
             z[i] = s / B->lv[B->ldp[i]];
         }
     }
@@ -779,7 +785,7 @@ void* or_bbd_setup(int64_t n, const int64_t* rp, const int32_t* ci, const double
                 /* u = U_TT^{-1} y */
                 for (int64_t r = hi - 1; r >= t0; --r) {
                     double s = u[r];
-                    for (int64_t q = B->ldp[r] + 1; q < B->lrp[r + 1]; ++q) s -= B->lv[q] * u[B->lci[q]];
+                    for (int64_t q = B->lrp[r + 1] - 1; q > B->ldp[r]; --q) s -= B->lv[q] * u[B->lci[q]];
                     u[r] = s / B->lv[B->ldp[r]];
                 }
                 /* S[:, c] -= F_T u */

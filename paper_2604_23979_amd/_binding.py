@@ -86,6 +86,7 @@ SIGNATURES = {
     "sdsl_precond_apply": (C.c_int, [H, C.c_int32, P, P]),
     "sdsl_residual": (C.c_int, [H, P, P, P, C.POINTER(C.c_double)]),
     "sdsl_get_factors": (C.c_int, [H, P, P, P, P, P]),
+    "sdsl_get_schur": (C.c_int, [H, P, P, P]),
 }
 
 _lib = None
@@ -196,7 +197,7 @@ class Solver:
             lrp = LowRank(U.shape[1], CSR(n, uv.shape[0], urp.ctypes.data_as(C.c_void_p),
                                           uci.ctypes.data_as(C.c_void_p), uv.ctypes.data_as(C.c_void_p),
                                           MEM_HOST), cc.ctypes.data_as(C.c_void_p))
-        self.n, self.nnz, self.nblocks = n, nnz, bp.shape[0] - 1
+        self.n, self.nnz, self.nblocks, self.n_border = n, nnz, bp.shape[0] - 1, int(n_border)
         self.stream = stream
         self._opts = self.options.c()
         h = C.c_void_p()
@@ -261,10 +262,8 @@ class Solver:
 
     def factors(self):
         info = self.info()
-        n_int = None
         kept = int(info["nnz_kept"])
-        # row_ptr length is n - n_border + 1; ask for it through nnz_kept's rows
-        rp = np.zeros(self.n + 1, dtype=np.int64)
+        rp = np.zeros(self.n + 1, dtype=np.int64)   # the first n - n_border + 1 are filled
         ci = np.zeros(max(kept, 1), dtype=np.int32)
         corr = np.zeros(max(kept, 1))
         lu = np.zeros(max(kept, 1))
@@ -272,8 +271,18 @@ class Solver:
         _check(self.h, lib().sdsl_get_factors(self.h, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
                                               corr.ctypes.data_as(C.c_void_p), lu.ctypes.data_as(C.c_void_p),
                                               sh.ctypes.data_as(C.c_void_p)))
-        del n_int
         return dict(row_ptr=rp, col=ci[:kept], corrected=corr[:kept], lu=lu[:kept], shifts=sh)
+
+    def schur(self):
+        """BBD handles: the border Schur complement's LU (row-major), pivot
+        rows and inverse, as numpy arrays."""
+        m = self.n_border
+        lu = np.zeros((m, m))
+        piv = np.zeros(m, dtype=np.int32)
+        inv = np.zeros((m, m))
+        _check(self.h, lib().sdsl_get_schur(self.h, lu.ctypes.data_as(C.c_void_p), piv.ctypes.data_as(C.c_void_p),
+                                            inv.ctypes.data_as(C.c_void_p)))
+        return lu, piv, inv
 
     def info(self) -> dict:
         inf = CInfo()

@@ -196,7 +196,8 @@ struct BJDev {
 
 // MODE 0: z = P^{-1} r.  MODE 1: PCG step (alpha from partials, x/r update,
 // ||r||^2 partial, z = P^{-1} r, (r,z) partial).  MODE 2: z = P^{-1} r and
-// (r,z) partial (PCG start).
+// (r,z) partial (PCG start).  MODE 3: y = L^{-1} r only.  MODE 4:
+// z = U^{-1} y only (y given).
 struct PcgVecs {
     void* x;
     void* r;
@@ -224,6 +225,46 @@ struct BorderDev {
 enum { PUPD_STEP = 0, PUPD_START = 1, PUPD_REAPPLY = 2 };
 template <typename V, typename F>
 void launch_bj(int mode, const BJDev& P, const PcgVecs& v, KrylovState* st, int it, hipStream_t s);
+constexpr int kMaxBasisHost = 64;  // GMRES basis columns handled per multi-dot call
+void launch_multidot(int n, int k, const double* V, int64_t ldv, const double* w, double* part, double* out,
+                     double* acc, hipStream_t s);
+void launch_multiaxpy(int n, int k, const double* V, int64_t ldv, const double* coef, double alpha, double* w,
+                      double* nrm_part, hipStream_t s);
+void launch_scale_inv_norm(int n, const double* nrm2, const double* w, double* v, hipStream_t s);
+// BBD tail data (one entry per interior block b; offsets into the packed
+// dense arrays): H_b = L_TT^{-1} E_T (t x ne, row-major), Gt_b (t x nf,
+// row-major) = (F U_TT^{-1})^T, ecols/frows the border columns/rows of E/F.
+struct TailDev {
+    const int* bp = nullptr;       // block boundaries (device)
+    const int* tail = nullptr;     // first tail row per block
+    const int* ne = nullptr;       // border columns touched by E_b
+    const int* nf = nullptr;       // border rows touched by F_b
+    const int64_t* hoff = nullptr; // H_b offset
+    const int64_t* goff = nullptr; // Gt_b offset
+    const int* ecoff = nullptr;    // offset of block b's ecols
+    const int* fvoff = nullptr;    // offset of block b's frows (and partials)
+    const int* trow = nullptr;     // first global tail-row number of block b
+    const int* ecols = nullptr;
+    const int* frows = nullptr;
+    double* H = nullptr;
+    double* G = nullptr;
+    int ntail = 0;                 // total tail rows
+};
+void launch_dgemm_sub(bool a_t, int M, int N, int K, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double* C, int64_t ldc, const int* rmap, const int* cmap, hipStream_t s);
+void launch_lu_panel(int n, int k0, int w, double* S, int* piv, int* bad, hipStream_t s);
+void launch_trsm_block(bool lower, int w, const double* T, int64_t ldt, int d0, double* X, int64_t ldx, int r0,
+                       int c0, int c1, hipStream_t s);
+void launch_perm_identity(int n, const int* o, double* Y, hipStream_t s);
+void launch_scatter_from(int64_t m, const int64_t* pos, const int64_t* at, const double* v, double* Out,
+                         hipStream_t s);
+void launch_tail_solves(const TailDev& T, int nblocks, int max_ne, int max_nf, const int* lrp, const int* lci,
+                        const double* lval, const int* urp, const int* uci, const double* uval,
+                        const double* udiag, hipStream_t s);
+void launch_bbd_mid(const TailDev& T, int nblocks, int max_nf, int nbd, const double* Sinv, const int* fptr,
+                    const int* fidx, double* gpart, const double* rb, double* g, double* w, double* xb,
+                    hipStream_t s);
+constexpr int kLuPanel = 64;
 void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp, int2* lch, int2* uch,
                       hipStream_t s);
 void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci, const int* urp, const int* uci,

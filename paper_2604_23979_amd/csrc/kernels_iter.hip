@@ -602,6 +602,97 @@ void launch_ir_update(int n, double* x, const double* nr2, const float* d, hipSt
     k_ir_update<<<g > 0 ? g : 1, 256, 0, s>>>(n, x, nr2, d);
 }
 
+// ------------------------------------------------------------------ GMRES
+// Arnoldi building blocks (Sec. 2.2, GMRES with right preconditioning).
+// Basis vectors are columns of V (n x k, column c at V + c * ldv).
+constexpr int kMaxBasis = 64;       // k <= kMaxBasis columns per call
+constexpr int kDotGrid = 512;       // workgroups of the multi-dot pass
+
+// part[w * kMaxBasis + c] = workgroup w's share of (V_c, w), c < k
+__global__ __launch_bounds__(256) void k_multidot(int n, int k, const double* __restrict__ V, int64_t ldv,
+                                                  const double* __restrict__ w, double* __restrict__ part) {
+    __shared__ double red[kMaxBasis][4];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        double acc[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const double wi = w[i];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (c0 + u < k) acc[u] = fma(V[(int64_t)(c0 + u) * ldv + i], wi, acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const double s = wave_sum(acc[u]);
+            if (lane == 0 && c0 + u < k) red[c0 + u][wave] = s;
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < k; c += blockDim.x)
+        part[(int64_t)blockIdx.x * kMaxBasis + c] = ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
+}
+// out[c] = sum over the grid of part[. * kMaxBasis + c] (fixed order); with
+// acc, acc[c] += out[c] as well
+__global__ __launch_bounds__(kMaxBasis) void k_multidot_reduce(int k, int grid, const double* __restrict__ part,
+                                                               double* __restrict__ out, double* acc) {
+    const int c = threadIdx.x;
+    if (c >= k) return;
+    double s = 0.0;
+    for (int w0 = 0; w0 < grid; w0 += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = w0 + u < grid ? part[(int64_t)(w0 + u) * kMaxBasis + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    out[c] = s;
+    if (acc) acc[c] += s;
+}
+void launch_multidot(int n, int k, const double* V, int64_t ldv, const double* w, double* part, double* out,
+                     double* acc, hipStream_t s) {
+    k_multidot<<<kDotGrid, 256, 0, s>>>(n, k, V, ldv, w, part);
+    k_multidot_reduce<<<1, kMaxBasis, 0, s>>>(k, kDotGrid, part, out, acc);
+}
+
+// w += alpha * sum_c V_c coef[c] (coef on the device); with nrm_part the
+// workgroup's share of ||w||^2 after the update goes to nrm_part[w]
+__global__ __launch_bounds__(256) void k_multiaxpy(int n, int k, const double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ coef, double alpha,
+                                                   double* __restrict__ w, double* __restrict__ nrm_part) {
+    __shared__ double cf[kMaxBasis];
+    __shared__ double red[8];
+    for (int c = threadIdx.x; c < k; c += blockDim.x) cf[c] = alpha * coef[c];
+    __syncthreads();
+    double sq = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double t = 0.0;
+        for (int c = 0; c < k; ++c) t = fma(V[(int64_t)c * ldv + i], cf[c], t);
+        const double wi = w[i] + t;
+        w[i] = wi;
+        sq = fma(wi, wi, sq);
+    }
+    if (nrm_part) {
+        const double tot = block_sum(sq, red);
+        if (threadIdx.x == 0) nrm_part[blockIdx.x] = tot;
+    }
+}
+void launch_multiaxpy(int n, int k, const double* V, int64_t ldv, const double* coef, double alpha, double* w,
+                      double* nrm_part, hipStream_t s) {
+    k_multiaxpy<<<kDotGrid, 256, 0, s>>>(n, k, V, ldv, coef, alpha, w, nrm_part);
+}
+// v = w / sqrt(*nrm2)
+__global__ void k_scale_inv_norm(int n, const double* __restrict__ nrm2, const double* __restrict__ w,
+                                 double* __restrict__ v) {
+    const double inv = 1.0 / sqrt(nrm2[0]);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = w[i] * inv;
+}
+void launch_scale_inv_norm(int n, const double* nrm2, const double* w, double* v, hipStream_t s) {
+    const int g = std::min(4096, (n + 255) / 256);
+    k_scale_inv_norm<<<std::max(g, 1), 256, 0, s>>>(n, nrm2, w, v);
+}
+
 // ------------------------------------------------------------------ BJ apply
 // One workgroup per diagonal block (all blocks in one launch).  Forward
 // substitution y = L^{-1} r then backward substitution z = U^{-1} y, each
@@ -968,8 +1059,10 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
     int pc[kPer];
     F pv[kPer];
 
-    // ---- forward substitution: y_i = r_i - sum_{j<i} l_ij y_j
-    if (lo < hi) {
+    // ---- forward substitution: y_i = r_i - sum_{j<i} l_ij y_j (MODE 4:
+    // y is given)
+    bool u_staged = false;
+    if (MODE != 4 && lo < hi) {
         auto T = [&](int q) { return q < kTab ? ltab[q] : LT[q]; };
         auto NL = [&](int q) { return q < kTab ? lnl[q] : P.lnl[lo + b + q]; };
         int m = 0;
@@ -1012,12 +1105,13 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
                 rp1 = live ? lrp[i + 1] : 0;
                 rv = live ? rin[i] : V(0);
                 lvn = live ? P.llev[i] : 0;
-            } else {
+            } else if (MODE != 3) {
                 // last forward chunk: the first backward chunk's entries do
                 // not depend on y, so they load while this chunk is solved
                 const int2 ua = utab[0], ub = utab[1];
                 const int un = ua.y - ub.y;
                 stage_issue(pc, pv, uci, uval, ub.y, un > kStage ? 0 : un, t);
+                u_staged = true;
             }
             // solve the current chunk
             const int ring_lo = c1 - kRing;
@@ -1063,22 +1157,23 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
     }
 
     // ---- backward substitution: z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii,
-    // chunks from the bottom of the block up
+    // chunks from the bottom of the block up (MODE 3: not done)
     double rz = 0.0;
-    if (lo < hi) {
+    if (MODE != 3 && lo < hi) {
         auto T = [&](int q) { return q < kTab ? utab[q] : UT[q]; };
         auto NL = [&](int q) { return q < kTab ? unl[q] : P.unl[lo + b + q]; };
         int m = 0;
         int2 ta = T(0), tb = T(1);  // chunk [tb.x, ta.x), entries [tb.y, ta.y)
         int2 tn = T(tb.x > lo ? 2 : 1);
         int nst = ta.y - tb.y;
-        bool big = nst > kStage;  // entries already in flight (last forward chunk)
+        bool big = nst > kStage;
+        if (!u_staged) stage_issue(pc, pv, uci, uval, tb.y, big ? 0 : nst, t);
         int i = ta.x - 1 - t;
         bool live = i >= tb.x;
         int rp0 = live ? urp[i] : 0, rp1 = live ? urp[i + 1] : 0;
         F yv = live ? y[i] : F(0);
         F dv = live ? udiag[i] : F(1);
-        V rv = (MODE != 0 && live) ? rin[i] : V(0);
+        V rv = ((MODE == 1 || MODE == 2) && live) ? rin[i] : V(0);
         int lvn = live ? P.ulev[i] : 0;
         while (true) {
             const int c_lo = tb.x, ebase = tb.y;
@@ -1110,7 +1205,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
                 rp1 = live ? urp[i + 1] : 0;
                 yv = live ? y[i] : F(0);
                 dv = live ? udiag[i] : F(1);
-                rv = (MODE != 0 && live) ? rin[i] : V(0);
+                rv = ((MODE == 1 || MODE == 2) && live) ? rin[i] : V(0);
                 lvn = live ? P.ulev[i] : 0;
             }
             // solve the current chunk.  Rows hold their entries in descending
@@ -1151,14 +1246,14 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
             if (row >= c_lo) {
                 const V zv = (V)from_bits<F>(ring[(row - lo) & (kRing - 1)]);
                 z[row] = zv;
-                if (MODE != 0) rz += (double)rrow * (double)zv;
+                if (MODE == 1 || MODE == 2) rz += (double)rrow * (double)zv;
             }
             __syncthreads();
             if (!more) break;
         }
     }
     if (bad && st) atomicExch(&st->spin_err, 1);
-    if (MODE != 0) {
+    if (MODE == 1 || MODE == 2) {
         rz = block_sum(rz, red);
         if (t == 0) Vv.part_rz[(it & 1) * nb + b] = rz;
     }
@@ -1167,9 +1262,13 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
 template <typename V, typename F>
 void launch_bj(int mode, const BJDev& P, const PcgVecs& v, KrylovState* st, int it, hipStream_t s) {
     if (P.nblocks <= 0) return;
-    if (mode == 0) k_bj<V, F, 0><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it);
-    else if (mode == 1) k_bj<V, F, 1><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it);
-    else k_bj<V, F, 2><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it);
+    switch (mode) {
+        case 0: k_bj<V, F, 0><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it); break;
+        case 1: k_bj<V, F, 1><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it); break;
+        case 2: k_bj<V, F, 2><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it); break;
+        case 3: k_bj<V, F, 3><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it); break;
+        default: k_bj<V, F, 4><<<P.nblocks, kBjThreads, 0, s>>>(P, v, st, it); break;
+    }
 }
 template void launch_bj<double, double>(int, const BJDev&, const PcgVecs&, KrylovState*, int, hipStream_t);
 template void launch_bj<double, float>(int, const BJDev&, const PcgVecs&, KrylovState*, int, hipStream_t);

@@ -92,6 +92,25 @@ struct sdsl_ctx {
     // kernel timing: three events per iteration (SpMV start, SpMV end = BJ
     // start, BJ end), reused across batches
     std::vector<hipEvent_t> ev;
+    // GMRES workspace (allocated on the first GMRES solve): basis V
+    // (m+1 columns of n), preconditioned basis Z (m columns), multi-dot
+    // partials, device coefficient columns, pinned host staging
+    int gm_cap = 0;
+    // BBD (Sec. 2.4): tails and dense tail factors, Schur LU and inverse
+    bool bbd = false;
+    TailDev tdev{};
+    int bbd_max_ne = 0, bbd_max_nf = 0;
+    std::vector<int> bbd_ne, bbd_nf, bbd_tail;
+    std::vector<int64_t> bbd_hoff, bbd_goff;
+    std::vector<int> bbd_ecoff, bbd_fvoff;
+    int64_t bbd_nh = 0, bbd_ng = 0, bbd_nc = 0;   // COO lengths (H, Gt, C)
+    int64_t *bbd_hpos = nullptr, *bbd_hat = nullptr, *bbd_gpos = nullptr, *bbd_gat = nullptr;
+    int64_t *bbd_cpos = nullptr, *bbd_cat = nullptr;
+    int *bbd_fptr = nullptr, *bbd_fidx = nullptr, *bbd_piv = nullptr, *bbd_ord = nullptr, *bbd_bad = nullptr;
+    double *bbd_S = nullptr, *bbd_Sinv = nullptr, *bbd_gpart = nullptr, *bbd_g = nullptr;
+    double *gV = nullptr, *gZ = nullptr, *gpart = nullptr, *gnrm = nullptr;
+    double *ghcol = nullptr, *gh2 = nullptr, *gy = nullptr;
+    double* gh_h = nullptr;  // pinned, kMaxBasisHost + 2 doubles
 
     template <typename T>
     T* alloc(size_t count) {
@@ -119,6 +138,7 @@ struct sdsl_ctx {
         if (st_h) (void)hipHostFree(st_h);
         if (scal_h) (void)hipHostFree(scal_h);
         if (vout_h) (void)hipHostFree(vout_h);
+        if (gh_h) (void)hipHostFree(gh_h);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
     void sync() { hip_check(hipStreamSynchronize(s), "stream synchronize"); }
@@ -204,6 +224,222 @@ void build_border(sdsl_ctx* h) {
     h->bd = BorderDev{k, h->lr.slices, h->lr.fold, h->W64, h->Kinv};
 }
 
+// ---------------------------------------------------------------- BBD
+// Structure of the bordered block diagonal form (Sec. 2.4), from the host
+// copy of the pattern: interior rows may couple only inside their block and
+// to the border; a block's tail starts at the first row with a border
+// column (E) or the first column referenced by a border row (F).  Per block
+// the distinct border columns of E and rows of F, the dense tail factor
+// layouts, and the positions of the E, F and C entries in the CSR (so that
+// new values only need a gather).
+void setup_bbd(sdsl_ctx* h, const std::vector<int64_t>& rp, const std::vector<int>& ci) {
+    const int n = h->n, ni = h->n_int, nbd = h->nbd, nb = h->nb;
+    const std::vector<int>& bp = h->bp_h;
+    std::vector<int> blk(ni);
+    for (int b = 0; b < nb; ++b)
+        for (int i = bp[b]; i < bp[b + 1]; ++i) blk[i] = b;
+    std::vector<int> tail(bp.begin() + 1, bp.end());
+    for (int i = 0; i < ni; ++i) {
+        const int b = blk[i];
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+            const int j = ci[q];
+            if (j >= ni) tail[b] = std::min(tail[b], i);
+            else if (j < bp[b] || j >= bp[b + 1])
+                fail(SDSL_E_STRUCTURE, "interior row " + std::to_string(i) + " couples to another block");
+        }
+    }
+    for (int i = ni; i < n; ++i)
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (ci[q] < ni) tail[blk[ci[q]]] = std::min(tail[blk[ci[q]]], ci[q]);
+    // distinct border columns (E) and rows (F) per block
+    std::vector<std::vector<int>> ecols(nb), frows(nb);
+    for (int i = 0; i < ni; ++i)
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (ci[q] >= ni) ecols[blk[i]].push_back(ci[q] - ni);
+    for (int i = ni; i < n; ++i)
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (ci[q] < ni) frows[blk[ci[q]]].push_back(i - ni);
+    h->bbd_ne.assign(nb, 0);
+    h->bbd_nf.assign(nb, 0);
+    h->bbd_hoff.assign(nb + 1, 0);
+    h->bbd_goff.assign(nb + 1, 0);
+    h->bbd_ecoff.assign(nb + 1, 0);
+    h->bbd_fvoff.assign(nb + 1, 0);
+    std::vector<int> trow(nb + 1, 0);
+    std::vector<int> ecat, frcat;
+    std::vector<int> epos(nbd, -1), fpos(nbd, -1);
+    std::vector<std::vector<std::pair<int, int>>> fslots(nbd);  // border row -> (block, column)
+    for (int b = 0; b < nb; ++b) {
+        std::sort(ecols[b].begin(), ecols[b].end());
+        ecols[b].erase(std::unique(ecols[b].begin(), ecols[b].end()), ecols[b].end());
+        std::sort(frows[b].begin(), frows[b].end());
+        frows[b].erase(std::unique(frows[b].begin(), frows[b].end()), frows[b].end());
+        const int t = bp[b + 1] - tail[b];
+        h->bbd_ne[b] = (int)ecols[b].size();
+        h->bbd_nf[b] = (int)frows[b].size();
+        h->bbd_hoff[b + 1] = h->bbd_hoff[b] + (int64_t)t * h->bbd_ne[b];
+        h->bbd_goff[b + 1] = h->bbd_goff[b] + (int64_t)t * h->bbd_nf[b];
+        h->bbd_ecoff[b + 1] = h->bbd_ecoff[b] + h->bbd_ne[b];
+        h->bbd_fvoff[b + 1] = h->bbd_fvoff[b] + h->bbd_nf[b];
+        trow[b + 1] = trow[b] + t;
+        ecat.insert(ecat.end(), ecols[b].begin(), ecols[b].end());
+        frcat.insert(frcat.end(), frows[b].begin(), frows[b].end());
+        for (int c = 0; c < h->bbd_nf[b]; ++c) fslots[frows[b][c]].push_back({b, c});
+        h->bbd_max_ne = std::max(h->bbd_max_ne, h->bbd_ne[b]);
+        h->bbd_max_nf = std::max(h->bbd_max_nf, h->bbd_nf[b]);
+    }
+    h->bbd_tail = tail;
+    // entry positions: H (E entries), Gt (F entries), C (border-border)
+    std::vector<int64_t> hpos, hat, gpos, gat, cpos, cat;
+    for (int b = 0; b < nb; ++b) {
+        for (int c = 0; c < h->bbd_ne[b]; ++c) epos[ecols[b][c]] = c;
+        for (int i = tail[b]; i < bp[b + 1]; ++i)
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+                if (ci[q] >= ni) {
+                    hpos.push_back(q);
+                    hat.push_back(h->bbd_hoff[b] + (int64_t)(i - tail[b]) * h->bbd_ne[b] + epos[ci[q] - ni]);
+                }
+        for (int c = 0; c < h->bbd_ne[b]; ++c) epos[ecols[b][c]] = -1;
+    }
+    for (int b = 0; b < nb; ++b) {
+        for (int c = 0; c < h->bbd_nf[b]; ++c) fpos[frows[b][c]] = c;
+        for (int i = ni; i < n; ++i) {
+            if (fpos[i - ni] < 0) continue;
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+                const int j = ci[q];
+                if (j >= bp[b] && j < bp[b + 1]) {
+                    gpos.push_back(q);
+                    gat.push_back(h->bbd_goff[b] + (int64_t)(j - tail[b]) * h->bbd_nf[b] + fpos[i - ni]);
+                }
+            }
+        }
+        for (int c = 0; c < h->bbd_nf[b]; ++c) fpos[frows[b][c]] = -1;
+    }
+    for (int i = ni; i < n; ++i)
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+            if (ci[q] >= ni) {
+                cpos.push_back(q);
+                cat.push_back((int64_t)(i - ni) * nbd + (ci[q] - ni));
+            }
+    std::vector<int> fptr(nbd + 1, 0), fidx;
+    for (int f = 0; f < nbd; ++f) {
+        for (auto& bc : fslots[f]) fidx.push_back(h->bbd_fvoff[bc.first] + bc.second);
+        fptr[f + 1] = (int)fidx.size();
+    }
+    auto up64 = [&](const std::vector<int64_t>& v) {
+        int64_t* d = h->alloc<int64_t>(v.size());
+        if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * 8, hipMemcpyHostToDevice), "copy");
+        return d;
+    };
+    auto up32 = [&](const std::vector<int>& v) {
+        int* d = h->alloc<int>(v.size());
+        if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * 4, hipMemcpyHostToDevice), "copy");
+        return d;
+    };
+    h->bbd_nh = (int64_t)hpos.size();
+    h->bbd_ng = (int64_t)gpos.size();
+    h->bbd_nc = (int64_t)cpos.size();
+    h->bbd_hpos = up64(hpos);
+    h->bbd_hat = up64(hat);
+    h->bbd_gpos = up64(gpos);
+    h->bbd_gat = up64(gat);
+    h->bbd_cpos = up64(cpos);
+    h->bbd_cat = up64(cat);
+    h->bbd_fptr = up32(fptr);
+    h->bbd_fidx = up32(fidx);
+    TailDev T;
+    T.bp = h->bp;
+    T.tail = up32(tail);
+    T.ne = up32(h->bbd_ne);
+    T.nf = up32(h->bbd_nf);
+    T.hoff = up64(h->bbd_hoff);
+    T.goff = up64(h->bbd_goff);
+    T.ecoff = up32(h->bbd_ecoff);
+    T.fvoff = up32(h->bbd_fvoff);
+    T.trow = up32(trow);
+    T.ecols = up32(ecat);
+    T.frows = up32(frcat);
+    T.H = h->alloc<double>(h->bbd_hoff[nb]);
+    T.G = h->alloc<double>(h->bbd_goff[nb]);
+    T.ntail = trow[nb];
+    h->tdev = T;
+    h->bbd_S = h->alloc<double>((size_t)nbd * nbd);
+    h->bbd_Sinv = h->alloc<double>((size_t)nbd * nbd);
+    h->bbd_piv = h->alloc<int>(nbd);
+    h->bbd_ord = h->alloc<int>(nbd);
+    h->bbd_bad = h->alloc<int>(1);
+    h->bbd_gpart = h->alloc<double>(std::max(1, h->bbd_fvoff[nb]));
+    h->bbd_g = h->alloc<double>(nbd);
+    h->bbd = true;
+}
+
+// Schur complement S = C - sum_b Gt_b^T H_b (MFMA), its LU with partial
+// pivoting (blocked: panel, triangular solve, MFMA trailing update) and its
+// inverse U^{-1} L^{-1} P (MFMA updates); rebuilt with every factorisation.
+void build_bbd(sdsl_ctx* h) {
+    if (!h->bbd) return;
+    hipStream_t s = h->s;
+    const int nbd = h->nbd, nb = h->nb;
+    TailDev& T = h->tdev;
+    hip_check(hipMemsetAsync(T.H, 0, std::max<int64_t>(1, h->bbd_hoff[nb]) * 8, s), "memset");
+    hip_check(hipMemsetAsync(T.G, 0, std::max<int64_t>(1, h->bbd_goff[nb]) * 8, s), "memset");
+    hip_check(hipMemsetAsync(h->bbd_S, 0, (size_t)nbd * nbd * 8, s), "memset");
+    hip_check(hipMemsetAsync(h->bbd_bad, 0, sizeof(int), s), "memset");
+    launch_scatter_from(h->bbd_nh, h->bbd_hpos, h->bbd_hat, h->v, T.H, s);
+    launch_scatter_from(h->bbd_ng, h->bbd_gpos, h->bbd_gat, h->v, T.G, s);
+    launch_scatter_from(h->bbd_nc, h->bbd_cpos, h->bbd_cat, h->v, h->bbd_S, s);
+    launch_tail_solves(T, nb, h->bbd_max_ne, h->bbd_max_nf, h->lrp, h->lci, h->lval, h->urp, h->uci, h->uval,
+                       h->udiag, s);
+    for (int b = 0; b < nb; ++b) {
+        const int t = h->bp_h[b + 1] - h->bbd_tail[b];
+        launch_dgemm_sub(true, h->bbd_nf[b], h->bbd_ne[b], t, T.G + h->bbd_goff[b], h->bbd_nf[b],
+                         T.H + h->bbd_hoff[b], h->bbd_ne[b], h->bbd_S, nbd, T.frows + h->bbd_fvoff[b],
+                         T.ecols + h->bbd_ecoff[b], s);
+    }
+    double* S = h->bbd_S;
+    const int P = kLuPanel;
+    for (int k0 = 0; k0 < nbd; k0 += P) {
+        const int w = std::min(P, nbd - k0);
+        launch_lu_panel(nbd, k0, w, S, h->bbd_piv, h->bbd_bad, s);
+        if (k0 + w < nbd) {
+            launch_trsm_block(true, w, S, nbd, k0, S, nbd, k0, k0 + w, nbd, s);
+            const int m = nbd - k0 - w;
+            launch_dgemm_sub(false, m, m, w, S + (int64_t)(k0 + w) * nbd + k0, nbd, S + (int64_t)k0 * nbd + k0 + w,
+                             nbd, S + (int64_t)(k0 + w) * nbd + k0 + w, nbd, nullptr, nullptr, s);
+        }
+    }
+    h->check_launch();
+    int bad = 0;
+    std::vector<int> piv(nbd);
+    hip_check(hipMemcpyAsync(&bad, h->bbd_bad, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    hip_check(hipMemcpyAsync(piv.data(), h->bbd_piv, nbd * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    h->sync();
+    if (bad) fail(SDSL_E_BREAKDOWN, "the border Schur complement is singular (zero pivot)");
+    // inverse: Y = P I, Y = L^{-1} Y, Sinv = U^{-1} Y
+    std::vector<int> ord(nbd);
+    for (int i = 0; i < nbd; ++i) ord[i] = i;
+    for (int kk = 0; kk < nbd; ++kk) std::swap(ord[kk], ord[piv[kk]]);
+    hip_check(hipMemcpy(h->bbd_ord, ord.data(), nbd * sizeof(int), hipMemcpyHostToDevice), "copy");
+    double* X = h->bbd_Sinv;
+    launch_perm_identity(nbd, h->bbd_ord, X, s);
+    for (int k0 = 0; k0 < nbd; k0 += P) {
+        const int w = std::min(P, nbd - k0);
+        launch_trsm_block(true, w, S, nbd, k0, X, nbd, k0, 0, nbd, s);
+        if (k0 + w < nbd)
+            launch_dgemm_sub(false, nbd - k0 - w, nbd, w, S + (int64_t)(k0 + w) * nbd + k0, nbd,
+                             X + (int64_t)k0 * nbd, nbd, X + (int64_t)(k0 + w) * nbd, nbd, nullptr, nullptr, s);
+    }
+    for (int k0 = ((nbd - 1) / P) * P; k0 >= 0; k0 -= P) {
+        const int w = std::min(P, nbd - k0);
+        launch_trsm_block(false, w, S, nbd, k0, X, nbd, k0, 0, nbd, s);
+        if (k0 > 0)
+            launch_dgemm_sub(false, k0, nbd, w, S + k0, nbd, X + (int64_t)k0 * nbd, nbd, X, nbd, nullptr, nullptr,
+                             s);
+    }
+    h->check_launch();
+    h->sync();
+}
+
 void build_precond(sdsl_ctx* h) {
     const double t0 = now_ms();
     hipStream_t s = h->s;
@@ -257,6 +493,7 @@ void build_precond(sdsl_ctx* h) {
                                        std::to_string((int)h->o.pivot) + ")");
     h->sync();
     build_border(h);
+    build_bbd(h);
     h->info.setup_ms = now_ms() - t0;
     // algorithmic bytes: every array a launch must touch, once.  Index 0: FP64
     // values and vectors; index 1: FP32 values/factors with FP64 vectors.
@@ -450,6 +687,37 @@ double true_residual(sdsl_ctx* h, const double* b, const double* x, double* r) {
     return std::sqrt(reduce_to_host(h, h->part_res, h->grid, 0));
 }
 
+// FP64 operator y = M x (+ U diag(c) U^T x)
+void apply_op64(sdsl_ctx* h, const double* x, double* y) {
+    const CsrView A{h->n, h->rp, h->ci, h->halo};
+    if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, x, nullptr, LR_SCALED, nullptr, h->s);
+    launch_spmv<double, double>(A, h->v, h->lr, x, y, nullptr, nullptr, h->lanes, h->grid, h->s);
+}
+
+// FP64 preconditioner z = P^{-1} r (block Jacobi, with the border
+// correction of the low-rank term when present)
+void apply_prec64(sdsl_ctx* h, const double* r, double* z) {
+    PcgVecs V{};
+    V.r = const_cast<double*>(r);
+    V.z = z;
+    V.y = h->y;
+    if (h->bbd) {
+        // Sec. 2.4: w = L^{-1} r_I; g = r_G - F U_TT^{-1} w_T; x_G = S^{-1} g;
+        // w_T -= L_TT^{-1} E_T x_G; z_I = U^{-1} w
+        const int ni = h->n_int;
+        launch_bj<double, double>(3, bj_dev(h, false), V, nullptr, 0, h->s);
+        launch_bbd_mid(h->tdev, h->nb, h->bbd_max_nf, h->nbd, h->bbd_Sinv, h->bbd_fptr, h->bbd_fidx, h->bbd_gpart,
+                       r + ni, h->bbd_g, h->y, z + ni, h->s);
+        launch_bj<double, double>(4, bj_dev(h, false), V, nullptr, 0, h->s);
+        return;
+    }
+    launch_bj<double, double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
+    if (h->bd.k > 0) {
+        launch_lowrank_tdot<double>(h->lr, z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
+        launch_border_fix<double>(h->n, z, h->bd, h->s);
+    }
+}
+
 __global__ void k_axpy1(int n, double* __restrict__ x, const double* __restrict__ d) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = x[i] + d[i];
 }
@@ -470,7 +738,7 @@ struct SolveTask {
     bool finished = false;
     double t0 = 0.0;
 
-    enum Phase { P64, PMIX, P32_RESTART } phase = P64;
+    enum Phase { P64, PMIX, P32_RESTART, PGMRES } phase = P64;
     Pcg<double, double> pcg64{};
     Pcg<double, float> pcgmix{};
     Pcg<double, double> pcghand{};  // FP64 continuation of the pcgmix recurrence
@@ -508,7 +776,9 @@ struct SolveTask {
         pcghand.init();
         pcg32 = Pcg<float, float>{h, h->x32, h->r32, h->z32, h->p32, h->q32, h->y32, h->v32};
         pcg32.init();
-        if (h->o.precision == SDSL_FP64) {
+        if (h->o.krylov == SDSL_GMRES) {
+            gm_begin();
+        } else if (h->o.precision == SDSL_FP64) {
             start64(b, xout, tol, nb);
         } else if (h->o.precision == SDSL_FP32_IR) {
             // FP64 recurrence over the FP32 operator and factors; the true
@@ -588,8 +858,109 @@ struct SolveTask {
                nr / nb);
     }
 
+    // ---- GMRES(m), right preconditioned, FP64 (Sec. 2.2): Arnoldi with
+    // classical Gram-Schmidt applied twice, Givens rotations on the host,
+    // x += Z y at the end of a cycle, restart from the true residual
+    int gm_m = 0, gm_j = 0;
+    std::vector<double> gH, gcs, gsn, gg;
+    void gm_begin() {
+        phase = PGMRES;
+        gm_m = std::max(1, std::min(h->o.restart, kMaxBasisHost - 1));
+        const int n = h->n;
+        if (h->gm_cap < gm_m) {
+            h->gV = h->alloc<double>((size_t)(gm_m + 1) * n);
+            h->gZ = h->alloc<double>((size_t)gm_m * n);
+            if (!h->gpart) {
+                h->gpart = h->alloc<double>((size_t)512 * kMaxBasisHost);
+                h->gnrm = h->alloc<double>(512);
+                h->ghcol = h->alloc<double>(kMaxBasisHost);
+                h->gh2 = h->alloc<double>(kMaxBasisHost);
+                h->gy = h->alloc<double>(kMaxBasisHost);
+                hip_check(hipHostMalloc((void**)&h->gh_h, (kMaxBasisHost + 2) * sizeof(double), hipHostMallocDefault),
+                          "pinned alloc");
+            }
+            h->gm_cap = gm_m;
+        }
+        gH.assign((size_t)(gm_m + 1) * gm_m, 0.0);
+        gcs.assign(gm_m, 0.0);
+        gsn.assign(gm_m, 0.0);
+        gg.assign(gm_m + 1, 0.0);
+        gm_cycle();
+    }
+    void gm_cycle() {
+        // r = b - M x (compensated), scal[0] = ||r||^2
+        nr = true_residual(h, b, xout, h->r);
+        if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
+        if (total_its >= max_iter()) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
+        if (outer > 0) restarts++;
+        outer++;
+        launch_scale_inv_norm(h->n, h->scal + 0, h->r, h->gV, h->s);
+        std::fill(gg.begin(), gg.end(), 0.0);
+        gg[0] = nr;
+        gm_j = 0;
+    }
+    void gm_step() {
+        const int n = h->n, j = gm_j;
+        double* vj = h->gV + (size_t)j * n;
+        double* zj = h->gZ + (size_t)j * n;
+        double* w = h->gV + (size_t)(j + 1) * n;
+        apply_prec64(h, vj, zj);
+        apply_op64(h, zj, w);
+        launch_multidot(n, j + 1, h->gV, n, w, h->gpart, h->ghcol, nullptr, h->s);
+        launch_multiaxpy(n, j + 1, h->gV, n, h->ghcol, -1.0, w, nullptr, h->s);
+        launch_multidot(n, j + 1, h->gV, n, w, h->gpart, h->gh2, h->ghcol, h->s);
+        launch_multiaxpy(n, j + 1, h->gV, n, h->gh2, -1.0, w, h->gnrm, h->s);
+        launch_sum_partials(h->gnrm, 512, h->scal + 2, h->s);
+        h->check_launch();
+        hip_check(hipMemcpyAsync(h->gh_h, h->ghcol, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, h->s), "copy");
+        hip_check(hipMemcpyAsync(h->gh_h + kMaxBasisHost, h->scal + 2, sizeof(double), hipMemcpyDeviceToHost, h->s),
+                  "copy");
+        h->sync();
+        double* col = &gH[(size_t)j * (gm_m + 1)];
+        for (int i = 0; i <= j; ++i) col[i] = h->gh_h[i];
+        const double hn = std::sqrt(h->gh_h[kMaxBasisHost]);
+        col[j + 1] = hn;
+        double cnorm = 0.0;
+        for (int i = 0; i <= j + 1; ++i) cnorm = std::max(cnorm, std::fabs(col[i]));
+        for (int i = 0; i < j; ++i) {
+            const double a = col[i], c = col[i + 1];
+            col[i] = gcs[i] * a + gsn[i] * c;
+            col[i + 1] = -gsn[i] * a + gcs[i] * c;
+        }
+        const double t = col[j], u = col[j + 1];
+        const double rr = std::hypot(t, u);
+        gcs[j] = rr > 0.0 ? t / rr : 1.0;
+        gsn[j] = rr > 0.0 ? u / rr : 0.0;
+        col[j] = rr;
+        col[j + 1] = 0.0;
+        gg[j + 1] = -gsn[j] * gg[j];
+        gg[j] = gcs[j] * gg[j];
+        total_its++;
+        gm_j = j + 1;
+        const bool happy = !(hn > 1e-14 * cnorm);
+        if (!happy) launch_scale_inv_norm(n, h->scal + 2, w, w, h->s);
+        if (std::fabs(gg[j + 1]) <= tol * nb || happy || gm_j == gm_m || total_its >= max_iter()) gm_update();
+    }
+    void gm_update() {
+        // y = R^{-1} g by back substitution; x += Z y
+        const int k = gm_j;
+        std::vector<double> yv(k, 0.0);
+        for (int i = k - 1; i >= 0; --i) {
+            double s = gg[i];
+            for (int c = i + 1; c < k; ++c) s -= gH[(size_t)c * (gm_m + 1) + i] * yv[c];
+            const double d = gH[(size_t)i * (gm_m + 1) + i];
+            yv[i] = d != 0.0 ? s / d : 0.0;
+        }
+        for (int i = 0; i < k; ++i) h->gh_h[i] = yv[i];
+        hip_check(hipMemcpyAsync(h->gy, h->gh_h, k * sizeof(double), hipMemcpyHostToDevice, h->s), "copy");
+        launch_multiaxpy(h->n, k, h->gZ, h->n, h->gy, 1.0, xout, nullptr, h->s);
+        h->check_launch();
+        gm_cycle();
+    }
+
     void step() {
         if (finished) return;
+        if (phase == PGMRES) { gm_step(); return; }
         if (phase == P64) { step64(); return; }
         if (phase == PMIX) { step_mixed(); return; }
         // classical refinement: wait for the inner solve to stop
@@ -702,14 +1073,19 @@ sdsl_status guard(sdsl_ctx* h, const std::function<void()>& fn) {
 
 void check_options(const sdsl_options* o) {
     if (o->method != SDSL_BJ && o->method != SDSL_BBD) fail(SDSL_E_INVALID, "unknown method");
-    if (o->method == SDSL_BBD) fail(SDSL_E_INVALID, "the BBD method is not available in this library");
+    if (o->method == SDSL_BBD && (o->krylov != SDSL_GMRES || o->precision != SDSL_FP64))
+        fail(SDSL_E_INVALID, "the BBD preconditioner runs with GMRES in FP64");
     if (o->filter < SDSL_FILTER_NONE || o->filter > SDSL_FILTER_GEOMEAN) fail(SDSL_E_INVALID, "unknown filter");
     if (!(o->tau >= 0.0)) fail(SDSL_E_INVALID, "tau must be >= 0");
     if (!(o->delta >= 0.0) || !std::isfinite(o->delta)) fail(SDSL_E_INVALID, "delta must be finite and >= 0");
     if (o->pivot < SDSL_PIVOT_FAIL || o->pivot > SDSL_PIVOT_SHIFT) fail(SDSL_E_INVALID, "unknown pivot policy");
     if (o->pivot == SDSL_PIVOT_SHIFT && !(o->shift0 > 0.0 && std::isfinite(o->shift0)))
         fail(SDSL_E_INVALID, "shift0 must be positive");
-    if (o->krylov != SDSL_PCG) fail(SDSL_E_INVALID, "only PCG is available in this library");
+    if (o->krylov != SDSL_PCG && o->krylov != SDSL_GMRES) fail(SDSL_E_INVALID, "unknown Krylov method");
+    if (o->krylov == SDSL_GMRES && o->precision != SDSL_FP64)
+        fail(SDSL_E_INVALID, "GMRES runs in FP64 (precision must be SDSL_FP64)");
+    if (o->krylov == SDSL_GMRES && (o->restart < 1 || o->restart >= kMaxBasisHost))
+        fail(SDSL_E_INVALID, "GMRES restart must be in [1, 63]");
     if (o->max_iter < 1 || o->check_every < 1) fail(SDSL_E_INVALID, "max_iter and check_every must be >= 1");
     if (o->precision < SDSL_FP64 || o->precision > SDSL_FP32_IR_RESTART) fail(SDSL_E_INVALID, "unknown precision");
     if (o->precision == SDSL_FP32_IR_RESTART && (!(o->inner_tol > 0.0 && o->inner_tol < 1.0) || o->max_outer < 1))
@@ -899,6 +1275,16 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->part_res = h->alloc<double>(h->grid);
         h->scal = h->alloc<double>(4);
         h->st = h->alloc<KrylovState>(1);
+        if (o->method == SDSL_BBD) {
+            if (lr && lr->k > 0) fail(SDSL_E_INVALID, "the BBD method takes no low-rank term");
+            if (h->nbd <= 0) fail(SDSL_E_INVALID, "the BBD method needs a border (n_border > 0)");
+            std::vector<int64_t> rph(n + 1);
+            std::vector<int> cih(nnz);
+            const hipMemcpyKind dk = A->mem == SDSL_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+            hip_check(hipMemcpy(rph.data(), A->row_ptr, (n + 1) * sizeof(int64_t), dk), "copy");
+            hip_check(hipMemcpy(cih.data(), A->col, nnz * sizeof(int), dk), "copy");
+            setup_bbd(h, rph, cih);
+        }
         build_precond(h);
         h->sync();
         h->release(rp64, (size_t)(n + 1) * sizeof(int64_t));
@@ -1007,9 +1393,7 @@ sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y) {
         if (!x || !y) fail(SDSL_E_INVALID, "null vector");
         const CsrView A{h->n, h->rp, h->ci, h->halo};
         if (prec == SDSL_FP64) {
-            if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, (const double*)x, nullptr, LR_SCALED, nullptr, h->s);
-            launch_spmv<double, double>(A, h->v, h->lr, (const double*)x, (double*)y, nullptr, nullptr, h->lanes,
-                                        h->grid, h->s);
+            apply_op64(h, (const double*)x, (double*)y);
         } else {
             if (h->lr.k > 0) launch_lowrank_tdot<float>(h->lr, (const float*)x, nullptr, LR_SCALED, nullptr, h->s);
             launch_spmv<float, float>(A, h->v32, h->lr, (const float*)x, (float*)y, nullptr, nullptr, h->lanes,
@@ -1029,12 +1413,7 @@ sdsl_status sdsl_precond_apply(sdsl_handle h, int32_t prec, const void* r, void*
         V.z = z;
         hip_check(hipMemsetAsync(h->spin_err, 0, sizeof(int), h->s), "memset");
         if (prec == SDSL_FP64) {
-            V.y = h->y;
-            launch_bj<double, double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
-            if (h->bd.k > 0) {
-                launch_lowrank_tdot<double>(h->lr, (const double*)z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
-                launch_border_fix<double>(h->n, (double*)z, h->bd, h->s);
-            }
+            apply_prec64(h, (const double*)r, (double*)z);
         } else {
             V.y = h->y32;
             launch_bj<float, float>(0, bj_dev(h, true), V, nullptr, 0, h->s);
@@ -1072,6 +1451,18 @@ sdsl_status sdsl_get_factors(sdsl_handle h, int64_t* row_ptr, int32_t* col, doub
         if (corrected) hip_check(hipMemcpy(corrected, h->pv_corr, m * sizeof(double), hipMemcpyDeviceToHost), "copy");
         if (lu) hip_check(hipMemcpy(lu, h->pv, m * sizeof(double), hipMemcpyDeviceToHost), "copy");
         if (shifts) hip_check(hipMemcpy(shifts, h->shifts, h->nb * sizeof(double), hipMemcpyDeviceToHost), "copy");
+    });
+}
+
+sdsl_status sdsl_get_schur(sdsl_handle h, double* lu, int32_t* piv, double* inv) {
+    if (!h) return SDSL_E_INVALID;
+    return guard(h, [&] {
+        if (!h->bbd) fail(SDSL_E_STATE, "not a BBD handle");
+        h->sync();
+        const size_t m = (size_t)h->nbd * h->nbd;
+        if (lu) hip_check(hipMemcpy(lu, h->bbd_S, m * sizeof(double), hipMemcpyDeviceToHost), "copy");
+        if (piv) hip_check(hipMemcpy(piv, h->bbd_piv, h->nbd * sizeof(int), hipMemcpyDeviceToHost), "copy");
+        if (inv) hip_check(hipMemcpy(inv, h->bbd_Sinv, m * sizeof(double), hipMemcpyDeviceToHost), "copy");
     });
 }
 

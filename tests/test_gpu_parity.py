@@ -372,3 +372,158 @@ def test_solve_batch_equals_solo():
         assert np.array_equal(xs[i].cpu().numpy(), solo[i][0])
     for sv in solvers:
         sv.close()
+
+
+def nonsym_system(n=6000, nblocks=4, seed=3):
+    """Nonsymmetric, weakly diagonally dominant banded system (random band
+    entries, diagonal 0.6 x the row's magnitude sum, diagonal included)."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), 9)
+    cols = np.clip(rows + rng.integers(-300, 300, size=rows.shape[0]), 0, n - 1)
+    a = sp.coo_matrix((rng.standard_normal(rows.shape[0]), (rows, cols)), shape=(n, n)).tocsr()
+    a.setdiag(0.0)
+    a.eliminate_zeros()
+    off = np.asarray(abs(a).sum(axis=1)).ravel()
+    a = (a + sp.diags(1.5 * off + 1e-3)).tocsr()
+    a.sort_indices()
+    bp = np.linspace(0, n, nblocks + 1).astype(np.int32)
+    return gen.System("nonsym", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data,
+                      rng.standard_normal(n), bp)
+
+
+@pytest.mark.parametrize("which", ["nonsym", "nonsym-7blocks"])
+def test_gmres_bj_matches_oracle(which):
+    """Right-preconditioned GMRES(30) with the block-Jacobi preconditioner on
+    nonsymmetric systems: true relres <= 1e-8 and inner iterations within
+    10% (or 2) of the oracle's; both orthogonalise with classical
+    Gram-Schmidt applied twice."""
+    print(f"[gmres {which}]", flush=True)
+    s = nonsym_system() if which == "nonsym" else nonsym_system(n=9000, nblocks=7, seed=4)
+    o = opts(krylov=sd.GMRES, spd=False)
+    sv = sd.from_system(s, o)
+    P = O.BJ(s, **oracle_opts(o))
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+    x_o, its_o, rr_o, st_o, _ = O.gmres_bj(s, P, tol=1e-8, m=30, maxit=20_000)
+    true_rr = O.relres(s, x.cpu().numpy())
+    print(f"  GPU its {its} relres {true_rr:.2e}; oracle its {its_o} relres {rr_o:.2e}")
+    assert st == sd.OK and st_o == O.OK
+    assert true_rr <= 1e-8 and abs(rr - true_rr) <= 1e-3 * true_rr + 1e-15
+    assert abs(its - its_o) <= max(2, 0.1 * its_o)
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(xs - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    sv.close()
+
+
+def test_gmres_c1_reaches_tolerance():
+    """C1 with GMRES(30): restarted GMRES on this SPD system with a 1e8
+    spread of D stagnates between restarts, and its iteration count moves by
+    tens of percent with rounding alone (the oracle needs 3821 iterations
+    with modified and 4632 with twice-applied classical Gram-Schmidt), so
+    only the true residual is gated here; the counts are printed."""
+    s = gen.c1()
+    o = opts(krylov=sd.GMRES, max_iter=20_000)
+    sv = sd.from_system(s, o)
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+    true_rr = O.relres(s, x.cpu().numpy())
+    _, its_o, rr_o, st_o, _ = O.gmres_bj(s, O.BJ(s), tol=1e-8, m=30, maxit=20_000)
+    print(f"  C1 GMRES: GPU its {its} relres {true_rr:.2e}; oracle its {its_o}")
+    assert st == sd.OK and true_rr <= 1e-8
+    sv.close()
+
+
+def test_gmres_exact_preconditioner_one_step():
+    """Tridiagonal nonsymmetric single block: ILU(0) is exact, so right-
+    preconditioned GMRES converges in one step."""
+    rng = np.random.default_rng(5)
+    n = 4000
+    lo, up = rng.standard_normal(n - 1), rng.standard_normal(n - 1)
+    dg = np.abs(np.r_[lo, 0]) + np.abs(np.r_[0, up]) + 1.0
+    a = sp.diags([lo, dg, up], [-1, 0, 1]).tocsr()
+    a.sort_indices()
+    s = gen.System("tri-ns", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data,
+                   rng.standard_normal(n), np.array([0, n], dtype=np.int32))
+    sv = sd.from_system(s, opts(krylov=sd.GMRES, spd=False))
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-12)
+    assert st == sd.OK and its == 1 and O.relres(s, x.cpu().numpy()) <= 1e-12
+    sv.close()
+
+
+# ------------------------------------------------------------------ BBD
+
+BBD_OPTS = dict(method=sd.BBD, krylov=sd.GMRES, spd=False)
+
+
+@pytest.fixture(scope="module", params=["C3x0.004", "C3x0.02"])
+def bbd_case(request):
+    print(f"\n[bbd case {request.param}]", flush=True)
+    s = gen.c3(float(request.param[3:]))
+    sv = sd.from_system(s, opts(**BBD_OPTS))
+    P = O.BBD(s)
+    assert P.status == O.OK
+    yield request.param, s, sv, P
+    sv.close()
+
+
+def test_bbd_schur_lu_matches_oracle(bbd_case):
+    """Dense border Schur complement: GPU (MFMA assembly, blocked LU) and
+    oracle (column-by-column assembly, unblocked LU) take the same pivots and
+    agree to rounding; the GPU inverse inverts the oracle's S."""
+    name, s, sv, P = bbd_case
+    lu, piv, inv = sv.schur()
+    parts = P.parts()
+    lu_o, piv_o = parts["S"], parts["piv"]
+    m = s.n_border
+    assert np.array_equal(piv, piv_o.astype(np.int32))
+    assert np.max(np.abs(lu - lu_o)) <= 1e-10 * np.max(np.abs(lu_o))
+    L = np.tril(lu_o, -1) + np.eye(m)
+    U = np.triu(lu_o)
+    S = L @ U
+    for k in reversed(range(m)):           # undo the row swaps
+        S[[k, piv_o[k]]] = S[[piv_o[k], k]]
+    assert np.max(np.abs(inv @ S - np.eye(m))) <= 1e-9
+    print(f"  {name}: border {m}, max |LU - LU_oracle| / max |LU| = "
+          f"{np.max(np.abs(lu - lu_o)) / np.max(np.abs(lu_o)):.2e}")
+
+
+def test_bbd_apply_matches_oracle(bbd_case):
+    name, s, sv, P = bbd_case
+    r = np.random.default_rng(21).standard_normal(s.n)
+    z = sv.precond_apply(tdev(r)).cpu().numpy()
+    zo = P.apply(r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
+def test_bbd_gmres_matches_oracle(bbd_case):
+    name, s, sv, P = bbd_case
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+    x_o, its_o, rr_o, st_o, _ = O.gmres_bbd(s, P, tol=1e-8, m=30)
+    true_rr = O.relres(s, x.cpu().numpy())
+    print(f"  {name}: GPU its {its} relres {true_rr:.2e}; oracle its {its_o} relres {rr_o:.2e}")
+    assert st == sd.OK and st_o == O.OK and true_rr <= 1e-8
+    assert abs(its - its_o) <= max(2, 0.1 * its_o)
+    assert np.linalg.norm(x.cpu().numpy() - x_o) <= 1e-6 * np.linalg.norm(x_o)
+
+
+def test_bbd_exact_blocks_one_step():
+    """Tridiagonal interior blocks: ILU(0) is exact, the BBD preconditioner
+    is M itself and GMRES converges in one step."""
+    s = gen.bbd_system(nblocks=4, block_rows=500, n_border=96, nnz_off=1, half_band=1, tail_frac=0.1,
+                       border_c=2, seed=16, name="bbd-tri")
+    sv = sd.from_system(s, opts(**BBD_OPTS))
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-10)
+    assert st == sd.OK and its == 1 and O.relres(s, x.cpu().numpy()) <= 1e-10
+    sv.close()
+
+
+def test_bbd_rejects_block_coupling():
+    s = gen.bbd_system(nblocks=2, block_rows=300, n_border=64, nnz_off=2, half_band=4, tail_frac=0.2,
+                       border_c=1, seed=17)
+    M = s.scipy().tolil()
+    M[0, 450] = 1.0  # block 0 row -> block 1 column
+    M = M.tocsr()
+    M.sort_indices()
+    s2 = gen.System("bad", M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data, s.b,
+                    s.block_ptr, n_border=s.n_border)
+    with pytest.raises(sd.SdslError) as e:
+        sd.from_system(s2, opts(**BBD_OPTS))
+    assert e.value.status == sd.E_STRUCTURE
