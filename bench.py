@@ -99,6 +99,34 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol):
     return res
 
 
+def run_serving(sd, torch, gen, count, active):
+    """Served C5 stream: the first `count` requests of the seeded stream
+    (built before timing), solved FP32-inner / FP64-refined to 1e-8 with the
+    C2 filter.  First all at t = 0 (saturated: the service rate mu), then
+    with Poisson arrivals at 0.8 mu; latency = arrival to completion."""
+    from paper_2604_23979_amd.serve import Request, Server
+    reqs = gen.c5_requests()[:count]
+    systems = []
+    for r in reqs:
+        systems.append(gen.c5_system(r))
+        log(f"  request {r['idx']}: n={systems[-1].n} nnz={systems[-1].nnz} blocks={r['nblocks']}")
+    o = sd.Options(precision=sd.FP32_IR, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
+                   pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
+    srv = Server(options=o, max_active=active)
+    srv.run([Request(s, 0.0, i) for i, s in enumerate(systems)])
+    closed = srv.stats()
+    log(f"  closed loop: {closed}")
+    mu = closed["solves_per_s"]
+    arr = gen.poisson_arrivals(count, 0.8 * mu)
+    srv2 = Server(options=o, max_active=active)
+    srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
+    open_ = srv2.stats()
+    log(f"  Poisson at 0.8 mu: {open_}")
+    return {"workload": f"C5: first {count} requests (rows log-uniform 1e4..5e5, 6-10 per column, D spread 1e8, "
+                        f"8-128 blocks)", "closed_loop": closed, "poisson_0.8mu": open_,
+            "rate_per_s": 0.8 * mu, "all_ok": closed["ok"] == count and open_["ok"] == count}
+
+
 def measured_traffic(which, mode):
     """HBM bytes per launch from the committed counter summary of this kernel
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
@@ -155,6 +183,9 @@ def main():
     ap.add_argument("--refine-delta", type=float, default=0.3)
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling run: only this many iterations per mode, no JSON line")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also run this many served C5 requests (closed loop, then Poisson at 0.8x that rate)")
+    ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="profiling run: first copy a buffer of this many bytes three times (counter scale)")
     args = ap.parse_args()
@@ -233,6 +264,7 @@ def main():
         cpu = cpu_baseline(system, fp64_its, args.cpu_seconds,
                            dict(mode=2, tau=1e-3, flags=2, delta=0.0, spd=True, policy=2, shift0=1e-2, border=True))
         log(f"  oracle: {cpu['value']:.5f} solves/s")
+    serving = run_serving(sd, torch, gen, args.serve, args.serve_active) if args.serve > 0 else None
     line = {
         "metric": METRIC, "value": round(r["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_solve"], 2),
@@ -244,7 +276,7 @@ def main():
                    "n": system.n, "nnz": system.nnz, "nblocks": system.nblocks, "mode": best},
         "p50_ms": round(r["p50_ms"], 2), "p99_ms": round(r["p99_ms"], 2),
         "hbm_gbps": round(r.get("spmv_gbps", 0.0), 1), "iterations": r["iterations"][-1],
-        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu,
+        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu, "serving": serving,
         "modes": {k: {kk: (float(f"{vv:.5g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in modes.items()},
     }

@@ -221,6 +221,20 @@ sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, in
 sdsl_status sdsl_solve_batch(int32_t k, const sdsl_handle* hs, const double* const* b,
                              double* const* x, double tol, int32_t* iters, double* relres);
 
+/* Asynchronous form of sdsl_solve for serving loops that keep several
+ * handles in flight.  sdsl_solve_begin starts the solve (same arguments and
+ * semantics as sdsl_solve; b and x must stay valid until sdsl_solve_end).
+ * sdsl_solve_step never waits for the device: while the handle's stream is
+ * still running earlier launches it returns at once with *done = 0;
+ * otherwise it takes the next step (reads the device state, launches the
+ * next batch of iterations) and sets *done = 1 once the solve has finished.
+ * sdsl_solve_end (only after *done = 1) returns the solve's status and its
+ * iterations and true relative residual.  One running solve per handle
+ * (SDSL_E_STATE otherwise).  The result equals that of sdsl_solve. */
+sdsl_status sdsl_solve_begin(sdsl_handle h, const double* b, double* x, double tol);
+sdsl_status sdsl_solve_step(sdsl_handle h, int32_t* done);
+sdsl_status sdsl_solve_end(sdsl_handle h, int32_t* iters, double* relres);
+
 sdsl_status sdsl_get_info(sdsl_handle h, sdsl_info* out);
 
 /* Last error message of h (or of the calling thread when h is NULL). */

@@ -87,6 +87,9 @@ SIGNATURES = {
     "sdsl_residual": (C.c_int, [H, P, P, P, C.POINTER(C.c_double)]),
     "sdsl_get_factors": (C.c_int, [H, P, P, P, P, P]),
     "sdsl_get_schur": (C.c_int, [H, P, P, P]),
+    "sdsl_solve_begin": (C.c_int, [H, P, P, C.c_double]),
+    "sdsl_solve_step": (C.c_int, [H, P]),
+    "sdsl_solve_end": (C.c_int, [H, P, P]),
 }
 
 _lib = None
@@ -223,6 +226,33 @@ class Solver:
         st = lib().sdsl_solve(self.h, _dptr(b), _dptr(x), tol, C.byref(its), C.byref(rr))
         if check and st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN):
             _check(self.h, st)
+        return x, its.value, rr.value, st
+
+    # -- asynchronous solve (serving loops)
+    def solve_begin(self, b, x, tol: float = 1e-8):
+        """Start M x = b without waiting; b and x (CUDA float64) must stay
+        alive until solve_end."""
+        import torch
+        assert b.is_cuda and b.dtype == torch.float64 and b.numel() == self.n and x.numel() == self.n
+        self._order()
+        self._async = (b, x)
+        _check(self.h, lib().sdsl_solve_begin(self.h, _dptr(b), _dptr(x), tol))
+
+    def solve_step(self) -> bool:
+        """Advance the running solve if its stream is idle; True once done."""
+        done = C.c_int32(0)
+        _check(self.h, lib().sdsl_solve_step(self.h, C.byref(done)))
+        return bool(done.value)
+
+    def solve_end(self):
+        """(x, iters, relres, status) of the finished solve."""
+        its = C.c_int32(0)
+        rr = C.c_double(0.0)
+        st = lib().sdsl_solve_end(self.h, C.byref(its), C.byref(rr))
+        if st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN):
+            _check(self.h, st)
+        x = self._async[1]
+        self._async = None
         return x, its.value, rr.value, st
 
     def _order(self):

@@ -40,8 +40,14 @@ double now_ms() {
 }  // namespace
 
 // -------------------------------------------------------------------- handle
+namespace {
+struct SolveTask;
+void delete_task(SolveTask* t);
+}  // namespace
+
 struct sdsl_ctx {
     hipStream_t s = nullptr;
+    SolveTask* task = nullptr;  // solve started by sdsl_solve_begin
     sdsl_options o{};
     int n = 0, n_int = 0, nbd = 0, nb = 0;
     int64_t nnz = 0;
@@ -134,6 +140,7 @@ struct sdsl_ctx {
     }
     ~sdsl_ctx() {
         if (s) (void)hipStreamSynchronize(s);
+        if (task) delete_task(task);
         for (void* a : allocs) (void)hipFree(a);
         if (st_h) (void)hipHostFree(st_h);
         if (scal_h) (void)hipHostFree(scal_h);
@@ -1051,6 +1058,8 @@ struct SolveTask {
     }
 };
 
+void delete_task(SolveTask* t) { delete t; }
+
 sdsl_status guard(sdsl_ctx* h, const std::function<void()>& fn) {
     try {
         fn();
@@ -1334,6 +1343,50 @@ sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, in
         if (iters) *iters = t.total_its;
         if (relres) *relres = t.relres;
         result = t.status;
+    });
+    if (st == SDSL_OK && result != SDSL_OK)
+        h->err = result == SDSL_E_BREAKDOWN ? "Krylov breakdown" : "tolerance not reached";
+    return st != SDSL_OK ? st : result;
+}
+
+sdsl_status sdsl_solve_begin(sdsl_handle h, const double* b, double* x, double tol) {
+    if (!h) return SDSL_E_INVALID;
+    return guard(h, [&] {
+        if (!b || !x) fail(SDSL_E_INVALID, "null vector");
+        if (!(tol > 0.0)) fail(SDSL_E_INVALID, "tol must be positive");
+        if (h->task && !h->task->finished) fail(SDSL_E_STATE, "a solve is already running on this handle");
+        if (h->task) delete_task(h->task);
+        h->task = new SolveTask();
+        h->task->begin(h, b, x, tol);
+    });
+}
+
+sdsl_status sdsl_solve_step(sdsl_handle h, int32_t* done) {
+    if (!h || !done) return SDSL_E_INVALID;
+    *done = 0;
+    return guard(h, [&] {
+        if (!h->task) fail(SDSL_E_STATE, "no solve was begun on this handle");
+        SolveTask& t = *h->task;
+        if (!t.finished) {
+            const hipError_t q = hipStreamQuery(h->s);
+            if (q == hipErrorNotReady) return;  // its launches are still running
+            if (q != hipSuccess) hip_check(q, "stream query");
+            t.step();
+        }
+        *done = t.finished ? 1 : 0;
+    });
+}
+
+sdsl_status sdsl_solve_end(sdsl_handle h, int32_t* iters, double* relres) {
+    if (!h) return SDSL_E_INVALID;
+    sdsl_status result = SDSL_OK;
+    sdsl_status st = guard(h, [&] {
+        if (!h->task || !h->task->finished) fail(SDSL_E_STATE, "the solve has not finished");
+        if (iters) *iters = h->task->total_its;
+        if (relres) *relres = h->task->relres;
+        result = h->task->status;
+        delete_task(h->task);
+        h->task = nullptr;
     });
     if (st == SDSL_OK && result != SDSL_OK)
         h->err = result == SDSL_E_BREAKDOWN ? "Krylov breakdown" : "tolerance not reached";

@@ -527,3 +527,46 @@ def test_bbd_rejects_block_coupling():
     with pytest.raises(sd.SdslError) as e:
         sd.from_system(s2, opts(**BBD_OPTS))
     assert e.value.status == sd.E_STRUCTURE
+
+
+# ------------------------------------------------------------------ serving
+
+def test_serving_mix_equals_alone():
+    """Continuous batching: requests of different sizes admitted while
+    others run, each on its own stream; every result is bitwise the one the
+    same request gets when solved alone."""
+    from paper_2604_23979_amd.serve import Request, Server
+    reqs = gen.c5_requests(count=6, seed=3, m_lo=3000, m_hi=30000)
+    systems = [gen.c5_system(r) for r in reqs]
+    o = opts(precision=sd.FP32_IR, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    alone = []
+    for s in systems:
+        sv = sd.from_system(s, o)
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        alone.append((x.cpu().numpy(), its, st))
+        sv.close()
+    srv = Server(options=o, tol=1e-8, max_active=4)
+    done = srv.run([Request(s, arrival=0.002 * i, tag=i) for i, s in enumerate(systems)])
+    stats = srv.stats()
+    print(f"  serving: {stats}")
+    assert stats["requests"] == len(systems) and stats["max_concurrency"] >= 2
+    for r in done:
+        xa, its_a, st_a = alone[r.tag]
+        assert r.status == st_a == sd.OK and r.iters == its_a
+        assert np.array_equal(r.x.cpu().numpy(), xa)
+        assert O.relres(systems[r.tag], xa) <= 1e-8
+
+
+def test_async_solve_equals_solve():
+    s = gen.c1()
+    sv = sd.from_system(s)
+    b = tdev(s.b)
+    x1, its1, rr1, st1 = sv.solve(b)
+    x2 = torch.empty_like(b)
+    sv.solve_begin(b, x2)
+    while not sv.solve_step():
+        pass
+    x2, its2, rr2, st2 = sv.solve_end()
+    assert st1 == st2 == sd.OK and its1 == its2 and rr1 == rr2
+    assert torch.equal(x1, x2)
+    sv.close()
