@@ -127,6 +127,59 @@ def run_serving(sd, torch, gen, count, active):
             "rate_per_s": 0.8 * mu, "all_ok": closed["ok"] == count and open_["ok"] == count}
 
 
+def run_ipm_sequence(sd, torch, gen, steps, rows):
+    """IPM sequence (C4): `steps` consecutive systems A D_k A^T + 1e-8 I on
+    one pattern, blocks of ~20k rows, GEOMEAN 1e-3 + DROPSUM, FP32-inner / FP64-refined
+    PCG; the preconditioner is refactored every 5 systems and reused (new
+    operator values only) in between.  Every returned solution is checked
+    with the oracle's compensated residual on the host."""
+    import oracle as O
+    t0 = time.time()
+    nblocks = max(1, int(round(rows / 20_312)))   # the full-size block height (5.2M rows / 256 blocks)
+    q = gen.IPMSequence(m=rows, nblocks=nblocks, steps=max(steps, 2),
+                        progress=lambda msg: log(f"  IPM sequence: {msg}"))
+    log(f"  IPM sequence: n={rows} nnz={q.col.shape[0]} built in {time.time() - t0:.1f} s")
+    o = sd.Options(precision=sd.FP32_IR, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
+                   pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
+    recs = []
+    sv = None
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for k in range(steps):
+        sk = q.system(k)
+        vals = torch.as_tensor(sk.val, device="cuda:0")
+        b = torch.as_tensor(sk.b, device="cuda:0")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if sv is None:
+            sv = sd.from_system(sk, o)
+            kind = "setup"
+        elif k % 5 == 0:
+            sv.refactor(vals)
+            kind = "refactor"
+        else:
+            sv.update_values(vals)
+            kind = "reuse"
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        x, its, rr, st = sv.solve(b, tol=1e-8)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        true_rr = O.relres(sk, x.cpu().numpy())
+        recs.append(dict(k=k, kind=kind, prep_ms=round(1e3 * (t2 - t1), 1), solve_ms=round(1e3 * (t3 - t2), 1),
+                         iterations=its, status=st, relres=true_rr))
+        log(f"  system {k} ({kind}): prep {1e3 * (t2 - t1):.0f} ms, {its} its, {1e3 * (t3 - t2):.0f} ms, "
+            f"status {st}, oracle relres {true_rr:.2e}")
+    total = time.perf_counter() - t_all
+    sv.close()
+    gpu_s = sum(r["prep_ms"] + r["solve_ms"] for r in recs) / 1e3
+    return {"workload": f"C4: {steps} systems, n={rows}, {nblocks} blocks of ~20k rows, refactor every 5",
+            "systems": recs,
+            "gpu_seconds": round(gpu_s, 3), "wall_seconds_incl_host_checks": round(total, 1),
+            "systems_per_s": round(steps / gpu_s, 4),
+            "all_converged": all(r["status"] == sd.OK and r["relres"] <= 1e-8 for r in recs)}
+
+
 def measured_traffic(which, mode):
     """HBM bytes per launch from the committed counter summary of this kernel
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
@@ -186,6 +239,9 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="also run this many served C5 requests (closed loop, then Poisson at 0.8x that rate)")
     ap.add_argument("--serve-active", type=int, default=8)
+    ap.add_argument("--c4", type=int, default=0,
+                    help="also run the IPM sequence (this many systems, refactor every 5) at --c4-rows rows")
+    ap.add_argument("--c4-rows", type=int, default=520_000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="profiling run: first copy a buffer of this many bytes three times (counter scale)")
     args = ap.parse_args()
@@ -265,6 +321,7 @@ def main():
                            dict(mode=2, tau=1e-3, flags=2, delta=0.0, spd=True, policy=2, shift0=1e-2, border=True))
         log(f"  oracle: {cpu['value']:.5f} solves/s")
     serving = run_serving(sd, torch, gen, args.serve, args.serve_active) if args.serve > 0 else None
+    ipm_seq = run_ipm_sequence(sd, torch, gen, args.c4, args.c4_rows) if args.c4 > 0 else None
     line = {
         "metric": METRIC, "value": round(r["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_solve"], 2),
@@ -276,7 +333,7 @@ def main():
                    "n": system.n, "nnz": system.nnz, "nblocks": system.nblocks, "mode": best},
         "p50_ms": round(r["p50_ms"], 2), "p99_ms": round(r["p99_ms"], 2),
         "hbm_gbps": round(r.get("spmv_gbps", 0.0), 1), "iterations": r["iterations"][-1],
-        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu, "serving": serving,
+        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu, "serving": serving, "ipm_sequence": ipm_seq,
         "modes": {k: {kk: (float(f"{vv:.5g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in modes.items()},
     }

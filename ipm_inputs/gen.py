@@ -335,18 +335,21 @@ class IPMSequence:
     """
 
     def __init__(self, m: int = 5_200_000, ratio: float = 1.6, c: int = 4, nblocks: int = 256,
-                 steps: int = 30, seed: int = 0, model: str = "loc"):
+                 steps: int = 30, seed: int = 0, model: str = "loc", progress=None):
+        say = progress or (lambda msg: None)
         r_pat, r_val, r_d, r_b, _, _ = streams(seed)
         self.m, self.steps, self.nblocks = m, steps, nblocks
         n_a = int(round(ratio * m))
         self.n_a = n_a
         col_ptr, rows = a_pattern(r_pat, m, n_a, c, model)
+        say(f"pattern of A: {rows.shape[0]} nonzeros")
         vals = r_val.standard_normal(rows.shape[0])
         A = sp.csc_matrix((vals, rows, col_ptr), shape=(m, n_a))
         # pattern of M (upper triangle incl. diagonal) via a structural product
         M0 = normal_equations(A, np.ones(n_a))
         self.row_ptr = M0.indptr.astype(np.int64)
         self.col = M0.indices.astype(np.int32)
+        say(f"pattern of M: {self.col.shape[0]} nonzeros")
         n = m
         nnz = self.col.shape[0]
         rows_of = np.repeat(np.arange(n, dtype=np.int64), np.diff(self.row_ptr))
@@ -377,6 +380,7 @@ class IPMSequence:
         pos[order] = pos_s
         del key_start, starts, keys
         self.G = sp.csr_matrix((np.concatenate(gv), (pos, np.concatenate(gk))), shape=(nnz, n_a))
+        say(f"value map G: {self.G.nnz} entries")
         self.is_diag = (rows_of == self.col.astype(np.int64))
         # mirror map: lower entries copy their transposed upper entry
         lower = np.nonzero(rows_of > self.col)[0]

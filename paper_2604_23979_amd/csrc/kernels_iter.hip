@@ -878,29 +878,30 @@ __device__ __forceinline__ void stage_commit(const int (&pc)[kPer], const F (&pv
     }
 }
 
-// Take the terms [pos, lim) of one row, four at a time, while their slots
+// Take the terms [pos, lim) of one row, eight at a time, while their slots
 // hold final values; returns with pos at the first pending term (or lim).
 template <typename F, typename Bits>
 __device__ __forceinline__ void take_ready(int& pos, int lim, F& acc, const int* scol, const F* sval,
                                            const Bits* ring, int lo) {
     constexpr Bits SENT = Sentinel<F>::bits;
+    constexpr int W = 8;
     bool blocked = false;
     while (pos < lim && !blocked) {
-        int jj[4];
-        F ww[4];
-        Bits raw[4];
+        int jj[W];
+        F ww[W];
+        Bits raw[W];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < W; ++u) {
             const int e = min(pos + u, lim - 1);
             jj[u] = scol[e];
             ww[u] = sval[e];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < W; ++u)
             raw[u] = __hip_atomic_load(&ring[(jj[u] - lo) & (kRing - 1)], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < W; ++u) {
             const bool take = !blocked && (pos < lim) && (raw[u] != SENT);
             acc = take ? acc - ww[u] * from_bits<F>(raw[u]) : acc;
             blocked = blocked || !take;
