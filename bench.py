@@ -99,32 +99,39 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol):
     return res
 
 
-def run_serving(sd, torch, gen, count, active):
+def run_serving(sd, torch, gen, count, active, modes):
     """Served C5 stream: the first `count` requests of the seeded stream
-    (built before timing), solved FP32-inner / FP64-refined to 1e-8 with the
-    C2 filter.  First all at t = 0 (saturated: the service rate mu), then
-    with Poisson arrivals at 0.8 mu; latency = arrival to completion."""
+    (built before timing), solved to 1e-8 with the C2 filter in each of
+    `modes`.  Per mode all requests arrive at t = 0 (saturated: the service
+    rate mu); the first mode is run again with Poisson arrivals at 0.8 mu.
+    Latency = arrival to completion."""
     from paper_2604_23979_amd.serve import Request, Server
     reqs = gen.c5_requests()[:count]
     systems = []
     for r in reqs:
         systems.append(gen.c5_system(r))
         log(f"  request {r['idx']}: n={systems[-1].n} nnz={systems[-1].nnz} blocks={r['nblocks']}")
-    o = sd.Options(precision=sd.FP32_IR, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
-                   pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
-    srv = Server(options=o, max_active=active)
-    srv.run([Request(s, 0.0, i) for i, s in enumerate(systems)])
-    closed = srv.stats()
-    log(f"  closed loop: {closed}")
-    mu = closed["solves_per_s"]
-    arr = gen.poisson_arrivals(count, 0.8 * mu)
-    srv2 = Server(options=o, max_active=active)
-    srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
-    open_ = srv2.stats()
-    log(f"  Poisson at 0.8 mu: {open_}")
-    return {"workload": f"C5: first {count} requests (rows log-uniform 1e4..5e5, 6-10 per column, D spread 1e8, "
-                        f"8-128 blocks)", "closed_loop": closed, "poisson_0.8mu": open_,
-            "rate_per_s": 0.8 * mu, "all_ok": closed["ok"] == count and open_["ok"] == count}
+    prec = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR}
+    out = {"workload": f"C5: first {count} requests (rows log-uniform 1e4..5e5, 6-10 per column, D spread 1e8, "
+                       f"8-128 blocks)", "closed_loop": {}}
+    for mode in modes:
+        o = sd.Options(precision=prec[mode], filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
+                       pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
+        srv = Server(options=o, max_active=active)
+        srv.run([Request(s, 0.0, i) for i, s in enumerate(systems)])
+        st = srv.stats()
+        st["iterations"] = int(sum(r.iters for r in srv.done))
+        out["closed_loop"][mode] = st
+        log(f"  closed loop {mode}: {st}")
+        if mode == modes[0]:
+            mu = st["solves_per_s"]
+            arr = gen.poisson_arrivals(count, 0.8 * mu)
+            srv2 = Server(options=o, max_active=active)
+            srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
+            out["poisson_0.8mu"] = dict(srv2.stats(), mode=mode, rate_per_s=0.8 * mu)
+            log(f"  Poisson at 0.8 mu ({mode}): {out['poisson_0.8mu']}")
+    out["all_ok"] = all(v["ok"] == count for v in out["closed_loop"].values())
+    return out
 
 
 def run_ipm_sequence(sd, torch, gen, steps, rows):
@@ -239,6 +246,8 @@ def main():
     ap.add_argument("--serve", type=int, default=0,
                     help="also run this many served C5 requests (closed loop, then Poisson at 0.8x that rate)")
     ap.add_argument("--serve-active", type=int, default=8)
+    ap.add_argument("--serve-modes", default="fp32ir,fp64",
+                    help="precisions of the served stream (the first also gets the Poisson run)")
     ap.add_argument("--c4", type=int, default=0,
                     help="also run the IPM sequence (this many systems, refactor every 5) at --c4-rows rows")
     ap.add_argument("--c4-rows", type=int, default=520_000)
@@ -320,7 +329,8 @@ def main():
         cpu = cpu_baseline(system, fp64_its, args.cpu_seconds,
                            dict(mode=2, tau=1e-3, flags=2, delta=0.0, spd=True, policy=2, shift0=1e-2, border=True))
         log(f"  oracle: {cpu['value']:.5f} solves/s")
-    serving = run_serving(sd, torch, gen, args.serve, args.serve_active) if args.serve > 0 else None
+    serving = (run_serving(sd, torch, gen, args.serve, args.serve_active, args.serve_modes.split(","))
+               if args.serve > 0 else None)
     ipm_seq = run_ipm_sequence(sd, torch, gen, args.c4, args.c4_rows) if args.c4 > 0 else None
     line = {
         "metric": METRIC, "value": round(r["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
