@@ -192,6 +192,18 @@ struct BJDev {
     const int* ulev;  // per-row level inside its backward chunk
     const int* lnl;   // levels per forward chunk (chunk-table indexing)
     const int* unl;   // levels per backward chunk
+    const int* lell_c;   // chunk-interleaved newest entries of L rows (k_bj_ell)
+    const void* lell_v;  // their values (factor type)
+    const int* uell_c;   // the same for U rows
+    const void* uell_v;
+    const int* lorp;     // older entries of L rows (all but the newest kBjEllWidth): CSR
+    const int* loci;
+    const void* lov;     // their values (factor type)
+    const int* uorp;     // the same for U rows
+    const int* uoci;
+    const void* uov;
+    const int* lperm;    // row solved by each thread of a forward chunk (level order)
+    const int* uperm;    // the same for backward chunks
 };
 
 // MODE 0: z = P^{-1} r.  MODE 1: PCG step (alpha from partials, x/r update,
@@ -265,10 +277,16 @@ void launch_bbd_mid(const TailDev& T, int nblocks, int max_nf, int nbd, const do
                     const int* fidx, double* gpart, const double* rb, double* g, double* w, double* xb,
                     hipStream_t s);
 constexpr int kLuPanel = 64;
+void launch_bj_ell(int nblocks, const int* bp, const int* rp, const int* ci, const double* val, const int* pos,
+                   bool fwd, int* ec, double* ev64, float* ev32, hipStream_t s);
+constexpr int kBjEllWidth = 24;  // entries per row in the interleaved copies
+void launch_bj_old(int n, const int* rp, const int* ci, const double* val, int* cnt, int* tmp, int* orp, int* oci,
+                   double* ov64, float* ov32, hipStream_t s);
 void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp, int2* lch, int2* uch,
                       hipStream_t s);
 void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci, const int* urp, const int* uci,
-                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, hipStream_t s);
+                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, int* lperm,
+                      int* uperm, int* lpos, int* upos, hipStream_t s);
 
 template <typename T>
 void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, const BorderDev& bd, KrylovState* st, int it,

@@ -696,28 +696,41 @@ void launch_scale_inv_norm(int n, const double* nrm2, const double* w, double* v
 // ------------------------------------------------------------------ BJ apply
 // One workgroup per diagonal block (all blocks in one launch).  Forward
 // substitution y = L^{-1} r then backward substitution z = U^{-1} y, each
-// over chunks of at most kBjThreads consecutive rows, one row per thread.
-// The chunk partition and the level of every row inside its chunk are fixed
-// by the factor's pattern and built once per factorisation (k_bj_chunks,
-// k_bj_levels): a chunk is the longest run of rows whose factor entries fit
-// the LDS stage (kStage entries); a single row that does not fit is a chunk
-// of its own and reads its entries from memory.  While a chunk is solved,
-// the next chunk's entries and row data are already in flight into
-// registers, so each chunk costs about one memory round trip.
-// The block's most recent kRing solution values live in an LDS ring (slot =
-// local row mod kRing).  Per row, the terms on earlier chunks (final: in the
-// ring, or in memory once evicted) are taken in one straight pass at the
-// start of the chunk; the same-chunk terms wait for the row's level: levels
+// over chunks of kBjThreads consecutive rows, one row per thread: forward
+// chunks are cut from the top of the block, backward chunks from the bottom.
+// The level of every row inside its chunk is fixed by the factor's pattern
+// and built once per factorisation (k_bj_levels).
+// Factor entries: the newest kEll entries of a row (those nearest the
+// diagonal) sit in a chunk-interleaved copy (k_bj_ell) that is read with
+// coalesced loads straight into registers one chunk ahead; the older
+// entries of longer rows sit in a CSR of their own whose range for a whole
+// chunk is contiguous, and are staged into LDS with coalesced loads, also
+// one chunk ahead.
+// The block's most recent solution values live in an LDS ring (slot = local
+// row mod ring size); older values are read from memory.  At the start of a
+// chunk every row subtracts, in one straight pass, its terms on earlier
+// chunks (all final); the same-chunk terms wait for the row's level: levels
 // are separated by workgroup barriers, so at its level every term of a row
-// is final.  Terms are always subtracted in ascending column order with a
-// separate product and difference, the order of a plain substitution.  The
-// solve runs in the factor type F (FP32 factors: FP32 arithmetic); vectors
-// have type V.
+// is final.  Those terms are prepared at the start of the chunk as (ring
+// offset, weight) pairs, so that a level runs without branches; unused
+// pairs point at a zero slot with a zero weight, which leaves the sum
+// unchanged.  Terms are subtracted in the order of a plain substitution
+// (forward: ascending columns, backward: descending), each with a separate
+// product and difference.  The solve runs in the factor type F (FP32
+// factors: FP32 arithmetic); vectors have type V.
 constexpr int kBjThreads = 512;
-constexpr int kRing = 4096;
-constexpr int kStage = 8192;
-constexpr int kPer = kStage / kBjThreads;
-constexpr int kTab = 128;  // chunk-table entries per sweep cached in LDS
+constexpr int kEll = kBjEllWidth;
+constexpr int kHeld = 8;                   // newest slots kept in registers through the levels
+constexpr int kPark = kEll - kHeld;        // the others, parked in LDS
+constexpr int kStageOld = 2 * kBjThreads;  // older entries of a chunk staged in LDS
+constexpr int kOldLevel = 4;               // level at which the next chunk's older entries load
+constexpr int kTab = 128;                  // per-chunk level counts cached in LDS
+// solution values kept in LDS per block (FP64 solves leave room for the
+// parked FP64 weights)
+template <typename F>
+struct BjRing {
+    static constexpr int size = sizeof(F) == 8 ? 4096 : 8192;
+};
 
 template <typename T>
 __device__ __forceinline__ T from_bits(typename Sentinel<T>::Bits b) {
@@ -732,40 +745,38 @@ __device__ __forceinline__ typename Sentinel<T>::Bits to_bits(T v) {
     return b;
 }
 
-// Chunk tables of block b, both with room for hi - lo + 1 entries at offset
-// lo + b: lch[m] = {first row of forward chunk m, lrp[that row]} with
-// lch[nch] = {hi, lrp[hi]}; uch[m] = {end row of backward chunk m, urp[that
-// row]} from uch[0] = {hi, urp[hi]} down to {lo, urp[lo]}.
-__global__ __launch_bounds__(kBjThreads) void k_bj_chunks(const int* __restrict__ bp, const int* __restrict__ lrp,
-                                                          const int* __restrict__ urp, int2* __restrict__ lch,
-                                                          int2* __restrict__ uch) {
-    const int b = blockIdx.x, t = threadIdx.x;
+// Rows [ca, cb) of sweep chunk m of the block [lo, hi).
+template <bool FWD>
+__device__ __forceinline__ void bj_chunk(int lo, int hi, int m, int& ca, int& cb) {
+    if (FWD) {
+        ca = lo + m * kBjThreads;
+        cb = min(hi, ca + kBjThreads);
+    } else {
+        cb = hi - m * kBjThreads;
+        ca = max(lo, cb - kBjThreads);
+    }
+}
+
+// Chunk tables of block b in the layout k_bj_levels reads, both with room
+// for hi - lo + 1 entries at offset lo + b: lch[m] = {first row of forward
+// chunk m, lrp[that row]}, lch[nch] = {hi, lrp[hi]}; uch[m] = {end row of
+// backward chunk m, urp[that row]} from {hi, urp[hi]} down to {lo, urp[lo]}.
+__global__ __launch_bounds__(256) void k_bj_chunks(const int* __restrict__ bp, const int* __restrict__ lrp,
+                                                   const int* __restrict__ urp, int2* __restrict__ lch,
+                                                   int2* __restrict__ uch) {
+    const int b = blockIdx.x;
     const int lo = bp[b], hi = bp[b + 1];
-    int2* L = lch + lo + b;
-    int2* U = uch + lo + b;
-    int m = 0;
-    for (int c0 = lo; c0 < hi; ++m) {
-        if (t == 0) L[m] = make_int2(c0, lrp[c0]);
-        const int ebase = lrp[c0];
-        const bool fits = (c0 + t < hi) && (lrp[c0 + t + 1] - ebase <= kStage);
-        const int nrows = __syncthreads_count(fits);
-        c0 += nrows > 0 ? nrows : 1;
+    const int nch = (hi - lo + kBjThreads - 1) / kBjThreads;
+    for (int m = threadIdx.x; m <= nch; m += blockDim.x) {
+        const int a = min(hi, lo + m * kBjThreads);
+        lch[lo + b + m] = make_int2(a, lrp[a]);
+        const int e = max(lo, hi - m * kBjThreads);
+        uch[lo + b + m] = make_int2(e, urp[e]);
     }
-    if (t == 0) L[m] = make_int2(hi, lrp[hi]);
-    m = 0;
-    for (int c_hi = hi; c_hi > lo; ++m) {
-        if (t == 0) U[m] = make_int2(c_hi, urp[c_hi]);
-        const int top = urp[c_hi];
-        const int rowt = c_hi - 1 - t;
-        const bool fits = (rowt >= lo) && (top - urp[rowt] <= kStage);
-        const int nrows = __syncthreads_count(fits);
-        c_hi -= nrows > 0 ? nrows : 1;
-    }
-    if (t == 0) U[m] = make_int2(lo, urp[lo]);
 }
 void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp, int2* lch, int2* uch,
                       hipStream_t s) {
-    if (nblocks > 0) k_bj_chunks<<<nblocks, kBjThreads, 0, s>>>(bp, lrp, urp, lch, uch);
+    if (nblocks > 0) k_bj_chunks<<<nblocks, 256, 0, s>>>(bp, lrp, urp, lch, uch);
 }
 
 // Local levels of the rows of every chunk: level(i) = 0 if row i has no
@@ -775,13 +786,20 @@ void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp
 // number of levels per chunk (same indexing as the chunk tables).  Computed
 // in rounds: a row gets its level once all its same-chunk dependencies have
 // one; a chain of r rows needs r rounds and at most nrows rounds are run.
+// The sweeps give the rows of a chunk to threads in level order, so that
+// the rows of one level share as few wavefronts as possible: lperm/uperm
+// hold, at the chunk's first row + p, the row solved by thread p, and
+// lpos/upos the inverse (inside a level, rows keep their chunk order).
 __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict__ bp, const int* __restrict__ lrp,
                                                           const int* __restrict__ lci, const int* __restrict__ urp,
                                                           const int* __restrict__ uci, const int2* __restrict__ lch,
                                                           const int2* __restrict__ uch, int* __restrict__ llev,
                                                           int* __restrict__ ulev, int* __restrict__ lnl,
-                                                          int* __restrict__ unl) {
+                                                          int* __restrict__ unl, int* __restrict__ lperm,
+                                                          int* __restrict__ uperm, int* __restrict__ lpos,
+                                                          int* __restrict__ upos) {
     __shared__ int slev[kBjThreads];
+    __shared__ int hist[kBjThreads];
     __shared__ int smax;
     const int b = blockIdx.x, t = threadIdx.x;
     const int lo = bp[b], hi = bp[b + 1];
@@ -792,6 +810,8 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
         const int* rp = dir == 0 ? lrp : urp;
         const int* ci = dir == 0 ? lci : uci;
         int* lev = dir == 0 ? llev : ulev;
+        int* perm = dir == 0 ? lperm : uperm;
+        int* pos = dir == 0 ? lpos : upos;
         int* nl = (dir == 0 ? lnl : unl) + lo + b;
         const int end = dir == 0 ? hi : lo;
         for (int m = 0; T[m].x != end; ++m) {
@@ -813,7 +833,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
                     while (f > q0 && ci[f - 1] < a) --f;
                 q0 = f;
             }
-            if (t < kBjThreads) slev[t] = -1;
+            slev[t] = -1;
             if (t == 0) smax = 0;
             __syncthreads();
             int mine = live ? -1 : 0;
@@ -835,177 +855,407 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
                 }
                 if (__syncthreads_count(mine < 0) == 0) break;
             }
+            hist[t] = 0;
+            __syncthreads();
             if (live) {
                 lev[i] = mine;
                 atomicMax(&smax, mine + 1);
+                atomicAdd(&hist[mine], 1);
             }
             __syncthreads();
-            if (t == 0) nl[m] = smax;
+            if (t == 0) {
+                nl[m] = smax;
+                int run = 0;
+                for (int l = 0; l < smax; ++l) {
+                    const int c = hist[l];
+                    hist[l] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            if (live) {
+                // rank inside the level: the threads before this one with
+                // the same level (a stable order, the same in every setup)
+                int rank = 0;
+                for (int q = 0; q < t; ++q) rank += slev[q] == mine ? 1 : 0;
+                const int first = dir == 0 ? a : e;  // lowest row of the chunk
+                const int p = hist[mine] + rank;
+                perm[first + p] = i;
+                pos[i] = p;
+            }
             __syncthreads();
         }
     }
 }
 void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci, const int* urp, const int* uci,
-                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, hipStream_t s) {
+                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, int* lperm,
+                      int* uperm, int* lpos, int* upos, hipStream_t s) {
     if (nblocks > 0)
-        k_bj_levels<<<nblocks, kBjThreads, 0, s>>>(bp, lrp, lci, urp, uci, lch, uch, llev, ulev, lnl, unl);
+        k_bj_levels<<<nblocks, kBjThreads, 0, s>>>(bp, lrp, lci, urp, uci, lch, uch, llev, ulev, lnl, unl, lperm,
+                                                   uperm, lpos, upos);
 }
 
-// Issue the loads of a chunk's entries [ebase, ebase + nst) into registers
-// (entry t + u * kBjThreads goes to slot u); commit writes them to LDS.
-template <typename F>
-__device__ __forceinline__ void stage_issue(int (&pc)[kPer], F (&pv)[kPer], const int* __restrict__ ci,
-                                            const F* __restrict__ val, int ebase, int nst, int t) {
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = t + u * kBjThreads;
-        if (e < nst) {
-            pc[u] = ci[ebase + e];
-            pv[u] = val[ebase + e];
+// Chunk-interleaved copy of the newest kEll entries of every row of one
+// triangle, right-aligned: slot u of the row at position t of its chunk
+// [ca, cb) (t = pos[row], the thread that solves it) sits at
+// ca * kEll + u * (cb - ca) + t (the chunk's slab is [ca, cb) * kEll) and
+// holds the row's entry kEll - u from its end, so slot kEll - 1 is the
+// entry nearest the diagonal; in FP64 and rounded to FP32.  Empty slots
+// (below kEll - row length) hold a column no sweep takes before the row's
+// level (forward: the row itself; backward: the row itself) and weight 0.
+__global__ __launch_bounds__(256) void k_bj_ell(const int* __restrict__ bp, const int* __restrict__ rp,
+                                                const int* __restrict__ ci, const double* __restrict__ val,
+                                                const int* __restrict__ pos, int fwd, int* __restrict__ ec,
+                                                double* __restrict__ ev64, float* __restrict__ ev32) {
+    const int b = blockIdx.x;
+    const int lo = bp[b], hi = bp[b + 1];
+    for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
+        int ca, cb;
+        if (fwd)
+            bj_chunk<true>(lo, hi, (i - lo) / kBjThreads, ca, cb);
+        else
+            bj_chunk<false>(lo, hi, (hi - 1 - i) / kBjThreads, ca, cb);
+        const int nrows = cb - ca;
+        const int r1 = rp[i + 1];
+        const int nh = min(r1 - rp[i], kEll);
+        const int64_t base = (int64_t)ca * kEll + pos[i];
+        for (int u = 0; u < kEll - nh; ++u) {
+            const int64_t at = base + (int64_t)u * nrows;
+            ec[at] = i;
+            ev64[at] = 0.0;
+            ev32[at] = 0.0f;
+        }
+        for (int u = kEll - nh; u < kEll; ++u) {
+            const int64_t at = base + (int64_t)u * nrows;
+            const int e = r1 - kEll + u;
+            const double w = val[e];
+            ec[at] = ci[e];
+            ev64[at] = w;
+            ev32[at] = (float)w;
         }
     }
 }
-template <typename F>
-__device__ __forceinline__ void stage_commit(const int (&pc)[kPer], const F (&pv)[kPer], int* scol, F* sval, int nst,
-                                             int t) {
+void launch_bj_ell(int nblocks, const int* bp, const int* rp, const int* ci, const double* val, const int* pos,
+                   bool fwd, int* ec, double* ev64, float* ev32, hipStream_t s) {
+    if (nblocks > 0) k_bj_ell<<<nblocks, 256, 0, s>>>(bp, rp, ci, val, pos, fwd ? 1 : 0, ec, ev64, ev32);
+}
+
+// Count and copy of the older entries of every row of one triangle (all
+// but the newest kEll, in stored order) into a CSR of their own (orp, oci,
+// ov64/ov32), so that the older entries of a chunk's rows are one
+// contiguous range.
+__global__ __launch_bounds__(256) void k_bj_old_count(int n, const int* __restrict__ rp, int* __restrict__ cnt) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) cnt[i] = max(0, rp[i + 1] - rp[i] - kEll);
+}
+__global__ __launch_bounds__(256) void k_bj_old_copy(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const double* __restrict__ val, const int* __restrict__ orp,
+                                                     int* __restrict__ oci, double* __restrict__ ov64,
+                                                     float* __restrict__ ov32) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int r0 = rp[i], o0 = orp[i], no = orp[i + 1] - o0;
+    for (int k = 0; k < no; ++k) {
+        oci[o0 + k] = ci[r0 + k];
+        ov64[o0 + k] = val[r0 + k];
+        ov32[o0 + k] = (float)val[r0 + k];
+    }
+}
+void launch_bj_old(int n, const int* rp, const int* ci, const double* val, int* cnt, int* tmp, int* orp, int* oci,
+                   double* ov64, float* ov32, hipStream_t s) {
+    const int g = (n + 255) / 256;
+    if (n > 0) k_bj_old_count<<<g, 256, 0, s>>>(n, rp, cnt);
+    launch_scan(n, cnt, orp, tmp, s);
+    if (n > 0) k_bj_old_copy<<<g, 256, 0, s>>>(n, rp, ci, val, orp, oci, ov64, ov32);
+}
+
+// What a thread holds of its row in a chunk, loaded one chunk ahead.
+template <typename V, typename F>
+struct BjRow {
+    int ec[kEll];  // newest entries (ELL copy, right-aligned)
+    F ev[kEll];
+    int len;       // entries in the row
+    int o0;        // first older entry (older CSR)
+    int obase;     // first older entry of the chunk
+    int ocnt;      // older entries of the chunk
+    F a0;          // r_i (forward) or y_i (backward)
+    F dg;          // u_ii (backward)
+    V rr;          // r_i for (r, z) (backward, MODE 1/2)
+    int lev;       // level inside the chunk
+    int i;         // the row
+};
+
+// Row solved by thread t in chunk m (any row of the chunk for a thread past
+// its end).
+template <bool FWD>
+__device__ __forceinline__ int bj_row(const BJDev& P, int lo, int hi, int m, int t) {
+    int ca, cb;
+    bj_chunk<FWD>(lo, hi, m, ca, cb);
+    return (FWD ? P.lperm : P.uperm)[ca + min(t, cb - ca - 1)];
+}
+
+// Issue the loads of thread t's row i of chunk m.
+template <bool FWD, int MODE, typename V, typename F>
+__device__ __forceinline__ void bj_load(BjRow<V, F>& R, const BJDev& P, const V* rin, const F* y, int lo, int hi,
+                                        int m, int t, int i) {
+    int ca, cb;
+    bj_chunk<FWD>(lo, hi, m, ca, cb);
+    const int nrows = cb - ca;
+    R.i = i;
+    const int* __restrict__ rp = FWD ? P.lrp : P.urp;
+    const int* __restrict__ orp = FWD ? P.lorp : P.uorp;
+    const int* __restrict__ ec = FWD ? P.lell_c : P.uell_c;
+    const F* __restrict__ ev = (const F*)(FWD ? P.lell_v : P.uell_v);
+    R.obase = orp[ca];
+    R.ocnt = orp[cb] - R.obase;
+    if (t < nrows) {
+        R.len = rp[i + 1] - rp[i];
+        R.o0 = orp[i];
+        const unsigned base = (unsigned)ca * kEll + t;  // the copies hold fewer than 2^31 entries
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int e = t + u * kBjThreads;
-        if (e < nst) {
-            scol[e] = pc[u];
-            sval[e] = pv[u];
+        for (int u = 0; u < kEll; ++u) {
+            R.ec[u] = ec[base + (unsigned)(u * nrows)];
+            R.ev[u] = ev[base + (unsigned)(u * nrows)];
         }
+        R.lev = FWD ? P.llev[i] : P.ulev[i];
+        if (FWD) {
+            R.a0 = (F)rin[i];
+        } else {
+            R.a0 = y[i];
+            R.dg = ((const F*)P.udiag)[i];
+            if (MODE == 1 || MODE == 2) R.rr = rin[i];
+        }
+    } else {
+        R.len = 0;
+        R.o0 = 0;
+        R.lev = -1;
     }
 }
 
-// Take the terms [pos, lim) of one row, eight at a time, while their slots
-// hold final values; returns with pos at the first pending term (or lim).
-template <typename F, typename Bits>
-__device__ __forceinline__ void take_ready(int& pos, int lim, F& acc, const int* scol, const F* sval,
-                                           const Bits* ring, int lo) {
+// Solution value of row j from the ring or, when it has left the ring,
+// from memory (forward: y; backward: z).
+template <bool FWD, int RING, typename V, typename F, typename Bits>
+__device__ __forceinline__ F bj_value(int j, bool inring, const Bits* ring, int lo, const F* y, const V* z) {
+    if (inring) return from_bits<F>(ring[(j - lo) & (RING - 1)]);
+    return FWD ? y[j] : (F)z[j];
+}
+
+template <bool FWD, int MODE, typename V, typename F>
+__device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* z, int lo, int hi, int t,
+                                         typename Sentinel<F>::Bits* ring, int* pka, F* pkw, int* soc, F* sov,
+                                         const int* nltab, const int* nlg, double& rz, int& bad) {
+    using Bits = typename Sentinel<F>::Bits;
     constexpr Bits SENT = Sentinel<F>::bits;
-    constexpr int W = 8;
-    bool blocked = false;
-    while (pos < lim && !blocked) {
-        int jj[W];
-        F ww[W];
-        Bits raw[W];
+    constexpr int RING = BjRing<F>::size;
+    constexpr unsigned ZOFF = RING * sizeof(Bits);  // byte offset of the ring's zero slot
+    const int nch = (hi - lo + kBjThreads - 1) / kBjThreads;
+    const int* __restrict__ oci = FWD ? P.loci : P.uoci;
+    const F* __restrict__ oval = (const F*)(FWD ? P.lov : P.uov);
+    const char* rbase = (const char*)ring;
+    auto rd = [&](unsigned off) { return from_bits<F>(*(const Bits*)(rbase + off)); };
+    BjRow<V, F> nx, cu;
+    int sc[kStageOld / kBjThreads];
+    F sv[kStageOld / kBjThreads];
+    // row indices run one chunk ahead of the row loads
+    bj_load<FWD, MODE>(nx, P, rin, y, lo, hi, 0, t, bj_row<FWD>(P, lo, hi, 0, t));
+    int inext = bj_row<FWD>(P, lo, hi, min(1, nch - 1), t);
+    auto stage_load = [&]() {
 #pragma unroll
-        for (int u = 0; u < W; ++u) {
-            const int e = min(pos + u, lim - 1);
-            jj[u] = scol[e];
-            ww[u] = sval[e];
-        }
-#pragma unroll
-        for (int u = 0; u < W; ++u)
-            raw[u] = __hip_atomic_load(&ring[(jj[u] - lo) & (kRing - 1)], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-        for (int u = 0; u < W; ++u) {
-            const bool take = !blocked && (pos < lim) && (raw[u] != SENT);
-            acc = take ? acc - ww[u] * from_bits<F>(raw[u]) : acc;
-            blocked = blocked || !take;
-            pos += take ? 1 : 0;
-        }
-    }
-}
-
-// Subtract the terms [q0, q1) of a row whose solution slots are final, in
-// order, four loads in flight; a slot still holding the sentinel means the
-// level table does not match the factor and sets `bad`.
-template <typename F, typename Bits>
-__device__ __forceinline__ F take_final(int q0, int q1, F acc, const int* scol, const F* sval, const Bits* ring,
-                                        int lo, int& bad) {
-    constexpr Bits SENT = Sentinel<F>::bits;
-    for (int q = q0; q < q1; q += 4) {
-        int jj[4];
-        F ww[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = min(q + u, q1 - 1);
-            jj[u] = scol[e];
-            ww[u] = sval[e];
-        }
-        Bits raw[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) raw[u] = ring[(jj[u] - lo) & (kRing - 1)];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (q + u < q1) {
-                bad |= raw[u] == SENT;
-                acc = acc - ww[u] * from_bits<F>(raw[u]);
+        for (int k = 0; k < kStageOld / kBjThreads; ++k) {
+            const int e = t + k * kBjThreads;
+            if (e < nx.ocnt) {
+                sc[k] = oci[nx.obase + e];
+                sv[k] = oval[nx.obase + e];
             }
         }
-    }
-    return acc;
-}
-
-// The same-chunk terms of a row (the tail of its entries) are held in
-// registers, kHold of them, from the start of the chunk; at the row's level
-// their slots are read in one round.
-constexpr int kHold = 8;
-template <typename F>
-__device__ __forceinline__ void hold_terms(int (&cj)[kHold], F (&cw)[kHold], int pos, int lim, const int* scol,
-                                           const F* sval) {
+    };
+    stage_load();
+    for (int m = 0; m < nch; ++m) {
+        cu = nx;
+        int ca, cb;
+        bj_chunk<FWD>(lo, hi, m, ca, cb);
+        const bool live = t < cb - ca;
+        const int i = cu.i;
+        // rows whose values are in the ring: forward [cb - RING, cb),
+        // backward [ca, ca + RING); earlier chunks: forward j < ca,
+        // backward j >= cb
+        const int ring_edge = FWD ? cb - RING : ca + RING;
+        const bool all_ring = FWD ? ring_edge <= lo : ring_edge >= hi;
+        auto in_ring = [&](int j) { return FWD ? j >= ring_edge : j < ring_edge; };
+        auto earlier = [&](int j) { return FWD ? j < ca : j >= cb; };
+        auto roff = [&](int j) { return (unsigned)((j - lo) & (RING - 1)) * (unsigned)sizeof(Bits); };
+        // the chunk's older entries go to LDS
+        if (cu.ocnt > 0) {
 #pragma unroll
-    for (int u = 0; u < kHold; ++u) {
-        const int e = min(pos + u, lim - 1);
-        cj[u] = scol[e];
-        cw[u] = sval[e];
-    }
-}
-template <typename F, typename Bits>
-__device__ __forceinline__ F take_held(const int (&cj)[kHold], const F (&cw)[kHold], int n, F acc, const Bits* ring,
-                                       int lo, int& bad) {
-    constexpr Bits SENT = Sentinel<F>::bits;
-    Bits raw[kHold];
-#pragma unroll
-    for (int u = 0; u < kHold; ++u) raw[u] = ring[(cj[u] - lo) & (kRing - 1)];
-#pragma unroll
-    for (int u = 0; u < kHold; ++u) {
-        if (u < n) {
-            bad |= raw[u] == SENT;
-            acc = acc - cw[u] * from_bits<F>(raw[u]);
+            for (int k = 0; k < kStageOld / kBjThreads; ++k) {
+                const int e = t + k * kBjThreads;
+                if (e < cu.ocnt) {
+                    soc[e] = sc[k];
+                    sov[e] = sv[k];
+                }
+            }
         }
+        if (live) ring[(i - lo) & (RING - 1)] = SENT;
+        __syncthreads();
+        F acc = cu.a0;
+        const int nold = max(0, cu.len - kEll);
+        const int first = kEll - min(cu.len, kEll);  // first occupied ELL slot
+        int opos = 0;                                 // older entries taken
+        int next = first;                             // first ELL slot not yet taken
+        // older entry k of this row: staged in LDS, or from memory past the stage
+        auto old_at = [&](int k, int& j, F& w) {
+            const int s = cu.o0 - cu.obase + k;
+            if (s < kStageOld) {
+                j = soc[s];
+                w = sov[s];
+            } else {
+                j = oci[cu.o0 + k];
+                w = oval[cu.o0 + k];
+            }
+        };
+        if (live) {
+            // older entries while on earlier chunks
+            bool open = true;
+            while (open && opos < nold) {
+                int j;
+                F w;
+                old_at(opos, j, w);
+                if (!earlier(j)) {
+                    open = false;
+                } else {
+                    acc = acc - w * bj_value<FWD, RING, V, F>(j, in_ring(j), ring, lo, y, z);
+                    ++opos;
+                }
+            }
+            if (opos == nold) {
+                // ELL slots on earlier chunks: a prefix, by the sort order.
+                // Slots not taken read the zero slot with a zero weight.
+                if (all_ring) {
+#pragma unroll
+                    for (int u = 0; u < kEll; ++u) {
+                        const bool tk = u >= first && earlier(cu.ec[u]);
+                        const F w = tk ? cu.ev[u] : F(0);
+                        acc = acc - w * rd(tk ? roff(cu.ec[u]) : ZOFF);
+                        next = tk ? u + 1 : next;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kEll; ++u) {
+                        if (u >= first && earlier(cu.ec[u])) {
+                            acc = acc - cu.ev[u] * bj_value<FWD, RING, V, F>(cu.ec[u], in_ring(cu.ec[u]), ring, lo,
+                                                                              y, z);
+                            next = u + 1;
+                        }
+                    }
+                }
+            }
+        }
+        // what is left is on this chunk (the entries are sorted), so in the
+        // ring at the row's level: the newest kHeld slots stay in registers
+        // as (ring offset, weight), the others are parked in this thread's
+        // LDS list, padded to a multiple of four with zero terms
+        unsigned hoff[kHeld];
+        F hw[kHeld];
+#pragma unroll
+        for (int h = 0; h < kHeld; ++h) {
+            const int u = kPark + h;
+            const bool keep = live && u >= next;
+            hoff[h] = keep ? roff(cu.ec[u]) : ZOFF;
+            hw[h] = keep ? cu.ev[u] : F(0);
+        }
+        const int npark = live ? max(0, kPark - next) : 0;
+#pragma unroll
+        for (int u = 0; u < kPark; ++u) {
+            if (live && u >= next) {
+                pka[(u - next) * kBjThreads + t] = (int)roff(cu.ec[u]);
+                pkw[(u - next) * kBjThreads + t] = cu.ev[u];
+            }
+        }
+        const int npad = (npark + 3) & ~3;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (npark + q < npad) {
+                pka[(npark + q) * kBjThreads + t] = (int)ZOFF;
+                pkw[(npark + q) * kBjThreads + t] = F(0);
+            }
+        }
+        // the next chunk's rows load while this one is solved (not hoisted
+        // above the straight pass, whose registers they would otherwise
+        // share); the last chunk loads itself again, so that the loads, and
+        // the registers they fill, are unconditional
+        __builtin_amdgcn_sched_barrier(0);
+        bj_load<FWD, MODE>(nx, P, rin, y, lo, hi, min(m + 1, nch - 1), t, inext);
+        inext = bj_row<FWD>(P, lo, hi, min(m + 2, nch - 1), t);
+        const int cnl = m < kTab ? nltab[m] : nlg[m];
+        auto level = [&](int lv) {
+            if (live && cu.lev == lv) {
+                // older entries left (only when an older entry is on this chunk)
+                for (; opos < nold; ++opos) {
+                    int j;
+                    F w;
+                    old_at(opos, j, w);
+                    const Bits vb = ring[(j - lo) & (RING - 1)];
+                    bad |= vb == SENT;
+                    acc = acc - w * from_bits<F>(vb);
+                }
+                for (int k = 0; k < npad; k += 4) {
+                    unsigned oo[4];
+                    F ww[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        oo[u] = (unsigned)pka[(k + u) * kBjThreads + t];
+                        ww[u] = pkw[(k + u) * kBjThreads + t];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc = acc - ww[u] * rd(oo[u]);
+                }
+#pragma unroll
+                for (int h = 0; h < kHeld; ++h) acc = acc - hw[h] * rd(hoff[h]);
+                const F out = FWD ? acc : acc / cu.dg;
+                // a sentinel read turns the row into NaN
+                bad |= (out != out) && (cu.a0 == cu.a0);
+                ring[(i - lo) & (RING - 1)] = to_bits<F>(out);
+                if (FWD) {
+                    y[i] = out;
+                } else {
+                    const V zv = (V)out;
+                    z[i] = zv;
+                    if (MODE == 1 || MODE == 2) rz += (double)cu.rr * (double)zv;
+                }
+            }
+            __syncthreads();
+        };
+        // the next chunk's older entries load after a few levels, once the
+        // chunk's range has arrived
+        const int l1 = min(kOldLevel, cnl);
+        for (int lv = 0; lv < l1; ++lv) level(lv);
+        stage_load();
+        for (int lv = l1; lv < cnl; ++lv) level(lv);
     }
-    return acc;
 }
 
 template <typename V, typename F, int MODE>
 __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovState* st, int it) {
     using Bits = typename Sentinel<F>::Bits;
-    constexpr Bits SENT = Sentinel<F>::bits;
-    __shared__ Bits ring[kRing];
-    __shared__ int scol[kStage];
-    __shared__ F sval[kStage];
+    constexpr int RING = BjRing<F>::size;
+    __shared__ Bits ring[RING + 1];
+    __shared__ int pka[kPark * kBjThreads];
+    __shared__ F pkw[kPark * kBjThreads];
+    __shared__ int soc[kStageOld];
+    __shared__ F sov[kStageOld];
     __shared__ double red[16];
     __shared__ int shd;
-    __shared__ int2 ltab[kTab];
-    __shared__ int2 utab[kTab];
     __shared__ int lnl[kTab];
     __shared__ int unl[kTab];
     const int b = blockIdx.x, t = threadIdx.x;
     const int nb = P.nblocks;
     const int lo = P.bp[b], hi = P.bp[b + 1];
-    // The block's chunk tables (hi - lo + 1 entries each, of which the
-    // first nch + 1 are used) are cached in LDS up to kTab entries; a
-    // uniform branch reads any further entries from memory.
-    const int2* LT = P.lch + lo + b;
-    const int2* UT = P.uch + lo + b;
     for (int q = t; q < kTab && q <= hi - lo; q += kBjThreads) {
-        ltab[q] = LT[q];
-        utab[q] = UT[q];
         lnl[q] = P.lnl[lo + b + q];
         unl[q] = P.unl[lo + b + q];
     }
+    if (t == 0) ring[RING] = to_bits<F>(F(0));
     __syncthreads();
-    const int* __restrict__ lrp = P.lrp;
-    const int* __restrict__ lci = P.lci;
-    const F* __restrict__ lval = (const F*)P.lval;
-    const int* __restrict__ urp = P.urp;
-    const int* __restrict__ uci = P.uci;
-    const F* __restrict__ uval = (const F*)P.uval;
-    const F* __restrict__ udiag = (const F*)P.udiag;
     V* __restrict__ z = (V*)Vv.z;
     F* __restrict__ y = (F*)Vv.y;
     V* r = (V*)Vv.r;
@@ -1055,204 +1305,12 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
         rr = block_sum(rr, red);  // also orders the r updates before the sweeps read them
         if (t == 0) Vv.part_rr[b] = rr;
     }
-    const V* rin = r;
     int bad = 0;
-    int pc[kPer];
-    F pv[kPer];
-
-    // ---- forward substitution: y_i = r_i - sum_{j<i} l_ij y_j (MODE 4:
-    // y is given)
-    bool u_staged = false;
-    if (MODE != 4 && lo < hi) {
-        auto T = [&](int q) { return q < kTab ? ltab[q] : LT[q]; };
-        auto NL = [&](int q) { return q < kTab ? lnl[q] : P.lnl[lo + b + q]; };
-        int m = 0;
-        int2 ta = T(0), tb = T(1);
-        int2 tn = T(tb.x < hi ? 2 : 1);
-        int nst = tb.y - ta.y;
-        bool big = nst > kStage;
-        stage_issue(pc, pv, lci, lval, ta.y, big ? 0 : nst, t);
-        int i = ta.x + t;
-        bool live = i < tb.x;
-        int rp0 = live ? lrp[i] : 0, rp1 = live ? lrp[i + 1] : 0;
-        V rv = live ? rin[i] : V(0);
-        int lvn = live ? P.llev[i] : 0;
-        while (true) {
-            // current chunk [c0, c1), entries from ebase
-            const int c1 = tb.x, ebase = ta.y;
-            const bool cbig = big;
-            stage_commit(pc, pv, scol, sval, cbig ? 0 : nst, t);
-            if (live) ring[(i - lo) & (kRing - 1)] = SENT;
-            __syncthreads();
-            const int row = i;
-            bool fin = !live;
-            int pos = rp0 - ebase;
-            const int pend = rp1 - ebase;
-            F acc = (F)rv;
-            const int clev = lvn, cnl = NL(m);
-            // prefetch the next chunk
-            ++m;
-            ta = tb;
-            tb = tn;
-            const bool more = ta.x < hi;
-            if (more) {
-                tn = T(tb.x < hi ? m + 2 : m + 1);
-                nst = tb.y - ta.y;
-                big = nst > kStage;
-                stage_issue(pc, pv, lci, lval, ta.y, big ? 0 : nst, t);
-                i = ta.x + t;
-                live = i < tb.x;
-                rp0 = live ? lrp[i] : 0;
-                rp1 = live ? lrp[i + 1] : 0;
-                rv = live ? rin[i] : V(0);
-                lvn = live ? P.llev[i] : 0;
-            } else if (MODE != 3) {
-                // last forward chunk: the first backward chunk's entries do
-                // not depend on y, so they load while this chunk is solved
-                const int2 ua = utab[0], ub = utab[1];
-                const int un = ua.y - ub.y;
-                stage_issue(pc, pv, uci, uval, ub.y, un > kStage ? 0 : un, t);
-                u_staged = true;
-            }
-            // solve the current chunk
-            const int ring_lo = c1 - kRing;
-            if (!fin && cbig) {
-                // oversized row: every dependency lies in an earlier chunk
-                for (; pos < pend; ++pos) {
-                    const int j = lci[ebase + pos];
-                    const F yj = (j >= ring_lo) ? from_bits<F>(ring[(j - lo) & (kRing - 1)]) : y[j];
-                    acc = acc - lval[ebase + pos] * yj;
-                }
-            }
-            if (!fin && ring_lo > lo) {
-                // dependencies evicted from the ring: final, in memory
-                while (pos < pend) {
-                    const int j = scol[pos];
-                    if (j >= ring_lo) break;
-                    acc = acc - sval[pos] * y[j];
-                    ++pos;
-                }
-            }
-            // terms on earlier chunks (final, in the ring) in one straight
-            // pass; it stops at the first same-chunk term still pending
-            if (!fin) take_ready(pos, pend, acc, scol, sval, ring, lo);
-            // same-chunk terms, level by level: at its level every term a
-            // row has left is final
-            int cj[kHold];
-            F cw[kHold];
-            const int nh = fin ? 0 : min(pend - pos, kHold);
-            if (nh > 0) hold_terms(cj, cw, pos, pend, scol, sval);
-            for (int lv = 0; lv < cnl; ++lv) {
-                if (!fin && clev == lv) {
-                    if (nh > 0) acc = take_held(cj, cw, nh, acc, ring, lo, bad);
-                    acc = take_final(pos + nh, pend, acc, scol, sval, ring, lo, bad);
-                    ring[(row - lo) & (kRing - 1)] = to_bits<F>(acc);
-                    fin = true;
-                }
-                __syncthreads();
-            }
-            if (row < c1) y[row] = from_bits<F>(ring[(row - lo) & (kRing - 1)]);
-            __syncthreads();
-            if (!more) break;
-        }
-    }
-
-    // ---- backward substitution: z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii,
-    // chunks from the bottom of the block up (MODE 3: not done)
     double rz = 0.0;
-    if (MODE != 3 && lo < hi) {
-        auto T = [&](int q) { return q < kTab ? utab[q] : UT[q]; };
-        auto NL = [&](int q) { return q < kTab ? unl[q] : P.unl[lo + b + q]; };
-        int m = 0;
-        int2 ta = T(0), tb = T(1);  // chunk [tb.x, ta.x), entries [tb.y, ta.y)
-        int2 tn = T(tb.x > lo ? 2 : 1);
-        int nst = ta.y - tb.y;
-        bool big = nst > kStage;
-        if (!u_staged) stage_issue(pc, pv, uci, uval, tb.y, big ? 0 : nst, t);
-        int i = ta.x - 1 - t;
-        bool live = i >= tb.x;
-        int rp0 = live ? urp[i] : 0, rp1 = live ? urp[i + 1] : 0;
-        F yv = live ? y[i] : F(0);
-        F dv = live ? udiag[i] : F(1);
-        V rv = ((MODE == 1 || MODE == 2) && live) ? rin[i] : V(0);
-        int lvn = live ? P.ulev[i] : 0;
-        while (true) {
-            const int c_lo = tb.x, ebase = tb.y;
-            const bool cbig = big;
-            stage_commit(pc, pv, scol, sval, cbig ? 0 : nst, t);
-            if (live) ring[(i - lo) & (kRing - 1)] = SENT;
-            __syncthreads();
-            const int row = i;
-            bool fin = !live;
-            int pos = rp0 - ebase;
-            const int pend = rp1 - ebase;
-            const F dgv = dv;
-            F acc = yv;
-            const V rrow = rv;
-            const int clev = lvn, cnl = NL(m);
-            // prefetch the next chunk
-            ++m;
-            ta = tb;
-            tb = tn;
-            const bool more = ta.x > lo;
-            if (more) {
-                tn = T(tb.x > lo ? m + 2 : m + 1);
-                nst = ta.y - tb.y;
-                big = nst > kStage;
-                stage_issue(pc, pv, uci, uval, tb.y, big ? 0 : nst, t);
-                i = ta.x - 1 - t;
-                live = i >= tb.x;
-                rp0 = live ? urp[i] : 0;
-                rp1 = live ? urp[i + 1] : 0;
-                yv = live ? y[i] : F(0);
-                dv = live ? udiag[i] : F(1);
-                rv = ((MODE == 1 || MODE == 2) && live) ? rin[i] : V(0);
-                lvn = live ? P.ulev[i] : 0;
-            }
-            // solve the current chunk.  Rows hold their entries in descending
-            // column order: terms evicted from the ring (in memory), then the
-            // other terms on earlier chunks (in the ring), then the same-chunk
-            // ones.
-            const int ring_hi = c_lo + kRing;
-            if (!fin && cbig) {
-                // oversized row: every dependency lies in an earlier chunk
-                for (; pos < pend; ++pos) {
-                    const int j = uci[ebase + pos];
-                    const F zj = (j < ring_hi) ? from_bits<F>(ring[(j - lo) & (kRing - 1)]) : (F)z[j];
-                    acc = acc - uval[ebase + pos] * zj;
-                }
-            }
-            if (!fin && ring_hi < hi) {
-                while (pos < pend) {
-                    const int j = scol[pos];
-                    if (j < ring_hi) break;
-                    acc = acc - sval[pos] * (F)z[j];
-                    ++pos;
-                }
-            }
-            if (!fin) take_ready(pos, pend, acc, scol, sval, ring, lo);
-            int cj[kHold];
-            F cw[kHold];
-            const int nh = fin ? 0 : min(pend - pos, kHold);
-            if (nh > 0) hold_terms(cj, cw, pos, pend, scol, sval);
-            for (int lv = 0; lv < cnl; ++lv) {
-                if (!fin && clev == lv) {
-                    if (nh > 0) acc = take_held(cj, cw, nh, acc, ring, lo, bad);
-                    acc = take_final(pos + nh, pend, acc, scol, sval, ring, lo, bad);
-                    ring[(row - lo) & (kRing - 1)] = to_bits<F>(acc / dgv);
-                    fin = true;
-                }
-                __syncthreads();
-            }
-            if (row >= c_lo) {
-                const V zv = (V)from_bits<F>(ring[(row - lo) & (kRing - 1)]);
-                z[row] = zv;
-                if (MODE == 1 || MODE == 2) rz += (double)rrow * (double)zv;
-            }
-            __syncthreads();
-            if (!more) break;
-        }
-    }
+    // forward substitution y_i = r_i - sum_{j<i} l_ij y_j (MODE 4: y given)
+    if (MODE != 4 && lo < hi) bj_sweep<true, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, lnl, P.lnl + lo + b, rz, bad);
+    // backward substitution z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii (MODE 3: not done)
+    if (MODE != 3 && lo < hi) bj_sweep<false, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, unl, P.unl + lo + b, rz, bad);
     if (bad && st) atomicExch(&st->spin_err, 1);
     if (MODE == 1 || MODE == 2) {
         rz = block_sum(rz, red);

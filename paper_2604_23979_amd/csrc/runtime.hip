@@ -76,6 +76,15 @@ struct sdsl_ctx {
     int *lnl = nullptr, *unl = nullptr, *llev = nullptr, *ulev = nullptr;  // chunk-local levels
     double *lval = nullptr, *uval = nullptr, *udiag = nullptr;
     float *lval32 = nullptr, *uval32 = nullptr, *udiag32 = nullptr;
+    // chunk-interleaved newest entries of every factor row (the sweeps' copies)
+    int *lell_c = nullptr, *uell_c = nullptr;
+    double *lell_v = nullptr, *uell_v = nullptr;
+    float *lell_v32 = nullptr, *uell_v32 = nullptr;
+    // older entries of the longer factor rows (CSR per triangle)
+    int *lorp = nullptr, *loci = nullptr, *uorp = nullptr, *uoci = nullptr;
+    int *lperm = nullptr, *uperm = nullptr, *lpos = nullptr, *upos = nullptr;  // level-order row placement
+    double *lov = nullptr, *uov = nullptr;
+    float *lov32 = nullptr, *uov32 = nullptr;
     int p_nnz = 0;
     // border correction of the low-rank term (W = P^{-1} U, K^{-1})
     double* W64 = nullptr;
@@ -197,6 +206,18 @@ BJDev bj_dev(sdsl_ctx* h, bool fp32) {
     P.ulev = h->ulev;
     P.lnl = h->lnl;
     P.unl = h->unl;
+    P.lell_c = h->lell_c;
+    P.uell_c = h->uell_c;
+    P.lell_v = fp32 ? (const void*)h->lell_v32 : (const void*)h->lell_v;
+    P.uell_v = fp32 ? (const void*)h->uell_v32 : (const void*)h->uell_v;
+    P.lorp = h->lorp;
+    P.loci = h->loci;
+    P.lov = fp32 ? (const void*)h->lov32 : (const void*)h->lov;
+    P.uorp = h->uorp;
+    P.uoci = h->uoci;
+    P.uov = fp32 ? (const void*)h->uov32 : (const void*)h->uov;
+    P.lperm = h->lperm;
+    P.uperm = h->uperm;
     return P;
 }
 
@@ -468,7 +489,11 @@ void build_precond(sdsl_ctx* h) {
                     h->udiag, s);
     launch_bj_chunks(h->nb, h->bp, h->lrp, h->urp, h->lch, h->uch, s);
     launch_bj_levels(h->nb, h->bp, h->lrp, h->lci, h->urp, h->uci, h->lch, h->uch, h->llev, h->ulev, h->lnl, h->unl,
-                     s);
+                     h->lperm, h->uperm, h->lpos, h->upos, s);
+    launch_bj_ell(h->nb, h->bp, h->lrp, h->lci, h->lval, h->lpos, true, h->lell_c, h->lell_v, h->lell_v32, s);
+    launch_bj_ell(h->nb, h->bp, h->urp, h->uci, h->uval, h->upos, false, h->uell_c, h->uell_v, h->uell_v32, s);
+    launch_bj_old(h->n_int, h->lrp, h->lci, h->lval, h->cnt, h->scan_tmp, h->lorp, h->loci, h->lov, h->lov32, s);
+    launch_bj_old(h->n_int, h->urp, h->uci, h->uval, h->cnt, h->scan_tmp, h->uorp, h->uoci, h->uov, h->uov32, s);
     h->check_launch();
     int kept = 0, nfix = 0, spin = 0, nl = 0, nu = 0;
     hip_check(hipMemcpyAsync(&kept, h->prp + h->n_int, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
@@ -1233,6 +1258,8 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         setup_lowrank(h, lr);
         // preconditioner buffers (capacity: every entry of M)
         const int ni = h->n_int;
+        if ((int64_t)ni * kBjEllWidth >= (int64_t(1) << 31))
+            fail(SDSL_E_INVALID, "block-Jacobi part limited to 2^31 / " + std::to_string(kBjEllWidth) + " rows");
         h->prp = h->alloc<int>(ni + 1);
         h->pci = h->alloc<int>(nnz);
         h->pv_corr = h->alloc<double>(nnz);
@@ -1262,6 +1289,24 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->lval32 = h->alloc<float>(nnz);
         h->uval32 = h->alloc<float>(nnz);
         h->udiag32 = h->alloc<float>(ni);
+        h->lell_c = h->alloc<int>((size_t)ni * kBjEllWidth);
+        h->uell_c = h->alloc<int>((size_t)ni * kBjEllWidth);
+        h->lell_v = h->alloc<double>((size_t)ni * kBjEllWidth);
+        h->uell_v = h->alloc<double>((size_t)ni * kBjEllWidth);
+        h->lell_v32 = h->alloc<float>((size_t)ni * kBjEllWidth);
+        h->uell_v32 = h->alloc<float>((size_t)ni * kBjEllWidth);
+        h->lperm = h->alloc<int>(ni);
+        h->uperm = h->alloc<int>(ni);
+        h->lpos = h->alloc<int>(ni);
+        h->upos = h->alloc<int>(ni);
+        h->lorp = h->alloc<int>(ni + 1);
+        h->uorp = h->alloc<int>(ni + 1);
+        h->loci = h->alloc<int>(nnz);
+        h->uoci = h->alloc<int>(nnz);
+        h->lov = h->alloc<double>(nnz);
+        h->uov = h->alloc<double>(nnz);
+        h->lov32 = h->alloc<float>(nnz);
+        h->uov32 = h->alloc<float>(nnz);
         // Krylov workspace
         h->x = h->alloc<double>(n);
         h->r = h->alloc<double>(n);
