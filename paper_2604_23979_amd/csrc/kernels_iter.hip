@@ -1114,28 +1114,40 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
             }
         };
         if (live) {
-            // older entries while on earlier chunks
+            // older entries while on earlier chunks, four in flight
             bool open = true;
             while (open && opos < nold) {
-                int j;
-                F w;
-                old_at(opos, j, w);
-                if (!earlier(j)) {
-                    open = false;
-                } else {
-                    acc = acc - w * bj_value<FWD, RING, V, F>(j, in_ring(j), ring, lo, y, z);
-                    ++opos;
+                int jj[4];
+                F ww[4], vv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (opos + u < nold) old_at(opos + u, jj[u], ww[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (opos + u < nold && earlier(jj[u]))
+                        vv[u] = bj_value<FWD, RING, V, F>(jj[u], in_ring(jj[u]), ring, lo, y, z);
+                const int o4 = opos;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (open && o4 + u < nold) {
+                        if (earlier(jj[u])) {
+                            acc = acc - ww[u] * vv[u];
+                            ++opos;
+                        } else {
+                            open = false;
+                        }
+                    }
                 }
             }
             if (opos == nold) {
-                // ELL slots on earlier chunks: a prefix, by the sort order.
-                // Slots not taken read the zero slot with a zero weight.
+                // ELL slots on earlier chunks: a prefix, by the sort order
+                // (empty slots hold the row itself, never earlier).  Slots
+                // not taken read the zero slot; their weights are finite.
                 if (all_ring) {
 #pragma unroll
                     for (int u = 0; u < kEll; ++u) {
-                        const bool tk = u >= first && earlier(cu.ec[u]);
-                        const F w = tk ? cu.ev[u] : F(0);
-                        acc = acc - w * rd(tk ? roff(cu.ec[u]) : ZOFF);
+                        const bool tk = earlier(cu.ec[u]);
+                        acc = acc - cu.ev[u] * rd(tk ? roff(cu.ec[u]) : ZOFF);
                         next = tk ? u + 1 : next;
                     }
                 } else {
@@ -1161,7 +1173,7 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
             const int u = kPark + h;
             const bool keep = live && u >= next;
             hoff[h] = keep ? roff(cu.ec[u]) : ZOFF;
-            hw[h] = keep ? cu.ev[u] : F(0);
+            hw[h] = cu.ev[u];  // finite; a slot not kept reads the zero slot
         }
         const int npark = live ? max(0, kPark - next) : 0;
 #pragma unroll
