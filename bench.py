@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -130,7 +132,31 @@ def run_serving(sd, torch, gen, count, active, modes):
             srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
             out["poisson_0.8mu"] = dict(srv2.stats(), mode=mode, rate_per_s=0.8 * mu)
             log(f"  Poisson at 0.8 mu ({mode}): {out['poisson_0.8mu']}")
-    out["all_ok"] = all(v["ok"] == count for v in out["closed_loop"].values())
+    # the plain FP64 GPU solve: one request at a time, setup + solve on one
+    # stream, no overlap
+    o64 = sd.Options(precision=sd.FP64, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
+                     pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, its_tot, ok = [], 0, 0
+    for s in systems:
+        b = torch.as_tensor(s.b, device="cuda:0")
+        sv = sd.from_system(s, o64)
+        _, its, _, st = sv.solve(b, tol=1e-8)
+        torch.cuda.synchronize()
+        sv.close()
+        lat.append(1e3 * (time.perf_counter() - t0))
+        its_tot += its
+        ok += st == sd.OK
+    span = time.perf_counter() - t0
+    out["plain_fp64"] = dict(requests=count, ok=ok, makespan_s=round(span, 3), solves_per_s=round(count / span, 4),
+                             p50_ms=round(float(np.percentile(lat, 50)), 1),
+                             p99_ms=round(float(np.percentile(lat, 99)), 1), iterations=its_tot)
+    log(f"  plain FP64, one at a time: {out['plain_fp64']}")
+    served = out["closed_loop"].get("fp32ir")
+    if served:
+        out["served_fp32ir_over_plain_fp64"] = round(served["solves_per_s"] / out["plain_fp64"]["solves_per_s"], 3)
+    out["all_ok"] = all(v["ok"] == count for v in out["closed_loop"].values()) and ok == count
     return out
 
 

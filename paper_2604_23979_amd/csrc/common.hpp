@@ -202,8 +202,8 @@ struct BJDev {
     const int* uorp;     // the same for U rows
     const int* uoci;
     const void* uov;
-    const int* lperm;    // row solved by each thread of a forward chunk (level order)
-    const int* uperm;    // the same for backward chunks
+    const int2* lperm;   // {row, entries} solved by each thread of a forward chunk (level order)
+    const int2* uperm;   // the same for backward chunks
 };
 
 // MODE 0: z = P^{-1} r.  MODE 1: PCG step (alpha from partials, x/r update,
@@ -285,8 +285,8 @@ void launch_bj_old(int n, const int* rp, const int* ci, const double* val, int* 
 void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp, int2* lch, int2* uch,
                       hipStream_t s);
 void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci, const int* urp, const int* uci,
-                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, int* lperm,
-                      int* uperm, int* lpos, int* upos, hipStream_t s);
+                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, int2* lperm,
+                      int2* uperm, int* lpos, int* upos, hipStream_t s);
 
 template <typename T>
 void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, const BorderDev& bd, KrylovState* st, int it,

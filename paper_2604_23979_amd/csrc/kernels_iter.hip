@@ -788,15 +788,16 @@ void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp
 // one; a chain of r rows needs r rounds and at most nrows rounds are run.
 // The sweeps give the rows of a chunk to threads in level order, so that
 // the rows of one level share as few wavefronts as possible: lperm/uperm
-// hold, at the chunk's first row + p, the row solved by thread p, and
-// lpos/upos the inverse (inside a level, rows keep their chunk order).
+// hold, at the chunk's first row + p, {the row solved by thread p, its
+// number of entries}, and lpos/upos the inverse (inside a level, rows keep
+// their chunk order).
 __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict__ bp, const int* __restrict__ lrp,
                                                           const int* __restrict__ lci, const int* __restrict__ urp,
                                                           const int* __restrict__ uci, const int2* __restrict__ lch,
                                                           const int2* __restrict__ uch, int* __restrict__ llev,
                                                           int* __restrict__ ulev, int* __restrict__ lnl,
-                                                          int* __restrict__ unl, int* __restrict__ lperm,
-                                                          int* __restrict__ uperm, int* __restrict__ lpos,
+                                                          int* __restrict__ unl, int2* __restrict__ lperm,
+                                                          int2* __restrict__ uperm, int* __restrict__ lpos,
                                                           int* __restrict__ upos) {
     __shared__ int slev[kBjThreads];
     __shared__ int hist[kBjThreads];
@@ -810,7 +811,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
         const int* rp = dir == 0 ? lrp : urp;
         const int* ci = dir == 0 ? lci : uci;
         int* lev = dir == 0 ? llev : ulev;
-        int* perm = dir == 0 ? lperm : uperm;
+        int2* perm = dir == 0 ? lperm : uperm;
         int* pos = dir == 0 ? lpos : upos;
         int* nl = (dir == 0 ? lnl : unl) + lo + b;
         const int end = dir == 0 ? hi : lo;
@@ -822,10 +823,11 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
             const bool live = t < nrows;
             // same-chunk dependencies: the tail of the row in both directions
             // (forward rows ascend, j >= a; backward rows descend, j < a)
-            int q0 = 0, q1 = 0;
+            int q0 = 0, q1 = 0, rlen = 0;
             if (live) {
                 q0 = rp[i];
                 q1 = rp[i + 1];
+                rlen = q1 - q0;
                 int f = q1;
                 if (dir == 0)
                     while (f > q0 && ci[f - 1] >= a) --f;
@@ -880,7 +882,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
                 for (int q = 0; q < t; ++q) rank += slev[q] == mine ? 1 : 0;
                 const int first = dir == 0 ? a : e;  // lowest row of the chunk
                 const int p = hist[mine] + rank;
-                perm[first + p] = i;
+                perm[first + p] = make_int2(i, rlen);
                 pos[i] = p;
             }
             __syncthreads();
@@ -888,8 +890,8 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
     }
 }
 void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci, const int* urp, const int* uci,
-                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, int* lperm,
-                      int* uperm, int* lpos, int* upos, hipStream_t s) {
+                      const int2* lch, const int2* uch, int* llev, int* ulev, int* lnl, int* unl, int2* lperm,
+                      int2* uperm, int* lpos, int* upos, hipStream_t s) {
     if (nblocks > 0)
         k_bj_levels<<<nblocks, kBjThreads, 0, s>>>(bp, lrp, lci, urp, uci, lch, uch, llev, ulev, lnl, unl, lperm,
                                                    uperm, lpos, upos);
@@ -985,37 +987,44 @@ struct BjRow {
     int i;         // the row
 };
 
-// Row solved by thread t in chunk m (any row of the chunk for a thread past
-// its end).
+// {row, entries} solved by thread t in chunk m (any row of the chunk for a
+// thread past its end).
 template <bool FWD>
-__device__ __forceinline__ int bj_row(const BJDev& P, int lo, int hi, int m, int t) {
+__device__ __forceinline__ int2 bj_row(const BJDev& P, int lo, int hi, int m, int t) {
     int ca, cb;
     bj_chunk<FWD>(lo, hi, m, ca, cb);
     return (FWD ? P.lperm : P.uperm)[ca + min(t, cb - ca - 1)];
 }
 
-// Issue the loads of thread t's row i of chunk m.
+// Issue the loads of thread t's row il = {i, entries} of chunk m; only the
+// occupied ELL slots are read.
 template <bool FWD, int MODE, typename V, typename F>
 __device__ __forceinline__ void bj_load(BjRow<V, F>& R, const BJDev& P, const V* rin, const F* y, int lo, int hi,
-                                        int m, int t, int i) {
+                                        int m, int t, int2 il) {
     int ca, cb;
     bj_chunk<FWD>(lo, hi, m, ca, cb);
     const int nrows = cb - ca;
+    const int i = il.x;
     R.i = i;
-    const int* __restrict__ rp = FWD ? P.lrp : P.urp;
     const int* __restrict__ orp = FWD ? P.lorp : P.uorp;
     const int* __restrict__ ec = FWD ? P.lell_c : P.uell_c;
     const F* __restrict__ ev = (const F*)(FWD ? P.lell_v : P.uell_v);
     R.obase = orp[ca];
     R.ocnt = orp[cb] - R.obase;
     if (t < nrows) {
-        R.len = rp[i + 1] - rp[i];
+        R.len = il.y;
         R.o0 = orp[i];
         const unsigned base = (unsigned)ca * kEll + t;  // the copies hold fewer than 2^31 entries
+        const int first = kEll - min(il.y, kEll);
 #pragma unroll
         for (int u = 0; u < kEll; ++u) {
-            R.ec[u] = ec[base + (unsigned)(u * nrows)];
-            R.ev[u] = ev[base + (unsigned)(u * nrows)];
+            if (u >= first) {
+                R.ec[u] = ec[base + (unsigned)(u * nrows)];
+                R.ev[u] = ev[base + (unsigned)(u * nrows)];
+            } else {
+                R.ec[u] = i;  // empty slot: the row itself, weight 0
+                R.ev[u] = F(0);
+            }
         }
         R.lev = FWD ? P.llev[i] : P.ulev[i];
         if (FWD) {
@@ -1058,7 +1067,7 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
     F sv[kStageOld / kBjThreads];
     // row indices run one chunk ahead of the row loads
     bj_load<FWD, MODE>(nx, P, rin, y, lo, hi, 0, t, bj_row<FWD>(P, lo, hi, 0, t));
-    int inext = bj_row<FWD>(P, lo, hi, min(1, nch - 1), t);
+    int2 inext = bj_row<FWD>(P, lo, hi, min(1, nch - 1), t);
     auto stage_load = [&]() {
 #pragma unroll
         for (int k = 0; k < kStageOld / kBjThreads; ++k) {

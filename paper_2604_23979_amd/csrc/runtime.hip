@@ -82,7 +82,8 @@ struct sdsl_ctx {
     float *lell_v32 = nullptr, *uell_v32 = nullptr;
     // older entries of the longer factor rows (CSR per triangle)
     int *lorp = nullptr, *loci = nullptr, *uorp = nullptr, *uoci = nullptr;
-    int *lperm = nullptr, *uperm = nullptr, *lpos = nullptr, *upos = nullptr;  // level-order row placement
+    int2 *lperm = nullptr, *uperm = nullptr;  // level-order row placement
+    int *lpos = nullptr, *upos = nullptr;
     double *lov = nullptr, *uov = nullptr;
     float *lov32 = nullptr, *uov32 = nullptr;
     int p_nnz = 0;
@@ -1295,8 +1296,8 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->uell_v = h->alloc<double>((size_t)ni * kBjEllWidth);
         h->lell_v32 = h->alloc<float>((size_t)ni * kBjEllWidth);
         h->uell_v32 = h->alloc<float>((size_t)ni * kBjEllWidth);
-        h->lperm = h->alloc<int>(ni);
-        h->uperm = h->alloc<int>(ni);
+        h->lperm = h->alloc<int2>(ni);
+        h->uperm = h->alloc<int2>(ni);
         h->lpos = h->alloc<int>(ni);
         h->upos = h->alloc<int>(ni);
         h->lorp = h->alloc<int>(ni + 1);
