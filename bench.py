@@ -160,6 +160,43 @@ def run_serving(sd, torch, gen, count, active, modes):
     return out
 
 
+def run_bbd(sd, torch, gen, steps):
+    """C3: BBD-preconditioned GMRES(30) on the 1.5M-row bordered system (32
+    blocks of 46,750 rows, 4,096-row border); setup (ILU(0) of the blocks, the
+    dense Schur complement on MFMA and its LU) is timed apart from the
+    solves, and the last solution is checked with the oracle's compensated
+    residual on the host."""
+    import oracle as O
+    t0 = time.time()
+    s = gen.c3(1.0)
+    log(f"  C3: n={s.n} nnz={s.nnz} border={s.n_border} blocks={s.nblocks} built in {time.time() - t0:.1f} s")
+    o = sd.Options(method=sd.BBD, krylov=sd.GMRES, restart=30, spd=False, max_iter=10_000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sv = sd.from_system(s, o)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t1
+    b = torch.as_tensor(s.b, device="cuda:0")
+    times, its = [], []
+    x = None
+    for _ in range(max(1, steps)):
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        x, it, rr, st = sv.solve(b, tol=1e-8)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t2))
+        its.append(it)
+        log(f"  C3 solve: status {st}, {it} GMRES iterations, relres {rr:.2e}, {times[-1]:.1f} ms")
+    true_rr = O.relres(s, x.cpu().numpy())
+    sv.close()
+    out = dict(workload="C3: 32 x 46,750 banded-random blocks + 4,096 border, GMRES(30), BBD, FP64 dense Schur",
+               n=s.n, nnz=s.nnz, border=s.n_border, setup_s=round(setup_s, 3), iterations=its,
+               ms_per_solve=round(float(np.median(times)), 2), solves_per_s=round(1e3 / float(np.median(times)), 3),
+               oracle_relres=true_rr)
+    log(f"  C3: {out}")
+    return out
+
+
 def run_ipm_sequence(sd, torch, gen, steps, rows):
     """IPM sequence (C4): `steps` consecutive systems A D_k A^T + 1e-8 I on
     one pattern, blocks of ~20k rows, GEOMEAN 1e-3 + DROPSUM, FP32-inner / FP64-refined
@@ -277,6 +314,8 @@ def main():
     ap.add_argument("--c4", type=int, default=0,
                     help="also run the IPM sequence (this many systems, refactor every 5) at --c4-rows rows")
     ap.add_argument("--c4-rows", type=int, default=520_000)
+    ap.add_argument("--c3", type=int, default=0,
+                    help="also run the BBD / GMRES(30) system C3 (setup, then this many solves)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="profiling run: first copy a buffer of this many bytes three times (counter scale)")
     args = ap.parse_args()
@@ -321,6 +360,8 @@ def main():
             torch.cuda.synchronize()
             log(f"profile {m}: {its} iterations, status {st}, relres {rr:.2e}")
             sv.close()
+        if args.c3 > 0:
+            run_bbd(sd, torch, gen, args.c3)
         return
     modes = {}
     for m in args.modes.split(","):
@@ -358,6 +399,7 @@ def main():
     serving = (run_serving(sd, torch, gen, args.serve, args.serve_active, args.serve_modes.split(","))
                if args.serve > 0 else None)
     ipm_seq = run_ipm_sequence(sd, torch, gen, args.c4, args.c4_rows) if args.c4 > 0 else None
+    bbd = run_bbd(sd, torch, gen, args.c3) if args.c3 > 0 else None
     line = {
         "metric": METRIC, "value": round(r["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_solve"], 2),
@@ -369,7 +411,7 @@ def main():
                    "n": system.n, "nnz": system.nnz, "nblocks": system.nblocks, "mode": best},
         "p50_ms": round(r["p50_ms"], 2), "p99_ms": round(r["p99_ms"], 2),
         "hbm_gbps": round(r.get("spmv_gbps", 0.0), 1), "iterations": r["iterations"][-1],
-        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu, "serving": serving, "ipm_sequence": ipm_seq,
+        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu, "serving": serving, "ipm_sequence": ipm_seq, "bbd": bbd,
         "modes": {k: {kk: (float(f"{vv:.5g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in modes.items()},
     }
