@@ -277,6 +277,7 @@ void launch_bbd_mid(const TailDev& T, int nblocks, int max_nf, int nbd, const do
                     const int* fidx, double* gpart, const double* rb, double* g, double* w, double* xb,
                     hipStream_t s);
 constexpr int kLuPanel = 64;
+constexpr int kLuSub = 16;    // columns factored by one workgroup inside a panel
 void launch_bj_ell(int nblocks, const int* bp, const int* rp, const int* ci, const double* val, const int* pos,
                    bool fwd, int* ec, double* ev64, float* ev32, hipStream_t s);
 constexpr int kBjEllWidth = 24;  // entries per row in the interleaved copies

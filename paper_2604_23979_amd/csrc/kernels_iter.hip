@@ -273,6 +273,23 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
             vv[u] = p < e ? __builtin_nontemporal_load(&v[p]) : F(0);
             cc[u] = p < e ? __builtin_nontemporal_load(&ci[p]) : r0;
         }
+        // low-rank entries of a step's rows (first G of each row), loaded one
+        // step ahead like the operator's entries
+        auto lr_load = [&](int j, double& w, int& c) {
+            w = 0.0;
+            c = 0;
+            if (LR && j < nrow) {
+                const int row_j = min(j + grp, nrow - 1);
+                const int ua = __shfl(my_u0, row_j, kWave), ue = __shfl(my_u1, row_j, kWave);
+                if (j + grp < nrow && ua + gl < ue) {
+                    w = ((const double*)lr.uv)[ua + gl];
+                    c = lr.uci[ua + gl];
+                }
+            }
+        };
+        double lw = 0.0, nlw = 0.0;
+        int lc = 0, nlc = 0;
+        lr_load(0, lw, lc);
         for (int j = 0; j < nrow; j += RPS) {
             // next step's entries in flight while this one gathers
             const int jn = j + RPS;
@@ -286,6 +303,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
                 nv[u] = ok ? __builtin_nontemporal_load(&v[p]) : F(0);
                 nc[u] = ok ? __builtin_nontemporal_load(&ci[p]) : r0;
             }
+            lr_load(jn, nlw, nlc);
             F s = F(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) s = fma(vv[u], gather(cc[u]), s);
@@ -300,9 +318,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
             // low-rank term of the step's rows, FP64, one entry per lane
             double t = 0.0;
             if (LR) {
+                t = lw * tk[lc];
                 const int row_j = min(j + grp, nrow - 1);
                 const int ua = __shfl(my_u0, row_j, kWave), ue = __shfl(my_u1, row_j, kWave);
-                for (int q = ua + gl; q < ue; q += G)
+                for (int q = ua + gl + G; q < ue; q += G)
                     t = fma(((const double*)lr.uv)[q], tk[lr.uci[q]], t);
             }
             s = dpp_sum<G>(s);
@@ -318,6 +337,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
                 vv[u] = nv[u];
                 cc[u] = nc[u];
             }
+            lw = nlw;
+            lc = nlc;
             a = an;
             e = en;
         }

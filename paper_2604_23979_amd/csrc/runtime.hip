@@ -429,7 +429,19 @@ void build_bbd(sdsl_ctx* h) {
     const int P = kLuPanel;
     for (int k0 = 0; k0 < nbd; k0 += P) {
         const int w = std::min(P, nbd - k0);
-        launch_lu_panel(nbd, k0, w, S, h->bbd_piv, h->bbd_bad, s);
+        // the block column [k0, k0 + w) in sub-panels of kLuSub columns: each
+        // is factored by one workgroup, then the block's later columns get
+        // its triangular solve and rank-kLuSub update on many workgroups
+        for (int s0 = k0; s0 < k0 + w; s0 += kLuSub) {
+            const int ws = std::min(kLuSub, k0 + w - s0);
+            launch_lu_panel(nbd, s0, ws, S, h->bbd_piv, h->bbd_bad, s);
+            if (s0 + ws < k0 + w) {
+                launch_trsm_block(true, ws, S, nbd, s0, S, nbd, s0, s0 + ws, k0 + w, s);
+                launch_dgemm_sub(false, nbd - s0 - ws, k0 + w - s0 - ws, ws, S + (int64_t)(s0 + ws) * nbd + s0, nbd,
+                                 S + (int64_t)s0 * nbd + s0 + ws, nbd, S + (int64_t)(s0 + ws) * nbd + s0 + ws, nbd,
+                                 nullptr, nullptr, s);
+            }
+        }
         if (k0 + w < nbd) {
             launch_trsm_block(true, w, S, nbd, k0, S, nbd, k0, k0 + w, nbd, s);
             const int m = nbd - k0 - w;
