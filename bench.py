@@ -197,22 +197,27 @@ def run_bbd(sd, torch, gen, steps):
     return out
 
 
-def run_ipm_sequence(sd, torch, gen, steps, rows):
+def run_ipm_sequence(sd, torch, gen, steps, rows, policy="fixed", precision="fp32ir"):
     """IPM sequence (C4): `steps` consecutive systems A D_k A^T + 1e-8 I on
-    one pattern, blocks of ~20k rows, GEOMEAN 1e-3 + DROPSUM, FP32-inner / FP64-refined
-    PCG; the preconditioner is refactored every 5 systems and reused (new
-    operator values only) in between.  Every returned solution is checked
-    with the oracle's compensated residual on the host."""
+    one pattern, blocks of ~20k rows, GEOMEAN 1e-3 + DROPSUM PCG; the
+    preconditioner is refactored every 5 systems and reused (new operator
+    values only) in between.  policy "adaptive" also ends a reuse period on
+    convergence degradation (a reused solve capped at 1.5x the iterations of
+    the last fresh one is refactored and solved again).  Every returned
+    solution is checked with the oracle's compensated residual on the host."""
     import oracle as O
+    from paper_2604_23979_amd.ipm import SequenceSolver
     t0 = time.time()
     nblocks = max(1, int(round(rows / 20_312)))   # the full-size block height (5.2M rows / 256 blocks)
     q = gen.IPMSequence(m=rows, nblocks=nblocks, steps=max(steps, 2),
                         progress=lambda msg: log(f"  IPM sequence: {msg}"))
     log(f"  IPM sequence: n={rows} nnz={q.col.shape[0]} built in {time.time() - t0:.1f} s")
-    o = sd.Options(precision=sd.FP32_IR, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
+    prec = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR}[precision]
+    o = sd.Options(precision=prec, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
                    pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
+    seq = SequenceSolver(lambda system, opts: sd.from_system(system, opts), o, reuse_every=5,
+                         degrade=1.5 if policy == "adaptive" else float("inf"))
     recs = []
-    sv = None
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for k in range(steps):
@@ -221,29 +226,19 @@ def run_ipm_sequence(sd, torch, gen, steps, rows):
         b = torch.as_tensor(sk.b, device="cuda:0")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        if sv is None:
-            sv = sd.from_system(sk, o)
-            kind = "setup"
-        elif k % 5 == 0:
-            sv.refactor(vals)
-            kind = "refactor"
-        else:
-            sv.update_values(vals)
-            kind = "reuse"
+        x, rec = seq.step(k, sk, vals, b, tol=1e-8)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        x, its, rr, st = sv.solve(b, tol=1e-8)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
         true_rr = O.relres(sk, x.cpu().numpy())
-        recs.append(dict(k=k, kind=kind, prep_ms=round(1e3 * (t2 - t1), 1), solve_ms=round(1e3 * (t3 - t2), 1),
-                         iterations=its, status=st, relres=true_rr))
-        log(f"  system {k} ({kind}): prep {1e3 * (t2 - t1):.0f} ms, {its} its, {1e3 * (t3 - t2):.0f} ms, "
-            f"status {st}, oracle relres {true_rr:.2e}")
+        recs.append(dict(k=k, kind=rec.kind, ms=round(1e3 * (t2 - t1), 1), iterations=rec.iterations,
+                         status=rec.status, relres=true_rr))
+        log(f"  system {k} ({rec.kind}): {rec.iterations} its, {1e3 * (t2 - t1):.0f} ms, "
+            f"status {rec.status}, oracle relres {true_rr:.2e}")
     total = time.perf_counter() - t_all
-    sv.close()
-    gpu_s = sum(r["prep_ms"] + r["solve_ms"] for r in recs) / 1e3
-    return {"workload": f"C4: {steps} systems, n={rows}, {nblocks} blocks of ~20k rows, refactor every 5",
+    seq.close()
+    gpu_s = sum(r["ms"] for r in recs) / 1e3
+    return {"workload": f"C4: {steps} systems, n={rows}, {nblocks} blocks of ~20k rows, refactor every 5, "
+                        f"policy {policy}, {precision}",
             "systems": recs,
             "gpu_seconds": round(gpu_s, 3), "wall_seconds_incl_host_checks": round(total, 1),
             "systems_per_s": round(steps / gpu_s, 4),
@@ -314,6 +309,9 @@ def main():
     ap.add_argument("--c4", type=int, default=0,
                     help="also run the IPM sequence (this many systems, refactor every 5) at --c4-rows rows")
     ap.add_argument("--c4-rows", type=int, default=520_000)
+    ap.add_argument("--c4-policy", default="fixed", choices=["fixed", "adaptive"],
+                    help="fixed: refactor every 5 systems; adaptive: also on convergence degradation")
+    ap.add_argument("--c4-precision", default="fp32ir", choices=["fp32ir", "fp64"])
     ap.add_argument("--c3", type=int, default=0,
                     help="also run the BBD / GMRES(30) system C3 (setup, then this many solves)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -398,7 +396,8 @@ def main():
         log(f"  oracle: {cpu['value']:.5f} solves/s")
     serving = (run_serving(sd, torch, gen, args.serve, args.serve_active, args.serve_modes.split(","))
                if args.serve > 0 else None)
-    ipm_seq = run_ipm_sequence(sd, torch, gen, args.c4, args.c4_rows) if args.c4 > 0 else None
+    ipm_seq = (run_ipm_sequence(sd, torch, gen, args.c4, args.c4_rows, args.c4_policy, args.c4_precision)
+               if args.c4 > 0 else None)
     bbd = run_bbd(sd, torch, gen, args.c3) if args.c3 > 0 else None
     line = {
         "metric": METRIC, "value": round(r["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,

@@ -214,6 +214,13 @@ sdsl_status sdsl_update_values(sdsl_handle h, const double* new_val);
 sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, int32_t* iters,
                        double* relres);
 
+/* Iteration limit of the handle's later solves (Krylov iterations, inner
+ * ones summed for FP32_IR); max_iter >= 1.  A driver that reuses a
+ * preconditioner (Sec. 3.4) caps a reused solve with it so that convergence
+ * degradation shows as SDSL_E_NOT_CONVERGED early.  SDSL_E_STATE while an
+ * asynchronous solve runs on h. */
+sdsl_status sdsl_set_max_iter(sdsl_handle h, int32_t max_iter);
+
 /* Solves k independent systems, one per handle, with their launches
  * interleaved on the handles' streams so that they overlap on the device.
  * Each result equals that of sdsl_solve on the same handle.  iters/relres

@@ -77,6 +77,7 @@ SIGNATURES = {
                              C.POINTER(H)]),
     "sdsl_refactor": (C.c_int, [H, P]),
     "sdsl_update_values": (C.c_int, [H, P]),
+    "sdsl_set_max_iter": (C.c_int, [H, C.c_int32]),
     "sdsl_solve": (C.c_int, [H, P, P, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "sdsl_solve_batch": (C.c_int, [C.c_int32, P, P, P, C.c_double, P, P]),
     "sdsl_get_info": (C.c_int, [H, C.POINTER(CInfo)]),
@@ -269,6 +270,9 @@ class Solver:
     def update_values(self, vals):
         self._order()
         _check(self.h, lib().sdsl_update_values(self.h, _dptr(vals.contiguous())))
+
+    def set_max_iter(self, max_iter: int):
+        _check(self.h, lib().sdsl_set_max_iter(self.h, int(max_iter)))
 
     # -- single steps
     def spmv(self, x, fp32: bool = False):

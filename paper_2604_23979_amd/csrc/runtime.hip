@@ -1389,6 +1389,15 @@ sdsl_status sdsl_update_values(sdsl_handle h, const double* new_val) {
     });
 }
 
+sdsl_status sdsl_set_max_iter(sdsl_handle h, int32_t max_iter) {
+    if (!h) return SDSL_E_INVALID;
+    return guard(h, [&] {
+        if (max_iter < 1) fail(SDSL_E_INVALID, "max_iter must be positive");
+        if (h->task && !h->task->finished) fail(SDSL_E_STATE, "a solve is running on this handle");
+        h->o.max_iter = max_iter;
+    });
+}
+
 sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, int32_t* iters, double* relres) {
     if (!h) return SDSL_E_INVALID;
     sdsl_status result = SDSL_OK;
