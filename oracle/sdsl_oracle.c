@@ -1187,7 +1187,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     int st = OR_NOT_CONVERGED, it = 0, slow = 0, last = 0;
     out[0] = out[1] = out[2] = 0;
     memset(x, 0, (size_t)n * 8);
-    double nr = nb, prev = nb;
+    double nr = nb, ref = nb;
     if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
     memcpy(r, b, (size_t)n * 8);
     double rr0 = dot(n, r, r);
@@ -1198,7 +1198,21 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         mx_spmv(&S, &A, p, xs, q);
         double pq = dot(n, p, q);
         double alpha = rz / pq;
-        if (!(pq > 0.0) || !isfinite(alpha)) { st = OR_BREAKDOWN; break; }
+        if (!(pq > 0.0) || !isfinite(alpha)) {
+            /* the FP32 operator or factors are not positive definite here:
+             * FP64 PCG solves the residual equation from the current x */
+            nr = op_true_res(&A, x, b, r);
+            if (nr <= tol * nb) { st = OR_OK; break; }
+            double* dd = calloc(n, 8);
+            int32_t its = 0; double r2 = 0.0;
+            st = pcg_run(&A, pf, pc, r, dd, tol * nb / nr, maxit - it, &its, &r2, NULL);
+            for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
+            free(dd);
+            it += its; out[2] += 1;
+            nr = op_true_res(&A, x, b, r);
+            st = (nr <= tol * nb) ? OR_OK : (st == OR_BREAKDOWN ? OR_BREAKDOWN : OR_NOT_CONVERGED);
+            break;
+        }
         for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
         ++it;
         double rr = dot(n, r, r);
@@ -1206,10 +1220,10 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         int upd = rr < delta * delta * rr0 || (every > 0 && it - last >= every);
         if (conv || upd) {
             out[0] += 1;
-            prev = nr;
             nr = op_true_res(&A, x, b, r);
             if (nr <= tol * nb) { st = OR_OK; break; }
-            slow = (nr > 0.5 * prev) ? slow + 1 : 0;
+            /* progress against the residual at the last halving */
+            if (nr <= 0.5 * ref) { ref = nr; slow = 0; } else slow++;
             if (slow >= 3) {
                 double* dd = calloc(n, 8);
                 int32_t its = 0; double r2 = 0.0;

@@ -798,6 +798,7 @@ struct SolveTask {
     // refinement bookkeeping
     double nr = 0.0, prev = 0.0;
     int slow = 0;
+    double ref_nr = 0.0;  // true residual at the last halving (mixed mode)
 
     int max_iter() const { return h->o.max_iter; }
 
@@ -829,7 +830,7 @@ struct SolveTask {
             // FP64 recurrence over the FP32 operator and factors; the true
             // FP64 residual replaces the recurrence one at refinement points
             phase = PMIX;
-            nr = prev = nb;
+            nr = prev = ref_nr = nb;
             launch_copy<double>(h->n, b, h->r, h->s);
             launch_init_state(h->st, h->part_b, h->grid, tol, h->o.refine_delta, h->s);
             launch_refine_state(h->st, h->part_b, h->grid, 0, h->o.refine_every, h->s);
@@ -1044,15 +1045,30 @@ struct SolveTask {
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
         if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
-        slow = (nr > 0.5 * prev) ? slow + 1 : 0;
+        // progress is measured against the residual at the last halving, so
+        // that a residual that oscillates without improving still counts as
+        // stalled
+        if (nr <= 0.5 * ref_nr) {
+            ref_nr = nr;
+            slow = 0;
+        } else {
+            slow++;
+        }
         if (at_limit) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
-        if ((slow >= 3 || (s.done && s.breakdown)) && !handed) {
+        if (s.done && s.breakdown) {
+            // (p, Mp) <= 0: the FP32 operator or factors are not positive
+            // definite for this system, so the search direction is not
+            // continued; FP64 PCG solves the residual equation instead
+            start_fallback();
+            return;
+        }
+        if (slow >= 3 && !handed) {
             // the FP32 operator or factors stall the recurrence: it continues
             // with the FP64 ones from the same search direction
             handed = true;
             fallbacks++;
             slow = 0;
-        } else if (slow >= 3 || (s.done && s.breakdown) || (!s.conv && !s.update)) {
+        } else if (slow >= 3 || (!s.conv && !s.update)) {
             start_fallback();
             return;
         }

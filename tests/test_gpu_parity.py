@@ -570,3 +570,26 @@ def test_async_solve_equals_solve():
     assert st1 == st2 == sd.OK and its1 == its2 and rr1 == rr2
     assert torch.equal(x1, x2)
     sv.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
+def test_set_max_iter_caps_a_solve(prec):
+    """A capped solve stops at the cap with E_NOT_CONVERGED; raising the cap
+    again gives the uncapped result (the handle keeps no state of the capped
+    solve)."""
+    s = gen.c1()
+    p = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR}[prec]
+    sv = sd.from_system(s, sd.Options(precision=p))
+    b = tdev(s.b)
+    x0, its0, rr0, st0 = sv.solve(b)
+    assert st0 == sd.OK and its0 > 20
+    sv.set_max_iter(10)
+    _, its1, rr1, st1 = sv.solve(b)
+    assert st1 == sd.E_NOT_CONVERGED and its1 <= 11 and rr1 > 1e-8  # an FP64 fallback may take one more
+    sv.set_max_iter(100_000)
+    x2, its2, rr2, st2 = sv.solve(b)
+    assert st2 == sd.OK and its2 == its0 and rr2 == rr0
+    assert torch.equal(x0, x2)
+    with pytest.raises(sd.SdslError):
+        sv.set_max_iter(0)
+    sv.close()
