@@ -1187,7 +1187,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     int st = OR_NOT_CONVERGED, it = 0, slow = 0, last = 0;
     out[0] = out[1] = out[2] = 0;
     memset(x, 0, (size_t)n * 8);
-    double nr = nb, ref = nb;
+    double nr = nb, prev = nb;
     if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
     memcpy(r, b, (size_t)n * 8);
     double rr0 = dot(n, r, r);
@@ -1220,10 +1220,10 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         int upd = rr < delta * delta * rr0 || (every > 0 && it - last >= every);
         if (conv || upd) {
             out[0] += 1;
+            prev = nr;
             nr = op_true_res(&A, x, b, r);
             if (nr <= tol * nb) { st = OR_OK; break; }
-            /* progress against the residual at the last halving */
-            if (nr <= 0.5 * ref) { ref = nr; slow = 0; } else slow++;
+            slow = (nr > 0.5 * prev) ? slow + 1 : 0;
             if (slow >= 3) {
                 double* dd = calloc(n, 8);
                 int32_t its = 0; double r2 = 0.0;

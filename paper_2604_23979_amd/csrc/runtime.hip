@@ -798,7 +798,6 @@ struct SolveTask {
     // refinement bookkeeping
     double nr = 0.0, prev = 0.0;
     int slow = 0;
-    double ref_nr = 0.0;  // true residual at the last halving (mixed mode)
 
     int max_iter() const { return h->o.max_iter; }
 
@@ -830,7 +829,7 @@ struct SolveTask {
             // FP64 recurrence over the FP32 operator and factors; the true
             // FP64 residual replaces the recurrence one at refinement points
             phase = PMIX;
-            nr = prev = ref_nr = nb;
+            nr = prev = nb;
             launch_copy<double>(h->n, b, h->r, h->s);
             launch_init_state(h->st, h->part_b, h->grid, tol, h->o.refine_delta, h->s);
             launch_refine_state(h->st, h->part_b, h->grid, 0, h->o.refine_every, h->s);
@@ -1045,15 +1044,7 @@ struct SolveTask {
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
         if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
-        // progress is measured against the residual at the last halving, so
-        // that a residual that oscillates without improving still counts as
-        // stalled
-        if (nr <= 0.5 * ref_nr) {
-            ref_nr = nr;
-            slow = 0;
-        } else {
-            slow++;
-        }
+        slow = (nr > 0.5 * prev) ? slow + 1 : 0;
         if (at_limit) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
         if (s.done && s.breakdown) {
             // (p, Mp) <= 0: the FP32 operator or factors are not positive
