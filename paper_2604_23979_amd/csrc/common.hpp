@@ -157,10 +157,14 @@ struct LowRankDev {
 enum LrFold { LR_NONE = 0, LR_SCALED = 1, LR_BORDER = 2 };
 constexpr int kMaxRank = 64;
 
+int spmv_rows(int n, int grid);
 int spmv_grid(int n);
 void launch_spmv_near(int n, int grid, const int* rp, const int* ci, int halo, unsigned long long* count,
                       hipStream_t s);
-constexpr int kSpmvHalo = 2176;  // near-window halo (FP64 window: 36 KB of LDS)
+constexpr int kSpmvThreads = 1024;
+constexpr int kSpmvRows = 256;      // rows per SpMV workgroup for small systems
+constexpr int kSpmvMaxRows = 1024;  // at most 16 waves x 64 rows
+constexpr int kSpmvHalo = 2176;  // near-window halo (FP64 window: 36-43 KB of LDS)
 int spmv_lanes(double mean_row);
 
 template <typename T>

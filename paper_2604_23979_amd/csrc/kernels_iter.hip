@@ -34,11 +34,22 @@ __device__ __forceinline__ int xcd_swizzle(int w, int g) {
 }
 
 int spmv_grid(int n) {
-    // one workgroup per 256 rows (kSpmvRows), a multiple of 8 so that the
-    // XCD swizzle is a permutation (the extra workgroups have no rows)
-    int g = (n + 255) / 256;
+    // about kSpmvRows rows per workgroup, but no more than two workgroups per
+    // CU (512) while a workgroup stays within kSpmvMaxRows rows, so that a
+    // large SpMV runs as one wave of resident workgroups; a multiple of 8 so
+    // that the XCD swizzle is a permutation (the extra workgroups have no
+    // rows)
+    int g = (n + kSpmvRows - 1) / kSpmvRows;
+    g = std::min(g, std::max(512, (n + kSpmvMaxRows - 1) / kSpmvMaxRows));
     g = (g + 7) / 8 * 8;
     return g < 8 ? 8 : g;
+}
+
+// rows per SpMV workgroup for a grid: a multiple of 16 (one share per wave)
+int spmv_rows(int n, int grid) {
+    int r = (n + grid - 1) / grid;
+    r = (r + 15) / 16 * 16;
+    return r < 16 ? 16 : r;
 }
 
 // lanes per row of the SpMV (4 loads per lane per round): the smallest
@@ -171,9 +182,9 @@ template void launch_lowrank_tdot<float>(const LowRankDev&, const float*, const 
 // added in FP64.  With part_dot the workgroup's share of (x, y) is written
 // to part_dot[w].
 //
-// Layout of the launch: a workgroup of kSpmvThreads threads owns
-// kSpmvRows consecutive rows (XCD-swizzled); each of its waves takes
-// kSpmvRows / 16 of them, 64 / G rows per step with G lanes per row and U
+// Layout of the launch: a workgroup of kSpmvThreads threads owns `rows`
+// consecutive rows (spmv_rows; XCD-swizzled); each of its waves takes
+// rows / 16 of them, 64 / G rows per step with G lanes per row and U
 // loads per lane per round, and the loads of the next step are issued before
 // the current step gathers x.  Row sums use DPP lane exchanges (no LDS).
 //
@@ -181,8 +192,6 @@ template void launch_lowrank_tdot<float>(const LowRankDev&, const float*, const 
 // r1 + halo) (rounded to F) into LDS; entries whose column falls inside are
 // gathered from LDS, the others from memory.  Banded-plus-scattered
 // patterns keep most gathers off the L2.
-constexpr int kSpmvThreads = 1024;
-constexpr int kSpmvRows = 256;
 
 // v moved by DPP control CTRL within the enabled rows (others give 0)
 template <int CTRL, int ROWM = 0xF>
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
                                                        const int* __restrict__ ci, const F* __restrict__ v,
                                                        const V* __restrict__ x, V* __restrict__ y,
                                                        double* __restrict__ part_dot, const KrylovState* st,
-                                                       LowRankDev lr, int halo) {
+                                                       LowRankDev lr, int halo, int rows) {
     extern __shared__ double xwin_lds[];
     __shared__ double red[16];
     __shared__ double tk[kMaxRank];
@@ -229,7 +238,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
     }
     const int g = gridDim.x;
     const int lw = xcd_swizzle(blockIdx.x, g);
-    const int r0 = min(n, lw * kSpmvRows), r1 = min(n, r0 + kSpmvRows);
+    const int r0 = min(n, lw * rows), r1 = min(n, r0 + rows);
     F* xs = reinterpret_cast<F*>(xwin_lds);
     const int wlo = halo > 0 ? max(0, r0 - halo) : 0;
     const int whi = halo > 0 ? min(n, r1 + halo) - 1 : -1;  // empty window without halo
@@ -250,7 +259,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
     auto gather = [&](int c) -> F { return (c >= wlo && c <= whi) ? xs[c - wlo] : (F)x[c]; };
 
     constexpr int RPS = kWave / G;
-    constexpr int RW = kSpmvRows / (kSpmvThreads / kWave);  // rows per wave
+    const int RW = rows / (kSpmvThreads / kWave);  // rows per wave (at most 64)
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int grp = lane / G, gl = lane % G;
     const int base = r0 + wave * RW;
@@ -352,9 +361,9 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
 // Entries of the SpMV workgroups' rows whose column lies in the near window
 // [r0 - halo, r1 + halo): count[0] += their number.
 __global__ __launch_bounds__(256) void k_spmv_near(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                   int halo, unsigned long long* count) {
+                                                   int halo, int rows, unsigned long long* count) {
     const int w = blockIdx.x;
-    const int r0 = min(n, w * kSpmvRows), r1 = min(n, r0 + kSpmvRows);
+    const int r0 = min(n, w * rows), r1 = min(n, r0 + rows);
     const int lo = max(0, r0 - halo), hi = min(n, r1 + halo);
     unsigned long long c = 0;
     for (int p = rp[r0] + (int)threadIdx.x; p < rp[r1]; p += blockDim.x) c += (ci[p] >= lo && ci[p] < hi);
@@ -362,20 +371,21 @@ __global__ __launch_bounds__(256) void k_spmv_near(int n, const int* __restrict_
 }
 void launch_spmv_near(int n, int grid, const int* rp, const int* ci, int halo, unsigned long long* count,
                       hipStream_t s) {
-    k_spmv_near<<<grid, 256, 0, s>>>(n, rp, ci, halo, count);
+    k_spmv_near<<<grid, 256, 0, s>>>(n, rp, ci, halo, spmv_rows(n, grid), count);
 }
 
 template <typename V, typename F, bool LR>
 static void spmv_dispatch(const CsrView& A, const F* v, const LowRankDev& lr, const V* x, V* y, double* pd,
                           const KrylovState* st, int lanes, int grid, hipStream_t s) {
-    const size_t shm = A.halo > 0 ? (size_t)(kSpmvRows + 2 * A.halo) * sizeof(F) : 0;
+    const int rows = spmv_rows(A.n, grid);
+    const size_t shm = A.halo > 0 ? (size_t)(rows + 2 * A.halo) * sizeof(F) : 0;
     constexpr int T = kSpmvThreads;
     switch (lanes) {
-        case 64: k_spmv<V, F, 64, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
-        case 32: k_spmv<V, F, 32, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
-        case 16: k_spmv<V, F, 16, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
-        case 8: k_spmv<V, F, 8, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
-        default: k_spmv<V, F, 4, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo); break;
+        case 64: k_spmv<V, F, 64, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo, rows); break;
+        case 32: k_spmv<V, F, 32, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo, rows); break;
+        case 16: k_spmv<V, F, 16, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo, rows); break;
+        case 8: k_spmv<V, F, 8, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo, rows); break;
+        default: k_spmv<V, F, 4, 4, LR><<<grid, T, shm, s>>>(A.n, A.rp, A.ci, v, x, y, pd, st, lr, A.halo, rows); break;
     }
 }
 
