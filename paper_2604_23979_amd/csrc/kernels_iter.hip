@@ -1460,8 +1460,9 @@ __global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, c
 template <typename T>
 void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, const BorderDev& bd, KrylovState* st, int it,
                         int mode, hipStream_t s) {
-    int g = (n + 1023) / 1024;
-    if (g > 2048) g = 2048;
+    // one row per thread (every workgroup resident at once up to ~1M rows)
+    int g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
     if (g < 1) g = 1;
     if (bd.k > 0)
         k_pcg_pupdate<T, true><<<g, 256, 0, s>>>(n, (T*)v.p, (const T*)v.z, v.part_rz, v.part_rr, nblocks, bd, st,
