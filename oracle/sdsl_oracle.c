@@ -1182,6 +1182,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     or_prec_fn pf = border ? bjb_apply : bj_apply;
     void* pc = border ? border : (void*)&P;
     double *r = calloc(n, 8), *z = calloc(n, 8), *p = calloc(n, 8), *q = calloc(n, 8);
+    double *xr = calloc(n, 8);  /* x at the last refinement point */
     float *xs = calloc(n, 4), *zs = calloc(n, 4);
     double nb = nrm2(n, b);
     int st = OR_NOT_CONVERGED, it = 0, slow = 0, last = 0;
@@ -1200,7 +1201,10 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         double alpha = rz / pq;
         if (!(pq > 0.0) || !isfinite(alpha)) {
             /* the FP32 operator or factors are not positive definite here:
-             * FP64 PCG solves the residual equation from the current x */
+             * back to x at the last refinement point (the steps since may
+             * already have gone astray), then FP64 PCG solves the residual
+             * equation */
+            memcpy(x, xr, (size_t)n * 8);
             nr = op_true_res(&A, x, b, r);
             if (nr <= tol * nb) { st = OR_OK; break; }
             double* dd = calloc(n, 8);
@@ -1237,6 +1241,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
             }
             rr0 = dot(n, r, r);
             last = it;
+            memcpy(xr, x, (size_t)n * 8);
         }
         mx_prec(&S, border, r, xs, zs, z);
         double rz2 = dot(n, r, z);
@@ -1248,6 +1253,6 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     *relres = nr / nb;
     out[1] = it;
 done:
-    free(r); free(z); free(p); free(q); free(xs); free(zs); free(S.v); free(S.pv);
+    free(r); free(z); free(p); free(q); free(xs); free(zs); free(S.v); free(S.pv); free(xr);
     return st;
 }

@@ -94,6 +94,7 @@ struct sdsl_ctx {
     BorderDev bd{};
     // Krylov workspace
     double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *d = nullptr, *rf = nullptr;
+    double* xref = nullptr;  // mixed mode: the solution at the last refinement point
     double* y = nullptr;     // forward-sweep scratch of the FP64 solve
     float* y32 = nullptr;    // forward-sweep scratch of FP32 solves
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
@@ -831,6 +832,7 @@ struct SolveTask {
             phase = PMIX;
             nr = prev = nb;
             launch_copy<double>(h->n, b, h->r, h->s);
+            launch_fill<double>(h->n, h->xref, 0.0, h->s);
             launch_init_state(h->st, h->part_b, h->grid, tol, h->o.refine_delta, h->s);
             launch_refine_state(h->st, h->part_b, h->grid, 0, h->o.refine_every, h->s);
             pcgmix.start(0);
@@ -1049,7 +1051,11 @@ struct SolveTask {
         if (s.done && s.breakdown) {
             // (p, Mp) <= 0: the FP32 operator or factors are not positive
             // definite for this system, so the search direction is not
-            // continued; FP64 PCG solves the residual equation instead
+            // continued: back to the solution of the last refinement point
+            // (the steps since may already have gone astray), then FP64 PCG
+            // solves the residual equation
+            launch_copy<double>(h->n, h->xref, xout, h->s);
+            nr = true_residual(h, b, xout, h->r);
             start_fallback();
             return;
         }
@@ -1065,6 +1071,7 @@ struct SolveTask {
         }
         // the true residual (now in r) replaces the recurrence one; the
         // recurrence continues with its search direction
+        launch_copy<double>(h->n, xout, h->xref, h->s);
         launch_refine_state(h->st, h->part_res, h->grid, its, h->o.refine_every, h->s);
         if (handed) e64.reapply(its - 1);
         else pcgmix.reapply(its - 1);
@@ -1201,9 +1208,14 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
     b += (n + 1) * 4 + nnz * (4 + 8 + 4) + n * 8;                  // operator + FP32 copy + diag
     b += (n + 1) * 4 + nnz * (4 + 8 + 8) + n * (4 + 4 + 4 + 8);     // filtered pattern, values, factors
     b += nnz * (4 + 8 + 4) + 2 * (n + 1) * 4 + n * (8 + 4);         // split factors + FP32 copies
-    b += n * (8 * 8 + 6 * 4);                                       // Krylov vectors
+    b += (size_t)2 * n * kBjEllWidth * (4 + 8 + 4);                 // interleaved newest entries (L, U)
+    b += (size_t)2 * ((n + 1) * 4 + nnz * (4 + 8 + 4));             // older entries (L, U)
+    b += (size_t)2 * n * (8 + 4);                                   // level-order placement
+    b += n * (9 * 8 + 6 * 4);                                       // Krylov vectors
     b += (nb + 1) * 4 + nb * (8 + 4) + 2048 * 8 * 4 + nb * 8 * 3;
-    if (lr && lr->k > 0) b += (size_t)lr->U.nnz * 2 * (4 + 8) + (n + 1) * 4 + (size_t)lr->k * n * 8;
+    if (lr && lr->k > 0)  // U twice (CSR, CSC), W = P^{-1} U, K and its inverse, reduction partials
+        b += (size_t)lr->U.nnz * 2 * (4 + 8) + (n + 1) * 4 + (size_t)lr->k * n * 8 + (size_t)lr->k * lr->k * 16 +
+             64 * 1024;
     b += (n + 1023) / 1024 * 4 + 4096;
     return b;
 }
@@ -1336,6 +1348,7 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->y = h->alloc<double>(n);
         h->d = h->alloc<double>(n);
         h->rf = h->alloc<double>(n);
+        h->xref = h->alloc<double>(n);
         h->x32 = h->alloc<float>(n);
         h->r32 = h->alloc<float>(n);
         h->z32 = h->alloc<float>(n);

@@ -46,7 +46,16 @@ def footprint(system, options: B.Options) -> int:
     bp = np.ascontiguousarray(system.block_ptr, dtype=np.int32)
     part = B.Partition(bp.shape[0] - 1, bp.ctypes.data_as(C.c_void_p), int(getattr(system, "n_border", 0)))
     o = options.c()
-    return int(B.lib().sdsl_footprint_bytes(C.byref(A), C.byref(part), C.byref(o), None))
+    lr = None
+    low = getattr(system, "lowrank", None)
+    if low is not None:
+        # only the sizes are read: k, nnz(U), n
+        U = low[0]
+        urp = np.ascontiguousarray(U.indptr, dtype=np.int64)
+        lr = B.LowRank(U.shape[1], B.CSR(rp.shape[0] - 1, int(U.nnz), urp.ctypes.data_as(C.c_void_p), None, None,
+                                         B.MEM_HOST), None)
+    return int(B.lib().sdsl_footprint_bytes(C.byref(A), C.byref(part), C.byref(o),
+                                            C.byref(lr) if lr is not None else None))
 
 
 class Server:

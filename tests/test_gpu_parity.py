@@ -593,3 +593,18 @@ def test_set_max_iter_caps_a_solve(prec):
     with pytest.raises(sd.SdslError):
         sv.set_max_iter(0)
     sv.close()
+
+
+@pytest.mark.parametrize("name", ["C1", "C2x0.02"])
+def test_footprint_prediction_covers_the_handle(name):
+    """The admission control's prediction (sdsl_footprint_bytes) is at least
+    what a handle really holds on the device, the Krylov workspace
+    included."""
+    from paper_2604_23979_amd.serve import footprint
+    s = gen.c1() if name == "C1" else gen.c2(0.02)
+    o = sd.Options(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    sv = sd.from_system(s, o)
+    sv.solve(tdev(s.b))
+    held = sv.info()["device_bytes"]
+    assert footprint(s, o) >= held
+    sv.close()

@@ -581,3 +581,16 @@ def test_reliable_update_fp32_reaches_tolerance_near_fp64_count():
     Pt = O.BJ(t)
     x, pts, it, fb, rr, st = O.ru_pcg_bj(t, Pt, tol=1e-12, delta=0.1)
     assert st == O.OK and rr <= 1e-12 and it <= 4
+
+
+def test_mixed_recurrence_breakdown_falls_back_to_fp64():
+    """An IPM system whose FP32 rounding is not positive definite (rows of M
+    that hold only the 1e-8 regularisation): the mixed recurrence breaks down
+    and the FP64 residual-equation solve, started from the solution of the
+    last refinement point, still reaches the tolerance."""
+    q = gen.IPMSequence(m=20000, nblocks=1, steps=30)
+    s = q.system(1)
+    P = O.BJ(s, mode=O.FILTER_GEOMEAN, tau=1e-3, flags=O.DIAG_DROPSUM)
+    x, points, its, fallbacks, rr, st = O.mx_pcg_bj(s, P, tol=1e-8, delta=0.3, every=500, maxit=20000)
+    assert st == O.OK and fallbacks >= 1 and its < 1000
+    assert O.relres(s, x) <= 1e-8
