@@ -1205,9 +1205,11 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
     if (!A || !p || !o || A->n <= 0 || A->nnz < 0) return 0;
     const size_t n = (size_t)A->n, nnz = (size_t)A->nnz, nb = (size_t)std::max(p->nblocks, 1);
     size_t b = 0;
-    b += (n + 1) * 4 + nnz * (4 + 8 + 4) + n * 8;                  // operator + FP32 copy + diag
+    b += (n + 1) * (8 + 4) + nnz * (4 + 8 + 4) + n * 8;            // operator + FP32 copy + diag
     b += (n + 1) * 4 + nnz * (4 + 8 + 8) + n * (4 + 4 + 4 + 8);     // filtered pattern, values, factors
-    b += nnz * (4 + 8 + 4) + 2 * (n + 1) * 4 + n * (8 + 4);         // split factors + FP32 copies
+    // split factors (L and U each sized for every entry) + FP32 copies, the
+    // U diagonal, chunk tables, levels
+    b += (size_t)2 * nnz * (4 + 8 + 4) + 2 * (n + 1) * 4 + n * (8 + 4 + 2 * (8 + 4 + 4)) + 2 * nb * 12;
     b += (size_t)2 * n * kBjEllWidth * (4 + 8 + 4);                 // interleaved newest entries (L, U)
     b += (size_t)2 * ((n + 1) * 4 + nnz * (4 + 8 + 4));             // older entries (L, U)
     b += (size_t)2 * n * (8 + 4);                                   // level-order placement
