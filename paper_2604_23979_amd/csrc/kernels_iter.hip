@@ -1083,7 +1083,7 @@ __device__ __forceinline__ F bj_value(int j, bool inring, const Bits* ring, int 
 template <bool FWD, int MODE, typename V, typename F>
 __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* z, int lo, int hi, int t,
                                          typename Sentinel<F>::Bits* ring, int* pka, F* pkw, int* soc, F* sov,
-                                         const int* nltab, const int* nlg, double& rz, int& bad) {
+                                         F* spr, const int* nltab, const int* nlg, double& rz, int& bad) {
     using Bits = typename Sentinel<F>::Bits;
     constexpr Bits SENT = Sentinel<F>::bits;
     constexpr int RING = BjRing<F>::size;
@@ -1124,7 +1124,9 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
         auto in_ring = [&](int j) { return FWD ? j >= ring_edge : j < ring_edge; };
         auto earlier = [&](int j) { return FWD ? j < ca : j >= cb; };
         auto roff = [&](int j) { return (unsigned)((j - lo) & (RING - 1)) * (unsigned)sizeof(Bits); };
-        // the chunk's older entries go to LDS
+        // the chunk's older entries go to LDS; for one on an earlier chunk
+        // (its solution value is final) the thread staging it also forms its
+        // product, so that the rows only subtract
         if (cu.ocnt > 0) {
 #pragma unroll
             for (int k = 0; k < kStageOld / kBjThreads; ++k) {
@@ -1132,6 +1134,8 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
                 if (e < cu.ocnt) {
                     soc[e] = sc[k];
                     sov[e] = sv[k];
+                    spr[e] = earlier(sc[k]) ? sv[k] * bj_value<FWD, RING, V, F>(sc[k], in_ring(sc[k]), ring, lo, y, z)
+                                            : F(0);
                 }
             }
         }
@@ -1154,8 +1158,34 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
             }
         };
         if (live) {
-            // older entries while on earlier chunks, four in flight
+            // older entries while on earlier chunks: the staged ones as
+            // ready products, four at a time; any past the stage through the
+            // general path
             bool open = true;
+            const int sb = cu.o0 - cu.obase;
+            while (open && opos < nold && sb + opos < kStageOld) {
+                int jj[4];
+                F pp[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (opos + u < nold && sb + opos + u < kStageOld) {
+                        jj[u] = soc[sb + opos + u];
+                        pp[u] = spr[sb + opos + u];
+                    }
+                }
+                const int o4 = opos;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (open && o4 + u < nold && sb + o4 + u < kStageOld) {
+                        if (earlier(jj[u])) {
+                            acc = acc - pp[u];
+                            ++opos;
+                        } else {
+                            open = false;
+                        }
+                    }
+                }
+            }
             while (open && opos < nold) {
                 int jj[4];
                 F ww[4], vv[4];
@@ -1295,6 +1325,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
     __shared__ F pkw[kPark * kBjThreads];
     __shared__ int soc[kStageOld];
     __shared__ F sov[kStageOld];
+    __shared__ F spr[kStageOld];
     __shared__ double red[16];
     __shared__ int shd;
     __shared__ int lnl[kTab];
@@ -1360,9 +1391,9 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
     int bad = 0;
     double rz = 0.0;
     // forward substitution y_i = r_i - sum_{j<i} l_ij y_j (MODE 4: y given)
-    if (MODE != 4 && lo < hi) bj_sweep<true, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, lnl, P.lnl + lo + b, rz, bad);
+    if (MODE != 4 && lo < hi) bj_sweep<true, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, spr, lnl, P.lnl + lo + b, rz, bad);
     // backward substitution z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii (MODE 3: not done)
-    if (MODE != 3 && lo < hi) bj_sweep<false, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, unl, P.unl + lo + b, rz, bad);
+    if (MODE != 3 && lo < hi) bj_sweep<false, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, spr, unl, P.unl + lo + b, rz, bad);
     if (bad && st) atomicExch(&st->spin_err, 1);
     if (MODE == 1 || MODE == 2) {
         rz = block_sum(rz, red);
