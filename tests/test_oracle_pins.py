@@ -583,6 +583,97 @@ def test_reliable_update_fp32_reaches_tolerance_near_fp64_count():
     assert st == O.OK and rr <= 1e-12 and it <= 4
 
 
+def _mixed_case(lowrank, border, n=60, seed=40):
+    s, a = _small_spd(n, seed)
+    md = a.copy()
+    if lowrank:
+        rng = np.random.default_rng(seed + 1)
+        U = sp.random(n, 3, density=0.5, random_state=rng, data_rvs=rng.standard_normal, format="csr")
+        U.sort_indices()
+        c = rng.uniform(0.5, 2.0, 3)
+        s.lowrank = (U, c)
+        ud = U.toarray()
+        md = md + ud @ np.diag(c) @ ud.T
+    P = O.BJ(s, policy=O.PIVOT_FAIL, spd=True, border=border)
+    assert P.status == O.OK
+    L, Uf = unpack_lu(P.rp, P.ci, P.v, n)
+    pm = L @ Uf
+    if lowrank and border:
+        pm = pm + ud @ np.diag(c) @ ud.T
+    return s, P, md, np.linalg.inv(pm)
+
+
+@pytest.mark.parametrize("lowrank,border", [(False, False), (True, False), (True, True)],
+                         ids=["plain", "lowrank", "border"])
+def test_mixed_recurrence_is_fp64_cg_up_to_fp32_rounding(lowrank, border):
+    """Before its first refinement point the mixed recurrence is preconditioned
+    CG (Sec. 2.2) whose operator product and preconditioner apply are rounded
+    to FP32: its k-th iterate is the M-norm minimiser over
+    K_k(P^-1 M, P^-1 b), computed here in FP64 with dense algebra, up to a
+    perturbation of order k * u32 * kappa(P^-1 M) (u32 = 2^-24).  Both
+    halves are pinned: the iterate is that close (a dropped term, a wrong
+    sign or a transposed factor is off by O(1)), and no closer than FP64
+    rounding allows (the FP32 rounding really happens)."""
+    s, P, md, pinv = _mixed_case(lowrank, border)
+    kappa = np.linalg.cond(pinv @ md)
+    u32 = 2.0 ** -24
+    devs = []
+    for k in range(1, 7):
+        # delta 0 and no periodic refresh: no refinement point before maxit
+        x, points, its, fallbacks, rr, st = O.mx_pcg_bj(s, P, tol=1e-30, delta=0.0, every=0, maxit=k)
+        assert (points, its, fallbacks, st) == (0, k, 0, O.NOT_CONVERGED)
+        K = [pinv @ s.b]
+        for _ in range(k - 1):
+            K.append(pinv @ (md @ K[-1]))
+        Q, _ = np.linalg.qr(np.array(K).T)
+        xb = Q @ np.linalg.solve(Q.T @ md @ Q, Q.T @ s.b)
+        e = x - xb
+        devs.append(np.sqrt(e @ md @ e) / np.sqrt(xb @ md @ xb))
+        assert devs[-1] <= k * u32 * kappa, (k, devs[-1], k * u32 * kappa)
+        assert rr == pytest.approx(np.linalg.norm(s.b - md @ x) / np.linalg.norm(s.b), rel=1e-10)
+    assert min(devs) >= 1e-10
+
+
+def test_mixed_first_step_rounds_only_the_sparse_product_to_fp32():
+    """One-row blocks with power-of-two diagonals and FP32-representable
+    data: the FP32 preconditioner apply is exact, so after one step the mixed
+    iterate differs from FP64 CG (x1 = (b,z)/(z,Mz) z with z = D^-1 b) only
+    through the FP32 sparse product.  The textbook bound for a rounded
+    product, |fl(Az) - Az| <= gamma_m |A||z| (m = longest row), limits the
+    relative change of the step length to gamma_m (|z|,|A||z|)/(z,Mz); the
+    low-rank term, kept in FP64, adds nothing to it (its weights are large, so
+    an FP32 rounding of that term would exceed the bound).  The change must
+    also be above FP64 rounding: the product really is rounded to FP32."""
+    n = 80
+    rng = np.random.default_rng(42)
+    off = sp.random(n, n, density=0.08, random_state=rng, data_rvs=rng.standard_normal).toarray()
+    off = np.triu(off, 1)
+    off = (off + off.T).astype(np.float32).astype(np.float64)
+    d = 2.0 ** np.ceil(np.log2(np.abs(off).sum(axis=1) + 1.0))
+    a = off + np.diag(d)
+    m = csr_of(a)
+    b = rng.standard_normal(n).astype(np.float32).astype(np.float64)
+    U = sp.random(n, 2, density=0.6, random_state=rng, data_rvs=rng.standard_normal, format="csr")
+    U.sort_indices()
+    c = np.array([4000.0, 2500.0])
+    s = gen.System("jac", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, b,
+                   np.arange(n + 1, dtype=np.int32), lowrank=(U, c))
+    P = O.BJ(s, policy=O.PIVOT_FAIL, spd=True)
+    assert P.status == O.OK
+    ud = U.toarray()
+    md = a + ud @ np.diag(c) @ ud.T
+    z = b / d
+    x1 = (b @ z) / (z @ md @ z) * z
+    x, points, its, fallbacks, rr, st = O.mx_pcg_bj(s, P, tol=1e-30, delta=0.0, every=0, maxit=1)
+    assert (points, its, fallbacks) == (0, 1, 0)
+    rows = np.diff(m.indptr).max()
+    u32 = 2.0 ** -24
+    gamma = rows * u32 / (1 - rows * u32)
+    bound = gamma * (np.abs(z) @ (np.abs(a) @ np.abs(z))) / (z @ md @ z) + 1e-13
+    dev = np.linalg.norm(x - x1) / np.linalg.norm(x1)
+    assert 1e-12 < dev <= bound, (dev, bound)
+
+
 def test_mixed_recurrence_breakdown_falls_back_to_fp64():
     """An IPM system whose FP32 rounding is not positive definite (rows of M
     that hold only the 1e-8 regularisation): the mixed recurrence breaks down
