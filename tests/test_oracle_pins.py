@@ -106,6 +106,48 @@ def test_compensated_residual_is_exact_to_rounding():
         assert abs(r[i] - ex) <= 4 * np.finfo(float).eps * abs(ex) + 1e-300
 
 
+def test_compensated_residual_low_rank_projection_is_exact_to_rounding():
+    """With the low-rank term the projections U^T x are themselves compensated
+    sums: when they cancel almost completely, the residual still equals the
+    exact rational one up to the rounding of each projection and of c_j
+    (a few ulps of |u_ip| c_j |t_j|) and of the final row sum."""
+    rng = np.random.default_rng(3)
+    n, k = 40, 3
+    a = rand_sparse(n, 0.2, rng)
+    x = rng.standard_normal(n)
+    Ud = np.where(rng.random((n, k)) < 0.4, rng.standard_normal((n, k)), 0.0)
+    Ud[-1] = 1.0
+    for j in range(k):
+        # last entry of each column makes sum_i u_ij x_i cancel to ~1e-10
+        Ud[-1, j] = (1e-10 - Ud[:-1, j] @ x[:-1]) / x[-1]
+    c = rng.uniform(0.5, 2.0, k)
+    U = sp.csr_matrix(Ud)
+    U.sort_indices()
+    b = a @ x + 1e-10 * rng.standard_normal(n)
+    m = csr_of(a)
+    r, _ = O.residual(m.indptr, m.indices, m.data, x, b, lowrank=(U, c))
+    t = []
+    for j in range(k):
+        tj = Fraction(0)
+        for i in range(n):
+            if Ud[i, j] != 0.0:
+                tj += Fraction(Ud[i, j]) * Fraction(x[i])
+        t.append(tj)
+    assert max(abs(float(tj)) for tj in t) < 1e-8  # the projections do cancel
+    eps = np.finfo(float).eps
+    for i in range(n):
+        exact = Fraction(b[i])
+        for p in range(m.indptr[i], m.indptr[i + 1]):
+            exact -= Fraction(m.data[p]) * Fraction(x[m.indices[p]])
+        slack = 0.0
+        for j in range(k):
+            if Ud[i, j] != 0.0:
+                exact -= Fraction(Ud[i, j]) * Fraction(c[j]) * t[j]
+                slack += abs(Ud[i, j]) * c[j] * abs(float(t[j]))
+        ex = float(exact)
+        assert abs(r[i] - ex) <= 4 * eps * abs(ex) + 4 * eps * slack + 1e-300
+
+
 # --------------------------------------------------------------- filter / correction
 
 def _golden_filter(mode, kept_key, ds_key, diag_key):
@@ -211,6 +253,20 @@ def test_delta_correction_sign_rule():
     assert dg[1] == 1e-12         # sign(0) = +1 (reading)
 
 
+def test_delta_and_dropsum_corrections_add():
+    """Both flags: the diagonal moves away from zero by delta plus the row's
+    dropped magnitude (Eq. (diagcorr) with the drop-sum variant)."""
+    a = np.array([[4.0, 0.01, 1.0], [0.01, -5.0, 0.0], [1.0, 0.0, 3.0]])
+    m = csr_of(a)
+    rp, ci, v, ds = O.filter_correct(m.indptr, m.indices, m.data, np.array([0, 3]), O.FILTER_MIN, 0.1,
+                                     O.DIAG_DELTA | O.DIAG_DROPSUM, 0.5)
+    dg = {i: v[p] for i in range(3) for p in range(rp[i], rp[i + 1]) if ci[p] == i}
+    assert list(ds) == [0.01, 0.01, 0.0]
+    assert dg[0] == pytest.approx(4.51, rel=1e-15)
+    assert dg[1] == pytest.approx(-5.51, rel=1e-15)
+    assert dg[2] == pytest.approx(3.5, rel=1e-15)
+
+
 # --------------------------------------------------------------- ILU(0)
 
 def test_ilu0_hand_example_tridiagonal():
@@ -279,8 +335,21 @@ def test_ilu0_breakdown_policies():
                    b=np.ones(5), block_ptr=np.array([0, 5], dtype=np.int32))
     fail = O.BJ(s, policy=O.PIVOT_FAIL)
     assert fail.status == O.BREAKDOWN
-    sh = O.BJ(s, policy=O.PIVOT_SHIFT, shift0=0.01)
-    assert sh.status == O.OK and sh.shifts[0] > 0
+    # REPLACE: the failed (last) pivot becomes the corrected diagonal, counted
+    rep = O.BJ(s, policy=O.PIVOT_REPLACE)
+    assert rep.status == O.OK and rep.nfix == 1 and rep.v[rep.dp[4]] == a[4, 4]
+    # SHIFT on a non-unit diagonal (symmetric scaling keeps SPD and the
+    # breakdown): the shift is relative, d + a d, and the doubling from a
+    # small shift0 stops at the first a that works
+    sc = np.array([2.0, 0.5, 3.0, 1.5, 0.25])
+    a = sc[:, None] * a * sc[None, :]
+    s = gen.System("t", *(lambda m: (m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data))(csr_of(a)),
+                   b=np.ones(5), block_ptr=np.array([0, 5], dtype=np.int32))
+    shift0 = 1e-4
+    sh = O.BJ(s, policy=O.PIVOT_SHIFT, shift0=shift0)
+    assert sh.status == O.OK and sh.shifts[0] > shift0
+    j = np.log2(sh.shifts[0] / shift0)
+    assert j == np.round(j)  # shift0 * 2^j
     a2 = a + np.diag(sh.shifts[0] * np.diag(a))
     m2 = csr_of(a2)
     v, dp, st, _, _ = O.ilu0(m2.indptr, m2.indices, m2.data, spd=True)
@@ -288,7 +357,16 @@ def test_ilu0_breakdown_policies():
     # the smaller shift a/2 still breaks down (first success of the doubling)
     a3 = a + np.diag(sh.shifts[0] / 2 * np.diag(a))
     m3 = csr_of(a3)
-    assert sh.shifts[0] == 0.01 or O.ilu0(m3.indptr, m3.indices, m3.data, spd=True)[2] == O.BREAKDOWN
+    assert O.ilu0(m3.indptr, m3.indices, m3.data, spd=True)[2] == O.BREAKDOWN
+
+
+def test_ilu0_zero_pivot_is_a_breakdown_in_spd_mode():
+    """A positive semidefinite block whose elimination gives an exactly zero
+    pivot: SPD mode needs a positive pivot, so FAIL reports a breakdown."""
+    a = np.array([[1.0, 1.0], [1.0, 1.0]])
+    m = csr_of(a)
+    v, dp, st, nfix, bad = O.ilu0(m.indptr, m.indices, m.data, spd=True)
+    assert st == O.BREAKDOWN and bad == 1
 
 
 # --------------------------------------------------------------- BJ apply
@@ -389,6 +467,27 @@ def test_pcg_c1_true_residual():
     assert np.sqrt(e @ (M @ e)) / np.sqrt(xs @ (M @ xs)) < 1e-4
 
 
+def test_pcg_stops_on_the_true_residual_only():
+    """An IPM system whose attainable accuracy (about 5e-10, set by the 1e-8
+    regularisation) is above the requested 1e-10: the recurrence residual
+    falls below the tolerance, but PCG only stops when the true residual
+    does, so the solve ends not converged and reports the true residual."""
+    q = gen.IPMSequence(m=3000, nblocks=4, steps=30)
+    s = q.system(5)
+    P = O.BJ(s, mode=O.FILTER_GEOMEAN, tau=1e-3, flags=O.DIAG_DROPSUM)
+    x, its, rr, st, h = O.pcg_bj(s, P, tol=1e-10, maxit=1000, hist=True)
+    assert np.any(h <= 1e-10)  # the recurrence met the tolerance
+    assert st == O.NOT_CONVERGED and its == 1000
+    # the true residual at this level needs more than FP64 (a plain FP64
+    # product is ~10% off here): x86 extended precision, 64-bit mantissa
+    M = s.scipy()
+    ld = np.longdouble
+    prod = M.data.astype(ld) * x[M.indices].astype(ld)
+    res = s.b.astype(ld) - np.add.reduceat(prod, M.indptr[:-1])
+    true = float(np.sqrt(np.sum(res * res)) / np.sqrt(np.sum(s.b.astype(ld) ** 2)))
+    assert rr > 1e-10 and rr == pytest.approx(true, rel=1e-3)
+
+
 # --------------------------------------------------------------- GMRES
 
 def test_gmres_iterates_minimise_residual():
@@ -429,6 +528,34 @@ def test_gmres_full_dimension_converges():
     assert st == O.OK and its <= n
 
 
+def test_gmres_cycles_keep_the_arnoldi_residual_true():
+    """Restarted GMRES on badly row-scaled systems it cannot solve in 600
+    steps: in exact arithmetic the least-squares residual |g_{j+1}| at the end
+    of a cycle is the true residual of the updated iterate, and no cycle
+    raises the residual above that of the previous one.  Both survive
+    rounding only while the Krylov basis stays orthogonal to working
+    accuracy, which classical Gram-Schmidt applied twice provides and a
+    single pass does not (there the two differ by factors of 2-10)."""
+    for seed in range(3):
+        rng = np.random.default_rng(100 + seed)
+        n = 400
+        a = rand_sparse(n, 0.02, rng, dd=0.05)
+        a = np.diag(10.0 ** rng.uniform(-5, 5, n)) @ a
+        m = csr_of(a)
+        s = gen.System("ns", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                       rng.standard_normal(n), gen.contiguous_blocks(n, 40))
+        P = O.BJ(s, spd=False, policy=O.PIVOT_FAIL)
+        prev = 1.0
+        for cycles in (2, 5, 10):
+            x, its, rr, st, h = O.gmres_bj(s, P, tol=1e-13, m=60, maxit=60 * cycles, hist=True)
+            assert its == 60 * cycles
+            true = np.linalg.norm(s.b - a @ x) / np.linalg.norm(s.b)
+            assert rr == pytest.approx(true, rel=1e-8)
+            assert abs(h[-1] / rr - 1.0) <= 1e-2, (seed, cycles, h[-1], rr)
+            assert rr <= prev * (1 + 1e-6)
+            prev = rr
+
+
 # --------------------------------------------------------------- BBD
 
 def _bbd_dense_parts(s, P):
@@ -441,9 +568,25 @@ def _bbd_dense_parts(s, P):
     return M, L, U, E, F, Cc, parts
 
 
-def test_bbd_schur_and_apply_match_dense():
+def _with_early_border_rows(s):
+    """Border rows that reach interior columns left of every row with a
+    border-column entry: the tail must start at those columns."""
+    M = s.scipy().tolil()
+    ni = s.n - s.n_border
+    M[ni, int(s.block_ptr[0]) + 1] = 0.3
+    M[ni + 5, int(s.block_ptr[2]) + 7] = -0.4
+    M = M.tocsr()
+    M.sort_indices()
+    return gen.System("bbd-early", M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data, s.b,
+                      s.block_ptr, n_border=s.n_border)
+
+
+@pytest.mark.parametrize("early", [False, True], ids=["generated", "early-border-rows"])
+def test_bbd_schur_and_apply_match_dense(early):
     s = gen.bbd_system(nblocks=3, block_rows=60, n_border=12, nnz_off=4, half_band=10, tail_frac=0.2,
                        border_c=2, seed=14, name="bbd-tiny")
+    if early:
+        s = _with_early_border_rows(s)
     P = O.BBD(s)
     assert P.status == O.OK
     M, L, U, E, F, Cc, parts = _bbd_dense_parts(s, P)
@@ -473,6 +616,8 @@ def test_bbd_schur_and_apply_match_dense():
         rows_e = np.nonzero(np.any(E[lo:hi] != 0, axis=1))[0]
         cols_f = np.nonzero(np.any(F[:, lo:hi] != 0, axis=0))[0]
         assert parts["tail"][b] == lo + min(rows_e.min(), cols_f.min())
+    if early:
+        assert parts["tail"][0] == s.block_ptr[0] + 1 and parts["tail"][2] == s.block_ptr[2] + 7
 
 
 def test_bbd_exact_blocks_gmres_one_step():
@@ -486,11 +631,13 @@ def test_bbd_exact_blocks_gmres_one_step():
     assert st == O.OK and its == 1 and rr <= 1e-10
 
 
-def test_bbd_rejects_block_coupling():
+@pytest.mark.parametrize("row,col", [(0, 45), (29, 30), (30, 29)],
+                         ids=["inside", "next-block-first-column", "previous-block-last-column"])
+def test_bbd_rejects_block_coupling(row, col):
     s = gen.bbd_system(nblocks=2, block_rows=30, n_border=6, nnz_off=2, half_band=4, tail_frac=0.2,
                        border_c=1, seed=17)
     M = s.scipy().tolil()
-    M[0, 45] = 1.0  # block 0 row -> block 1 column
+    M[row, col] = 1.0  # an interior row of one block -> an interior column of another
     M = M.tocsr()
     M.sort_indices()
     s2 = gen.System("bad", M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data, s.b,
@@ -507,6 +654,12 @@ def test_dense_lu_matches_lapack():
     assert np.allclose(lu, lu_ref, rtol=1e-12, atol=1e-13)
     b = rng.standard_normal(70)
     assert np.allclose(O.dense_lu_solve(lu, piv, b), np.linalg.solve(a, b), rtol=1e-10)
+    # ties in the first column: the first row of largest magnitude is taken
+    a[:, 0] = rng.choice([-3.0, -2.0, 1.0, 2.0, 3.0], 70)
+    lu, piv, st = O.dense_lu(a)
+    lu_ref, piv_ref = sl.lu_factor(a)
+    assert st == O.OK and piv[0] == np.flatnonzero(np.abs(a[:, 0]) == 3.0)[0]
+    assert np.array_equal(piv, piv_ref)
 
 
 # --------------------------------------------------------------- IR
