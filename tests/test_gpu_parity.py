@@ -320,8 +320,23 @@ def test_breakdown_policies_on_device():
     sv.close()
     sv = sd.from_system(s, sd.Options(pivot=sd.PIVOT_REPLACE))
     P = O.BJ(s, policy=O.PIVOT_REPLACE)
-    assert np.array_equal(sv.factors()["lu"], P.v) and sv.info()["pivot_fixes"] == P.nfix
+    assert np.array_equal(sv.factors()["lu"], P.v) and sv.info()["pivot_fixes"] == P.nfix == 1
+    assert P.v[P.dp[4]] == a[4, 4]
     sv.close()
+    # non-unit diagonal and a small first shift: the relative shift d + a d
+    # after several doublings, bit for bit as in the oracle
+    sc = np.array([2.0, 0.5, 3.0, 1.5, 0.25])
+    s = _tiny(sc[:, None] * a * sc[None, :], [0, 5])
+    sv = sd.from_system(s, sd.Options(pivot=sd.PIVOT_SHIFT, shift0=1e-4))
+    P = O.BJ(s, policy=O.PIVOT_SHIFT, shift0=1e-4)
+    f = sv.factors()
+    assert P.shifts[0] > 1e-4
+    assert np.array_equal(f["shifts"], P.shifts) and np.array_equal(f["lu"], P.v)
+    sv.close()
+    # an exactly zero pivot is a breakdown in SPD mode
+    with pytest.raises(sd.SdslError) as e:
+        sd.from_system(_tiny([[1.0, 1.0], [1.0, 1.0]], [0, 2]), sd.Options(pivot=sd.PIVOT_FAIL))
+    assert e.value.status == sd.E_BREAKDOWN
 
 
 def test_not_converged_and_max_iter():
@@ -330,6 +345,33 @@ def test_not_converged_and_max_iter():
     x, its, rr, st = sv.solve(tdev(s.b))
     assert st == sd.E_NOT_CONVERGED and its == 3
     assert abs(rr - O.relres(s, x.cpu().numpy())) <= 1e-10
+    sv.close()
+
+
+def test_pcg_stops_on_the_true_residual_only():
+    """An IPM system on which the recurrence residual of PCG meets 1e-10
+    before the true residual does (both the oracle, which stalls near 5e-10,
+    and the GPU restart from the true residual).  Whatever the rounding
+    history, OK means the true residual meets the tolerance, anything else
+    ends at max_iter, and the reported residual is the true one (checked in
+    x86 extended precision)."""
+    q = gen.IPMSequence(m=3000, nblocks=4, steps=30)
+    s = q.system(5)
+    o = opts(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM, max_iter=1000)
+    sv = sd.from_system(s, o)
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-10)
+    xs = x.cpu().numpy()
+    M = s.scipy()
+    ld = np.longdouble
+    res = s.b.astype(ld) - np.add.reduceat(M.data.astype(ld) * xs[M.indices].astype(ld), M.indptr[:-1])
+    true = float(np.sqrt(np.sum(res * res)) / np.sqrt(np.sum(s.b.astype(ld) ** 2)))
+    print(f"  its {its} status {st} relres {rr:.3e} (extended {true:.3e}) restarts {sv.info()['restarts']}")
+    assert sv.info()["restarts"] >= 1
+    assert rr == pytest.approx(true, rel=1e-3)
+    if st == sd.OK:
+        assert true <= 1e-10 and its < 1000
+    else:
+        assert st == sd.E_NOT_CONVERGED and its == 1000 and true > 1e-10
     sv.close()
 
 
@@ -411,6 +453,38 @@ def test_gmres_bj_matches_oracle(which):
     assert abs(its - its_o) <= max(2, 0.1 * its_o)
     xs = x.cpu().numpy()
     assert np.linalg.norm(xs - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    sv.close()
+
+
+def _row_scaled_system(seed, n=400):
+    """Nonsymmetric, weakly dominant, rows scaled over 1e-5..1e5: GMRES(60)
+    makes slow progress, which keeps a long run of cycles meaningful."""
+    rng = np.random.default_rng(100 + seed)
+    a = sp.random(n, n, density=0.02, random_state=rng, data_rvs=rng.standard_normal).toarray()
+    np.fill_diagonal(a, 0.0)
+    np.fill_diagonal(a, 0.05 * np.abs(a).sum(axis=1) + 1.0)
+    a = np.diag(10.0 ** rng.uniform(-5, 5, n)) @ a
+    m = sp.csr_matrix(a)
+    m.sort_indices()
+    return gen.System("rowscaled", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                      rng.standard_normal(n), gen.contiguous_blocks(n, 40))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gmres_long_run_on_row_scaled_system(seed):
+    """600 steps of GMRES(60) that do not converge: the true residual after
+    the run matches the oracle's (both orthogonalise with classical
+    Gram-Schmidt applied twice; a basis that lost orthogonality would let
+    the residual drift by factors of 2-10) and stays below ||b||."""
+    s = _row_scaled_system(seed)
+    o = opts(krylov=sd.GMRES, spd=False, pivot=sd.PIVOT_FAIL, restart=60, max_iter=600)
+    sv = sd.from_system(s, o)
+    P = O.BJ(s, **oracle_opts(o))
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-13)
+    x_o, its_o, rr_o, st_o, _ = O.gmres_bj(s, P, tol=1e-13, m=60, maxit=600)
+    print(f"  seed {seed}: GPU its {its} relres {rr:.4e}; oracle its {its_o} relres {rr_o:.4e}")
+    assert st == sd.E_NOT_CONVERGED and its == its_o == 600
+    assert rr <= 1.0 and abs(rr - rr_o) <= 0.05 * rr_o
     sv.close()
 
 
@@ -515,11 +589,48 @@ def test_bbd_exact_blocks_one_step():
     sv.close()
 
 
-def test_bbd_rejects_block_coupling():
+def test_bbd_early_border_rows_match_oracle():
+    """Border rows that reach interior columns far left of every row with a
+    border-column entry: the tails start at those columns (nearly whole
+    blocks), and the Schur LU, the apply and the GMRES solve still match the
+    oracle."""
+    s = gen.bbd_system(nblocks=3, block_rows=600, n_border=96, nnz_off=4, half_band=10, tail_frac=0.1,
+                       border_c=2, seed=14, name="bbd-early")
+    M = s.scipy().tolil()
+    ni = s.n - s.n_border
+    M[ni, 1] = 0.3
+    M[ni + 5, 1207] = -0.4
+    M = M.tocsr()
+    M.sort_indices()
+    s = gen.System("bbd-early", M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data, s.b,
+                   s.block_ptr, n_border=s.n_border)
+    sv = sd.from_system(s, opts(**BBD_OPTS))
+    P = O.BBD(s)
+    assert P.status == O.OK
+    assert list(P.parts()["tail"][[0, 2]]) == [1, 1207]
+    lu, piv, inv = sv.schur()
+    parts = P.parts()
+    assert np.array_equal(piv, parts["piv"].astype(np.int32))
+    assert np.max(np.abs(lu - parts["S"])) <= 1e-10 * np.max(np.abs(parts["S"]))
+    r = np.random.default_rng(22).standard_normal(s.n)
+    z = sv.precond_apply(tdev(r)).cpu().numpy()
+    zo = P.apply(r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+    x_o, its_o, rr_o, st_o, _ = O.gmres_bbd(s, P, tol=1e-8, m=30)
+    print(f"  GPU its {its} relres {rr:.2e}; oracle its {its_o} relres {rr_o:.2e}")
+    assert st == sd.OK and st_o == O.OK and O.relres(s, x.cpu().numpy()) <= 1e-8
+    assert abs(its - its_o) <= max(2, 0.1 * its_o)
+    sv.close()
+
+
+@pytest.mark.parametrize("row,col", [(0, 450), (299, 300), (300, 299)],
+                         ids=["inside", "next-block-first-column", "previous-block-last-column"])
+def test_bbd_rejects_block_coupling(row, col):
     s = gen.bbd_system(nblocks=2, block_rows=300, n_border=64, nnz_off=2, half_band=4, tail_frac=0.2,
                        border_c=1, seed=17)
     M = s.scipy().tolil()
-    M[0, 450] = 1.0  # block 0 row -> block 1 column
+    M[row, col] = 1.0  # an interior row of one block -> an interior column of another
     M = M.tocsr()
     M.sort_indices()
     s2 = gen.System("bad", M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data, s.b,

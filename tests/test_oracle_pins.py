@@ -468,10 +468,10 @@ def test_pcg_c1_true_residual():
 
 
 def test_pcg_stops_on_the_true_residual_only():
-    """An IPM system whose attainable accuracy (about 5e-10, set by the 1e-8
-    regularisation) is above the requested 1e-10: the recurrence residual
-    falls below the tolerance, but PCG only stops when the true residual
-    does, so the solve ends not converged and reports the true residual."""
+    """An IPM system on which this PCG's true residual stalls near 5e-10
+    while its recurrence residual falls below the requested 1e-10: PCG only
+    stops when the true residual meets the tolerance, so the solve ends not
+    converged and reports the true residual."""
     q = gen.IPMSequence(m=3000, nblocks=4, steps=30)
     s = q.system(5)
     P = O.BJ(s, mode=O.FILTER_GEOMEAN, tau=1e-3, flags=O.DIAG_DROPSUM)
