@@ -25,11 +25,13 @@
  *     restarts from the true residual.
  * Every function below is pinned by tests that compare it against dense
  * linear algebra, closed forms, error bounds or brute force on small inputs,
- * with one exception.  In the mixed FP32/FP64 PCG (or_mx_pcg_bj) the
- * iterates between refinement points are pinned to FP64 CG within FP32
- * rounding, but the refinement schedule (when a point is taken, the stall
- * rule, the FP64 hand-off) is parity unpinned: the iteration count it leads
- * to depends on FP32 rounding and is checked only by reaching the tolerance.
+ * with one exception.  In the two FP32 refinement solvers (or_mx_pcg_bj,
+ * or_ir_pcg_bj) the inner iterates are pinned to FP64 CG within FP32
+ * rounding, and the mixed recurrence's refinement trigger is pinned too.
+ * Their stall rules (how many weak refinement steps hand the solve to FP64,
+ * and what counts as weak) are parity unpinned: that hand-off depends on
+ * FP32 rounding, so it is checked only by reaching the tolerance and by the
+ * breakdown case.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared sdsl_oracle.c -lm
  * (-ffp-contract=off keeps every a*b+c as two roundings unless fma() is

@@ -787,6 +787,52 @@ def test_mixed_recurrence_is_fp64_cg_up_to_fp32_rounding(lowrank, border):
     assert min(devs) >= 1e-10
 
 
+def _krylov_minimiser(md, pinv, b, k):
+    K = [pinv @ b]
+    for _ in range(k - 1):
+        K.append(pinv @ (md @ K[-1]))
+    Q, _ = np.linalg.qr(np.array(K).T)
+    return Q @ np.linalg.solve(Q.T @ md @ Q, Q.T @ b)
+
+
+@pytest.mark.parametrize("lowrank,border", [(False, False), (True, False), (True, True)],
+                         ids=["plain", "lowrank", "border"])
+def test_mixed_refinement_point_when_residual_falls_below_delta(lowrank, border):
+    """A refinement point is taken at the first iteration whose recurrence
+    residual is below delta times its value at the previous point (here
+    ||b||).  With delta at the geometric midpoint of the exact CG residuals
+    after 2 and 3 steps, no point is taken in 2 iterations and exactly one
+    in 3."""
+    s, P, md, pinv = _mixed_case(lowrank, border)
+    nb = np.linalg.norm(s.b)
+    h = [np.linalg.norm(s.b - md @ _krylov_minimiser(md, pinv, s.b, k)) / nb for k in (1, 2, 3)]
+    assert h[2] < 0.8 * h[1] and h[2] < h[0]
+    delta = np.sqrt(h[1] * h[2])
+    for maxit, points_expected in ((2, 0), (3, 1)):
+        x, points, its, fallbacks, rr, st = O.mx_pcg_bj(s, P, tol=1e-30, delta=delta, every=0, maxit=maxit)
+        assert (points, its, fallbacks) == (points_expected, maxit, 0)
+
+
+@pytest.mark.parametrize("lowrank,border", [(False, False), (True, False), (True, True)],
+                         ids=["plain", "lowrank", "border"])
+def test_fp32_inner_pcg_is_fp64_cg_up_to_fp32_rounding(lowrank, border):
+    """One refinement step of k inner FP32 PCG iterations gives ||b|| times
+    the k-th FP32 iterate for M d = b / ||b||: the FP64 Krylov minimiser up
+    to k * u32 * kappa(P^-1 M), now with FP32 vectors, FP32 step lengths,
+    the FP32 low-rank term and the FP32 border correction (a dropped term, a
+    wrong sign or a missing rescaling by ||b|| is off by O(1))."""
+    s, P, md, pinv = _mixed_case(lowrank, border)
+    kappa = np.linalg.cond(pinv @ md)
+    u32 = 2.0 ** -24
+    for k in range(1, 7):
+        x, outer, inner, fb, rr, st = O.ir_pcg_bj(s, P, tol=1e-30, inner_tol=1e-30, max_outer=1, maxit=k)
+        assert (outer, inner, fb, st) == (1, k, 0, O.NOT_CONVERGED)
+        xb = _krylov_minimiser(md, pinv, s.b, k)
+        e = x - xb
+        dev = np.sqrt(e @ md @ e) / np.sqrt(xb @ md @ xb)
+        assert 1e-10 < dev <= k * u32 * kappa, (k, dev, k * u32 * kappa)
+
+
 def test_mixed_first_step_rounds_only_the_sparse_product_to_fp32():
     """One-row blocks with power-of-two diagonals and FP32-representable
     data: the FP32 preconditioner apply is exact, so after one step the mixed
