@@ -4,8 +4,6 @@ import ctypes as C
 import os
 import re
 
-import pytest
-
 import paper_2604_23979_amd as sd
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))

@@ -1,7 +1,6 @@
 """Host logic of the interior-point sequence driver (preconditioner reuse with
 a refresh on convergence degradation, Sec. 3.4; block Jacobi -> BBD switch on
 failure, Alg. 1), checked with scripted stand-in solvers on the CPU."""
-import pytest
 
 from paper_2604_23979_amd._binding import E_NOT_CONVERGED, E_STRUCTURE, OK, Options, SdslError, BBD
 from paper_2604_23979_amd.ipm import SequenceSolver
