@@ -180,8 +180,12 @@ typedef struct {
  * refine_every 500. */
 void sdsl_default_options(sdsl_options* o);
 
-/* Device bytes a handle for this problem will hold (for admission control).
- * Returns 0 on invalid arguments. */
+/* Device bytes a handle for this problem will hold (for admission control),
+ * the GMRES basis included when o->krylov is SDSL_GMRES.  For SDSL_BBD the
+ * tail factors depend on the pattern, so A->row_ptr and A->col must then be
+ * readable host memory (A->mem = SDSL_MEM_HOST); otherwise only the sizes are
+ * read.  Returns 0 on invalid arguments, including a BBD pattern that is not
+ * in bordered block diagonal form. */
 size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o,
                             const sdsl_lowrank* lr);
 

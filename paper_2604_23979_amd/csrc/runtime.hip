@@ -262,33 +262,58 @@ void build_border(sdsl_ctx* h) {
 // the distinct border columns of E and rows of F, the dense tail factor
 // layouts, and the positions of the E, F and C entries in the CSR (so that
 // new values only need a gather).
-void setup_bbd(sdsl_ctx* h, const std::vector<int64_t>& rp, const std::vector<int>& ci) {
-    const int n = h->n, ni = h->n_int, nbd = h->nbd, nb = h->nb;
-    const std::vector<int>& bp = h->bp_h;
+struct BbdPattern {
+    std::vector<int> tail;                     // first local row of each block's tail
+    std::vector<std::vector<int>> ecols, frows;  // distinct border columns of E, rows of F
+};
+// The structure above from a validated host pattern (rows [0, n), interior
+// rows [0, ni), blocks bp); the E columns and F rows of a block are sorted
+// and distinct.  Returns the first interior row that couples to another
+// block, or -1.
+static int bbd_pattern(int n, int ni, const std::vector<int>& bp, const int64_t* rp, const int* ci,
+                       BbdPattern& P) {
+    const int nb = (int)bp.size() - 1;
     std::vector<int> blk(ni);
     for (int b = 0; b < nb; ++b)
         for (int i = bp[b]; i < bp[b + 1]; ++i) blk[i] = b;
-    std::vector<int> tail(bp.begin() + 1, bp.end());
+    P.tail.assign(bp.begin() + 1, bp.end());
     for (int i = 0; i < ni; ++i) {
         const int b = blk[i];
         for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
             const int j = ci[q];
-            if (j >= ni) tail[b] = std::min(tail[b], i);
-            else if (j < bp[b] || j >= bp[b + 1])
-                fail(SDSL_E_STRUCTURE, "interior row " + std::to_string(i) + " couples to another block");
+            if (j >= ni) P.tail[b] = std::min(P.tail[b], i);
+            else if (j < bp[b] || j >= bp[b + 1]) return i;
         }
     }
     for (int i = ni; i < n; ++i)
         for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
-            if (ci[q] < ni) tail[blk[ci[q]]] = std::min(tail[blk[ci[q]]], ci[q]);
-    // distinct border columns (E) and rows (F) per block
-    std::vector<std::vector<int>> ecols(nb), frows(nb);
+            if (ci[q] < ni) P.tail[blk[ci[q]]] = std::min(P.tail[blk[ci[q]]], ci[q]);
+    P.ecols.assign(nb, {});
+    P.frows.assign(nb, {});
     for (int i = 0; i < ni; ++i)
         for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
-            if (ci[q] >= ni) ecols[blk[i]].push_back(ci[q] - ni);
+            if (ci[q] >= ni) P.ecols[blk[i]].push_back(ci[q] - ni);
     for (int i = ni; i < n; ++i)
         for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
-            if (ci[q] < ni) frows[blk[ci[q]]].push_back(i - ni);
+            if (ci[q] < ni) P.frows[blk[ci[q]]].push_back(i - ni);
+    for (int b = 0; b < nb; ++b) {
+        std::sort(P.ecols[b].begin(), P.ecols[b].end());
+        P.ecols[b].erase(std::unique(P.ecols[b].begin(), P.ecols[b].end()), P.ecols[b].end());
+        std::sort(P.frows[b].begin(), P.frows[b].end());
+        P.frows[b].erase(std::unique(P.frows[b].begin(), P.frows[b].end()), P.frows[b].end());
+    }
+    return -1;
+}
+
+void setup_bbd(sdsl_ctx* h, const std::vector<int64_t>& rp, const std::vector<int>& ci) {
+    const int n = h->n, ni = h->n_int, nbd = h->nbd, nb = h->nb;
+    const std::vector<int>& bp = h->bp_h;
+    BbdPattern P;
+    const int bad = bbd_pattern(n, ni, bp, rp.data(), ci.data(), P);
+    if (bad >= 0) fail(SDSL_E_STRUCTURE, "interior row " + std::to_string(bad) + " couples to another block");
+    std::vector<int>& tail = P.tail;
+    std::vector<std::vector<int>>& ecols = P.ecols;
+    std::vector<std::vector<int>>& frows = P.frows;
     h->bbd_ne.assign(nb, 0);
     h->bbd_nf.assign(nb, 0);
     h->bbd_hoff.assign(nb + 1, 0);
@@ -300,10 +325,6 @@ void setup_bbd(sdsl_ctx* h, const std::vector<int64_t>& rp, const std::vector<in
     std::vector<int> epos(nbd, -1), fpos(nbd, -1);
     std::vector<std::vector<std::pair<int, int>>> fslots(nbd);  // border row -> (block, column)
     for (int b = 0; b < nb; ++b) {
-        std::sort(ecols[b].begin(), ecols[b].end());
-        ecols[b].erase(std::unique(ecols[b].begin(), ecols[b].end()), ecols[b].end());
-        std::sort(frows[b].begin(), frows[b].end());
-        frows[b].erase(std::unique(frows[b].begin(), frows[b].end()), frows[b].end());
         const int t = bp[b + 1] - tail[b];
         h->bbd_ne[b] = (int)ecols[b].size();
         h->bbd_nf[b] = (int)frows[b].size();
@@ -1219,6 +1240,49 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
         b += (size_t)lr->U.nnz * 2 * (4 + 8) + (n + 1) * 4 + (size_t)lr->k * n * 8 + (size_t)lr->k * lr->k * 16 +
              64 * 1024;
     b += (n + 1023) / 1024 * 4 + 4096;
+    if (o->krylov == SDSL_GMRES) {  // basis V (m + 1 columns), Z = P^{-1} V (m columns), reduction partials
+        const size_t m = (size_t)std::max(1, std::min(o->restart, kMaxBasisHost - 1));
+        b += (2 * m + 1) * n * 8 + ((size_t)512 * kMaxBasisHost + 512 + 3 * kMaxBasisHost) * 8;
+    }
+    if (o->method == SDSL_BBD) {
+        // the tail factors depend on the pattern, which must be readable here
+        const int nbd = p->n_border, ni = A->n - nbd;
+        if (A->mem != SDSL_MEM_HOST || !A->row_ptr || !A->col || !p->block_ptr || nbd <= 0 || ni <= 0 ||
+            p->nblocks <= 0 || A->nnz > INT32_MAX)
+            return 0;
+        const int64_t* rp = A->row_ptr;
+        if (rp[0] != 0 || rp[A->n] != A->nnz) return 0;
+        for (int i = 0; i < A->n; ++i)
+            if (rp[i + 1] < rp[i]) return 0;
+        for (int64_t q = 0; q < A->nnz; ++q)
+            if (A->col[q] < 0 || A->col[q] >= A->n) return 0;
+        const std::vector<int> bp(p->block_ptr, p->block_ptr + p->nblocks + 1);
+        if (bp[0] != 0 || bp[p->nblocks] != ni) return 0;
+        for (int q = 0; q < p->nblocks; ++q)
+            if (bp[q + 1] < bp[q]) return 0;
+        BbdPattern P;
+        if (bbd_pattern(A->n, ni, bp, rp, A->col, P) >= 0) return 0;
+        size_t hg = 0, sne = 0, snf = 0;
+        for (int q = 0; q < p->nblocks; ++q) {
+            const size_t t = (size_t)(bp[q + 1] - P.tail[q]);
+            hg += t * (P.ecols[q].size() + P.frows[q].size());
+            sne += P.ecols[q].size();
+            snf += P.frows[q].size();
+        }
+        size_t ne = 0, nf = 0, nc = 0;  // entries of E, F and the border block C
+        for (int i = 0; i < A->n; ++i)
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+                const bool bc = A->col[q] >= ni;
+                if (i < ni) ne += bc;
+                else if (bc) ++nc;
+                else ++nf;
+            }
+        b += hg * 8;                                       // tail factors H and Gt
+        b += (ne + nf + nc) * 2 * 8;                       // entry positions and targets
+        b += (size_t)2 * nbd * nbd * 8 + (size_t)nbd * (2 * 4 + 8 + 4) + 4;  // S, S^{-1}, pivots, order, g, fptr
+        b += (sne + 2 * snf) * 4 + snf * 8;                // E columns, F rows, F slots, border partials
+        b += (size_t)(p->nblocks + 1) * (6 * 4 + 2 * 8) + 64 * 8;  // per-block tables, one-element minimums
+    }
     return b;
 }
 

@@ -42,7 +42,9 @@ class Request:
 def footprint(system, options: B.Options) -> int:
     """Device bytes a handle for this system is predicted to hold."""
     rp = np.ascontiguousarray(system.row_ptr, dtype=np.int64)
-    A = B.CSR(rp.shape[0] - 1, int(rp[-1]), rp.ctypes.data_as(C.c_void_p), None, None, B.MEM_HOST)
+    ci = np.ascontiguousarray(system.col, dtype=np.int32)   # read for BBD (tail factors)
+    A = B.CSR(rp.shape[0] - 1, int(rp[-1]), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p), None,
+              B.MEM_HOST)
     bp = np.ascontiguousarray(system.block_ptr, dtype=np.int32)
     part = B.Partition(bp.shape[0] - 1, bp.ctypes.data_as(C.c_void_p), int(getattr(system, "n_border", 0)))
     o = options.c()

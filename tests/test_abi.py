@@ -42,6 +42,51 @@ def test_default_options_and_footprint_host_only():
     assert sd.lib().sdsl_footprint_bytes(C.byref(A), C.byref(part), C.byref(o), None) > 0
 
 
+def test_footprint_counts_gmres_basis_and_bbd_tail_factors_host_only():
+    """The admission prediction grows by at least the GMRES basis for GMRES
+    and by the dense Schur complement and its inverse plus the tail factors
+    (per block: tail rows x (distinct border columns + rows)) for BBD.  The
+    tails come from the oracle, the distinct counts from the pattern.  A BBD
+    prediction needs the pattern on the host: without it, or for a pattern
+    that is not bordered block diagonal, the answer is 0."""
+    import numpy as np
+
+    import oracle as O
+    from ipm_inputs import gen
+    from paper_2604_23979_amd.serve import footprint
+
+    s = gen.bbd_system(nblocks=3, block_rows=60, n_border=12, nnz_off=4, half_band=10, tail_frac=0.2,
+                       border_c=2, seed=14, name="bbd-tiny")
+    n, nbd = s.n, s.n_border
+    ni = n - nbd
+    pcg = footprint(s, sd.Options(spd=False))
+    gm = footprint(s, sd.Options(krylov=sd.GMRES, spd=False, restart=30))
+    bbd = footprint(s, sd.Options(method=sd.BBD, krylov=sd.GMRES, spd=False, restart=30))
+    assert gm >= pcg + (2 * 30 + 1) * n * 8
+    tails = O.BBD(s).parts()["tail"]
+    M = s.scipy().tocsr()
+    hg = 0
+    for b in range(s.nblocks):
+        lo, hi = int(s.block_ptr[b]), int(s.block_ptr[b + 1])
+        ne = np.unique(M[lo:hi, ni:].nonzero()[1]).size
+        nf = np.unique(M[ni:, lo:hi].nonzero()[0]).size
+        hg += (hi - int(tails[b])) * (ne + nf)
+    assert bbd >= gm + 2 * nbd * nbd * 8 + 8 * hg
+    o = sd.Options(method=sd.BBD, krylov=sd.GMRES, spd=False).c()
+    rp = np.ascontiguousarray(s.row_ptr, dtype=np.int64)
+    bp = np.ascontiguousarray(s.block_ptr, dtype=np.int32)
+    part = sd._binding.Partition(s.nblocks, bp.ctypes.data_as(C.c_void_p), nbd)
+    A = sd._binding.CSR(n, s.nnz, rp.ctypes.data_as(C.c_void_p), None, None, sd._binding.MEM_HOST)
+    assert sd.lib().sdsl_footprint_bytes(C.byref(A), C.byref(part), C.byref(o), None) == 0
+    bad = M.tolil()
+    bad[0, 70] = 1.0  # block 0 row -> block 1 column
+    bad = bad.tocsr()
+    bad.sort_indices()
+    s_bad = gen.System("bad", bad.indptr.astype(np.int64), bad.indices.astype(np.int32), bad.data, s.b,
+                       s.block_ptr, n_border=nbd)
+    assert footprint(s_bad, sd.Options(method=sd.BBD, krylov=sd.GMRES, spd=False)) == 0
+
+
 def test_setup_rejects_bad_arguments_without_touching_the_device():
     o = sd._binding.COptions()
     sd.lib().sdsl_default_options(C.byref(o))

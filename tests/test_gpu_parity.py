@@ -706,16 +706,25 @@ def test_set_max_iter_caps_a_solve(prec):
     sv.close()
 
 
-@pytest.mark.parametrize("name", ["C1", "C2x0.02"])
+@pytest.mark.parametrize("name", ["C1", "C2x0.02", "C1-gmres", "C3x0.05-bbd"])
 def test_footprint_prediction_covers_the_handle(name):
     """The admission control's prediction (sdsl_footprint_bytes) is at least
-    what a handle really holds on the device, the Krylov workspace
-    included."""
+    what a handle really holds on the device after a solve, the Krylov
+    workspace (the GMRES basis) and, for BBD, the Schur complement, its
+    inverse and the tail factors included."""
     from paper_2604_23979_amd.serve import footprint
-    s = gen.c1() if name == "C1" else gen.c2(0.02)
-    o = sd.Options(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    if name == "C3x0.05-bbd":
+        s = gen.c3(0.05)
+        o = sd.Options(**BBD_OPTS)
+    else:
+        s = gen.c2(0.02) if name == "C2x0.02" else gen.c1()
+        o = sd.Options(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+        if name == "C1-gmres":
+            o = sd.Options(krylov=sd.GMRES, spd=False)
     sv = sd.from_system(s, o)
     sv.solve(tdev(s.b))
     held = sv.info()["device_bytes"]
-    assert footprint(s, o) >= held
+    pred = footprint(s, o)
+    print(f"  {name}: predicted {pred / 1e6:.1f} MB, held {held / 1e6:.1f} MB")
+    assert pred >= held
     sv.close()
