@@ -12,6 +12,48 @@ __device__ __forceinline__ bool krylov_done(const KrylovState* st) {
     return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
+// TwoSum (Knuth): s = fl(a + b) and e = (a + b) - s exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    const double z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+
+// Workgroup sum of (s, e) pairs in which every addition is a TwoSum whose
+// error joins e, so that s + e keeps the rounding of each step; the result
+// is in thread 0.  `scratch` holds >= 2 * blockDim.x / 64 doubles.  Must be
+// reached by all threads.
+__device__ __forceinline__ void block_sum2(double& s, double& e, double* scratch) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double so = __shfl_xor(s, o, kWave), eo = __shfl_xor(e, o, kWave);
+        double t, te;
+        two_sum(s, so, t, te);
+        s = t;
+        e = e + eo + te;
+    }
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (l == 0) {
+        scratch[w] = s;
+        scratch[nw + w] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t0 = scratch[0], e0 = scratch[nw];
+        for (int q = 1; q < nw; ++q) {
+            double t, te;
+            two_sum(t0, scratch[q], t, te);
+            t0 = t;
+            e0 = e0 + scratch[nw + q] + te;
+        }
+        s = t0;
+        e = e0;
+    }
+    __syncthreads();
+}
+
 // Block-uniform read of the done flag (one read, broadcast through LDS).
 __device__ __forceinline__ bool block_done(const KrylovState* st, int* sh) {
     if (threadIdx.x == 0) *sh = st ? (krylov_done(st) ? 1 : 0) : 0;
@@ -112,14 +154,13 @@ __global__ __launch_bounds__(256) void k_lowrank_tdot(LowRankDev lr, const T* __
         }
     }
     if (COMP) {
-        // fold the per-thread pairs; the error terms are summed separately
-        const double tot = block_sum(sum, red);
-        // error of combining the thread sums is bounded by u*sum(|sum_t|); add
-        // the per-thread corrections, which dominate for long columns
-        const double terr = block_sum(err, red);
+        // the thread pairs combine with TwoSum as well: under the cancellation
+        // of a converged residual, a plain sum of the thread sums would lose
+        // more than the residual itself once c_j is large
+        block_sum2(sum, err, red);
         if (threadIdx.x == 0) {
-            part[j * slices + s] = tot;
-            part[k * slices + j * slices + s] = terr;
+            part[j * slices + s] = sum;
+            part[k * slices + j * slices + s] = err;
         }
     } else {
         const double tot = block_sum(sum, red);
@@ -406,11 +447,6 @@ template void launch_spmv<float, float>(const CsrView&, const float*, const LowR
 // r = b - M x (- U diag(c) U^T x) with every row accumulated as an
 // error-free (TwoProduct / TwoSum) pair, then rounded once; part[w] gets the
 // workgroup's share of ||r||^2.
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-    s = a + b;
-    const double z = s - a;
-    e = (a - (s - z)) + (b - z);
-}
 
 template <int G, bool LR>
 __global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci,

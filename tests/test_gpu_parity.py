@@ -222,6 +222,68 @@ def test_fp32_inner_refinement(case, prec):
         sv.close()
 
 
+# ------------------------------------------------------------------ full size
+
+# the options the benchmark times on the full C2 system
+BENCH_C2 = dict(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM, pivot=sd.PIVOT_SHIFT, shift0=1e-2,
+                kernel_timing=True, max_iter=60_000, refine_delta=0.3, border=True)
+
+
+@pytest.fixture(scope="module")
+def c2_full():
+    print("\n[case C2 at full size, benchmark options]", flush=True)
+    s = gen.c2(1.0)
+    o = opts(**BENCH_C2)
+    solver = sd.from_system(s, o)
+    P = O.BJ(s, **oracle_opts(o))
+    yield "C2-full", s, o, solver, P
+    solver.close()
+
+
+def test_full_c2_setup_spmv_apply_residual(c2_full):
+    """At the benchmark's size and launch configuration, every output the
+    oracle computes in seconds: the filtered pattern (bitwise), corrected
+    values and factors, the FP64/FP32 SpMV with the low-rank term, the
+    bordered preconditioner apply, and the compensated residual."""
+    test_factor_parity(c2_full)
+    test_spmv_parity(c2_full)
+    test_precond_apply_parity(c2_full)
+    test_residual_parity(c2_full)
+
+
+def test_full_c2_solves(c2_full):
+    """The first PCG iterations against the oracle's (a full oracle solve
+    takes minutes), then complete FP64 and FP32-inner solves, whose true
+    residual the oracle recomputes at full size.  The recurrence on this
+    system amplifies rounding quickly: in the oracle itself, a one-ulp change
+    of b moves the iterate by 1e-14 after 5 iterations, 3e-11 after 10 and
+    2e-2 after 20, so the iterates are compared after 5."""
+    name, s, o, solver, P = c2_full
+    b = tdev(s.b)
+    k = 5
+    solver.set_max_iter(k)
+    x, its, rr, st = solver.solve(b, tol=1e-8)
+    solver.set_max_iter(o.max_iter)
+    xo, its_o, rr_o, st_o, _ = O.pcg_bj(s, P, tol=1e-8, maxit=k)
+    xg = x.cpu().numpy()
+    dx = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"  {k} iterations: GPU relres {rr:.9e}, oracle {rr_o:.9e}, |x - x_oracle| / |x_oracle| = {dx:.2e}")
+    assert st == sd.E_NOT_CONVERGED and its == its_o == k
+    assert abs(rr - rr_o) <= 1e-9 * rr_o and dx <= 1e-9
+    x, its, rr, st = solver.solve(b, tol=1e-8)
+    true_rr = O.relres(s, x.cpu().numpy())
+    print(f"  FP64: {its} iterations, relres {true_rr:.2e}")
+    assert st == sd.OK and true_rr <= 1e-8 and abs(rr - true_rr) <= 1e-3 * true_rr
+    sv = sd.from_system(s, sd.Options(**{**o.__dict__, "precision": sd.FP32_IR}))
+    try:
+        x, its32, rr, st = sv.solve(b, tol=1e-8)
+        true_rr = O.relres(s, x.cpu().numpy())
+        print(f"  FP32-inner: {its32} iterations, relres {true_rr:.2e}")
+        assert st == sd.OK and true_rr <= 1e-8 and abs(rr - true_rr) <= 1e-3 * true_rr
+    finally:
+        sv.close()
+
+
 # ------------------------------------------------------------------ edge cases
 
 def _tiny(a, bp, o=None, b=None):
