@@ -172,6 +172,9 @@ def test_pcg_fp64_matches_oracle(case):
     xo, its_o, rr_o, st_o, _ = O.pcg_bj(s, P, tol=1e-8, maxit=50_000)
     assert st_o == O.OK
     b = tdev(s.b)
+    # the residual of a converged solution, where b and M x cancel to 1e-8
+    _, nr_g = solver.residual(b, tdev(xo))
+    assert abs(nr_g / np.linalg.norm(s.b) - rr_o) <= 1e-6 * rr_o, (nr_g / np.linalg.norm(s.b), rr_o)
     x, its, rr, st = solver.solve(b, tol=1e-8)
     x = x.cpu().numpy()
     true_rr = O.relres(s, x)
