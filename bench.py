@@ -341,8 +341,8 @@ def main():
                     help="profiling run: first copy a buffer of this many bytes three times (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the per-GPU work is the whole workload on one MI355X)", file=sys.stderr)
+        print(f"the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the whole workload runs on one MI355X)", file=sys.stderr)
         sys.exit(2)
 
     import torch
