@@ -1143,8 +1143,10 @@ done:
 /* met the tolerance, or `every` iterations passed) the compensated FP64   */
 /* true residual replaces r; z, (r,z), beta and p are then recomputed and  */
 /* the recurrence continues (reliable updating).  Three consecutive points */
-/* that shrink the true residual by less than 2x switch to FP64 PCG on the */
-/* remaining correction.                                                   */
+/* that shrink the true residual by less than 2x hand the recurrence over  */
+/* to the FP64 operator and factors, same search direction; three more     */
+/* switch to FP64 PCG on the remaining correction.  A breakdown of the     */
+/* recurrence goes to that FP64 PCG directly.                              */
 /* out[0] = refinement points, out[1] = iterations, out[2] = fallbacks.    */
 /* ------------------------------------------------------------------ */
 static void mx_spmv(const or_f32sys* S, const or_op* A, const double* x, float* xs, double* y) {
@@ -1193,6 +1195,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     float *xs = calloc(n, 4), *zs = calloc(n, 4);
     double nb = nrm2(n, b);
     int st = OR_NOT_CONVERGED, it = 0, slow = 0, last = 0;
+    int handed = 0;  /* the recurrence runs on with the FP64 operator and factors */
     out[0] = out[1] = out[2] = 0;
     memset(x, 0, (size_t)n * 8);
     double nr = nb, prev = nb;
@@ -1203,7 +1206,8 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     memcpy(p, z, (size_t)n * 8);
     double rz = dot(n, r, z);
     while (it < maxit) {
-        mx_spmv(&S, &A, p, xs, q);
+        if (handed) op_apply(&A, p, q);
+        else mx_spmv(&S, &A, p, xs, q);
         double pq = dot(n, p, q);
         double alpha = rz / pq;
         if (!(pq > 0.0) || !isfinite(alpha)) {
@@ -1235,7 +1239,11 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
             nr = op_true_res(&A, x, b, r);
             if (nr <= tol * nb) { st = OR_OK; break; }
             slow = (nr > 0.5 * prev) ? slow + 1 : 0;
-            if (slow >= 3) {
+            if (slow >= 3 && !handed) {
+                handed = 1;
+                slow = 0;
+                out[2] += 1;
+            } else if (slow >= 3) {
                 double* dd = calloc(n, 8);
                 int32_t its = 0; double r2 = 0.0;
                 st = pcg_run(&A, pf, pc, r, dd, tol * nb / nr, maxit - it, &its, &r2, NULL);
@@ -1250,7 +1258,8 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
             last = it;
             memcpy(xr, x, (size_t)n * 8);
         }
-        mx_prec(&S, border, r, xs, zs, z);
+        if (handed) pf(pc, r, z);
+        else mx_prec(&S, border, r, xs, zs, z);
         double rz2 = dot(n, r, z);
         double beta = rz2 / rz;
         rz = rz2;
