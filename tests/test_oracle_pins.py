@@ -873,6 +873,19 @@ def test_mixed_first_step_rounds_only_the_sparse_product_to_fp32():
     assert 1e-12 < dev <= bound, (dev, bound)
 
 
+def test_mixed_recurrence_stall_hands_over_and_still_converges():
+    """A late IPM system (D spread about 1e9): the refinement points stop
+    halving the true residual, the recurrence is handed to the FP64 operator
+    and factors (and, if it stalls again, to an FP64 solve of the residual
+    equation), and the result still meets the tolerance, checked with scipy."""
+    q = gen.IPMSequence(m=20000, nblocks=4, steps=30)
+    s = q.system(20)
+    P = O.BJ(s, mode=O.FILTER_GEOMEAN, tau=1e-3, flags=O.DIAG_DROPSUM)
+    x, points, its, fallbacks, rr, st = O.mx_pcg_bj(s, P, tol=1e-8, delta=0.3, every=500, maxit=60000)
+    assert st == O.OK and points >= 3 and fallbacks >= 1
+    assert np.linalg.norm(s.b - s.scipy() @ x) / np.linalg.norm(s.b) <= 1.5e-8
+
+
 def test_mixed_recurrence_breakdown_falls_back_to_fp64():
     """An IPM system whose FP32 rounding is not positive definite (rows of M
     that hold only the 1e-8 regularisation): the mixed recurrence breaks down
