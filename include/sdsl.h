@@ -4,8 +4,8 @@
  *
  * The method is that of "SDSL-Solver: Scalable Distributed Sparse Linear
  * Solvers for Large-Scale Interior Point Methods" (arXiv 2604.23979): at every
- * IPM iteration a sparse system M x = b (Sec. 2.1, Eq. (schur); Alg. 1 takes
- * "Ax = b at each interior-point iteration" as its input) is solved by a
+ * IPM iteration a sparse system M x = b (Sec. 2.1, Eq. (schur); the system of
+ * each interior-point iteration is the input of Alg. 1) is solved by a
  * preconditioned Krylov method (Sec. 2.2, right preconditioning) with either
  *   - a block-Jacobi preconditioner (Sec. 2.3): contiguous row blocks, each
  *     diagonal block filtered (Sec. 3.2, Eq. (filter)), diagonally corrected
@@ -99,7 +99,7 @@ typedef struct {
     sdsl_mem mem;
 } sdsl_csr;
 
-/* Contiguous row blocks (Sec. 2.3 "partition"): block_ptr is a HOST array of
+/* Contiguous row blocks (Sec. 2.3, the row partition): block_ptr is a HOST array of
  * nblocks+1 increasing row indices with block_ptr[0] = 0 and
  * block_ptr[nblocks] = n - n_border.  For BBD the n_border trailing rows are
  * the border (Sec. 2.4); for BJ n_border must be 0. */
@@ -199,8 +199,8 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
 sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o,
                        const sdsl_lowrank* lr, void* hip_stream, sdsl_handle* out);
 
-/* New values for the same pattern (Sec. 3.4, "reuse the symbolic ... and
- * perform only the numerical factorization"): new_val (DEVICE, nnz doubles in
+/* New values for the same pattern (Sec. 3.4: the symbolic analysis is kept
+ * and only the numerical factorisation is redone): new_val (DEVICE, nnz doubles in
  * the CSR order given at setup) replaces the operator values, and the filter,
  * correction and factorisation are redone.  Stream-ordered; returns after the
  * factorisation finished. */

@@ -214,7 +214,7 @@ int64_t or_filter(int64_t n_int, const int64_t* rp, const int32_t* ci, const dou
 }
 
 /* ------------------------------------------------------------------ */
-/* ILU(0), IKJ form (paper Sec. 2.3 "ILU(0) or IC(0)", Sec. 3.1).        */
+/* ILU(0), IKJ form (paper Sec. 2.3 allows ILU(0) or IC(0); Sec. 3.1).   */
 /* For row i ascending and each k < i in its pattern, ascending:          */
 /*   l_ik = p_ik / u_kk;  p_ij -= l_ik u_kj for j > k in both patterns.   */
 /* In place: strict lower part holds L (unit diagonal implied), the rest  */
@@ -308,7 +308,7 @@ int or_bj_factor(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
 }
 
 /* z = U^{-1} L^{-1} r by forward then backward substitution (paper Sec. 2.3,
- * "solve the precondition system").  Works on any set of rows [lo, hi)
+ * the preconditioner solve of each iteration).  Works on any set of rows [lo, hi)
  * whose entries stay inside [lo, hi) (one block) or on a whole block
  * diagonal matrix.  The paper does not fix the order of the sums; each
  * substitution subtracts its terms in the order in which their unknowns
