@@ -64,10 +64,12 @@ typedef enum { SDSL_FILTER_NONE = 0, SDSL_FILTER_MIN = 1, SDSL_FILTER_GEOMEAN = 
 enum { SDSL_DIAG_DELTA = 1u, SDSL_DIAG_DROPSUM = 2u };
 
 /* What to do when ILU(0) meets a bad pivot (non-positive in SPD mode,
- * |u_ii| < 1e-14 |p_ii| otherwise).  FAIL returns SDSL_E_BREAKDOWN; REPLACE
- * replaces the pivot by its corrected diagonal; SHIFT refactors the block
- * with every diagonal raised to d + a*d for a = shift0, 2*shift0, ... (the
- * correction of Eq. (diagcorr) taken relative to the diagonal). */
+ * |u_ii| < 1e-14 |p_ii| otherwise); the paper states no pivot rule, so these
+ * are this library's breakdown policies.  FAIL returns SDSL_E_BREAKDOWN;
+ * REPLACE replaces the pivot by its corrected diagonal; SHIFT refactors the
+ * block with every diagonal raised to d + a*d for a = shift0, 2*shift0, ...
+ * up to 48 doublings: a shifted incomplete factorisation (Manteuffel, Math.
+ * Comp. 34 (1980)), not the small absolute correction of Eq. (diagcorr). */
 typedef enum { SDSL_PIVOT_FAIL = 0, SDSL_PIVOT_REPLACE = 1, SDSL_PIVOT_SHIFT = 2 } sdsl_pivot;
 
 typedef enum { SDSL_PCG = 0, SDSL_GMRES = 1 } sdsl_krylov;          /* Sec. 2.2 */
@@ -172,7 +174,27 @@ typedef struct {
     int64_t bj_launches[2];
     int64_t spmv_bytes[2];  /* algorithmic bytes of one SpMV launch          */
     int64_t bj_bytes[2];    /* algorithmic bytes of one fused PCG/BJ launch  */
+    /* FP32 modes: the decisions of the last solve (at most SDSL_RF_HISTORY
+     * are kept; rf_count counts them all).  Entry e: rf_it = iterations so
+     * far, rf_nr = the true residual norm the decision was taken on,
+     * rf_act = 0 done, 1 continue, 2 hand the recurrence to FP64, 3 solve
+     * the residual equation in FP64, 4 revert to the last refinement point
+     * and solve in FP64, 5 fail; rf_flag bit 0 = breakdown, bit 1 = a
+     * decision after an FP64 solve of the residual equation.  rf_nb = ||b||.
+     * The rule is a tuned choice of this library (the paper states no
+     * precision): a point is weak when its residual is above 0.5 times the
+     * previous point's; 3 weak points in a row hand the mixed recurrence to
+     * FP64, 3 more solve the residual equation in FP64; 2 weak classical
+     * refinement steps do the latter; at most 4 such solves, each to 0.5 of
+     * the remaining tolerance. */
+    int32_t rf_count;
+    int32_t rf_it[64];
+    double rf_nr[64];
+    int32_t rf_act[64];
+    int32_t rf_flag[64];
+    double rf_nb;
 } sdsl_info;
+#define SDSL_RF_HISTORY 64
 
 /* Fills *o with defaults: BJ, no filter, no correction, SHIFT(1e-2), SPD,
  * PCG, restart 30, max_iter 100000, FP64, inner_tol 1e-4, max_outer 30,

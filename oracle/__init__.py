@@ -78,16 +78,21 @@ def _declare(L):
     L.or_gmres_bj.restype = C.c_int
     L.or_gmres_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bbd.restype = C.c_int
-    L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P]
+    L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P,
+                               I32, P, P, P, P]
     L.or_ir_pcg_bj.restype = C.c_int
-    L.or_ru_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, P, P]
-    L.or_mx_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P]
+    L.or_mx_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P,
+                               I32, P, P, P, P]
     L.or_mx_pcg_bj.restype = C.c_int
+    L.or_refine_decide.argtypes = [I32, D, D, D, I32, I32, P]
+    L.or_refine_decide.restype = C.c_int
+    L.or_fallback_decide.argtypes = [D, D, I32, I32]
+    L.or_fallback_decide.restype = C.c_int
+    L.or_refine_constants.argtypes = [P]
     L.or_border_setup.argtypes = [I64, P, P, P, P, I32, P, P, P, P, P]
     L.or_border_setup.restype = P
     L.or_border_free.argtypes = [P]
     L.or_border_apply.argtypes = [P, P, P]
-    L.or_ru_pcg_bj.restype = C.c_int
 
 
 def _p(a):
@@ -252,52 +257,100 @@ def pcg_bj(sys_, P: BJ, tol=1e-8, maxit=10_000, hist=False):
     return x, its.value, rr.value, st, (h[:its.value] if hist else None)
 
 
-def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000):
+# refinement decisions of the FP32 modes (or_refine_decide)
+RF_DONE, RF_CONTINUE, RF_HANDOFF, RF_FALLBACK, RF_REVERT, RF_FAIL = range(6)
+RF_NAMES = ["done", "continue", "handoff", "fallback", "revert", "fail"]
+HIST_CAP = 256
+
+
+def refine_decide(mode, nr, prev, tol_nb, breakdown, handed, slow):
+    """One refinement-point decision: returns (action, new slow count).
+    mode 0 = mixed recurrence, 1 = classical refinement."""
+    s = C.c_int32(slow)
+    act = lib().or_refine_decide(mode, nr, prev, tol_nb, int(breakdown), int(handed), C.byref(s))
+    return act, s.value
+
+
+def fallback_decide(nr, tol_nb, st64, nsolves):
+    """Decision after an FP64 solve of the residual equation."""
+    return lib().or_fallback_decide(nr, tol_nb, st64, nsolves)
+
+
+def refine_constants():
+    """(weak ratio, hand-off count, slow count, max fallback solves,
+    fallback tolerance fraction) of the rule."""
+    out = np.zeros(5)
+    lib().or_refine_constants(_p(out))
+    return tuple(out)
+
+
+def _hist_arrays():
+    return (np.zeros(HIST_CAP, dtype=np.int32), np.zeros(HIST_CAP), np.zeros(HIST_CAP, dtype=np.int32),
+            np.zeros(HIST_CAP, dtype=np.int32))
+
+
+def _hist_list(n, h):
+    it, nr, act, flag = h
+    return [dict(it=int(it[e]), nr=float(nr[e]), act=int(act[e]), breakdown=bool(flag[e] & 1),
+                 after_fallback=bool(flag[e] & 2)) for e in range(min(n, HIST_CAP))]
+
+
+def replay_refine(hist, mode, nb, tol, maxit):
+    """Re-derive every decision of an FP32-mode history (a list of dicts with
+    it, nr, act, breakdown, after_fallback) with the rule alone; raises
+    AssertionError at the first decision the rule does not give."""
+    slow, handed, prev, nsolves = 0, False, nb, 0
+    for e, h in enumerate(hist):
+        if h["after_fallback"]:
+            nsolves += 1
+            want = fallback_decide(h["nr"], tol * nb, OK, nsolves)
+            if h["it"] >= maxit and h["nr"] > tol * nb:
+                want = RF_FAIL
+            # a FAIL also follows an FP64 solve that did not converge
+            assert h["act"] == want or (h["act"] == RF_FAIL and want == RF_FALLBACK), (e, h, want)
+            continue
+        want, slow = refine_decide(mode, h["nr"], prev, tol * nb, h["breakdown"], handed, slow)
+        assert h["act"] == want, (e, h, want)
+        handed = handed or want == RF_HANDOFF
+        prev = h["nr"]
+
+
+def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000, with_history=False):
     """FP32-inner PCG inside FP64 iterative refinement.  Returns (x, outer,
-    inner total, fp64 fallbacks, relres, status)."""
+    inner total, fp64 fallbacks, relres, status) and, with_history, the list
+    of decisions taken."""
     rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
     n = sys_.n
     k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
     x = np.zeros(n)
-    out = np.zeros(3, dtype=np.int32)
+    out = np.zeros(4, dtype=np.int32)
     rr = C.c_double(0.0)
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    h = _hist_arrays()
     st = lib().or_ir_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
                             _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, inner_tol, max_outer,
-                            maxit, _p(out), C.byref(rr))
-    return x, int(out[0]), int(out[1]), int(out[2]), rr.value, st
+                            maxit, _p(out), C.byref(rr), HIST_CAP, *[_p(a) for a in h])
+    res = (x, int(out[0]), int(out[1]), int(out[2]), rr.value, st)
+    return res + (_hist_list(int(out[3]), h),) if with_history else res
 
 
-def ru_pcg_bj(sys_, P: BJ, tol=1e-8, delta=0.1, maxit=100_000):
-    """FP32 PCG with FP64 reliable updates.  Returns (x, refinement points,
-    iterations, fp64 fallbacks, relres, status)."""
-    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
-    n = sys_.n
-    k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
-    x = np.zeros(n)
-    out = np.zeros(3, dtype=np.int32)
-    rr = C.c_double(0.0)
-    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
-    st = lib().or_ru_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
-                            _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, delta, maxit, _p(out),
-                            C.byref(rr))
-    return x, int(out[0]), int(out[1]), int(out[2]), rr.value, st
-
-
-def mx_pcg_bj(sys_, P: BJ, tol=1e-8, delta=0.1, every=500, maxit=100_000):
+def mx_pcg_bj(sys_, P: BJ, tol=1e-8, delta=0.1, every=500, maxit=100_000, with_history=False):
     """PCG with FP32 SpMV / preconditioner apply inside FP64 refinement.
-    Returns (x, refinement points, iterations, fp64 fallbacks, relres, status)."""
+    Returns (x, refinement points, iterations, fp64 fallbacks, relres,
+    status) and, with_history, the list of decisions taken."""
     rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
     n = sys_.n
     k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
     x = np.zeros(n)
-    out = np.zeros(3, dtype=np.int32)
+    out = np.zeros(4, dtype=np.int32)
     rr = C.c_double(0.0)
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    h = _hist_arrays()
     st = lib().or_mx_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
                             _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, delta, every, maxit,
-                            _p(out), C.byref(rr))
-    return x, int(out[0]), int(out[1]), int(out[2]), rr.value, st
+                            _p(out), C.byref(rr), HIST_CAP, *[_p(a) for a in h])
+    res = (x, int(out[0]), int(out[1]), int(out[2]), rr.value, st)
+    return res + (_hist_list(int(out[3]), h),) if with_history else res
 
 
 def gmres_bj(sys_, P: BJ, tol=1e-8, m=30, maxit=10_000, hist=False):

@@ -24,14 +24,14 @@
  *     recurrence residual meets it but the true one does not, the method
  *     restarts from the true residual.
  * Every function below is pinned by tests that compare it against dense
- * linear algebra, closed forms, error bounds or brute force on small inputs,
- * with one exception.  In the two FP32 refinement solvers (or_mx_pcg_bj,
- * or_ir_pcg_bj) the inner iterates are pinned to FP64 CG within FP32
- * rounding, and the mixed recurrence's refinement trigger is pinned too.
- * Their stall rules (how many weak refinement steps hand the solve to FP64,
- * and what counts as weak) are parity unpinned: that hand-off depends on
- * FP32 rounding, so it is checked only by reaching the tolerance and by the
- * breakdown case.
+ * linear algebra, closed forms, error bounds or brute force on small inputs.
+ * In the two FP32 refinement solvers (or_mx_pcg_bj, or_ir_pcg_bj) the inner
+ * iterates are pinned to FP64 CG within FP32 rounding and the refinement
+ * trigger is pinned too.  What they do at a refinement point (continue, hand
+ * the recurrence to FP64, solve the residual equation in FP64) is one rule,
+ * or_refine_decide / or_fallback_decide, pinned on scripted residual
+ * histories; that rule is a tuned choice (the paper states no precision),
+ * and the solvers report the history they applied it to.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared sdsl_oracle.c -lm
  * (-ffp-contract=off keeps every a*b+c as two roundings unless fma() is
@@ -273,10 +273,12 @@ int or_ilu0(int64_t n, const int64_t* rp, const int32_t* ci, double* v, int32_t 
  * the policy decides:
  *   FAIL    - return OR_BREAKDOWN;
  *   REPLACE - a failed pivot is replaced by its corrected diagonal (counted);
- *   SHIFT   - the block is refactored with every diagonal strengthened to
- *             d + a*d, a = shift0, 2*shift0, 4*shift0, ...: the correction of
- *             Eq. (diagcorr) taken in the unit-diagonal (MC64-scaled) frame,
- *             where it is the relative increase a of each diagonal.
+ *   SHIFT   - the block is refactored with every diagonal raised to
+ *             d + a*d, a = shift0, 2*shift0, 4*shift0, ...: a shifted
+ *             incomplete factorisation (Manteuffel, Math. Comp. 34 (1980)),
+ *             this build's breakdown policy for a point the paper leaves
+ *             open.  It is not the correction of Eq. (diagcorr), which adds
+ *             a small absolute delta to the diagonal of the preconditioner.
  * shifts[b] receives the a used for block b (0 if none). */
 int or_bj_factor(int64_t n, const int64_t* rp, const int32_t* ci, const double* pv,
                  int32_t nblocks, const int32_t* bp, int32_t spd, int32_t policy, double shift0,
@@ -949,13 +951,14 @@ static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int3
     while (it < maxit) {
         spmv32(S, p, q);
         double pq = dot32(n, p, q);
-        if (!(pq > 0.0)) { st = OR_BREAKDOWN; break; }
+        if (!(pq > 0.0) || !isfinite(rz / pq)) { st = OR_BREAKDOWN; break; }
         float a = (float)(rz / pq);
         for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + a * p[i]; r[i] = r[i] - a * q[i]; }
         ++it;
         if (sqrt(dot32(n, r, r)) <= itol * nb) { st = OR_OK; break; }
         prec32(S, r, z);
         double rz2 = dot32(n, r, z);
+        if (!isfinite(rz2 / rz)) { st = OR_BREAKDOWN; break; }
         float be = (float)(rz2 / rz);
         rz = rz2;
         for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
@@ -965,15 +968,125 @@ static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int3
     return st;
 }
 
-/* out[0] = outer steps, out[1] = inner iterations (sum), out[2] = FP64
- * fallbacks.  Stagnation (the true residual shrinking by less than 2x on two
- * consecutive outer steps) switches to an FP64 PCG on the remaining
- * correction. */
+/* ------------------------------------------------------------------ */
+/* Refinement decisions of the FP32 modes.  The paper states no precision, */
+/* so this rule is a tuned choice of this build, not a reading of the     */
+/* paper; the GPU library applies the same rule and reports the history  */
+/* it applied it to.                                                       */
+/*                                                                         */
+/* At every refinement point the true FP64 residual norm nr is compared    */
+/* with the one of the previous point (prev): the point is weak when       */
+/* nr > OR_RF_WEAK * prev, and `slow` counts weak points in a row.         */
+/*   mixed mode (mode 0): converged -> DONE; a breakdown of the recurrence */
+/*     -> REVERT (back to the last point's solution, then an FP64 solve of */
+/*     the residual equation); OR_RF_HAND weak points in a row -> HANDOFF  */
+/*     (the recurrence continues with the FP64 operator and factors, slow  */
+/*     restarts at 0) the first time, FALLBACK (FP64 solve of the residual */
+/*     equation) the second time; otherwise CONTINUE.                      */
+/*   classical refinement (mode 1): converged -> DONE; an inner solve that */
+/*     broke down before completing two iterations counts as OR_RF_SLOW    */
+/*     weak steps; OR_RF_SLOW weak steps in a row -> FALLBACK; otherwise   */
+/*     CONTINUE (the next inner solve).                                    */
+/* After an FP64 solve of the residual equation (to OR_RF_FBTOL of the     */
+/* remaining tolerance, so that rounding the correction into x keeps the   */
+/* true residual below it): converged -> DONE; another such solve when the */
+/* last one converged and fewer than OR_RF_MAXFB were run -> FALLBACK;     */
+/* otherwise FAIL.                                                          */
+/* ------------------------------------------------------------------ */
+#define OR_RF_DONE 0
+#define OR_RF_CONTINUE 1
+#define OR_RF_HANDOFF 2
+#define OR_RF_FALLBACK 3
+#define OR_RF_REVERT 4
+#define OR_RF_FAIL 5
+
+#define OR_RF_WEAK 0.5
+#define OR_RF_HAND 3
+#define OR_RF_SLOW 2
+#define OR_RF_MAXFB 4
+#define OR_RF_FBTOL 0.5
+
+int or_refine_decide(int32_t mode, double nr, double prev, double tol_nb, int32_t breakdown,
+                     int32_t handed, int32_t* slow) {
+    if (nr <= tol_nb) return OR_RF_DONE;
+    if (mode == 0) {
+        *slow = (nr > OR_RF_WEAK * prev) ? *slow + 1 : 0;
+        if (breakdown) return OR_RF_REVERT;
+        if (*slow >= OR_RF_HAND) {
+            if (!handed) { *slow = 0; return OR_RF_HANDOFF; }
+            return OR_RF_FALLBACK;
+        }
+        return OR_RF_CONTINUE;
+    }
+    if (breakdown) *slow = OR_RF_SLOW;
+    else *slow = (nr > OR_RF_WEAK * prev) ? *slow + 1 : 0;
+    return (*slow >= OR_RF_SLOW) ? OR_RF_FALLBACK : OR_RF_CONTINUE;
+}
+
+int or_fallback_decide(double nr, double tol_nb, int32_t st64, int32_t nsolves) {
+    if (nr <= tol_nb) return OR_RF_DONE;
+    if (st64 == OR_OK && nsolves < OR_RF_MAXFB) return OR_RF_FALLBACK;
+    return OR_RF_FAIL;
+}
+
+/* the rule's constants, for the tests: weak ratio, hand-off count, slow
+ * count, fallback solves, fallback tolerance fraction */
+void or_refine_constants(double* out) {
+    out[0] = OR_RF_WEAK; out[1] = OR_RF_HAND; out[2] = OR_RF_SLOW; out[3] = OR_RF_MAXFB; out[4] = OR_RF_FBTOL;
+}
+
+/* History of the decisions of one FP32-mode solve.  Entry e: it[e] = the
+ * iteration count when it was taken, nr[e] = the true residual norm it was
+ * taken on, act[e] = the action, flag[e] = bit 0: the recurrence or inner
+ * solve broke down; bit 1: a decision after an FP64 solve of the residual
+ * equation (or_fallback_decide) rather than at a refinement point. */
+typedef struct {
+    int32_t n, cap;
+    int32_t* it; double* nr; int32_t* act; int32_t* flag;
+} or_rf_hist;
+static void hist_add(or_rf_hist* H, int32_t it, double nr, int32_t act, int32_t flag) {
+    if (H && H->n < H->cap) {
+        H->it[H->n] = it; H->nr[H->n] = nr; H->act[H->n] = act; H->flag[H->n] = flag;
+    }
+    if (H) H->n++;
+}
+
+/* FP64 solves of the residual equation M d = r (r: the current true
+ * residual, norm nr, in r) until or_fallback_decide stops them; x += d after
+ * each.  Returns the final status; *it and *nsolves are advanced. */
+static int fallback_loop(const or_op* A, or_prec_fn pf, void* pc, const double* b, double* x, double* r,
+                         double nb, double tol, double* nr, int32_t maxit, int32_t* it, int32_t* nsolves,
+                         int32_t* fallbacks, or_rf_hist* H) {
+    int64_t n = A->n;
+    double* dd = calloc(n, 8);
+    int st = OR_NOT_CONVERGED;
+    for (;;) {
+        int32_t its = 0; double r2 = 0.0;
+        int st64 = pcg_run(A, pf, pc, r, dd, OR_RF_FBTOL * tol * nb / *nr, maxit - *it, &its, &r2, NULL);
+        for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
+        *it += its; *nsolves += 1; *fallbacks += 1;
+        *nr = op_true_res(A, x, b, r);
+        int act = (*it >= maxit && *nr > tol * nb) ? OR_RF_FAIL : or_fallback_decide(*nr, tol * nb, st64, *nsolves);
+        hist_add(H, *it, *nr, act, 2);
+        if (act == OR_RF_DONE) { st = OR_OK; break; }
+        if (act == OR_RF_FAIL) { st = (st64 == OR_BREAKDOWN) ? OR_BREAKDOWN : OR_NOT_CONVERGED; break; }
+    }
+    free(dd);
+    return st;
+}
+
+/* Classical refinement (FP32 inner solves restarted at every step):
+ * x0 = 0; r = b - M x in compensated FP64; the inner FP32 PCG solves
+ * M d = r / ||r|| to inner_tol; x += ||r|| d in FP64.  Decisions as above
+ * (mode 1).  out[0] = outer steps, out[1] = iterations (inner ones summed,
+ * FP64 fallback iterations included), out[2] = FP64 fallbacks, out[3] =
+ * decisions taken (the history may hold fewer: hcap). */
 int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                  int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
                  const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
                  void* border, const double* b, double* x, double tol, double inner_tol, int32_t max_outer,
-                 int32_t maxit, int32_t* out, double* relres) {
+                 int32_t maxit, int32_t* out, double* relres, int32_t hcap, int32_t* h_it, double* h_nr,
+                 int32_t* h_act, int32_t* h_flag) {
     or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
     int64_t nnz = rp[n], pnnz = prp[n], unnz = k > 0 ? urp[n] : 0;
     S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
@@ -992,143 +1105,41 @@ int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         or_bjb* B = (or_bjb*)border;
         S.bk = B->k; S.W = B->W32; S.K = B->K; S.Kpiv = B->piv; S.t = B->t;
     }
+    or_rf_hist H = {0, hcap, h_it, h_nr, h_act, h_flag};
     double *r = calloc(n, 8);
     float *rs = calloc(n, 4), *d = calloc(n, 4);
     double nb = nrm2(n, b);
     memset(x, 0, (size_t)n * 8);
-    out[0] = out[1] = out[2] = 0;
+    out[0] = out[1] = out[2] = out[3] = 0;
     int st = OR_NOT_CONVERGED;
+    int32_t it = 0, nsolves = 0, slow = 0;
     if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
-    double nr = op_true_res(&A, x, b, r), prev = nr;
-    int slow = 0;
-    while (out[0] < max_outer) {
-        if (nr <= tol * nb) { st = OR_OK; break; }
-        if (slow >= 2) {
-            /* FP64 fallback: PCG on M d = r to the remaining tolerance */
-            double* dd = calloc(n, 8);
-            int32_t its = 0; double rr = 0.0;
-            pcg_run(&A, pf, pc, r, dd, tol * nb / nr, maxit, &its, &rr, NULL);
-            for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
-            free(dd);
-            out[1] += its; out[2] += 1; out[0] += 1;
-            nr = op_true_res(&A, x, b, r);
-            slow = 0; prev = nr;
-            continue;
-        }
+    double nr = op_true_res(&A, x, b, r);
+    if (nr <= tol * nb) { st = OR_OK; goto finish; }
+    for (;;) {
+        if (out[0] >= max_outer || it >= maxit) { st = OR_NOT_CONVERGED; break; }
         for (int64_t i = 0; i < n; ++i) rs[i] = (float)(r[i] / nr);
         int32_t its = 0;
-        pcg32(&S, rs, d, inner_tol, maxit, &its);
+        int sti = pcg32(&S, rs, d, inner_tol, maxit - it, &its);
         for (int64_t i = 0; i < n; ++i) x[i] += nr * (double)d[i];
-        out[0] += 1; out[1] += its;
+        out[0] += 1; it += its;
+        double prev = nr;
         nr = op_true_res(&A, x, b, r);
-        slow = (nr > 0.5 * prev) ? slow + 1 : 0;
-        prev = nr;
-    }
-    if (nr <= tol * nb) st = OR_OK;
-    *relres = nr / nb;
-done:
-    free(r); free(rs); free(d); free(S.v); free(S.pv);
-    if (k > 0) { free(S.uv); free(S.c); }
-    return st;
-}
-
-/* ------------------------------------------------------------------ */
-/* FP32 PCG with FP64 reliable updates (refinement without restart).     */
-/* The inner recurrence (FP32 vectors, FP32 operator and factors, FP64    */
-/* dot products) solves M y = b / ||b||; whenever its residual norm has   */
-/* fallen below delta times its value at the last refinement point (or    */
-/* meets the tolerance), the FP32 correction is folded into the FP64      */
-/* solution, the FP64 true residual is formed and rounded back into the   */
-/* FP32 recurrence, which then continues with its search direction kept   */
-/* (reliable updating: Sleijpen and van der Vorst, Computing 56 (1996);   */
-/* mixed precision: Clark et al., Comput. Phys. Commun. 181 (2010)).       */
-/* out[0] = refinement points, out[1] = iterations, out[2] = FP64          */
-/* fallbacks (taken when two consecutive refinement points shrink the true */
-/* residual by less than 2x).                                             */
-/* ------------------------------------------------------------------ */
-int or_ru_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
-                 int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
-                 const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
-                 void* border, const double* b, double* x, double tol, double delta, int32_t maxit, int32_t* out,
-                 double* relres) {
-    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
-    int64_t nnz = rp[n], pnnz = prp[n], unnz = k > 0 ? urp[n] : 0;
-    S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
-    for (int64_t p = 0; p < nnz; ++p) S.v[p] = (float)v[p];
-    for (int64_t p = 0; p < pnnz; ++p) S.pv[p] = (float)pv[p];
-    if (k > 0) {
-        S.uv = malloc((size_t)unnz * 4 + 4); S.c = malloc((size_t)k * 4);
-        for (int64_t p = 0; p < unnz; ++p) S.uv[p] = (float)uv[p];
-        for (int32_t j = 0; j < k; ++j) S.c[j] = (float)c[j];
-    }
-    or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
-    or_bj P = {n, prp, pci, pv, pdp};
-    or_prec_fn pf = border ? bjb_apply : bj_apply;
-    void* pc = border ? border : (void*)&P;
-    if (border) {
-        or_bjb* B = (or_bjb*)border;
-        S.bk = B->k; S.W = B->W32; S.K = B->K; S.Kpiv = B->piv; S.t = B->t;
-    }
-    double* rh = calloc(n, 8);
-    float *xl = calloc(n, 4), *r = calloc(n, 4), *z = calloc(n, 4), *p = calloc(n, 4), *q = calloc(n, 4);
-    double nb = nrm2(n, b);
-    int st = OR_NOT_CONVERGED, it = 0;
-    out[0] = out[1] = out[2] = 0;
-    memset(x, 0, (size_t)n * 8);
-    double nr = nb;
-    if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
-    for (int64_t i = 0; i < n; ++i) r[i] = (float)(b[i] / nb);
-    double rr0 = dot32(n, r, r), prev = nb;
-    int slow = 0;
-    prec32(&S, r, z);
-    memcpy(p, z, (size_t)n * 4);
-    double rz = dot32(n, r, z);
-    while (it < maxit) {
-        spmv32(&S, p, q);
-        double pq = dot32(n, p, q);
-        if (!(pq > 0.0)) { st = OR_BREAKDOWN; break; }
-        float a = (float)(rz / pq);
-        for (int64_t i = 0; i < n; ++i) { xl[i] = xl[i] + a * p[i]; r[i] = r[i] - a * q[i]; }
-        ++it;
-        double rr = dot32(n, r, r);
-        if (rr <= tol * tol * 1.0 || rr < delta * delta * rr0) {
-            /* refinement point: x += ||b|| xl in FP64, true residual */
-            for (int64_t i = 0; i < n; ++i) { x[i] += nb * (double)xl[i]; xl[i] = 0.0f; }
-            nr = op_true_res(&A, x, b, rh);
-            out[0] += 1;
-            if (nr <= tol * nb) { st = OR_OK; break; }
-            slow = (nr > 0.5 * prev) ? slow + 1 : 0;
-            prev = nr;
-            if (slow >= 2) {
-                /* FP64 fallback on M d = r for the rest of the tolerance */
-                double* dd = calloc(n, 8);
-                int32_t its = 0; double r2 = 0.0;
-                st = pcg_run(&A, pf, pc, rh, dd, tol * nb / nr, maxit - it, &its, &r2, NULL);
-                for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
-                free(dd);
-                it += its; out[2] += 1;
-                nr = op_true_res(&A, x, b, rh);
-                st = (nr <= tol * nb) ? OR_OK : (st == OR_BREAKDOWN ? OR_BREAKDOWN : OR_NOT_CONVERGED);
-                break;
-            }
-            for (int64_t i = 0; i < n; ++i) r[i] = (float)(rh[i] / nb);
-            rr0 = dot32(n, r, r);
+        int bd = (sti == OR_BREAKDOWN && its <= 1);
+        int act = or_refine_decide(1, nr, prev, tol * nb, bd, 0, &slow);
+        hist_add(&H, it, nr, act, bd);
+        if (act == OR_RF_DONE) { st = OR_OK; break; }
+        if (act == OR_RF_FALLBACK) {
+            st = fallback_loop(&A, pf, pc, b, x, r, nb, tol, &nr, maxit, &it, &nsolves, &out[2], &H);
+            break;
         }
-        prec32(&S, r, z);
-        double rz2 = dot32(n, r, z);
-        float be = (float)(rz2 / rz);
-        rz = rz2;
-        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
     }
-    if (st == OR_NOT_CONVERGED) {
-        for (int64_t i = 0; i < n; ++i) x[i] += nb * (double)xl[i];
-        nr = op_true_res(&A, x, b, rh);
-        if (nr <= tol * nb) st = OR_OK;
-    }
+finish:
     *relres = nr / nb;
-    out[1] = it;
 done:
-    free(rh); free(xl); free(r); free(z); free(p); free(q); free(S.v); free(S.pv);
+    out[1] = it;
+    out[3] = H.n;
+    free(r); free(rs); free(d); free(S.v); free(S.pv);
     if (k > 0) { free(S.uv); free(S.c); }
     return st;
 }
@@ -1142,12 +1153,12 @@ done:
 /* recurrence residual fell below delta times its value at the last point, */
 /* met the tolerance, or `every` iterations passed) the compensated FP64   */
 /* true residual replaces r; z, (r,z), beta and p are then recomputed and  */
-/* the recurrence continues (reliable updating).  Three consecutive points */
-/* that shrink the true residual by less than 2x hand the recurrence over  */
-/* to the FP64 operator and factors, same search direction; three more     */
-/* switch to FP64 PCG on the remaining correction.  A breakdown of the     */
-/* recurrence goes to that FP64 PCG directly.                              */
-/* out[0] = refinement points, out[1] = iterations, out[2] = fallbacks.    */
+/* the recurrence continues (reliable updating: Sleijpen and van der       */
+/* Vorst, Computing 56 (1996)).  What happens next is decided by           */
+/* or_refine_decide (mode 0).                                              */
+/* out[0] = refinement points, out[1] = iterations, out[2] = fallbacks     */
+/* (hand-offs and FP64 solves of the residual equation), out[3] =          */
+/* decisions taken.                                                        */
 /* ------------------------------------------------------------------ */
 static void mx_spmv(const or_f32sys* S, const or_op* A, const double* x, float* xs, double* y) {
     for (int64_t i = 0; i < S->n; ++i) xs[i] = (float)x[i];
@@ -1180,7 +1191,8 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
                  int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
                  const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
                  void* border, const double* b, double* x, double tol, double delta, int32_t every,
-                 int32_t maxit, int32_t* out, double* relres) {
+                 int32_t maxit, int32_t* out, double* relres, int32_t hcap, int32_t* h_it, double* h_nr,
+                 int32_t* h_act, int32_t* h_flag) {
     or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
     int64_t nnz = rp[n], pnnz = prp[n];
     S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
@@ -1190,15 +1202,17 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     or_bj P = {n, prp, pci, pv, pdp};
     or_prec_fn pf = border ? bjb_apply : bj_apply;
     void* pc = border ? border : (void*)&P;
+    or_rf_hist H = {0, hcap, h_it, h_nr, h_act, h_flag};
     double *r = calloc(n, 8), *z = calloc(n, 8), *p = calloc(n, 8), *q = calloc(n, 8);
     double *xr = calloc(n, 8);  /* x at the last refinement point */
     float *xs = calloc(n, 4), *zs = calloc(n, 4);
     double nb = nrm2(n, b);
-    int st = OR_NOT_CONVERGED, it = 0, slow = 0, last = 0;
+    int st = OR_NOT_CONVERGED;
+    int32_t it = 0, slow = 0, last = 0, nsolves = 0;
     int handed = 0;  /* the recurrence runs on with the FP64 operator and factors */
-    out[0] = out[1] = out[2] = 0;
+    out[0] = out[1] = out[2] = out[3] = 0;
     memset(x, 0, (size_t)n * 8);
-    double nr = nb, prev = nb;
+    double nr = nb;
     if (nb == 0.0) { *relres = 0.0; st = OR_OK; goto done; }
     memcpy(r, b, (size_t)n * 8);
     double rr0 = dot(n, r, r);
@@ -1210,54 +1224,54 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         else mx_spmv(&S, &A, p, xs, q);
         double pq = dot(n, p, q);
         double alpha = rz / pq;
-        if (!(pq > 0.0) || !isfinite(alpha)) {
+        int bd = !(pq > 0.0) || !isfinite(alpha);
+        if (!bd) {
+            for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
+            ++it;
+            double rr = dot(n, r, r);
+            int conv = rr <= tol * tol * (nb * nb);
+            int upd = rr < delta * delta * rr0 || (every > 0 && it - last >= every);
+            if (!conv && !upd) {
+                if (handed) pf(pc, r, z);
+                else mx_prec(&S, border, r, xs, zs, z);
+                double rz2 = dot(n, r, z);
+                double beta = rz2 / rz;
+                if (isfinite(beta) && isfinite(rz2)) {
+                    rz = rz2;
+                    for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+                    continue;
+                }
+                bd = 1;  /* a non-finite step length ends the recurrence like (p, Mp) <= 0 */
+            }
+        }
+        /* refinement point */
+        out[0] += 1;
+        double prev = nr;
+        nr = op_true_res(&A, x, b, r);
+        int act = or_refine_decide(0, nr, prev, tol * nb, bd, handed, &slow);
+        hist_add(&H, it, nr, act, bd);
+        if (act == OR_RF_DONE) { st = OR_OK; break; }
+        if (act == OR_RF_REVERT) {
             /* the FP32 operator or factors are not positive definite here:
              * back to x at the last refinement point (the steps since may
-             * already have gone astray), then FP64 PCG solves the residual
+             * already have gone astray), then FP64 solves of the residual
              * equation */
             memcpy(x, xr, (size_t)n * 8);
             nr = op_true_res(&A, x, b, r);
-            if (nr <= tol * nb) { st = OR_OK; break; }
-            double* dd = calloc(n, 8);
-            int32_t its = 0; double r2 = 0.0;
-            st = pcg_run(&A, pf, pc, r, dd, tol * nb / nr, maxit - it, &its, &r2, NULL);
-            for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
-            free(dd);
-            it += its; out[2] += 1;
-            nr = op_true_res(&A, x, b, r);
-            st = (nr <= tol * nb) ? OR_OK : (st == OR_BREAKDOWN ? OR_BREAKDOWN : OR_NOT_CONVERGED);
+            st = fallback_loop(&A, pf, pc, b, x, r, nb, tol, &nr, maxit, &it, &nsolves, &out[2], &H);
             break;
         }
-        for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
-        ++it;
-        double rr = dot(n, r, r);
-        int conv = rr <= tol * tol * (nb * nb);
-        int upd = rr < delta * delta * rr0 || (every > 0 && it - last >= every);
-        if (conv || upd) {
-            out[0] += 1;
-            prev = nr;
-            nr = op_true_res(&A, x, b, r);
-            if (nr <= tol * nb) { st = OR_OK; break; }
-            slow = (nr > 0.5 * prev) ? slow + 1 : 0;
-            if (slow >= 3 && !handed) {
-                handed = 1;
-                slow = 0;
-                out[2] += 1;
-            } else if (slow >= 3) {
-                double* dd = calloc(n, 8);
-                int32_t its = 0; double r2 = 0.0;
-                st = pcg_run(&A, pf, pc, r, dd, tol * nb / nr, maxit - it, &its, &r2, NULL);
-                for (int64_t i = 0; i < n; ++i) x[i] += dd[i];
-                free(dd);
-                it += its; out[2] += 1;
-                nr = op_true_res(&A, x, b, r);
-                st = (nr <= tol * nb) ? OR_OK : (st == OR_BREAKDOWN ? OR_BREAKDOWN : OR_NOT_CONVERGED);
-                break;
-            }
-            rr0 = dot(n, r, r);
-            last = it;
-            memcpy(xr, x, (size_t)n * 8);
+        if (act == OR_RF_FALLBACK) {
+            st = fallback_loop(&A, pf, pc, b, x, r, nb, tol, &nr, maxit, &it, &nsolves, &out[2], &H);
+            break;
         }
+        if (act == OR_RF_HANDOFF) { handed = 1; out[2] += 1; }
+        if (it >= maxit) break;
+        /* the true residual replaces the recurrence one; the recurrence
+         * continues with its search direction */
+        rr0 = dot(n, r, r);
+        last = it;
+        memcpy(xr, x, (size_t)n * 8);
         if (handed) pf(pc, r, z);
         else mx_prec(&S, border, r, xs, zs, z);
         double rz2 = dot(n, r, z);
@@ -1269,6 +1283,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     *relres = nr / nb;
     out[1] = it;
 done:
+    out[3] = H.n;
     free(r); free(z); free(p); free(q); free(xs); free(zs); free(S.v); free(S.pv); free(xr);
     return st;
 }

@@ -63,7 +63,9 @@ class CInfo(C.Structure):
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("relres", C.c_double),
                 ("bytes_per_iter", C.c_int64), ("device_bytes", C.c_int64), ("spmv_ms", C.c_double * 2),
                 ("spmv_launches", C.c_int64 * 2), ("bj_ms", C.c_double * 2), ("bj_launches", C.c_int64 * 2),
-                ("spmv_bytes", C.c_int64 * 2), ("bj_bytes", C.c_int64 * 2)]
+                ("spmv_bytes", C.c_int64 * 2), ("bj_bytes", C.c_int64 * 2), ("rf_count", C.c_int32),
+                ("rf_it", C.c_int32 * 64), ("rf_nr", C.c_double * 64), ("rf_act", C.c_int32 * 64),
+                ("rf_flag", C.c_int32 * 64), ("rf_nb", C.c_double)]
 
 
 # every symbol the header declares, with its ctypes signature
@@ -326,6 +328,15 @@ class Solver:
             v = getattr(inf, f)
             out[f] = list(v) if hasattr(v, "__len__") else v
         return out
+
+    def rf_history(self) -> list:
+        """Decisions of the last FP32-mode solve: dicts with it, nr, act,
+        breakdown, after_fallback (see sdsl_info.rf_*)."""
+        inf = CInfo()
+        _check(self.h, lib().sdsl_get_info(self.h, C.byref(inf)))
+        return [dict(it=int(inf.rf_it[e]), nr=float(inf.rf_nr[e]), act=int(inf.rf_act[e]),
+                     breakdown=bool(inf.rf_flag[e] & 1), after_fallback=bool(inf.rf_flag[e] & 2))
+                for e in range(min(int(inf.rf_count), 64))]
 
     def close(self):
         if getattr(self, "h", None):

@@ -789,6 +789,48 @@ __global__ void k_axpy1(int n, double* __restrict__ x, const double* __restrict_
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = x[i] + d[i];
 }
 
+// ------------------------------------------------------------- refinement rule
+// What the FP32 modes do at a refinement point (a tuned rule; the paper
+// states no precision).  A point is weak when the true residual norm is above
+// kRfWeak times that of the previous point; `slow` counts weak points in a
+// row.  Mixed recurrence: converged -> done; a breakdown -> back to the last
+// point's solution and FP64 solves of the residual equation; kRfHand weak
+// points in a row -> the recurrence continues on the FP64 operator and
+// factors (once), then FP64 solves of the residual equation.  Classical
+// refinement: an inner solve that broke down before two iterations counts
+// as kRfSlow weak steps; kRfSlow weak steps in a row -> FP64 solves of the
+// residual equation.  After such a solve (to kRfFbTol of the remaining
+// tolerance): converged -> done; another one when it converged and fewer
+// than kRfMaxFb were run; otherwise the solve fails.
+enum RfAction { RF_DONE = 0, RF_CONTINUE = 1, RF_HANDOFF = 2, RF_FALLBACK = 3, RF_REVERT = 4, RF_FAIL = 5 };
+constexpr double kRfWeak = 0.5;
+constexpr int kRfHand = 3;
+constexpr int kRfSlow = 2;
+constexpr int kRfMaxFb = 4;
+constexpr double kRfFbTol = 0.5;
+constexpr int kRfHistory = SDSL_RF_HISTORY;
+
+int rf_decide(bool mixed, double nr, double prev, double tol_nb, bool breakdown, bool handed, int& slow) {
+    if (nr <= tol_nb) return RF_DONE;
+    if (mixed) {
+        slow = nr > kRfWeak * prev ? slow + 1 : 0;
+        if (breakdown) return RF_REVERT;
+        if (slow >= kRfHand) {
+            if (handed) return RF_FALLBACK;
+            slow = 0;
+            return RF_HANDOFF;
+        }
+        return RF_CONTINUE;
+    }
+    slow = breakdown ? kRfSlow : (nr > kRfWeak * prev ? slow + 1 : 0);
+    return slow >= kRfSlow ? RF_FALLBACK : RF_CONTINUE;
+}
+
+int fb_decide(double nr, double tol_nb, sdsl_status st64, int nsolves) {
+    if (nr <= tol_nb) return RF_DONE;
+    return (st64 == SDSL_OK && nsolves < kRfMaxFb) ? RF_FALLBACK : RF_FAIL;
+}
+
 // ------------------------------------------------------------- solve task
 // Resumable solve: `step()` reads the state of the pending device work and
 // issues the next stretch; sdsl_solve runs one task to the end,
@@ -820,6 +862,17 @@ struct SolveTask {
     // refinement bookkeeping
     double nr = 0.0, prev = 0.0;
     int slow = 0;
+    int nsolves = 0;  // FP64 solves of the residual equation
+    void record(int its, double res, int act, int flag) {
+        sdsl_info& I = h->info;
+        if (I.rf_count < kRfHistory) {
+            I.rf_it[I.rf_count] = its;
+            I.rf_nr[I.rf_count] = res;
+            I.rf_act[I.rf_count] = act;
+            I.rf_flag[I.rf_count] = flag;
+        }
+        I.rf_count++;
+    }
 
     int max_iter() const { return h->o.max_iter; }
 
@@ -830,9 +883,11 @@ struct SolveTask {
             h->info.spmv_ms[p] = h->info.bj_ms[p] = 0.0;
             h->info.spmv_launches[p] = h->info.bj_launches[p] = 0;
         }
+        h->info.rf_count = 0;
         launch_sqnorm_partials(h->n, b, h->part_b, h->grid, h->s);
         h->check_launch();
         nb = std::sqrt(reduce_to_host(h, h->part_b, h->grid, 1));  // scal[1] = ||b||^2
+        h->info.rf_nb = nb;
         launch_fill<double>(h->n, xout, 0.0, h->s);
         if (nb == 0.0) { finish(SDSL_OK, 0.0); return; }
         pcg64 = Pcg<double, double>{h, h->x, h->r, h->z, h->p, h->q, h->y, h->v};
@@ -861,6 +916,7 @@ struct SolveTask {
         } else {
             phase = P32_RESTART;
             nr = true_residual(h, b, xout, h->r);
+            if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
             restart_inner();
         }
     }
@@ -894,17 +950,16 @@ struct SolveTask {
     void start_fallback() {
         fallback = true;
         fallbacks++;
+        nsolves++;
         fb_base_its = total_its;
         launch_copy<double>(h->n, h->r, h->rf, h->s);
-        // half the needed reduction, so that the rounding of x += d keeps
+        // part of the needed reduction, so that the rounding of x += d keeps
         // the true residual below the tolerance
-        start64(h->rf, h->d, 0.5 * tol * nb / nr, nr);
+        start64(h->rf, h->d, kRfFbTol * tol * nb / nr, nr);
     }
     void restart_inner() {
         // classical refinement: inner FP32 PCG on M d = r / ||r|| to inner_tol
-        if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
         if (outer >= h->o.max_outer || total_its >= max_iter()) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
-        if (slow >= 2) { start_fallback(); return; }
         launch_ir_scale_cast(h->n, h->r, h->scal + 0, h->r32, h->s);
         launch_fill<float>(h->n, h->x32, 0.0f, h->s);
         launch_sqnorm_f32_partials(h->n, h->r32, h->part_res, h->grid, h->s);
@@ -918,12 +973,11 @@ struct SolveTask {
         h->check_launch();
         nr = true_residual(h, b, xout, h->r);
         fallback = false;
-        if (nr > tol * nb && st64 == SDSL_OK && fallbacks < 4 && total_its < max_iter()) {
-            start_fallback();  // the corrected solution is not there yet: once more
-            return;
-        }
-        finish(nr <= tol * nb ? SDSL_OK : (st64 == SDSL_E_BREAKDOWN ? SDSL_E_BREAKDOWN : SDSL_E_NOT_CONVERGED),
-               nr / nb);
+        const int act = (total_its >= max_iter() && nr > tol * nb) ? RF_FAIL : fb_decide(nr, tol * nb, st64, nsolves);
+        record(total_its, nr, act, 2);
+        if (act == RF_DONE) { finish(SDSL_OK, nr / nb); return; }
+        if (act == RF_FALLBACK) { start_fallback(); return; }
+        finish(st64 == SDSL_E_BREAKDOWN ? SDSL_E_BREAKDOWN : SDSL_E_NOT_CONVERGED, nr / nb);
     }
 
     // ---- GMRES(m), right preconditioned, FP64 (Sec. 2.2): Arnoldi with
@@ -1037,66 +1091,75 @@ struct SolveTask {
             pcg32.issue(std::min(h->o.check_every, max_iter() - total_its - pcg32.it));
             return;
         }
-        total_its += s.done ? s.iters : pcg32.it;
-        if (s.done && s.breakdown && s.iters <= 1) slow = 2;
+        const int inner = s.done ? s.iters : pcg32.it;
+        total_its += inner;
+        const bool bd = s.done && s.breakdown && inner <= 1;
         launch_ir_update(h->n, xout, h->scal + 0, h->x32, h->s);   // x += ||r|| d
         h->check_launch();
         outer++;
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
-        slow = (nr > 0.5 * prev) ? slow + 1 : (slow >= 2 ? slow : 0);
+        const int act = rf_decide(false, nr, prev, tol * nb, bd, false, slow);
+        record(total_its, nr, act, bd ? 1 : 0);
+        if (act == RF_DONE) { finish(SDSL_OK, nr / nb); return; }
+        if (act == RF_FALLBACK) { start_fallback(); return; }
         restart_inner();
     }
     void step_mixed() {
         Pcg<double, double>& e64 = pcghand;
         const KrylovState& s = handed ? e64.poll() : pcgmix.poll();
         const int it_now = handed ? e64.it : pcgmix.it;
-        const bool at_limit = it_now >= max_iter();
         auto issue = [&](int count) {
             if (handed) e64.issue(count);
             else pcgmix.issue(count);
         };
-        if (!s.done && !at_limit) {
-            issue(std::min(h->o.check_every, max_iter() - it_now));
+        if (!s.done) {
+            if (it_now < max_iter()) {
+                issue(std::min(h->o.check_every, max_iter() - it_now));
+                return;
+            }
+            // the iteration limit without a refinement point
+            total_its = it_now;
+            nr = true_residual(h, b, xout, h->r);
+            finish(SDSL_E_NOT_CONVERGED, nr / nb);
             return;
         }
         // refinement point: the true residual of the FP64 solution
-        const int its = s.done ? s.iters : it_now;
+        const int its = s.iters;
         total_its = its;
         outer++;
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
-        if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
-        slow = (nr > 0.5 * prev) ? slow + 1 : 0;
-        if (at_limit) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
-        if (s.done && s.breakdown) {
-            // (p, Mp) <= 0: the FP32 operator or factors are not positive
-            // definite for this system, so the search direction is not
-            // continued: back to the solution of the last refinement point
-            // (the steps since may already have gone astray), then FP64 PCG
-            // solves the residual equation
+        const bool bd = s.breakdown != 0;
+        const int act = rf_decide(true, nr, prev, tol * nb, bd, handed, slow);
+        record(its, nr, act, bd ? 1 : 0);
+        if (act == RF_DONE) { finish(SDSL_OK, nr / nb); return; }
+        if (act == RF_REVERT) {
+            // (p, Mp) <= 0 or a non-finite step: the FP32 operator or factors
+            // are not positive definite for this system, so the search
+            // direction is not continued: back to the solution of the last
+            // refinement point (the steps since may already have gone
+            // astray), then FP64 PCG solves the residual equation
             launch_copy<double>(h->n, h->xref, xout, h->s);
             nr = true_residual(h, b, xout, h->r);
             start_fallback();
             return;
         }
-        if (slow >= 3 && !handed) {
+        if (act == RF_FALLBACK) { start_fallback(); return; }
+        if (act == RF_HANDOFF) {
             // the FP32 operator or factors stall the recurrence: it continues
             // with the FP64 ones from the same search direction
             handed = true;
             fallbacks++;
-            slow = 0;
-        } else if (slow >= 3 || (!s.conv && !s.update)) {
-            start_fallback();
-            return;
         }
+        if (its >= max_iter()) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
         // the true residual (now in r) replaces the recurrence one; the
         // recurrence continues with its search direction
         launch_copy<double>(h->n, xout, h->xref, h->s);
         launch_refine_state(h->st, h->part_res, h->grid, its, h->o.refine_every, h->s);
         if (handed) e64.reapply(its - 1);
         else pcgmix.reapply(its - 1);
-        issue(std::min(h->o.check_every, max_iter() - (its)));
+        issue(std::min(h->o.check_every, max_iter() - its));
     }
     void step64() {
         const KrylovState& s = pcg64.poll();
