@@ -202,6 +202,21 @@ typedef struct {
  * refine_every 500. */
 void sdsl_default_options(sdsl_options* o);
 
+/* Device-memory provider of a handle (PyTorch's caching allocator in the
+ * Python binding).  alloc returns `bytes` of device memory of the current
+ * device, usable on `hip_stream` (the handle's stream), or NULL when it
+ * cannot; free returns a block that alloc gave, after the handle's stream has
+ * finished using it.  `ctx` is passed through and must stay valid while the
+ * handle lives.  Every device allocation of the handle (at setup, and the
+ * GMRES basis at its first GMRES solve) goes through it; pinned host staging
+ * buffers do not.  A NULL allocator, or alloc == NULL and free == NULL, uses
+ * hipMalloc / hipFree. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* hip_stream, void* ctx);
+    void (*free)(void* ptr, size_t bytes, void* hip_stream, void* ctx);
+    void* ctx;
+} sdsl_allocator;
+
 /* Device bytes a handle for this problem will hold (for admission control),
  * the GMRES basis included when o->krylov is SDSL_GMRES.  For SDSL_BBD the
  * tail factors depend on the pattern, so A->row_ptr and A->col must then be
@@ -215,11 +230,13 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
  * low-rank term, may be NULL) into handle-owned device memory, builds and
  * factors the preconditioner (filter Eq. (filter), correction Eq. (diagcorr),
  * ILU(0) of every block in one launch; for BBD also the dense Schur
- * complement and its LU).  `hip_stream` (a hipStream_t, NULL = default
- * stream) orders every later call of the handle.  The caller's arrays may be
- * freed when the call returns.  On error *out is NULL. */
+ * complement and its LU).  `al` (may be NULL) provides the handle's device
+ * memory; `hip_stream` (a hipStream_t, NULL = default stream) orders every
+ * later call of the handle.  The caller's arrays may be freed when the call
+ * returns.  On error *out is NULL and everything allocated was returned. */
 sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o,
-                       const sdsl_lowrank* lr, void* hip_stream, sdsl_handle* out);
+                       const sdsl_lowrank* lr, const sdsl_allocator* al, void* hip_stream,
+                       sdsl_handle* out);
 
 /* New values for the same pattern (Sec. 3.4: the symbolic analysis is kept
  * and only the numerical factorisation is redone): new_val (DEVICE, nnz doubles in
@@ -250,7 +267,8 @@ sdsl_status sdsl_set_max_iter(sdsl_handle h, int32_t max_iter);
 /* Solves k independent systems, one per handle, with their launches
  * interleaved on the handles' streams so that they overlap on the device.
  * Each result equals that of sdsl_solve on the same handle.  iters/relres
- * are HOST arrays of k entries.  Returns the first non-OK status. */
+ * are HOST arrays of k entries.  A handle may appear once per batch
+ * (SDSL_E_STATE for a repeat).  Returns the first non-OK status. */
 sdsl_status sdsl_solve_batch(int32_t k, const sdsl_handle* hs, const double* const* b,
                              double* const* x, double tol, int32_t* iters, double* relres);
 
@@ -262,8 +280,11 @@ sdsl_status sdsl_solve_batch(int32_t k, const sdsl_handle* hs, const double* con
  * otherwise it takes the next step (reads the device state, launches the
  * next batch of iterations) and sets *done = 1 once the solve has finished.
  * sdsl_solve_end (only after *done = 1) returns the solve's status and its
- * iterations and true relative residual.  One running solve per handle
- * (SDSL_E_STATE otherwise).  The result equals that of sdsl_solve. */
+ * iterations and true relative residual.  One running solve per handle:
+ * while it is unfinished, every call that uses the handle's vectors or
+ * factors (solve, solve_begin, solve_batch, refactor, update_values,
+ * set_max_iter, spmv, precond_apply, residual) returns SDSL_E_STATE.  The
+ * result equals that of sdsl_solve. */
 sdsl_status sdsl_solve_begin(sdsl_handle h, const double* b, double* x, double tol);
 sdsl_status sdsl_solve_step(sdsl_handle h, int32_t* done);
 sdsl_status sdsl_solve_end(sdsl_handle h, int32_t* iters, double* relres);

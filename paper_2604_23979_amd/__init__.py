@@ -7,11 +7,12 @@ from ._binding import (BBD, BJ, DIAG_DELTA, DIAG_DROPSUM, E_BREAKDOWN, E_DEVICE,
                        E_NOT_CONVERGED, E_STATE, E_STRUCTURE, FILTER_GEOMEAN, FILTER_MIN, FILTER_NONE, FP32_IR,
                        FP32_IR_RESTART,
                        FP64, GMRES, OK, PCG, PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT, SIGNATURES, LIB_PATH, Options,
-                       SdslError, Solver, lib, solve_batch)
+                       SdslError, Solver, lib, solve_batch, torch_allocator)
 
 
-def from_system(sys_, options=None, stream=None):
+def from_system(sys_, options=None, stream=None, torch_memory=True):
     """Solver for an object carrying row_ptr, col, val, block_ptr, n_border
     and lowrank (such as the seeded inputs' System)."""
     return Solver(sys_.row_ptr, sys_.col, sys_.val, sys_.block_ptr, n_border=getattr(sys_, "n_border", 0),
-                  lowrank=getattr(sys_, "lowrank", None), options=options, stream=stream)
+                  lowrank=getattr(sys_, "lowrank", None), options=options, stream=stream,
+                  torch_memory=torch_memory)

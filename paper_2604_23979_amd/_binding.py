@@ -6,9 +6,11 @@ if the library is missing, importing the solver raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import dataclasses
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -68,6 +70,55 @@ class CInfo(C.Structure):
                 ("rf_flag", C.c_int32 * 64), ("rf_nb", C.c_double)]
 
 
+class Allocator(C.Structure):
+    pass
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+Allocator._fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass  # interpreter shutdown: the process returns the memory
+
+
+_TORCH_ALLOC = None
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_solvers():
+    """Handles still open at exit are destroyed while PyTorch (which may own
+    their memory) is still alive."""
+    for s in list(_LIVE):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
+def torch_allocator() -> Allocator:
+    """The sdsl_allocator that serves handles from PyTorch's caching
+    allocator (kept alive for the life of the process)."""
+    global _TORCH_ALLOC
+    if _TORCH_ALLOC is None:
+        _TORCH_ALLOC = Allocator(ALLOC_FN(_torch_alloc), FREE_FN(_torch_free), None)
+    return _TORCH_ALLOC
+
+
 # every symbol the header declares, with its ctypes signature
 H = C.c_void_p
 P = C.c_void_p
@@ -75,8 +126,8 @@ SIGNATURES = {
     "sdsl_default_options": (None, [C.POINTER(COptions)]),
     "sdsl_footprint_bytes": (C.c_size_t, [C.POINTER(CSR), C.POINTER(Partition), C.POINTER(COptions),
                                           C.POINTER(LowRank)]),
-    "sdsl_setup": (C.c_int, [C.POINTER(CSR), C.POINTER(Partition), C.POINTER(COptions), C.POINTER(LowRank), P,
-                             C.POINTER(H)]),
+    "sdsl_setup": (C.c_int, [C.POINTER(CSR), C.POINTER(Partition), C.POINTER(COptions), C.POINTER(LowRank),
+                             C.POINTER(Allocator), P, C.POINTER(H)]),
     "sdsl_refactor": (C.c_int, [H, P]),
     "sdsl_update_values": (C.c_int, [H, P]),
     "sdsl_set_max_iter": (C.c_int, [H, C.c_int32]),
@@ -164,10 +215,12 @@ class Solver:
 
     ``row_ptr``/``col``/``val`` are numpy arrays (copied from host memory) or
     torch CUDA tensors (int64 / int32 / float64, copied device to device).
-    ``block_ptr`` is a host int array of contiguous row blocks."""
+    ``block_ptr`` is a host int array of contiguous row blocks.  With
+    ``torch_memory`` the handle's device memory comes from PyTorch's caching
+    allocator (sdsl_allocator), otherwise from hipMalloc."""
 
     def __init__(self, row_ptr, col, val, block_ptr, n_border: int = 0, lowrank=None,
-                 options: Optional[Options] = None, stream=None):
+                 options: Optional[Options] = None, stream=None, torch_memory: bool = True):
         import torch
         self.options = options or Options()
         self._keep = []
@@ -207,13 +260,17 @@ class Solver:
         self.stream = stream
         self._opts = self.options.c()
         h = C.c_void_p()
+        self._alloc = torch_allocator() if torch_memory else None
         st = lib().sdsl_setup(C.byref(A), C.byref(part), C.byref(self._opts),
-                              C.byref(lrp) if lrp is not None else None, _stream_ptr(stream), C.byref(h))
+                              C.byref(lrp) if lrp is not None else None,
+                              C.byref(self._alloc) if self._alloc is not None else None, _stream_ptr(stream),
+                              C.byref(h))
         self._keep = []
         if st != OK:
             msg = lib().sdsl_last_error(None)
             raise SdslError(st, msg.decode() if msg else "")
         self.h = h
+        _LIVE.add(self)
 
     # -- solves
     def solve(self, b, x=None, tol: float = 1e-8, check: bool = True):

@@ -52,8 +52,9 @@ struct sdsl_ctx {
     int n = 0, n_int = 0, nbd = 0, nb = 0;
     int64_t nnz = 0;
     std::vector<int> bp_h;
-    std::vector<void*> allocs;
+    std::vector<std::pair<void*, size_t>> allocs;
     size_t bytes = 0;
+    sdsl_allocator al{};  // caller's device-memory provider (alloc == NULL: hipMalloc / hipFree)
     std::string err;
 
     // operator
@@ -133,26 +134,35 @@ struct sdsl_ctx {
     T* alloc(size_t count) {
         void* ptr = nullptr;
         const size_t b = std::max<size_t>(count, 1) * sizeof(T);
-        if (hipMalloc(&ptr, b) != hipSuccess) {
+        if (al.alloc) {
+            ptr = al.alloc(b, (void*)s, al.ctx);
+        } else if (hipMalloc(&ptr, b) != hipSuccess) {
             (void)hipGetLastError();
-            fail(SDSL_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+            ptr = nullptr;
         }
-        allocs.push_back(ptr);
+        if (!ptr) fail(SDSL_E_NOMEM, "device allocation of " + std::to_string(b) + " bytes failed");
+        allocs.push_back({ptr, b});
         bytes += b;
         return (T*)ptr;
     }
-    void release(void* ptr, size_t b) {
-        auto it = std::find(allocs.begin(), allocs.end(), ptr);
-        if (it != allocs.end()) {
-            allocs.erase(it);
-            (void)hipFree(ptr);
-            bytes -= b;
-        }
+    void give_back(void* ptr, size_t b) {
+        if (al.alloc) al.free(ptr, b, (void*)s, al.ctx);
+        else (void)hipFree(ptr);
+    }
+    void release(void* ptr) {
+        for (auto it = allocs.begin(); it != allocs.end(); ++it)
+            if (it->first == ptr) {
+                const size_t b = it->second;
+                allocs.erase(it);
+                give_back(ptr, b);
+                bytes -= b;
+                return;
+            }
     }
     ~sdsl_ctx() {
         if (s) (void)hipStreamSynchronize(s);
         if (task) delete_task(task);
-        for (void* a : allocs) (void)hipFree(a);
+        for (auto& a : allocs) give_back(a.first, a.second);
         if (st_h) (void)hipHostFree(st_h);
         if (scal_h) (void)hipHostFree(scal_h);
         if (vout_h) (void)hipHostFree(vout_h);
@@ -1216,6 +1226,12 @@ sdsl_status guard(sdsl_ctx* h, const std::function<void()>& fn) {
     }
 }
 
+// one running solve per handle: calls that use the handle's vectors or
+// factors are refused while an asynchronous solve is unfinished
+void check_idle(sdsl_ctx* h) {
+    if (h->task && !h->task->finished) fail(SDSL_E_STATE, "an asynchronous solve is running on this handle");
+}
+
 void check_options(const sdsl_options* o) {
     if (o->method != SDSL_BJ && o->method != SDSL_BBD) fail(SDSL_E_INVALID, "unknown method");
     if (o->method == SDSL_BBD && (o->krylov != SDSL_GMRES || o->precision != SDSL_FP64))
@@ -1350,16 +1366,18 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
 }
 
 sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_options* o,
-                       const sdsl_lowrank* lr, void* hip_stream, sdsl_handle* out) {
+                       const sdsl_lowrank* lr, const sdsl_allocator* al, void* hip_stream, sdsl_handle* out) {
     if (out) *out = nullptr;
     sdsl_ctx* h = nullptr;
     sdsl_status st = guard(nullptr, [&] {
         if (!out) fail(SDSL_E_INVALID, "null output handle");
         check_partition(A, p, o);
         check_options(o);
+        if (al && (!al->alloc) != (!al->free)) fail(SDSL_E_INVALID, "the allocator needs both alloc and free");
         std::unique_ptr<sdsl_ctx> hp(new sdsl_ctx());
         h = hp.get();
         const double t0 = now_ms();
+        if (al) h->al = *al;
         h->s = (hipStream_t)hip_stream;
         h->o = *o;
         h->n = A->n;
@@ -1503,7 +1521,7 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         }
         build_precond(h);
         h->sync();
-        h->release(rp64, (size_t)(n + 1) * sizeof(int64_t));
+        h->release(rp64);
         h->info.device_bytes = (int64_t)h->bytes;
         h->info.nnz_dropped = 0;
         h->info.setup_ms = now_ms() - t0;
@@ -1516,6 +1534,7 @@ sdsl_status sdsl_refactor(sdsl_handle h, const double* new_val) {
     if (!h) return SDSL_E_INVALID;
     return guard(h, [&] {
         if (!new_val) fail(SDSL_E_INVALID, "null values");
+        check_idle(h);
         const double t0 = now_ms();
         check_values(h, new_val);
         hip_check(hipMemcpyAsync(h->v, new_val, h->nnz * sizeof(double), hipMemcpyDeviceToDevice, h->s), "copy");
@@ -1530,6 +1549,7 @@ sdsl_status sdsl_update_values(sdsl_handle h, const double* new_val) {
     if (!h) return SDSL_E_INVALID;
     return guard(h, [&] {
         if (!new_val) fail(SDSL_E_INVALID, "null values");
+        check_idle(h);
         check_values(h, new_val);
         hip_check(hipMemcpyAsync(h->v, new_val, h->nnz * sizeof(double), hipMemcpyDeviceToDevice, h->s), "copy");
         launch_cast_f32(h->nnz, h->v, h->v32, h->s);
@@ -1542,7 +1562,7 @@ sdsl_status sdsl_set_max_iter(sdsl_handle h, int32_t max_iter) {
     if (!h) return SDSL_E_INVALID;
     return guard(h, [&] {
         if (max_iter < 1) fail(SDSL_E_INVALID, "max_iter must be positive");
-        if (h->task && !h->task->finished) fail(SDSL_E_STATE, "a solve is running on this handle");
+        check_idle(h);
         h->o.max_iter = max_iter;
     });
 }
@@ -1553,6 +1573,7 @@ sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, in
     sdsl_status st = guard(h, [&] {
         if (!b || !x) fail(SDSL_E_INVALID, "null vector");
         if (!(tol > 0.0)) fail(SDSL_E_INVALID, "tol must be positive");
+        check_idle(h);
         SolveTask t;
         t.begin(h, b, x, tol);
         while (!t.finished) t.step();
@@ -1570,7 +1591,7 @@ sdsl_status sdsl_solve_begin(sdsl_handle h, const double* b, double* x, double t
     return guard(h, [&] {
         if (!b || !x) fail(SDSL_E_INVALID, "null vector");
         if (!(tol > 0.0)) fail(SDSL_E_INVALID, "tol must be positive");
-        if (h->task && !h->task->finished) fail(SDSL_E_STATE, "a solve is already running on this handle");
+        check_idle(h);
         if (h->task) delete_task(h->task);
         h->task = new SolveTask();
         h->task->begin(h, b, x, tol);
@@ -1620,6 +1641,9 @@ sdsl_status sdsl_solve_batch(int32_t k, const sdsl_handle* hs, const double* con
         res[i] = guard(hs[i], [&] {
             if (!b[i] || !x[i]) fail(SDSL_E_INVALID, "null vector");
             if (!(tol > 0.0)) fail(SDSL_E_INVALID, "tol must be positive");
+            for (int j = 0; j < i; ++j)
+                if (hs[j] == hs[i]) fail(SDSL_E_STATE, "the same handle appears twice in one batch");
+            check_idle(hs[i]);
             tasks[i].begin(hs[i], b[i], x[i], tol);
         });
         live[i] = res[i] == SDSL_OK;
@@ -1660,6 +1684,7 @@ sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y) {
     if (!h) return SDSL_E_INVALID;
     return guard(h, [&] {
         if (!x || !y) fail(SDSL_E_INVALID, "null vector");
+        check_idle(h);
         const CsrView A{h->n, h->rp, h->ci, h->halo};
         if (prec == SDSL_FP64) {
             apply_op64(h, (const double*)x, (double*)y);
@@ -1677,6 +1702,7 @@ sdsl_status sdsl_precond_apply(sdsl_handle h, int32_t prec, const void* r, void*
     if (!h) return SDSL_E_INVALID;
     return guard(h, [&] {
         if (!r || !z) fail(SDSL_E_INVALID, "null vector");
+        check_idle(h);
         PcgVecs V{};
         V.r = const_cast<void*>(r);
         V.z = z;
@@ -1700,6 +1726,7 @@ sdsl_status sdsl_residual(sdsl_handle h, const double* b, const double* x, doubl
     if (!h) return SDSL_E_INVALID;
     return guard(h, [&] {
         if (!b || !x || !r) fail(SDSL_E_INVALID, "null vector");
+        check_idle(h);
         const double nr = true_residual(h, b, x, r);
         if (norm) *norm = nr;
     });

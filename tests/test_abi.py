@@ -91,6 +91,20 @@ def test_setup_rejects_bad_arguments_without_touching_the_device():
     o = sd._binding.COptions()
     sd.lib().sdsl_default_options(C.byref(o))
     h = C.c_void_p()
-    assert sd.lib().sdsl_setup(None, None, C.byref(o), None, None, C.byref(h)) == sd.E_INVALID
+    assert sd.lib().sdsl_setup(None, None, C.byref(o), None, None, None, C.byref(h)) == sd.E_INVALID
     assert b"null" in sd.lib().sdsl_last_error(None)
+    assert not h.value
+    # an allocator needs both functions (checked before any device work)
+    import numpy as np
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    ci = np.array([0, 1], dtype=np.int32)
+    v = np.array([1.0, 1.0])
+    A = sd._binding.CSR(2, 2, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                        v.ctypes.data_as(C.c_void_p), sd._binding.MEM_HOST)
+    bp = np.array([0, 2], dtype=np.int32)
+    part = sd._binding.Partition(1, bp.ctypes.data_as(C.c_void_p), 0)
+    half = sd._binding.Allocator(sd._binding.ALLOC_FN(lambda nbytes, s, ctx: None), sd._binding.FREE_FN(), None)
+    assert sd.lib().sdsl_setup(C.byref(A), C.byref(part), C.byref(o), None, C.byref(half), None,
+                               C.byref(h)) == sd.E_INVALID
+    assert b"allocator" in sd.lib().sdsl_last_error(None)
     assert not h.value

@@ -779,6 +779,64 @@ def test_async_solve_equals_solve():
     sv.close()
 
 
+def test_calls_refused_while_an_async_solve_runs():
+    """One running solve per handle: while an asynchronous solve is
+    unfinished, every call that would share its vectors or factors returns
+    SDSL_E_STATE, and a batch may not name a handle twice."""
+    s = gen.c1()
+    sv = sd.from_system(s, opts())
+    try:
+        b = tdev(s.b)
+        x = torch.empty_like(b)
+        sv.solve_begin(b, x, 1e-8)
+        calls = {"solve": lambda: sv.solve(b), "refactor": lambda: sv.refactor(tdev(s.val)),
+                 "update_values": lambda: sv.update_values(tdev(s.val)), "spmv": lambda: sv.spmv(b),
+                 "precond_apply": lambda: sv.precond_apply(b), "residual": lambda: sv.residual(b, x),
+                 "set_max_iter": lambda: sv.set_max_iter(10), "solve_begin": lambda: sv.solve_begin(b, x)}
+        for name, call in calls.items():
+            with pytest.raises(sd.SdslError) as e:
+                call()
+            assert e.value.status == sd.E_STATE, name
+        while not sv.solve_step():
+            pass
+        _, its, rr, st = sv.solve_end()
+        assert st == sd.OK and rr <= 1e-8
+        x2 = torch.empty_like(b)
+        its2, rr2, st2 = sd.solve_batch([sv, sv], [b, b], [x, x2])
+        assert st2 == sd.E_STATE and its2[0] == its
+    finally:
+        sv.close()
+
+
+def test_handle_memory_comes_from_the_torch_allocator():
+    """With the allocator hook the handle's device memory is PyTorch's: it
+    shows in torch.cuda.memory_allocated() while the handle lives and goes
+    back to the caching allocator (not to hipFree) when it is destroyed."""
+    s = gen.c2(0.02)
+    o = opts(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    sv = sd.from_system(s, o)
+    held = torch.cuda.memory_allocated() - base
+    dev = sv.info()["device_bytes"]
+    assert dev > 0 and dev <= held <= 1.5 * dev + (64 << 20), (dev, held)
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+    assert st == sd.OK
+    del x
+    reserved = torch.cuda.memory_reserved()
+    sv.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= base + 8 * s.n + 512
+    assert torch.cuda.memory_reserved() == reserved  # cached, not freed
+    plain = sd.from_system(s, o, torch_memory=False)
+    try:
+        assert torch.cuda.memory_allocated() <= base + 8 * s.n + 512
+        _, its2, _, st2 = plain.solve(tdev(s.b), tol=1e-8)
+        assert st2 == sd.OK and its2 == its
+    finally:
+        plain.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32ir"])
 def test_set_max_iter_caps_a_solve(prec):
     """A capped solve stops at the cap with E_NOT_CONVERGED; raising the cap
