@@ -8,10 +8,16 @@ low-rank operator term, D log-uniform in [1e-6, 1e6], 64 contiguous blocks,
 GEOMEAN filter tau = 1e-3 with the dropped magnitude added to the diagonal,
 ILU(0) per block, tolerance 1e-8 on the true relative residual.
 
+The dense columns are also eliminated as a border of the preconditioner, and
+ILU(0) breakdowns are handled by the shifted refactorisation policy.
+
 A step is one complete solve (x0 = 0 to relres <= 1e-8) of that system with
 its inputs resident in HBM; the preconditioner is built once before timing.
 Both the plain FP64 PCG and the FP32-inner / FP64-refined form are timed; the
-line reports the faster as `value` and both under `modes`.
+line reports the faster as `value` and both under `modes`.  Beside it: the
+oracle on one thread and on the host cores, measured copy and read ceilings,
+and the SpMV / block-Jacobi launch times on the full-size C4 system (5.2M
+rows, 256 blocks), whose working set is far larger than the Infinity Cache.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -85,7 +91,11 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol):
     _, nr = solver.residual(b, x)
     relres = nr / float(torch.linalg.vector_norm(b).item())
     p = 1 if opts.precision == sd.FP32_IR else 0
+    # algorithmic bytes of the whole solve: every Krylov iteration moves
+    # bytes_per_iter (SpMV + fused PCG/block-Jacobi step + direction update)
+    solve_bytes = float(np.mean(its_all)) * info["bytes_per_iter"]
     res = dict(solves_per_s=steps / total, ms_per_solve=1e3 * total / steps, iterations=its_all,
+               solve_gbps=solve_bytes / (total / steps) / 1e9, bytes_per_iter=info["bytes_per_iter"],
                relres=relres, setup_s=setup_s, p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99),
                outer=info["outer_iters"], fallbacks=info["fp64_fallbacks"], restarts=info["restarts"],
                nnz_kept=info["nnz_kept"], shifted_blocks=info["shifted_blocks"], max_shift=info["max_shift"],
@@ -286,27 +296,122 @@ def measured_traffic(which, mode):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(system, gpu_iters, seconds, opts_o):
-    """The oracle (single-threaded C) on a bounded sample of the same solve:
-    the preconditioner build, then a fixed number of PCG iterations, scaled to
-    solves/s with the FP64 iteration count measured on the GPU."""
+def cpu_baseline(system, gpu_iters, seconds, opts_o, threads):
+    """The oracle (plain C; OpenMP only over independent rows and blocks) on
+    a bounded sample of the same solve: the preconditioner build, then a
+    fixed number of PCG iterations on `threads` threads, scaled to solves/s
+    with the FP64 iteration count measured on the GPU."""
     import oracle as O
-    t0 = time.perf_counter()
-    P = O.BJ(system, **opts_o)
-    setup = time.perf_counter() - t0
-    # calibrate, then run the sample
-    t0 = time.perf_counter()
-    O.pcg_bj(system, P, tol=1e-30, maxit=3)
-    per = (time.perf_counter() - t0) / 3
-    k = max(3, int(seconds / max(per, 1e-6)))
-    t0 = time.perf_counter()
-    O.pcg_bj(system, P, tol=1e-30, maxit=k)
-    t_iter = (time.perf_counter() - t0) / k
+    O.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        P = O.BJ(system, **opts_o)
+        setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.pcg_bj(system, P, tol=1e-30, maxit=3)
+        per = (time.perf_counter() - t0) / 3
+        k = max(3, int(seconds / max(per, 1e-6)))
+        t0 = time.perf_counter()
+        O.pcg_bj(system, P, tol=1e-30, maxit=k)
+        t_iter = (time.perf_counter() - t0) / k
+    finally:
+        O.set_threads(1)
     solve_s = t_iter * gpu_iters
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} FP64 PCG iterations of the full system ({t_iter * 1e3:.1f} ms each) scaled by the "
-                      f"{gpu_iters} iterations of one GPU FP64 solve; preconditioner build {setup:.2f} s "
-                      f"excluded like on the GPU"}
+    return {"value": round(1.0 / solve_s, 6), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} FP64 PCG iterations of the full system ({t_iter * 1e3:.2f} ms each on {threads} "
+                      f"thread(s)) scaled by the {gpu_iters} iterations of one GPU FP64 solve; preconditioner "
+                      f"build {setup:.2f} s excluded like on the GPU"}
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Measured bandwidth ceilings on this GPU: a plain device copy and a
+    device-wide read (sum) of `nbytes`, timed with events."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    bb = torch.empty_like(a)
+    for _ in range(3):
+        bb.copy_(a)
+        a.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bb.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy = 2 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    e0.record()
+    for _ in range(reps):
+        a.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read = nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del a, bb
+    torch.cuda.empty_cache()
+    return {"copy_gbps": round(copy, 1), "read_gbps": round(read, 1), "bytes": nbytes,
+            "kind": "torch copy_ and sum of a 1 GiB FP64 buffer, HIP events"}
+
+
+def host_cpu():
+    """CPU model and the cores this process may use (capped at the 16 of
+    one GPU's host share)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model, avail, max(1, min(16, avail))
+
+
+def run_c4_kernels(sd, torch, gen, iters):
+    """C4 at its full size (5.2M rows, 256 blocks, the first system of the
+    IPM sequence): the per-iteration cost and the SpMV and block-Jacobi
+    launch times on a working set far larger than the 256 MB Infinity Cache.
+    Only `iters` PCG iterations are run (HIP events on every launch): at this
+    size ILU(0) block Jacobi needs more than 10^4 iterations per system, so
+    complete solves do not fit the benchmark (the true residual after the
+    iterations is reported)."""
+    t0 = time.time()
+    q = gen.IPMSequence(steps=30)
+    s = q.system(0)
+    log(f"  C4: n={s.n} nnz={s.nnz} blocks={s.nblocks} built in {time.time() - t0:.1f} s")
+    b = torch.as_tensor(s.b, device="cuda:0")
+    out = {"workload": "C4 system 0 at full size: A 5,200,000 x 8,320,000, 4 N(0,1)/col localized, D spread 1e2, "
+                       "256 blocks, GEOMEAN tau=1e-3 + DROPSUM, SHIFT 1e-2, ILU(0), PCG; "
+                       f"{iters} iterations timed per mode, not a complete solve",
+           "n": s.n, "nnz": s.nnz, "nblocks": s.nblocks}
+    for name, prec in (("fp64", sd.FP64), ("fp32ir", sd.FP32_IR)):
+        o = sd.Options(precision=prec, filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
+                       pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=iters, kernel_timing=1, refine_every=10 ** 9)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sv = sd.from_system(s, o)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t1
+        sv.solve(b, tol=1e-8)  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, its, rr, st = sv.solve(b, tol=1e-8)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        inf = sv.info()
+        p = 1 if prec == sd.FP32_IR else 0
+        sp_us = 1e3 * inf["spmv_ms"][p] / max(1, inf["spmv_launches"][p])
+        bj_us = 1e3 * inf["bj_ms"][p] / max(1, inf["bj_launches"][p])
+        out[name] = {"setup_s": round(setup, 3), "iterations": its, "relres_after": rr,
+                     "ms_per_iteration": round(1e3 * dt / max(its, 1), 4), "nnz_kept": inf["nnz_kept"],
+                     "shifted_blocks": inf["shifted_blocks"],
+                     "spmv_us": round(sp_us, 2), "spmv_bytes": inf["spmv_bytes"][p],
+                     "spmv_gbps": round(inf["spmv_bytes"][p] / (sp_us * 1e-6) / 1e9, 1),
+                     "bj_us": round(bj_us, 2), "bj_bytes": inf["bj_bytes"][p],
+                     "bj_gbps": round(inf["bj_bytes"][p] / (bj_us * 1e-6) / 1e9, 1)}
+        log(f"  C4 {name}: {out[name]}")
+        sv.close()
+    return out
 
 
 def main():
@@ -318,7 +423,9 @@ def main():
     ap.add_argument("--modes", default="fp64,fp32ir")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP-event timing inside the solves")
+    ap.add_argument("--timing", type=int, default=64,
+                    help="HIP-event timing of the SpMV and block-Jacobi launches of every k-th iteration inside the "
+                         "timed solves (0: off)")
     ap.add_argument("--max-iter", type=int, default=60_000)
     ap.add_argument("--refine-delta", type=float, default=0.3)
     ap.add_argument("--profile-iters", type=int, default=0,
@@ -337,6 +444,8 @@ def main():
     ap.add_argument("--c1", type=int, default=0, help="also time this many solves of the small system C1")
     ap.add_argument("--c3", type=int, default=0,
                     help="also run the BBD / GMRES(30) system C3 (setup, then this many solves)")
+    ap.add_argument("--c4-kernels", type=int, default=300,
+                    help="PCG iterations timed on the full-size C4 system (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="profiling run: first copy a buffer of this many bytes three times (counter scale)")
     args = ap.parse_args()
@@ -369,7 +478,7 @@ def main():
     log(f"  {system.name}: n={system.n} nnz={system.nnz} blocks={system.nblocks} "
         f"low-rank k={system.lowrank[0].shape[1]} nnz_U={system.lowrank[0].nnz} ({time.time() - t0:.1f} s)")
     common = dict(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM, pivot=sd.PIVOT_SHIFT,
-                  shift0=1e-2, kernel_timing=bool(args.timing), max_iter=args.max_iter,
+                  shift0=1e-2, kernel_timing=args.timing, max_iter=args.max_iter,
                   refine_delta=args.refine_delta, border=True)
     if args.profile_iters > 0:
         b_dev = torch.as_tensor(system.b, device="cuda:0")
@@ -401,8 +510,8 @@ def main():
     # one launch over its average duration from HIP events inside the solves
     roof = None
     if r.get("spmv_gbps"):
-        sp_t = r["spmv_avg_us"] * r["spmv_launches"]
-        bj_t = r["bj_avg_us"] * r["bj_launches"]
+        sp_t = r["spmv_avg_us"]
+        bj_t = r["bj_avg_us"]
         which = "bj" if bj_t > sp_t else "spmv"
         prec = "FP64" if best == "fp64" else "FP32"
         name = {"bj": f"k_bj ({prec})", "spmv": f"k_spmv ({prec})"}[which]
@@ -411,14 +520,23 @@ def main():
                 "frac": round(gbps / HBM_PEAK_GBPS, 4),
                 "traffic": measured_traffic(which, best),
                 "bytes_per_launch": r[f"{which}_bytes"], "avg_launch_us": round(r[f"{which}_avg_us"], 2),
-                "launches": r[f"{which}_launches"],
-                "share_of_solve": round(max(sp_t, bj_t) / args.steps / (1e3 * r["ms_per_solve"]), 3)}
+                "timed_launches": r[f"{which}_launches"], "timing": f"HIP events on every {args.timing}th iteration",
+                "share_of_solve": round(r[f"{which}_avg_us"] * np.mean(r["iterations"]) /
+                                        (1e3 * r["ms_per_solve"]), 3)}
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(system, fp64_its, args.cpu_seconds,
-                           dict(mode=2, tau=1e-3, flags=2, delta=0.0, spd=True, policy=2, shift0=1e-2, border=True))
-        log(f"  oracle: {cpu['value']:.5f} solves/s")
+        model, avail, threads = host_cpu()
+        oo = dict(mode=2, tau=1e-3, flags=2, delta=0.0, spd=True, policy=2, shift0=1e-2, border=True)
+        log(f"cpu baseline (oracle) on {threads} threads ...")
+        cpu = cpu_baseline(system, fp64_its, args.cpu_seconds, oo, threads)
+        log(f"  oracle ({threads} threads): {cpu['value']:.5f} solves/s")
+        one = cpu_baseline(system, fp64_its, args.cpu_seconds, oo, 1) if threads > 1 else dict(cpu)
+        log(f"  oracle (1 thread): {one['value']:.5f} solves/s")
+        cpu.update(cpu_model=model, cores_available=avail, single_thread=one["value"],
+                   single_thread_sample=one["sample"])
+    ceiling = copy_ceiling(torch)
+    log(f"  bandwidth ceilings: {ceiling}")
+    c4k = run_c4_kernels(sd, torch, gen, args.c4_kernels) if args.c4_kernels > 0 and args.scale == 1.0 else None
     serving = (run_serving(sd, torch, gen, args.serve, args.serve_active, args.serve_modes.split(","))
                if args.serve > 0 else None)
     ipm_seq = (run_ipm_sequence(sd, torch, gen, args.c4, args.c4_rows, args.c4_policy, args.c4_precision)
@@ -431,12 +549,16 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if best == "fp64" else "f32-inner/f64-refined", "data": "synthetic",
         "config": {"workload": f"{system.name}: M = A D A^T + 1e-8 I, A 200000x500000 (scale {args.scale}), "
-                               "8 N(0,1)/col localized + 20 dense cols (low-rank), D log-uniform [1e-6,1e6], "
-                               "64 blocks, GEOMEAN tau=1e-3 + DROPSUM, ILU(0), PCG, tol 1e-8",
+                               "8 N(0,1)/col localized + 20 dense cols kept as a low-rank term, D log-uniform "
+                               "[1e-6,1e6], 64 blocks, GEOMEAN tau=1e-3 + DROPSUM, ILU(0) with the SHIFT breakdown "
+                               "policy, dense columns eliminated as a border (border=1), PCG, tol 1e-8 on the true "
+                               "residual; a step = one complete solve from x0 = 0",
                    "n": system.n, "nnz": system.nnz, "nblocks": system.nblocks, "mode": best},
         "p50_ms": round(r["p50_ms"], 2), "p99_ms": round(r["p99_ms"], 2),
-        "hbm_gbps": round(r.get("spmv_gbps", 0.0), 1), "iterations": r["iterations"][-1],
-        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu, "serving": serving, "ipm_sequence": ipm_seq, "bbd": bbd, "c1": small,
+        "hbm_gbps": round(r["solve_gbps"], 1), "hbm_gbps_kind": "algorithmic bytes of the whole solve / solve time",
+        "iterations": r["iterations"][-1],
+        "relres": r["relres"], "roofline": roof, "cpu_baseline": cpu, "bandwidth_ceiling": ceiling,
+        "c4_full_size": c4k, "serving": serving, "ipm_sequence": ipm_seq, "bbd": bbd, "c1": small,
         "modes": {k: {kk: (float(f"{vv:.5g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in modes.items()},
     }

@@ -82,9 +82,12 @@ typedef enum { SDSL_PCG = 0, SDSL_GMRES = 1 } sdsl_krylov;          /* Sec. 2.2 
  * (the recurrence residual fell by refine_delta, met the tolerance, or
  * refine_every iterations passed) the true residual is formed in FP64 and
  * replaces the recurrence one, which continues with its search direction
- * (reliable updating).
+ * (reliable updating).  When the refinement points stop halving the true
+ * residual the rest is solved in FP64 (sdsl_info.rf_*).
  * FP32_IR_RESTART: classical refinement; every step restarts the inner PCG
- * on the current residual and stops it at inner_tol. */
+ * on the current residual and stops it at inner_tol (or after refine_every
+ * iterations); an inner solve that breaks down is discarded and the rest is
+ * solved in FP64. */
 typedef enum { SDSL_FP64 = 0, SDSL_FP32_IR = 1, SDSL_FP32_IR_RESTART = 2 } sdsl_precision;
 
 typedef enum { SDSL_MEM_DEVICE = 0, SDSL_MEM_HOST = 1 } sdsl_mem;
@@ -137,8 +140,9 @@ typedef struct {
     double inner_tol;      /* FP32_IR: relative tolerance of each inner solve */
     int32_t max_outer;     /* FP32_IR: refinement steps                       */
     int32_t check_every;   /* iterations launched between convergence checks */
-    int32_t kernel_timing; /* 1: time the SpMV and block-Jacobi launches of
-                              every solve with HIP events (sdsl_info)        */
+    int32_t kernel_timing; /* k > 0: time the SpMV and block-Jacobi launches
+                              of every k-th PCG iteration with HIP events
+                              (sdsl_info; 1 = every iteration, 0 = off)     */
     int32_t border;        /* 1: with a low-rank term, the preconditioner
                               also eliminates its columns as a border:
                               (P + U C U^T)^{-1} through the k x k Schur
@@ -147,7 +151,8 @@ typedef struct {
     double refine_delta;   /* FP32_IR: residual reduction between refinement
                               points (0.1 typical)                           */
     int32_t refine_every;  /* FP32_IR: iterations after which a refinement
-                              point is taken regardless of the reduction     */
+                              point is taken regardless of the reduction;
+                              FP32_IR_RESTART: cap of one inner solve        */
 } sdsl_options;
 
 typedef struct {
@@ -158,16 +163,16 @@ typedef struct {
     double max_shift;       /* SHIFT policy: largest relative shift used     */
     int32_t outer_iters;    /* FP32_IR refinement points of the last solve   */
     int32_t inner_iters;    /* Krylov iterations of the last solve (total)   */
-    int32_t fp64_fallbacks; /* FP32_IR: inner solves redone in FP64          */
+    int32_t fp64_fallbacks; /* FP32 modes: FP64 solves of the residual eq.  */
     int32_t restarts;       /* restarts from the true residual               */
     double setup_ms;        /* last setup / refactor time                    */
     double solve_ms;        /* last solve time                               */
     double relres;          /* last true relative residual                   */
     int64_t bytes_per_iter; /* algorithmic bytes of one Krylov iteration     */
     int64_t device_bytes;   /* device memory held by the handle              */
-    /* kernel_timing: summed durations and counts of the launches made by the
-     * last solve before it converged (no-op launches after it are excluded);
-     * index 0 = FP64 kernels, 1 = FP32 kernels */
+    /* kernel_timing: summed durations and counts of the timed launches of
+     * the last solve made before it converged (no-op launches after it are
+     * excluded); index 0 = FP64 kernels, 1 = FP32 kernels */
     double spmv_ms[2];
     int64_t spmv_launches[2];
     double bj_ms[2];
@@ -177,16 +182,16 @@ typedef struct {
     /* FP32 modes: the decisions of the last solve (at most SDSL_RF_HISTORY
      * are kept; rf_count counts them all).  Entry e: rf_it = iterations so
      * far, rf_nr = the true residual norm the decision was taken on,
-     * rf_act = 0 done, 1 continue, 2 hand the recurrence to FP64, 3 solve
-     * the residual equation in FP64, 4 revert to the last refinement point
-     * and solve in FP64, 5 fail; rf_flag bit 0 = breakdown, bit 1 = a
-     * decision after an FP64 solve of the residual equation.  rf_nb = ||b||.
-     * The rule is a tuned choice of this library (the paper states no
+     * rf_act = 0 done, 1 continue, 2 solve the residual equation in FP64
+     * from the current solution, 3 revert to the last refinement point (or
+     * discard the broken-down inner solve) and solve in FP64, 4 fail; rf_flag bit 0 = breakdown, bit 1 = a decision
+     * after an FP64 solve of the residual equation.  rf_nb = ||b||.  The
+     * rule is a tuned choice of this library (the paper states no
      * precision): a point is weak when its residual is above 0.5 times the
-     * previous point's; 3 weak points in a row hand the mixed recurrence to
-     * FP64, 3 more solve the residual equation in FP64; 2 weak classical
-     * refinement steps do the latter; at most 4 such solves, each to 0.5 of
-     * the remaining tolerance. */
+     * previous point's; 3 weak points in a row of the mixed recurrence, or 2
+     * weak classical refinement steps, send the rest to FP64 solves of the
+     * residual equation (fresh PCG to 0.5 of the remaining tolerance, at
+     * most 4). */
     int32_t rf_count;
     int32_t rf_it[64];
     double rf_nr[64];

@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                _SRC, "-lm", "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
@@ -42,7 +42,14 @@ def lib():
         build(force=False)
         _lib = C.CDLL(_LIB)
         _declare(_lib)
+        _lib.or_set_threads(1)
     return _lib
+
+
+def set_threads(t: int) -> None:
+    """Threads of the oracle's row and block loops (results do not depend on
+    it: every sum keeps its sequential order)."""
+    lib().or_set_threads(int(t))
 
 
 P = C.c_void_p
@@ -72,24 +79,25 @@ def _declare(L):
     L.or_bbd_free.argtypes = [P]
     L.or_bbd_apply.argtypes = [P, P, P]
     L.or_bbd_get.argtypes = [P, P, P, P, P, P, P]
-    L.or_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, I32, P, P, P]
+    L.or_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, I32, P, P, P, P, D, I32, P, P, P]
     L.or_pcg_bj.restype = C.c_int
-    L.or_gmres_bj.argtypes = [I64, P, P, P, P, P, P, P, P, P, D, I32, I32, P, P, P]
+    L.or_gmres_bj.argtypes = [I64, P, P, P, P, P, P, P, I32, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bj.restype = C.c_int
     L.or_gmres_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bbd.restype = C.c_int
-    L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P,
-                               I32, P, P, P, P]
+    L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, I32, P, P, P, P, D, D, I32, I32,
+                               I32, P, P, I32, P, P, P, P]
     L.or_ir_pcg_bj.restype = C.c_int
-    L.or_mx_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, P, P, P, D, D, I32, I32, P, P,
-                               I32, P, P, P, P]
+    L.or_mx_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, I32, P, P, P, P, D, D, I32, I32,
+                               P, P, I32, P, P, P, P]
     L.or_mx_pcg_bj.restype = C.c_int
-    L.or_refine_decide.argtypes = [I32, D, D, D, I32, I32, P]
+    L.or_refine_decide.argtypes = [I32, D, D, D, I32, P]
     L.or_refine_decide.restype = C.c_int
     L.or_fallback_decide.argtypes = [D, D, I32, I32]
     L.or_fallback_decide.restype = C.c_int
     L.or_refine_constants.argtypes = [P]
-    L.or_border_setup.argtypes = [I64, P, P, P, P, I32, P, P, P, P, P]
+    L.or_border_setup.argtypes = [I64, P, P, P, P, I32, P, I32, P, P, P, P, P]
+    L.or_set_threads.argtypes = [I32]
     L.or_border_setup.restype = P
     L.or_border_free.argtypes = [P]
     L.or_border_apply.argtypes = [P, P, P]
@@ -197,6 +205,7 @@ class BJ:
         self.corrected = v0
         n = self.rp.shape[0] - 1
         bp = np.ascontiguousarray(sys_.block_ptr, dtype=np.int32)
+        self.bp, self.nb = bp, bp.shape[0] - 1
         self.v = np.empty_like(v0)
         self.dp = np.empty(max(n, 1), dtype=np.int64)
         self.shifts = np.zeros(bp.shape[0] - 1)
@@ -213,8 +222,9 @@ class BJ:
             self._bk = _csr(U.indptr, U.indices, U.data) + (np.ascontiguousarray(c, dtype=np.float64),)
             urp, uci, uv, cc = self._bk
             st = C.c_int32(0)
-            self.border = lib().or_border_setup(n, _p(self.rp), _p(self.ci), _p(self.v), _p(self.dp),
-                                                U.shape[1], _p(urp), _p(uci), _p(uv), _p(cc), C.byref(st))
+            self.border = lib().or_border_setup(n, _p(self.rp), _p(self.ci), _p(self.v), _p(self.dp), self.nb,
+                                                _p(self.bp), U.shape[1], _p(urp), _p(uci), _p(uv), _p(cc),
+                                                C.byref(st))
             self.border_status = st.value
 
     def apply(self, r):
@@ -252,22 +262,22 @@ def pcg_bj(sys_, P: BJ, tol=1e-8, maxit=10_000, hist=False):
     h = np.zeros(maxit) if hist else None
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
     st = lib().or_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
-                         _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, maxit, C.byref(its),
+                         _p(P.ci), _p(P.v), _p(P.dp), P.nb, _p(P.bp), P.border, _p(b), _p(x), tol, maxit, C.byref(its),
                          C.byref(rr), _p(h))
     return x, its.value, rr.value, st, (h[:its.value] if hist else None)
 
 
 # refinement decisions of the FP32 modes (or_refine_decide)
-RF_DONE, RF_CONTINUE, RF_HANDOFF, RF_FALLBACK, RF_REVERT, RF_FAIL = range(6)
-RF_NAMES = ["done", "continue", "handoff", "fallback", "revert", "fail"]
+RF_DONE, RF_CONTINUE, RF_FALLBACK, RF_REVERT, RF_FAIL = range(5)
+RF_NAMES = ["done", "continue", "fallback", "revert", "fail"]
 HIST_CAP = 256
 
 
-def refine_decide(mode, nr, prev, tol_nb, breakdown, handed, slow):
+def refine_decide(mode, nr, prev, tol_nb, breakdown, slow):
     """One refinement-point decision: returns (action, new slow count).
     mode 0 = mixed recurrence, 1 = classical refinement."""
     s = C.c_int32(slow)
-    act = lib().or_refine_decide(mode, nr, prev, tol_nb, int(breakdown), int(handed), C.byref(s))
+    act = lib().or_refine_decide(mode, nr, prev, tol_nb, int(breakdown), C.byref(s))
     return act, s.value
 
 
@@ -277,8 +287,8 @@ def fallback_decide(nr, tol_nb, st64, nsolves):
 
 
 def refine_constants():
-    """(weak ratio, hand-off count, slow count, max fallback solves,
-    fallback tolerance fraction) of the rule."""
+    """(weak ratio, weak points of the mixed mode, weak steps of classical
+    refinement, max fallback solves, fallback tolerance fraction)."""
     out = np.zeros(5)
     lib().or_refine_constants(_p(out))
     return tuple(out)
@@ -299,7 +309,7 @@ def replay_refine(hist, mode, nb, tol, maxit):
     """Re-derive every decision of an FP32-mode history (a list of dicts with
     it, nr, act, breakdown, after_fallback) with the rule alone; raises
     AssertionError at the first decision the rule does not give."""
-    slow, handed, prev, nsolves = 0, False, nb, 0
+    slow, prev, nsolves = 0, nb, 0
     for e, h in enumerate(hist):
         if h["after_fallback"]:
             nsolves += 1
@@ -309,16 +319,16 @@ def replay_refine(hist, mode, nb, tol, maxit):
             # a FAIL also follows an FP64 solve that did not converge
             assert h["act"] == want or (h["act"] == RF_FAIL and want == RF_FALLBACK), (e, h, want)
             continue
-        want, slow = refine_decide(mode, h["nr"], prev, tol * nb, h["breakdown"], handed, slow)
+        want, slow = refine_decide(mode, h["nr"], prev, tol * nb, h["breakdown"], slow)
         assert h["act"] == want, (e, h, want)
-        handed = handed or want == RF_HANDOFF
         prev = h["nr"]
 
 
-def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000, with_history=False):
-    """FP32-inner PCG inside FP64 iterative refinement.  Returns (x, outer,
-    inner total, fp64 fallbacks, relres, status) and, with_history, the list
-    of decisions taken."""
+def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000, every=500, with_history=False):
+    """FP32-inner PCG inside FP64 iterative refinement (each inner solve to
+    inner_tol or for at most `every` iterations).  Returns (x, outer, inner
+    total, fp64 fallbacks, relres, status) and, with_history, the list of
+    decisions taken."""
     rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
     n = sys_.n
     k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
@@ -328,8 +338,8 @@ def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000,
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
     h = _hist_arrays()
     st = lib().or_ir_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
-                            _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, inner_tol, max_outer,
-                            maxit, _p(out), C.byref(rr), HIST_CAP, *[_p(a) for a in h])
+                            _p(P.ci), _p(P.v), _p(P.dp), P.nb, _p(P.bp), P.border, _p(b), _p(x), tol, inner_tol, max_outer,
+                            every, maxit, _p(out), C.byref(rr), HIST_CAP, *[_p(a) for a in h])
     res = (x, int(out[0]), int(out[1]), int(out[2]), rr.value, st)
     return res + (_hist_list(int(out[3]), h),) if with_history else res
 
@@ -347,7 +357,7 @@ def mx_pcg_bj(sys_, P: BJ, tol=1e-8, delta=0.1, every=500, maxit=100_000, with_h
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
     h = _hist_arrays()
     st = lib().or_mx_pcg_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp),
-                            _p(P.ci), _p(P.v), _p(P.dp), P.border, _p(b), _p(x), tol, delta, every, maxit,
+                            _p(P.ci), _p(P.v), _p(P.dp), P.nb, _p(P.bp), P.border, _p(b), _p(x), tol, delta, every, maxit,
                             _p(out), C.byref(rr), HIST_CAP, *[_p(a) for a in h])
     res = (x, int(out[0]), int(out[1]), int(out[2]), rr.value, st)
     return res + (_hist_list(int(out[3]), h),) if with_history else res
@@ -361,8 +371,8 @@ def gmres_bj(sys_, P: BJ, tol=1e-8, m=30, maxit=10_000, hist=False):
     rr = C.c_double(0.0)
     h = np.zeros(maxit) if hist else None
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
-    st = lib().or_gmres_bj(n, _p(rp), _p(ci), _p(v), _p(P.rp), _p(P.ci), _p(P.v), _p(P.dp), _p(b),
-                           _p(x), tol, m, maxit, C.byref(its), C.byref(rr), _p(h))
+    st = lib().or_gmres_bj(n, _p(rp), _p(ci), _p(v), _p(P.rp), _p(P.ci), _p(P.v), _p(P.dp), P.nb, _p(P.bp),
+                           _p(b), _p(x), tol, m, maxit, C.byref(its), C.byref(rr), _p(h))
     return x, its.value, rr.value, st, (h[:its.value] if hist else None)
 
 

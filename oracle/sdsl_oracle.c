@@ -27,13 +27,19 @@
  * linear algebra, closed forms, error bounds or brute force on small inputs.
  * In the two FP32 refinement solvers (or_mx_pcg_bj, or_ir_pcg_bj) the inner
  * iterates are pinned to FP64 CG within FP32 rounding and the refinement
- * trigger is pinned too.  What they do at a refinement point (continue, hand
- * the recurrence to FP64, solve the residual equation in FP64) is one rule,
+ * trigger is pinned too.  What they do at a refinement point (continue, or
+ * solve the residual equation in FP64) is one rule,
  * or_refine_decide / or_fallback_decide, pinned on scripted residual
  * histories; that rule is a tuned choice (the paper states no precision),
  * and the solvers report the history they applied it to.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared sdsl_oracle.c -lm
+ * Threads: OpenMP loops run only over independent rows (products, residual
+ * rows) and independent blocks (triangular solves), with static chunks;
+ * every sum keeps its sequential order and every dot product is a plain
+ * sequential loop, so results do not depend on the thread count
+ * (or_set_threads, 1 by default from Python).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared sdsl_oracle.c -lm
  * (-ffp-contract=off keeps every a*b+c as two roundings unless fma() is
  * written out, so the arithmetic is exactly what is written here.)
  */
@@ -61,6 +67,7 @@ static double nrm2(int64_t n, const double* a) { return sqrt(dot(n, a, a)); }
 /* y = M x for M in CSR (paper Sec. 2.3, the local product of the SpMV). */
 void or_spmv(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
              const double* x, double* y) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += v[p] * x[ci[p]];
@@ -77,6 +84,7 @@ void or_lowrank_add(int64_t n, int32_t k, const int64_t* urp, const int32_t* uci
     for (int64_t i = 0; i < n; ++i)
         for (int64_t p = urp[i]; p < urp[i + 1]; ++p) t[uci[p]] += uv[p] * x[i];
     for (int32_t j = 0; j < k; ++j) t[j] *= c[j];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t p = urp[i]; p < urp[i + 1]; ++p) s += uv[p] * t[uci[p]];
@@ -121,7 +129,7 @@ double or_residual(int64_t n, const int64_t* rp, const int32_t* ci, const double
         for (int32_t j = 0; j < k; ++j) t[j] = (t[j] + te[j]) * c[j];
         free(te);
     }
-    double ss = 0.0;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = b[i], e = 0.0;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
@@ -140,8 +148,9 @@ double or_residual(int64_t n, const int64_t* rp, const int32_t* ci, const double
                 e += pe + se;
             }
         r[i] = s + e;
-        ss += r[i] * r[i];
     }
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) ss += r[i] * r[i];
     free(t);
     return sqrt(ss);
 }
@@ -351,15 +360,28 @@ typedef void (*or_prec_fn)(void* ctx, const double* r, double* z);
 /* block Jacobi: the factored block-diagonal matrix (Sec. 2.3) */
 typedef struct {
     int64_t n; const int64_t* rp; const int32_t* ci; const double* v; const int64_t* dp;
+    int32_t nb; const int32_t* bp;  /* the blocks (independent solves); bp NULL: one range */
 } or_bj;
 static void bj_apply(void* ctx, const double* r, double* z) {
     const or_bj* P = (const or_bj*)ctx;
-    or_lu_solve(0, P->n, P->rp, P->ci, P->v, P->dp, r, z);
+    if (!P->bp) { or_lu_solve(0, P->n, P->rp, P->ci, P->v, P->dp, r, z); return; }
+#pragma omp parallel for schedule(static)
+    for (int32_t b = 0; b < P->nb; ++b) or_lu_solve(P->bp[b], P->bp[b + 1], P->rp, P->ci, P->v, P->dp, r, z);
 }
 void or_bj_apply(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                  const int64_t* dp, const double* r, double* z) {
     or_lu_solve(0, n, rp, ci, v, dp, r, z);
 }
+
+/* threads of the OpenMP loops (rows of the products and residuals, blocks
+ * of the triangular solves); every sum keeps its sequential order, so the
+ * results do not depend on it */
+#ifdef _OPENMP
+#include <omp.h>
+void or_set_threads(int32_t t) { omp_set_num_threads(t > 0 ? t : 1); }
+#else
+void or_set_threads(int32_t t) { (void)t; }
+#endif
 
 /* ------------------------------------------------------------------ */
 /* Border correction for dense columns kept as a low-rank term.  The     */
@@ -386,10 +408,10 @@ typedef struct {
 } or_bjb;
 
 void* or_border_setup(int64_t n, const int64_t* prp, const int32_t* pci, const double* pv,
-                      const int64_t* pdp, int32_t k, const int64_t* urp, const int32_t* uci,
-                      const double* uv, const double* c, int32_t* status) {
+                      const int64_t* pdp, int32_t nblocks, const int32_t* bp, int32_t k, const int64_t* urp,
+                      const int32_t* uci, const double* uv, const double* c, int32_t* status) {
     or_bjb* B = (or_bjb*)calloc(1, sizeof(or_bjb));
-    B->bj.n = n; B->bj.rp = prp; B->bj.ci = pci; B->bj.v = pv; B->bj.dp = pdp;
+    B->bj.n = n; B->bj.rp = prp; B->bj.ci = pci; B->bj.v = pv; B->bj.dp = pdp; B->bj.nb = nblocks; B->bj.bp = bp;
     B->k = k; B->urp = urp; B->uci = uci; B->uv = uv;
     B->W = calloc((size_t)(n * k) + 1, 8);
     B->W32 = calloc((size_t)(n * k) + 1, 4);
@@ -842,20 +864,20 @@ void or_bbd_get(void* ctx, int64_t* tail, int64_t* lrp, int32_t* lci, double* lv
 int or_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
               int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
               const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
-              void* border, const double* b, double* x, double tol, int32_t maxit, int32_t* iters,
+              int32_t nblocks, const int32_t* bp, void* border, const double* b, double* x, double tol, int32_t maxit, int32_t* iters,
               double* relres, double* hist) {
     or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
-    or_bj P = {n, prp, pci, pv, pdp};
+    or_bj P = {n, prp, pci, pv, pdp, nblocks, bp};
     if (border) return pcg_run(&A, bjb_apply, border, b, x, tol, maxit, iters, relres, hist);
     return pcg_run(&A, bj_apply, &P, b, x, tol, maxit, iters, relres, hist);
 }
 
 int or_gmres_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                 const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
-                const double* b, double* x, double tol, int32_t m, int32_t maxit, int32_t* iters,
+                int32_t nblocks, const int32_t* bp, const double* b, double* x, double tol, int32_t m, int32_t maxit, int32_t* iters,
                 double* relres, double* hist) {
     or_op A = {n, rp, ci, v, 0, NULL, NULL, NULL, NULL};
-    or_bj P = {n, prp, pci, pv, pdp};
+    or_bj P = {n, prp, pci, pv, pdp, nblocks, bp};
     return gmres_run(&A, bj_apply, &P, b, x, tol, m, maxit, iters, relres, hist);
 }
 
@@ -881,9 +903,11 @@ typedef struct {
     const int64_t* prp; const int32_t* pci; float* pv; const int64_t* pdp;
     /* optional border correction of the preconditioner (see or_bjb) */
     int32_t bk; float* W; const double* K; const int32_t* Kpiv; double* t;
+    int32_t nb; const int32_t* bp;  /* blocks of the triangular solves (NULL: one range) */
 } or_f32sys;
 
 static void spmv32(const or_f32sys* S, const float* x, float* y) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < S->n; ++i) {
         float s = 0.0f;
         for (int64_t p = S->rp[i]; p < S->rp[i + 1]; ++p) s += S->v[p] * x[S->ci[p]];
@@ -919,17 +943,22 @@ static void prec32(const or_f32sys* S, const float* r, float* z) {
         z[i] = (float)((double)z[i] - s);
     }
 }
-static void lusolve32(const or_f32sys* S, const float* r, float* z) {
-    for (int64_t i = 0; i < S->n; ++i) {
+static void lusolve32_rows(const or_f32sys* S, int64_t lo, int64_t hi, const float* r, float* z) {
+    for (int64_t i = lo; i < hi; ++i) {
         float s = r[i];
         for (int64_t p = S->prp[i]; p < S->pdp[i]; ++p) s -= S->pv[p] * z[S->pci[p]];
         z[i] = s;
     }
-    for (int64_t i = S->n - 1; i >= 0; --i) {
+    for (int64_t i = hi - 1; i >= lo; --i) {
         float s = z[i];
         for (int64_t p = S->pdp[i] + 1; p < S->prp[i + 1]; ++p) s -= S->pv[p] * z[S->pci[p]];
         z[i] = s / S->pv[S->pdp[i]];
     }
+}
+static void lusolve32(const or_f32sys* S, const float* r, float* z) {
+    if (!S->bp) { lusolve32_rows(S, 0, S->n, r, z); return; }
+#pragma omp parallel for schedule(static)
+    for (int32_t b = 0; b < S->nb; ++b) lusolve32_rows(S, S->bp[b], S->bp[b + 1], r, z);
 }
 static double dot32(int64_t n, const float* a, const float* b) {
     double s = 0.0;
@@ -978,27 +1007,25 @@ static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int3
 /* with the one of the previous point (prev): the point is weak when       */
 /* nr > OR_RF_WEAK * prev, and `slow` counts weak points in a row.         */
 /*   mixed mode (mode 0): converged -> DONE; a breakdown of the recurrence */
-/*     -> REVERT (back to the last point's solution, then an FP64 solve of */
-/*     the residual equation); OR_RF_HAND weak points in a row -> HANDOFF  */
-/*     (the recurrence continues with the FP64 operator and factors, slow  */
-/*     restarts at 0) the first time, FALLBACK (FP64 solve of the residual */
-/*     equation) the second time; otherwise CONTINUE.                      */
+/*     -> REVERT (back to the last point's solution, then FP64 solves of   */
+/*     the residual equation); OR_RF_HAND weak points in a row -> FALLBACK */
+/*     (FP64 solves of the residual equation from the current solution);   */
+/*     otherwise CONTINUE.                                                 */
 /*   classical refinement (mode 1): converged -> DONE; an inner solve that */
-/*     broke down before completing two iterations counts as OR_RF_SLOW    */
-/*     weak steps; OR_RF_SLOW weak steps in a row -> FALLBACK; otherwise   */
-/*     CONTINUE (the next inner solve).                                    */
-/* After an FP64 solve of the residual equation (to OR_RF_FBTOL of the     */
-/* remaining tolerance, so that rounding the correction into x keeps the   */
-/* true residual below it): converged -> DONE; another such solve when the */
-/* last one converged and fewer than OR_RF_MAXFB were run -> FALLBACK;     */
-/* otherwise FAIL.                                                          */
+/*     broke down -> REVERT (its correction is discarded, then FP64 solves */
+/*     of the residual equation); OR_RF_SLOW weak steps in a row ->        */
+/*     FALLBACK; otherwise CONTINUE (the next inner solve).               */
+/* An FP64 solve of the residual equation M d = r is a fresh PCG (x0 = 0)  */
+/* to OR_RF_FBTOL of the remaining tolerance, so that rounding d into x    */
+/* keeps the true residual below it.  After one: converged -> DONE;        */
+/* another one when it converged and fewer than OR_RF_MAXFB were run ->    */
+/* FALLBACK; otherwise FAIL.                                               */
 /* ------------------------------------------------------------------ */
 #define OR_RF_DONE 0
 #define OR_RF_CONTINUE 1
-#define OR_RF_HANDOFF 2
-#define OR_RF_FALLBACK 3
-#define OR_RF_REVERT 4
-#define OR_RF_FAIL 5
+#define OR_RF_FALLBACK 2
+#define OR_RF_REVERT 3
+#define OR_RF_FAIL 4
 
 #define OR_RF_WEAK 0.5
 #define OR_RF_HAND 3
@@ -1006,20 +1033,15 @@ static int pcg32(const or_f32sys* S, const float* b, float* x, double itol, int3
 #define OR_RF_MAXFB 4
 #define OR_RF_FBTOL 0.5
 
-int or_refine_decide(int32_t mode, double nr, double prev, double tol_nb, int32_t breakdown,
-                     int32_t handed, int32_t* slow) {
+int or_refine_decide(int32_t mode, double nr, double prev, double tol_nb, int32_t breakdown, int32_t* slow) {
     if (nr <= tol_nb) return OR_RF_DONE;
     if (mode == 0) {
         *slow = (nr > OR_RF_WEAK * prev) ? *slow + 1 : 0;
         if (breakdown) return OR_RF_REVERT;
-        if (*slow >= OR_RF_HAND) {
-            if (!handed) { *slow = 0; return OR_RF_HANDOFF; }
-            return OR_RF_FALLBACK;
-        }
-        return OR_RF_CONTINUE;
+        return (*slow >= OR_RF_HAND) ? OR_RF_FALLBACK : OR_RF_CONTINUE;
     }
-    if (breakdown) *slow = OR_RF_SLOW;
-    else *slow = (nr > OR_RF_WEAK * prev) ? *slow + 1 : 0;
+    if (breakdown) return OR_RF_REVERT;
+    *slow = (nr > OR_RF_WEAK * prev) ? *slow + 1 : 0;
     return (*slow >= OR_RF_SLOW) ? OR_RF_FALLBACK : OR_RF_CONTINUE;
 }
 
@@ -1029,8 +1051,9 @@ int or_fallback_decide(double nr, double tol_nb, int32_t st64, int32_t nsolves) 
     return OR_RF_FAIL;
 }
 
-/* the rule's constants, for the tests: weak ratio, hand-off count, slow
- * count, fallback solves, fallback tolerance fraction */
+/* the rule's constants, for the tests: weak ratio, weak points of the mixed
+ * mode, weak steps of classical refinement, fallback solves, fallback
+ * tolerance fraction */
 void or_refine_constants(double* out) {
     out[0] = OR_RF_WEAK; out[1] = OR_RF_HAND; out[2] = OR_RF_SLOW; out[3] = OR_RF_MAXFB; out[4] = OR_RF_FBTOL;
 }
@@ -1077,17 +1100,18 @@ static int fallback_loop(const or_op* A, or_prec_fn pf, void* pc, const double* 
 
 /* Classical refinement (FP32 inner solves restarted at every step):
  * x0 = 0; r = b - M x in compensated FP64; the inner FP32 PCG solves
- * M d = r / ||r|| to inner_tol; x += ||r|| d in FP64.  Decisions as above
- * (mode 1).  out[0] = outer steps, out[1] = iterations (inner ones summed,
+ * M d = r / ||r|| to inner_tol, or for at most `every` iterations; x += ||r|| d
+ * in FP64 unless the inner solve broke down.  Decisions as above (mode 1).  out[0] = outer steps, out[1] = iterations (inner ones summed,
  * FP64 fallback iterations included), out[2] = FP64 fallbacks, out[3] =
  * decisions taken (the history may hold fewer: hcap). */
 int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                  int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
                  const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
-                 void* border, const double* b, double* x, double tol, double inner_tol, int32_t max_outer,
-                 int32_t maxit, int32_t* out, double* relres, int32_t hcap, int32_t* h_it, double* h_nr,
+                 int32_t nblocks, const int32_t* bp, void* border, const double* b, double* x, double tol, double inner_tol, int32_t max_outer,
+                 int32_t every, int32_t maxit, int32_t* out, double* relres, int32_t hcap, int32_t* h_it, double* h_nr,
                  int32_t* h_act, int32_t* h_flag) {
-    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
+    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL,
+                   nblocks, bp};
     int64_t nnz = rp[n], pnnz = prp[n], unnz = k > 0 ? urp[n] : 0;
     S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
     for (int64_t p = 0; p < nnz; ++p) S.v[p] = (float)v[p];
@@ -1098,7 +1122,7 @@ int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         for (int32_t j = 0; j < k; ++j) S.c[j] = (float)c[j];
     }
     or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
-    or_bj P = {n, prp, pci, pv, pdp};
+    or_bj P = {n, prp, pci, pv, pdp, nblocks, bp};
     or_prec_fn pf = border ? bjb_apply : bj_apply;
     void* pc = border ? border : (void*)&P;
     if (border) {
@@ -1120,16 +1144,20 @@ int or_ir_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         if (out[0] >= max_outer || it >= maxit) { st = OR_NOT_CONVERGED; break; }
         for (int64_t i = 0; i < n; ++i) rs[i] = (float)(r[i] / nr);
         int32_t its = 0;
-        int sti = pcg32(&S, rs, d, inner_tol, maxit - it, &its);
-        for (int64_t i = 0; i < n; ++i) x[i] += nr * (double)d[i];
+        int32_t cap = maxit - it;
+        if (every > 0 && every < cap) cap = every;
+        int sti = pcg32(&S, rs, d, inner_tol, cap, &its);
         out[0] += 1; it += its;
         double prev = nr;
-        nr = op_true_res(&A, x, b, r);
-        int bd = (sti == OR_BREAKDOWN && its <= 1);
-        int act = or_refine_decide(1, nr, prev, tol * nb, bd, 0, &slow);
+        int bd = (sti == OR_BREAKDOWN);
+        if (!bd) {
+            for (int64_t i = 0; i < n; ++i) x[i] += nr * (double)d[i];
+            nr = op_true_res(&A, x, b, r);
+        }
+        int act = or_refine_decide(1, nr, prev, tol * nb, bd, &slow);
         hist_add(&H, it, nr, act, bd);
         if (act == OR_RF_DONE) { st = OR_OK; break; }
-        if (act == OR_RF_FALLBACK) {
+        if (act == OR_RF_FALLBACK || act == OR_RF_REVERT) {
             st = fallback_loop(&A, pf, pc, b, x, r, nb, tol, &nr, maxit, &it, &nsolves, &out[2], &H);
             break;
         }
@@ -1156,12 +1184,12 @@ done:
 /* the recurrence continues (reliable updating: Sleijpen and van der       */
 /* Vorst, Computing 56 (1996)).  What happens next is decided by           */
 /* or_refine_decide (mode 0).                                              */
-/* out[0] = refinement points, out[1] = iterations, out[2] = fallbacks     */
-/* (hand-offs and FP64 solves of the residual equation), out[3] =          */
-/* decisions taken.                                                        */
+/* out[0] = refinement points, out[1] = iterations, out[2] = FP64 solves  */
+/* of the residual equation, out[3] = decisions taken.                    */
 /* ------------------------------------------------------------------ */
 static void mx_spmv(const or_f32sys* S, const or_op* A, const double* x, float* xs, double* y) {
     for (int64_t i = 0; i < S->n; ++i) xs[i] = (float)x[i];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < S->n; ++i) {
         float s = 0.0f;
         for (int64_t p = S->rp[i]; p < S->rp[i + 1]; ++p) s += S->v[p] * xs[S->ci[p]];
@@ -1190,16 +1218,17 @@ static void mx_prec(const or_f32sys* S, void* border, const double* r, float* rs
 int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                  int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
                  const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
-                 void* border, const double* b, double* x, double tol, double delta, int32_t every,
+                 int32_t nblocks, const int32_t* bp, void* border, const double* b, double* x, double tol, double delta, int32_t every,
                  int32_t maxit, int32_t* out, double* relres, int32_t hcap, int32_t* h_it, double* h_nr,
                  int32_t* h_act, int32_t* h_flag) {
-    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL};
+    or_f32sys S = {n, rp, ci, NULL, k, urp, uci, NULL, NULL, prp, pci, NULL, pdp, 0, NULL, NULL, NULL, NULL,
+                   nblocks, bp};
     int64_t nnz = rp[n], pnnz = prp[n];
     S.v = malloc((size_t)nnz * 4 + 4); S.pv = malloc((size_t)pnnz * 4 + 4);
     for (int64_t p = 0; p < nnz; ++p) S.v[p] = (float)v[p];
     for (int64_t p = 0; p < pnnz; ++p) S.pv[p] = (float)pv[p];
     or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
-    or_bj P = {n, prp, pci, pv, pdp};
+    or_bj P = {n, prp, pci, pv, pdp, nblocks, bp};
     or_prec_fn pf = border ? bjb_apply : bj_apply;
     void* pc = border ? border : (void*)&P;
     or_rf_hist H = {0, hcap, h_it, h_nr, h_act, h_flag};
@@ -1209,7 +1238,6 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     double nb = nrm2(n, b);
     int st = OR_NOT_CONVERGED;
     int32_t it = 0, slow = 0, last = 0, nsolves = 0;
-    int handed = 0;  /* the recurrence runs on with the FP64 operator and factors */
     out[0] = out[1] = out[2] = out[3] = 0;
     memset(x, 0, (size_t)n * 8);
     double nr = nb;
@@ -1220,8 +1248,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
     memcpy(p, z, (size_t)n * 8);
     double rz = dot(n, r, z);
     while (it < maxit) {
-        if (handed) op_apply(&A, p, q);
-        else mx_spmv(&S, &A, p, xs, q);
+        mx_spmv(&S, &A, p, xs, q);
         double pq = dot(n, p, q);
         double alpha = rz / pq;
         int bd = !(pq > 0.0) || !isfinite(alpha);
@@ -1232,8 +1259,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
             int conv = rr <= tol * tol * (nb * nb);
             int upd = rr < delta * delta * rr0 || (every > 0 && it - last >= every);
             if (!conv && !upd) {
-                if (handed) pf(pc, r, z);
-                else mx_prec(&S, border, r, xs, zs, z);
+                mx_prec(&S, border, r, xs, zs, z);
                 double rz2 = dot(n, r, z);
                 double beta = rz2 / rz;
                 if (isfinite(beta) && isfinite(rz2)) {
@@ -1248,7 +1274,7 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
         out[0] += 1;
         double prev = nr;
         nr = op_true_res(&A, x, b, r);
-        int act = or_refine_decide(0, nr, prev, tol * nb, bd, handed, &slow);
+        int act = or_refine_decide(0, nr, prev, tol * nb, bd, &slow);
         hist_add(&H, it, nr, act, bd);
         if (act == OR_RF_DONE) { st = OR_OK; break; }
         if (act == OR_RF_REVERT) {
@@ -1265,15 +1291,13 @@ int or_mx_pcg_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
             st = fallback_loop(&A, pf, pc, b, x, r, nb, tol, &nr, maxit, &it, &nsolves, &out[2], &H);
             break;
         }
-        if (act == OR_RF_HANDOFF) { handed = 1; out[2] += 1; }
         if (it >= maxit) break;
         /* the true residual replaces the recurrence one; the recurrence
          * continues with its search direction */
         rr0 = dot(n, r, r);
         last = it;
         memcpy(xr, x, (size_t)n * 8);
-        if (handed) pf(pc, r, z);
-        else mx_prec(&S, border, r, xs, zs, z);
+        mx_prec(&S, border, r, xs, zs, z);
         double rz2 = dot(n, r, z);
         double beta = rz2 / rz;
         rz = rz2;

@@ -181,7 +181,7 @@ class Options:
     inner_tol: float = 1e-4
     max_outer: int = 30
     check_every: int = 16
-    kernel_timing: bool = False
+    kernel_timing: int = 0
     border: bool = True
     refine_delta: float = 0.1
     refine_every: int = 500

@@ -702,22 +702,33 @@ struct Pcg {
         precondition(j, PUPD_REAPPLY);
         it = j + 1;
     }
+    // kernel timing: iterations whose index is a multiple of kernel_timing
+    // get three events (SpMV start, SpMV end = BJ start, BJ end); sampled[k]
+    // = the batch position of the k-th timed iteration
+    std::vector<int> sampled;
     void issue(int count) {
         const CsrView A{h->n, h->rp, h->ci, h->halo};
-        const bool timing = h->o.kernel_timing != 0;
-        if (timing && (int)h->ev.size() < 3 * count) {
-            const size_t old = h->ev.size();
-            h->ev.resize(3 * count);
-            for (size_t i = old; i < h->ev.size(); ++i) hip_check(hipEventCreate(&h->ev[i]), "event create");
-        }
+        const int period = h->o.kernel_timing;
         batch_start = it;
         batch_count = count;
+        sampled.clear();
         for (int k = 0; k < count; ++k, ++it) {
-            if (timing) hip_check(hipEventRecord(h->ev[3 * k], h->s), "event record");
+            const bool timed = period > 0 && it % period == 0;
+            int e = 0;
+            if (timed) {
+                e = 3 * (int)sampled.size();
+                if ((int)h->ev.size() < e + 3) {
+                    const size_t old = h->ev.size();
+                    h->ev.resize(e + 3);
+                    for (size_t i = old; i < h->ev.size(); ++i) hip_check(hipEventCreate(&h->ev[i]), "event create");
+                }
+                sampled.push_back(k);
+            }
+            if (timed) hip_check(hipEventRecord(h->ev[e], h->s), "event record");
             launch_spmv<V, F>(A, v, h->lr, p, q, h->part_pq, h->st, h->lanes, h->grid, h->s);
-            if (timing) hip_check(hipEventRecord(h->ev[3 * k + 1], h->s), "event record");
+            if (timed) hip_check(hipEventRecord(h->ev[e + 1], h->s), "event record");
             launch_bj<V, F>(1, P, Vv, h->st, it, h->s);
-            if (timing) hip_check(hipEventRecord(h->ev[3 * k + 2], h->s), "event record");
+            if (timed) hip_check(hipEventRecord(h->ev[e + 2], h->s), "event record");
             if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, h->st, LR_BORDER, h->bd.Kinv, h->s);
             launch_pcg_pupdate<V>(h->n, Vv, h->nb, h->bd, h->st, it, PUPD_STEP, h->s);
             if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
@@ -728,20 +739,21 @@ struct Pcg {
         hip_check(hipMemcpyAsync(h->st_h, h->st, sizeof(KrylovState), hipMemcpyDeviceToHost, h->s), "copy");
         h->sync();
         if (h->st_h->spin_err) fail(SDSL_E_DEVICE, "triangular solve met a term not yet solved at its level (stale level tables)");
-        if (h->o.kernel_timing && batch_count > 0) {
+        if (!sampled.empty()) {
             // only launches made before the state said done did work
             int live = batch_count;
             if (h->st_h->done) live = std::max(0, std::min(batch_count, h->st_h->iters - batch_start));
-            for (int k = 0; k < live; ++k) {
+            for (size_t q = 0; q < sampled.size() && sampled[q] < live; ++q) {
                 float a = 0.f, b = 0.f;
-                hip_check(hipEventElapsedTime(&a, h->ev[3 * k], h->ev[3 * k + 1]), "event time");
-                hip_check(hipEventElapsedTime(&b, h->ev[3 * k + 1], h->ev[3 * k + 2]), "event time");
+                hip_check(hipEventElapsedTime(&a, h->ev[3 * q], h->ev[3 * q + 1]), "event time");
+                hip_check(hipEventElapsedTime(&b, h->ev[3 * q + 1], h->ev[3 * q + 2]), "event time");
                 h->info.spmv_ms[kPrec] += a;
                 h->info.bj_ms[kPrec] += b;
+                h->info.spmv_launches[kPrec] += 1;
+                h->info.bj_launches[kPrec] += 1;
             }
-            h->info.spmv_launches[kPrec] += live;
-            h->info.bj_launches[kPrec] += live;
         }
+        sampled.clear();
         batch_count = 0;
         return *h->st_h;
     }
@@ -805,14 +817,13 @@ __global__ void k_axpy1(int n, double* __restrict__ x, const double* __restrict_
 // kRfWeak times that of the previous point; `slow` counts weak points in a
 // row.  Mixed recurrence: converged -> done; a breakdown -> back to the last
 // point's solution and FP64 solves of the residual equation; kRfHand weak
-// points in a row -> the recurrence continues on the FP64 operator and
-// factors (once), then FP64 solves of the residual equation.  Classical
-// refinement: an inner solve that broke down before two iterations counts
-// as kRfSlow weak steps; kRfSlow weak steps in a row -> FP64 solves of the
-// residual equation.  After such a solve (to kRfFbTol of the remaining
-// tolerance): converged -> done; another one when it converged and fewer
-// than kRfMaxFb were run; otherwise the solve fails.
-enum RfAction { RF_DONE = 0, RF_CONTINUE = 1, RF_HANDOFF = 2, RF_FALLBACK = 3, RF_REVERT = 4, RF_FAIL = 5 };
+// points in a row -> FP64 solves of the residual equation from the current
+// solution.  Classical refinement: an inner solve that broke down is
+// discarded and FP64 solves of the residual equation follow; kRfSlow weak
+// steps in a row -> FP64 solves of the residual equation.  Such a solve is a fresh FP64 PCG to
+// kRfFbTol of the remaining tolerance; after it: converged -> done; another
+// one when it converged and fewer than kRfMaxFb were run; otherwise fail.
+enum RfAction { RF_DONE = 0, RF_CONTINUE = 1, RF_FALLBACK = 2, RF_REVERT = 3, RF_FAIL = 4 };
 constexpr double kRfWeak = 0.5;
 constexpr int kRfHand = 3;
 constexpr int kRfSlow = 2;
@@ -820,19 +831,15 @@ constexpr int kRfMaxFb = 4;
 constexpr double kRfFbTol = 0.5;
 constexpr int kRfHistory = SDSL_RF_HISTORY;
 
-int rf_decide(bool mixed, double nr, double prev, double tol_nb, bool breakdown, bool handed, int& slow) {
+int rf_decide(bool mixed, double nr, double prev, double tol_nb, bool breakdown, int& slow) {
     if (nr <= tol_nb) return RF_DONE;
     if (mixed) {
         slow = nr > kRfWeak * prev ? slow + 1 : 0;
         if (breakdown) return RF_REVERT;
-        if (slow >= kRfHand) {
-            if (handed) return RF_FALLBACK;
-            slow = 0;
-            return RF_HANDOFF;
-        }
-        return RF_CONTINUE;
+        return slow >= kRfHand ? RF_FALLBACK : RF_CONTINUE;
     }
-    slow = breakdown ? kRfSlow : (nr > kRfWeak * prev ? slow + 1 : 0);
+    if (breakdown) return RF_REVERT;
+    slow = nr > kRfWeak * prev ? slow + 1 : 0;
     return slow >= kRfSlow ? RF_FALLBACK : RF_CONTINUE;
 }
 
@@ -860,8 +867,6 @@ struct SolveTask {
     enum Phase { P64, PMIX, P32_RESTART, PGMRES } phase = P64;
     Pcg<double, double> pcg64{};
     Pcg<double, float> pcgmix{};
-    Pcg<double, double> pcghand{};  // FP64 continuation of the pcgmix recurrence
-    bool handed = false;            // pcgmix stagnated: the recurrence runs on in FP64
     Pcg<float, float> pcg32{};
     // FP64 PCG target (the solve itself, or an FP64 fallback of an FP32 mode)
     const double* rhs64 = nullptr;
@@ -904,8 +909,6 @@ struct SolveTask {
         pcg64.init();
         pcgmix = Pcg<double, float>{h, xout, h->r, h->z, h->p, h->q, h->y32, h->v32};
         pcgmix.init();
-        pcghand = Pcg<double, double>{h, xout, h->r, h->z, h->p, h->q, h->y, h->v};
-        pcghand.init();
         pcg32 = Pcg<float, float>{h, h->x32, h->r32, h->z32, h->p32, h->q32, h->y32, h->v32};
         pcg32.init();
         if (h->o.krylov == SDSL_GMRES) {
@@ -975,7 +978,13 @@ struct SolveTask {
         launch_sqnorm_f32_partials(h->n, h->r32, h->part_res, h->grid, h->s);
         launch_init_state(h->st, h->part_res, h->grid, h->o.inner_tol, 0.0, h->s);
         pcg32.start(0);
-        pcg32.issue(std::min(h->o.check_every, max_iter() - total_its));
+        pcg32.issue(inner_batch());
+    }
+    // iterations of the next batch of a classical-refinement inner solve: it
+    // stops at inner_tol, after refine_every iterations or at max_iter
+    int inner_batch() const {
+        return std::max(0, std::min({h->o.check_every, max_iter() - total_its - pcg32.it,
+                                     h->o.refine_every - pcg32.it}));
     }
     void after_fallback(sdsl_status st64) {
         const int g = std::min(4096, (h->n + 255) / 256);
@@ -1097,35 +1106,32 @@ struct SolveTask {
         if (phase == PMIX) { step_mixed(); return; }
         // classical refinement: wait for the inner solve to stop
         const KrylovState& s = pcg32.poll();
-        if (!s.done && total_its + pcg32.it < max_iter()) {
-            pcg32.issue(std::min(h->o.check_every, max_iter() - total_its - pcg32.it));
+        if (!s.done && inner_batch() > 0) {
+            pcg32.issue(inner_batch());
             return;
         }
         const int inner = s.done ? s.iters : pcg32.it;
         total_its += inner;
-        const bool bd = s.done && s.breakdown && inner <= 1;
-        launch_ir_update(h->n, xout, h->scal + 0, h->x32, h->s);   // x += ||r|| d
-        h->check_launch();
+        const bool bd = s.done && s.breakdown;
         outer++;
         prev = nr;
-        nr = true_residual(h, b, xout, h->r);
-        const int act = rf_decide(false, nr, prev, tol * nb, bd, false, slow);
+        if (!bd) {
+            launch_ir_update(h->n, xout, h->scal + 0, h->x32, h->s);   // x += ||r|| d
+            h->check_launch();
+            nr = true_residual(h, b, xout, h->r);
+        }
+        const int act = rf_decide(false, nr, prev, tol * nb, bd, slow);
         record(total_its, nr, act, bd ? 1 : 0);
         if (act == RF_DONE) { finish(SDSL_OK, nr / nb); return; }
-        if (act == RF_FALLBACK) { start_fallback(); return; }
+        if (act == RF_FALLBACK || act == RF_REVERT) { start_fallback(); return; }
         restart_inner();
     }
     void step_mixed() {
-        Pcg<double, double>& e64 = pcghand;
-        const KrylovState& s = handed ? e64.poll() : pcgmix.poll();
-        const int it_now = handed ? e64.it : pcgmix.it;
-        auto issue = [&](int count) {
-            if (handed) e64.issue(count);
-            else pcgmix.issue(count);
-        };
+        const KrylovState& s = pcgmix.poll();
+        const int it_now = pcgmix.it;
         if (!s.done) {
             if (it_now < max_iter()) {
-                issue(std::min(h->o.check_every, max_iter() - it_now));
+                pcgmix.issue(std::min(h->o.check_every, max_iter() - it_now));
                 return;
             }
             // the iteration limit without a refinement point
@@ -1141,7 +1147,7 @@ struct SolveTask {
         prev = nr;
         nr = true_residual(h, b, xout, h->r);
         const bool bd = s.breakdown != 0;
-        const int act = rf_decide(true, nr, prev, tol * nb, bd, handed, slow);
+        const int act = rf_decide(true, nr, prev, tol * nb, bd, slow);
         record(its, nr, act, bd ? 1 : 0);
         if (act == RF_DONE) { finish(SDSL_OK, nr / nb); return; }
         if (act == RF_REVERT) {
@@ -1156,20 +1162,13 @@ struct SolveTask {
             return;
         }
         if (act == RF_FALLBACK) { start_fallback(); return; }
-        if (act == RF_HANDOFF) {
-            // the FP32 operator or factors stall the recurrence: it continues
-            // with the FP64 ones from the same search direction
-            handed = true;
-            fallbacks++;
-        }
         if (its >= max_iter()) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
         // the true residual (now in r) replaces the recurrence one; the
         // recurrence continues with its search direction
         launch_copy<double>(h->n, xout, h->xref, h->s);
         launch_refine_state(h->st, h->part_res, h->grid, its, h->o.refine_every, h->s);
-        if (handed) e64.reapply(its - 1);
-        else pcgmix.reapply(its - 1);
-        issue(std::min(h->o.check_every, max_iter() - its));
+        pcgmix.reapply(its - 1);
+        pcgmix.issue(std::min(h->o.check_every, max_iter() - its));
     }
     void step64() {
         const KrylovState& s = pcg64.poll();

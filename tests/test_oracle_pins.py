@@ -716,52 +716,47 @@ def test_border_removes_low_rank_outliers():
 def test_refine_rule_mixed_mode_scripted_histories():
     """The mixed mode's decision at a refinement point (a tuned rule; the
     paper states no precision): a point is weak when the true residual is
-    above half the previous point's; three weak points in a row hand the
-    recurrence to FP64 (once), three more solve the residual equation in
-    FP64; a breakdown reverts to the last point and solves in FP64; meeting
-    the tolerance ends the solve before anything else."""
+    above half the previous point's; three weak points in a row send the rest
+    to FP64 solves of the residual equation; a breakdown reverts to the last
+    point first; meeting the tolerance ends the solve before anything else."""
     assert O.refine_constants() == (0.5, 3.0, 2.0, 4.0, 0.5)
-    tol = 1e-8
-
-    def run(rel, handed=False, bd=()):
-        slow, acts, prev = 0, [], 1.0
-        for e, nr in enumerate(rel):
-            a, slow = O.refine_decide(0, nr, prev, tol, e in bd, handed, slow)
-            acts.append(O.RF_NAMES[a])
-            if a == O.RF_HANDOFF:
-                handed = True
-            prev = nr
-        return acts, slow
-    # halving exactly is not weak; a hair above half is
-    assert run([0.5, 0.25])[0] == ["continue", "continue"]
-    assert run([0.5, 0.2500001]) == (["continue", "continue"], 1)
-    # three weak points in a row hand over at the third, not earlier
-    assert run([0.9, 0.8, 0.7]) == (["continue", "continue", "handoff"], 0)
-    assert run([0.9, 0.8, 0.7, 0.6, 0.55, 0.5]) == (["continue", "continue", "handoff", "continue", "continue",
-                                                    "fallback"], 3)
-    # a strong point in between resets the count
-    assert run([0.9, 0.8, 0.3, 0.25, 0.2])[0] == ["continue"] * 5
-    # already handed (or handed before): three weak points solve in FP64
-    assert run([0.9, 0.8, 0.7], handed=True)[0] == ["continue", "continue", "fallback"]
-    # breakdown: revert, whatever the count; convergence wins over breakdown
-    assert run([0.1, 0.05], bd={1})[0] == ["continue", "revert"]
-    assert run([0.1, 5e-9], bd={1})[0] == ["continue", "done"]
-    assert run([0.9, 0.8, 1e-8])[0] == ["continue", "continue", "done"]
-    # just above the tolerance is not done: three weak points there hand over
-    assert run([1.5e-8, 1.2e-8, 1.1e-8, 1.0000001e-8]) == (["continue", "continue", "continue", "handoff"], 0)
-
-
-def test_refine_rule_restart_mode_and_fallback_scripted_histories():
-    """Classical refinement: two weak steps in a row (or an inner solve that
-    broke down before two iterations) send the rest to an FP64 solve of the
-    residual equation; after such a solve, another one follows only when it
-    converged and fewer than four were run."""
     tol = 1e-8
 
     def run(rel, bd=()):
         slow, acts, prev = 0, [], 1.0
         for e, nr in enumerate(rel):
-            a, slow = O.refine_decide(1, nr, prev, tol, e in bd, False, slow)
+            a, slow = O.refine_decide(0, nr, prev, tol, e in bd, slow)
+            acts.append(O.RF_NAMES[a])
+            prev = nr
+        return acts, slow
+    # halving exactly is not weak; a hair above half is
+    assert run([0.5, 0.25])[0] == ["continue", "continue"]
+    assert run([0.5, 0.2500001]) == (["continue", "continue"], 1)
+    # three weak points in a row: FP64 at the third, not earlier
+    assert run([0.9, 0.8]) == (["continue", "continue"], 2)
+    assert run([0.9, 0.8, 0.7]) == (["continue", "continue", "fallback"], 3)
+    # a strong point in between resets the count
+    assert run([0.9, 0.8, 0.3, 0.25, 0.2])[0] == ["continue"] * 5
+    assert run([0.9, 0.8, 0.3, 0.25, 0.2, 0.15])[0] == ["continue"] * 5 + ["fallback"]
+    # breakdown: revert, whatever the count; convergence wins over breakdown
+    assert run([0.1, 0.05], bd={1})[0] == ["continue", "revert"]
+    assert run([0.1, 5e-9], bd={1})[0] == ["continue", "done"]
+    assert run([0.9, 0.8, 1e-8])[0] == ["continue", "continue", "done"]
+    # just above the tolerance is not done: three weak points there go to FP64
+    assert run([1.5e-8, 1.2e-8, 1.1e-8, 1.0000001e-8]) == (["continue", "continue", "continue", "fallback"], 3)
+
+
+def test_refine_rule_restart_mode_and_fallback_scripted_histories():
+    """Classical refinement: two weak steps in a row send the rest to an FP64
+    solve of the residual equation; an inner solve that broke down is
+    discarded (revert) before that; after such a solve, another one follows
+    only when it converged and fewer than four were run."""
+    tol = 1e-8
+
+    def run(rel, bd=()):
+        slow, acts, prev = 0, [], 1.0
+        for e, nr in enumerate(rel):
+            a, slow = O.refine_decide(1, nr, prev, tol, e in bd, slow)
             acts.append(O.RF_NAMES[a])
             prev = nr
         return acts
@@ -770,7 +765,8 @@ def test_refine_rule_restart_mode_and_fallback_scripted_histories():
     assert run([0.9, 0.3, 0.2, 0.15]) == ["continue"] * 3 + ["fallback"]
     assert run([0.1, 0.01, 0.001]) == ["continue"] * 3
     assert run([0.5, 0.25, 0.125]) == ["continue"] * 3
-    assert run([0.1], bd={0}) == ["fallback"]
+    assert run([0.1], bd={0}) == ["revert"]
+    assert run([0.9, 0.9], bd={1}) == ["continue", "revert"]
     assert run([1e-9], bd={0}) == ["done"]
     fb = lambda nr, st, k: O.RF_NAMES[O.fallback_decide(nr, tol, st, k)]
     assert fb(1e-8, O.OK, 1) == "done"
@@ -783,20 +779,23 @@ def test_refine_rule_restart_mode_and_fallback_scripted_histories():
 
 def test_fp32_solvers_apply_the_refine_rule():
     """Both FP32 solvers take exactly the rule's decisions on their own
-    residual histories, on a late IPM system that stalls the FP32 recurrence
-    (hand-off and FP64 solves happen)."""
+    residual histories, on late IPM systems that stall the FP32 recurrence
+    (FP64 solves of the residual equation follow), and still meet the
+    tolerance, checked with scipy."""
     q = gen.IPMSequence(m=20000, nblocks=4, steps=30)
-    s = q.system(20)
-    P = O.BJ(s, mode=O.FILTER_GEOMEAN, tau=1e-3, flags=O.DIAG_DROPSUM)
-    nb = np.linalg.norm(s.b)
-    *_, fb, rr, st, hist = O.mx_pcg_bj(s, P, tol=1e-8, delta=0.3, every=500, maxit=60000, with_history=True)
-    assert st == O.OK and fb >= 1 and len(hist) >= 3
-    assert any(h["act"] == O.RF_HANDOFF for h in hist)
-    O.replay_refine(hist, 0, nb, 1e-8, 60000)
-    *_, fb, rr, st, hist = O.ir_pcg_bj(s, P, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=60000,
-                                       with_history=True)
-    assert st == O.OK and len(hist) >= 1
-    O.replay_refine(hist, 1, nb, 1e-8, 60000)
+    for k in (16, 20):
+        s = q.system(k)
+        P = O.BJ(s, mode=O.FILTER_GEOMEAN, tau=1e-3, flags=O.DIAG_DROPSUM)
+        nb = np.linalg.norm(s.b)
+        x, pts, its, fb, rr, st, hist = O.mx_pcg_bj(s, P, tol=1e-8, delta=0.3, every=500, maxit=60000,
+                                                    with_history=True)
+        assert st == O.OK and fb >= 1 and len(hist) >= 4
+        assert np.linalg.norm(s.b - s.scipy() @ x) / nb <= 1.5e-8
+        O.replay_refine(hist, 0, nb, 1e-8, 60000)
+        x, outer, its, fb, rr, st, hist = O.ir_pcg_bj(s, P, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=60000,
+                                                      with_history=True)
+        assert st == O.OK and len(hist) >= 1
+        O.replay_refine(hist, 1, nb, 1e-8, 60000)
 
 
 def _mixed_case(lowrank, border, n=60, seed=40):
