@@ -316,6 +316,20 @@ sdsl_status sdsl_precond_apply(sdsl_handle h, int32_t prec, const void* r, void*
 /* r = b - M x in compensated FP64; *norm receives ||r||_2.  DEVICE arrays. */
 sdsl_status sdsl_residual(sdsl_handle h, const double* b, const double* x, double* r, double* norm);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation): sdsl_residual computed
+ * with no allocation at all.  Same arguments, results and errors as
+ * sdsl_residual (r = b - M x in compensated FP64, *norm = ||r||_2); the
+ * reduction partials live in a 128 KiB scratch array of the library, one per
+ * device for the life of the process, instead of the handle's buffers.
+ * Limit: 1 + (SpMV workgroups) + 2 k 32 doubles for a low-rank term of k
+ * columns must fit 16384, which holds up to about 8M rows; larger systems get
+ * SDSL_E_INVALID with the sizes in sdsl_last_error.  Every call on one
+ * device shares that array, which keeps the last call's contents: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.  The handle's device must be the current one. */
+sdsl_status sdsl_residual_noalloc(sdsl_handle h, const double* b, const double* x, double* r, double* norm);
+
 /* Copies the filtered preconditioner pattern and its factors to HOST arrays
  * (any pointer may be NULL): row_ptr[n_int+1] (int64), col[nnz_kept],
  * corrected[nnz_kept] (filtered + corrected values before factorisation),

@@ -139,6 +139,7 @@ SIGNATURES = {
     "sdsl_spmv": (C.c_int, [H, C.c_int32, P, P]),
     "sdsl_precond_apply": (C.c_int, [H, C.c_int32, P, P]),
     "sdsl_residual": (C.c_int, [H, P, P, P, C.POINTER(C.c_double)]),
+    "sdsl_residual_noalloc": (C.c_int, [H, P, P, P, C.POINTER(C.c_double)]),
     "sdsl_get_factors": (C.c_int, [H, P, P, P, P, P]),
     "sdsl_get_schur": (C.c_int, [H, P, P, P]),
     "sdsl_solve_begin": (C.c_int, [H, P, P, C.c_double]),
@@ -352,6 +353,13 @@ class Solver:
         nr = C.c_double(0.0)
         _check(self.h, lib().sdsl_residual(self.h, _dptr(b), _dptr(x), _dptr(r), C.byref(nr)))
         return r, nr.value
+
+    def residual_noalloc(self, b, x, r):
+        """sdsl_residual_noalloc: r = b - M x into the caller's r (the library
+        allocates nothing); returns ||r||."""
+        nr = C.c_double(0.0)
+        _check(self.h, lib().sdsl_residual_noalloc(self.h, _dptr(b), _dptr(x), _dptr(r), C.byref(nr)))
+        return nr.value
 
     def factors(self):
         info = self.info()

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1272,6 +1273,37 @@ void check_partition(const sdsl_csr* A, const sdsl_partition* p, const sdsl_opti
 
 }  // namespace
 
+// -------------------------------------------- allocation-free residual
+// sdsl_residual_noalloc keeps its reduction partials in this file-scope
+// array instead of the handle's buffers: kNoAllocDoubles FP64 values
+// (128 KiB) on every device the library runs on, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel (in host code
+// the name is only a stand-in): the device address is taken once per device
+// with hipGetSymbolAddress and kept in g_scratch.
+constexpr size_t kNoAllocDoubles = 16384;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch[kNoAllocDevices] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+double* scratch_here() {
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "get device");
+    if (dev < 0 || dev >= kNoAllocDevices) fail(SDSL_E_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "address of the residual scratch");
+        if (!ptr) fail(SDSL_E_DEVICE, "no device address for the residual scratch");
+        g_scratch[dev] = (double*)ptr;
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
 // ===================================================================== C ABI
 extern "C" {
 
@@ -1728,6 +1760,33 @@ sdsl_status sdsl_residual(sdsl_handle h, const double* b, const double* x, doubl
         check_idle(h);
         const double nr = true_residual(h, b, x, r);
         if (norm) *norm = nr;
+    });
+}
+
+sdsl_status sdsl_residual_noalloc(sdsl_handle h, const double* b, const double* x, double* r, double* norm) {
+    if (!h) return SDSL_E_INVALID;
+    return guard(h, [&] {
+        if (!b || !x || !r) fail(SDSL_E_INVALID, "null vector");
+        check_idle(h);
+        // scratch layout: [0] = ||r||^2, [1, 1 + grid) = per-workgroup
+        // partials of ||r||^2, then the compensated U^T x slice sums of the
+        // low-rank term (2 k slices); every entry is written before it is read
+        const size_t lr_part = h->lr.k > 0 ? (size_t)2 * h->lr.k * h->lr.slices : 0;
+        const size_t need = 1 + (size_t)h->grid + lr_part;
+        if (need > kNoAllocDoubles)
+            fail(SDSL_E_INVALID, "the allocation-free residual needs " + std::to_string(need) +
+                                     " scratch doubles for this system; the limit is " +
+                                     std::to_string(kNoAllocDoubles) + " (about 8M rows)");
+        double* s = scratch_here();
+        LowRankDev lr = h->lr;
+        lr.part = s + 1 + h->grid;
+        const CsrView A{h->n, h->rp, h->ci, h->halo};
+        launch_residual(A, h->v, lr, b, x, r, s + 1, h->lanes, h->grid, h->s);
+        launch_sum_partials(s + 1, h->grid, s, h->s);
+        h->check_launch();
+        hip_check(hipMemcpyAsync(h->scal_h + 3, s, sizeof(double), hipMemcpyDeviceToHost, h->s), "copy");
+        h->sync();
+        if (norm) *norm = std::sqrt(h->scal_h[3]);
     });
 }
 
