@@ -72,7 +72,15 @@ enum { SDSL_DIAG_DELTA = 1u, SDSL_DIAG_DROPSUM = 2u };
  * Comp. 34 (1980)), not the small absolute correction of Eq. (diagcorr). */
 typedef enum { SDSL_PIVOT_FAIL = 0, SDSL_PIVOT_REPLACE = 1, SDSL_PIVOT_SHIFT = 2 } sdsl_pivot;
 
-typedef enum { SDSL_PCG = 0, SDSL_GMRES = 1 } sdsl_krylov;          /* Sec. 2.2 */
+/* Krylov methods (Sec. 2.2; Sec. 4.3 pairs BiCGSTAB with block Jacobi and
+ * GCR with BBD): PCG for SPD systems; GMRES(restart), BiCGSTAB and
+ * GCR(restart) with right preconditioning.  BiCGSTAB runs with the
+ * block-Jacobi preconditioner in FP64; one of its iterations makes two
+ * products and two applies.  GCR (Eisenstat, Elman and Schultz 1983) runs
+ * in FP64 with either preconditioner; it keeps restart directions and
+ * their products, orthonormal products within a cycle, and stops with
+ * SDSL_E_BREAKDOWN when a new direction adds nothing to the cycle's space. */
+typedef enum { SDSL_PCG = 0, SDSL_GMRES = 1, SDSL_BICGSTAB = 2, SDSL_GCR = 3 } sdsl_krylov;
 
 /* FP64: every step in FP64.
  * FP32_IR: the SpMV and the preconditioner apply run in FP32 (FP32 operator
@@ -134,7 +142,7 @@ typedef struct {
     double shift0;         /* first relative shift of SDSL_PIVOT_SHIFT       */
     int32_t spd;           /* 1: symmetric positive definite mode            */
     sdsl_krylov krylov;
-    int32_t restart;       /* GMRES(m) restart length                        */
+    int32_t restart;       /* GMRES(m) / GCR(m) restart length, in [1, 63]   */
     int32_t max_iter;      /* Krylov iterations (all inner iterations)       */
     sdsl_precision precision;
     double inner_tol;      /* FP32_IR: relative tolerance of each inner solve */
@@ -223,7 +231,7 @@ typedef struct {
 } sdsl_allocator;
 
 /* Device bytes a handle for this problem will hold (for admission control),
- * the GMRES basis included when o->krylov is SDSL_GMRES.  For SDSL_BBD the
+ * the GMRES/GCR basis included when o->krylov is SDSL_GMRES or SDSL_GCR.  For SDSL_BBD the
  * tail factors depend on the pattern, so A->row_ptr and A->col must then be
  * readable host memory (A->mem = SDSL_MEM_HOST); otherwise only the sizes are
  * read.  Returns 0 on invalid arguments, including a BBD pattern that is not

@@ -311,6 +311,43 @@ def bbd_system(nblocks: int = 32, block_rows: int = 46_750, n_border: int = 4096
     return _system_from_csr(name, M, b, block_ptr, n_border=nbd, meta=meta)
 
 
+def strong_border_system(gamma: float = 20.0, seed: int = 5) -> System:
+    """A small bordered system whose border couples strongly to its blocks:
+    the bbd_system layout (4 blocks of 400 rows, 40 border rows) with every
+    interior-border coupling multiplied by ``gamma``; interior diagonals are
+    1.5x their row's off-diagonal magnitude sum, border diagonals 1.5x the
+    sum over the border block only (+1e-3).  Block Jacobi, which drops the
+    couplings, stalls on it; the bordered form keeps them (the situation in
+    which Alg. 1 of the paper switches preconditioners)."""
+    s = bbd_system(nblocks=4, block_rows=400, n_border=40, nnz_off=6, half_band=60, tail_frac=0.1,
+                   border_c=2, seed=seed, name="strong-border")
+    n, ni = s.n, s.n - s.n_border
+    M = s.scipy().tocoo()
+    r, c, v = M.row, M.col, M.data.copy()
+    cross = (r != c) & (((r < ni) & (c >= ni)) | ((r >= ni) & (c < ni)))
+    v[cross] *= gamma
+    A = sp.csr_matrix((v, (r, c)), shape=(n, n))
+    A.setdiag(0.0)
+    A.eliminate_zeros()
+    off = np.asarray(abs(A).sum(axis=1)).ravel()
+    border_only = np.asarray(abs(A[:, ni:]).sum(axis=1)).ravel()
+    d = np.where(np.arange(n) < ni, 1.5 * off, 1.5 * border_only + 1e-3)
+    A = (A + sp.diags(d)).tocsr()
+    A.sort_indices()
+    return _system_from_csr(f"strong-border-x{gamma:g}", A, s.b, s.block_ptr, n_border=s.n_border,
+                            meta=dict(gamma=gamma, seed=seed))
+
+
+def as_block_jacobi(s: System) -> System:
+    """The same system with its border rows taken as one more contiguous
+    block (the partition block Jacobi needs)."""
+    if s.n_border == 0:
+        return s
+    bp = np.r_[s.block_ptr, s.n].astype(np.int32)
+    return System(name=s.name + "-bj", row_ptr=s.row_ptr, col=s.col, val=s.val, b=s.b, block_ptr=bp,
+                  n_border=0, lowrank=s.lowrank, meta=dict(s.meta))
+
+
 def c3(scale: float = 1.0, seed: int = 0) -> System:
     """BBD workload: 32 blocks of 46,750 rows, 4,096-row border.  ``scale``
     shrinks block rows (and the border proportionally, at least 64)."""

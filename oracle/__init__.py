@@ -83,6 +83,12 @@ def _declare(L):
     L.or_pcg_bj.restype = C.c_int
     L.or_gmres_bj.argtypes = [I64, P, P, P, P, P, P, P, I32, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bj.restype = C.c_int
+    L.or_bicgstab_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, I32, P, P, P, P, D, I32, P, P, P]
+    L.or_bicgstab_bj.restype = C.c_int
+    L.or_gcr_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, I32, P, P, P, P, D, I32, I32, P, P, P]
+    L.or_gcr_bj.restype = C.c_int
+    L.or_gcr_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
+    L.or_gcr_bbd.restype = C.c_int
     L.or_gmres_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bbd.restype = C.c_int
     L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, I32, P, P, P, P, D, D, I32, I32,
@@ -236,9 +242,12 @@ class BJ:
         return lu_solve(self.rp, self.ci, self.v, self.dp, r)
 
     def __del__(self):
-        if getattr(self, "border", None):
-            lib().or_border_free(self.border)
-            self.border = None
+        try:
+            if getattr(self, "border", None):
+                lib().or_border_free(self.border)
+                self.border = None
+        except Exception:
+            pass  # interpreter shutdown
 
 
 def _lr_args(lowrank):
@@ -322,6 +331,40 @@ def replay_refine(hist, mode, nb, tol, maxit):
         want, slow = refine_decide(mode, h["nr"], prev, tol * nb, h["breakdown"], slow)
         assert h["act"] == want, (e, h, want)
         prev = h["nr"]
+
+
+def bicgstab_bj(sys_, P: BJ, tol=1e-8, maxit=10_000, hist=False):
+    """Right-preconditioned BiCGSTAB with the block-Jacobi preconditioner.
+    Returns (x, iterations, relres, status, history)."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
+    x = np.zeros(n)
+    its = C.c_int32(0)
+    rr = C.c_double(0.0)
+    h = np.zeros(maxit) if hist else None
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_bicgstab_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp), _p(P.ci),
+                              _p(P.v), _p(P.dp), P.nb, _p(P.bp), P.border, _p(b), _p(x), tol, maxit,
+                              C.byref(its), C.byref(rr), _p(h))
+    return x, its.value, rr.value, st, (h[:its.value] if hist else None)
+
+
+def gcr_bj(sys_, P: BJ, tol=1e-8, m=30, maxit=10_000, hist=False):
+    """Right-preconditioned restarted GCR(m) with the block-Jacobi
+    preconditioner.  Returns (x, iterations, relres, status, history)."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    k, urp, uci, uv, c, _keep = _lr_args(sys_.lowrank)
+    x = np.zeros(n)
+    its = C.c_int32(0)
+    rr = C.c_double(0.0)
+    h = np.zeros(maxit) if hist else None
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_gcr_bj(n, _p(rp), _p(ci), _p(v), k, _p(urp), _p(uci), _p(uv), _p(c), _p(P.rp), _p(P.ci),
+                         _p(P.v), _p(P.dp), P.nb, _p(P.bp), P.border, _p(b), _p(x), tol, m, maxit,
+                         C.byref(its), C.byref(rr), _p(h))
+    return x, its.value, rr.value, st, (h[:its.value] if hist else None)
 
 
 def ir_pcg_bj(sys_, P: BJ, tol=1e-8, inner_tol=1e-4, max_outer=30, maxit=10_000, every=500, with_history=False):
@@ -412,9 +455,12 @@ class BBD:
         return dict(tail=tail, lrp=lrp, lci=lci, lv=lv, S=S, piv=piv)
 
     def __del__(self):
-        if getattr(self, "ctx", None):
-            lib().or_bbd_free(self.ctx)
-            self.ctx = None
+        try:
+            if getattr(self, "ctx", None):
+                lib().or_bbd_free(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass  # interpreter shutdown
 
 
 def gmres_bbd(sys_, P: BBD, tol=1e-8, m=30, maxit=10_000, hist=False):
@@ -427,6 +473,20 @@ def gmres_bbd(sys_, P: BBD, tol=1e-8, m=30, maxit=10_000, hist=False):
     b = np.ascontiguousarray(sys_.b, dtype=np.float64)
     st = lib().or_gmres_bbd(n, _p(rp), _p(ci), _p(v), P.ctx, _p(b), _p(x), tol, m, maxit,
                             C.byref(its), C.byref(rr), _p(h))
+    return x, its.value, rr.value, st, (h[:its.value] if hist else None)
+
+
+def gcr_bbd(sys_, P: BBD, tol=1e-8, m=30, maxit=10_000, hist=False):
+    """Right-preconditioned restarted GCR(m) with the BBD preconditioner."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    x = np.zeros(n)
+    its = C.c_int32(0)
+    rr = C.c_double(0.0)
+    h = np.zeros(maxit) if hist else None
+    b = np.ascontiguousarray(sys_.b, dtype=np.float64)
+    st = lib().or_gcr_bbd(n, _p(rp), _p(ci), _p(v), P.ctx, _p(b), _p(x), tol, m, maxit,
+                          C.byref(its), C.byref(rr), _p(h))
     return x, its.value, rr.value, st, (h[:its.value] if hist else None)
 
 

@@ -586,6 +586,167 @@ static int gmres_run(const or_op* A, or_prec_fn prec, void* pctx, const double* 
 }
 
 /* ------------------------------------------------------------------ */
+/* BiCGSTAB (van der Vorst, SIAM J. Sci. Stat. Comput. 13 (1992) 631), the */
+/* Krylov method the paper pairs with block Jacobi in its multi-node runs  */
+/* (Sec. 4.3), with right preconditioning (Sec. 2.2): the iterates solve  */
+/* A M^{-1} u = b and x = M^{-1} u, which the recurrence carries as        */
+/* x += alpha M^{-1} p + omega M^{-1} s.  x0 = 0, shadow residual r^ = r0. */
+/* One iteration = two products and two preconditioner applies.  When the */
+/* half-step residual s or the full residual r meets the tolerance the    */
+/* true residual decides; if it does not meet it, the method restarts     */
+/* from the true residual (r^ = r).  rho = (r^, r) = 0, (r^, v) = 0,      */
+/* (t, t) = 0 or omega = 0 without convergence is a breakdown.            */
+/* ------------------------------------------------------------------ */
+static int bicgstab_run(const or_op* A, or_prec_fn prec, void* pctx, const double* b, double* x,
+                        double tol, int32_t maxit, int32_t* iters, double* relres, double* hist) {
+    int64_t n = A->n;
+    double *r = calloc(n, 8), *rh = calloc(n, 8), *p = calloc(n, 8), *v = calloc(n, 8);
+    double *ph = calloc(n, 8), *s = calloc(n, 8), *sh = calloc(n, 8), *t = calloc(n, 8);
+    double nb = nrm2(n, b);
+    int st = OR_NOT_CONVERGED, it = 0, fresh = 1;
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    memset(x, 0, (size_t)n * 8);
+    if (nb == 0.0) { st = OR_OK; goto done; }
+    memcpy(r, b, (size_t)n * 8);
+    memcpy(rh, r, (size_t)n * 8);
+    while (it < maxit) {
+        double rho = dot(n, rh, r);
+        if (rho == 0.0 || !isfinite(rho)) { st = OR_BREAKDOWN; break; }
+        if (fresh) {
+            memcpy(p, r, (size_t)n * 8);
+        } else {
+            double beta = (rho / rho_prev) * (alpha / omega);
+            for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        fresh = 0;
+        prec(pctx, p, ph);
+        op_apply(A, ph, v);
+        double rv = dot(n, rh, v);
+        alpha = rho / rv;
+        if (rv == 0.0 || !isfinite(alpha)) { st = OR_BREAKDOWN; break; }
+        for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+        ++it;
+        int conv = 0;
+        if (nrm2(n, s) <= tol * nb) {
+            for (int64_t i = 0; i < n; ++i) x[i] += alpha * ph[i];
+            conv = 1;
+        } else {
+            prec(pctx, s, sh);
+            op_apply(A, sh, t);
+            double tt = dot(n, t, t);
+            omega = dot(n, t, s) / tt;
+            if (tt == 0.0 || !isfinite(omega)) { st = OR_BREAKDOWN; break; }
+            for (int64_t i = 0; i < n; ++i) {
+                x[i] += alpha * ph[i] + omega * sh[i];
+                r[i] = s[i] - omega * t[i];
+            }
+            conv = nrm2(n, r) <= tol * nb;
+            if (!conv && omega == 0.0) { st = OR_BREAKDOWN; break; }
+        }
+        if (hist) hist[it - 1] = (conv ? nrm2(n, s) : nrm2(n, r)) / nb;
+        if (conv) {
+            double tr = op_true_res(A, x, b, r);
+            if (tr <= tol * nb) { st = OR_OK; break; }
+            /* restart from the true residual (now in r) */
+            memcpy(rh, r, (size_t)n * 8);
+            fresh = 1;
+            continue;
+        }
+        rho_prev = rho;
+    }
+done:
+    *iters = it;
+    *relres = nb == 0.0 ? 0.0 : op_true_res(A, x, b, r) / nb;
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
+    return st;
+}
+
+int or_bicgstab_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+                   int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
+                   const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
+                   int32_t nblocks, const int32_t* bp, void* border, const double* b, double* x, double tol,
+                   int32_t maxit, int32_t* iters, double* relres, double* hist) {
+    or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
+    or_bj P = {n, prp, pci, pv, pdp, nblocks, bp};
+    if (border) return bicgstab_run(&A, bjb_apply, border, b, x, tol, maxit, iters, relres, hist);
+    return bicgstab_run(&A, bj_apply, &P, b, x, tol, maxit, iters, relres, hist);
+}
+
+/* ------------------------------------------------------------------ */
+/* Restarted GCR(m) (Eisenstat, Elman and Schultz, SIAM J. Numer. Anal. 20 */
+/* (1983) 345), the Krylov method of the paper's single-node and BBD runs */
+/* (Sec. 4.2, Sec. 4.3), right preconditioned (Sec. 2.2).  Each step takes */
+/* the preconditioned residual p = P^-1 r as a new search direction and    */
+/* q = A p, makes q orthogonal to the cycle's earlier q's (classical        */
+/* Gram-Schmidt applied twice; the same coefficients update p, so q = A p  */
+/* keeps holding), normalises q (and p by the same factor), then           */
+/* alpha = (r, q), x += alpha p, r -= alpha q: the residual norm is the    */
+/* minimum over the cycle's space, as in GMRES(m) from the same start.     */
+/* A cycle ends after m steps or when the recurrence residual meets the    */
+/* tolerance; every cycle starts from the true residual.  A q that the    */
+/* projections leave below 1e-14 of its norm (the new direction adds      */
+/* nothing to the space) is a breakdown.                                  */
+/* ------------------------------------------------------------------ */
+static int gcr_run(const or_op* A, or_prec_fn prec, void* pctx, const double* b, double* x,
+                   double tol, int32_t m, int32_t maxit, int32_t* iters, double* relres, double* hist) {
+    int64_t n = A->n;
+    double nb = nrm2(n, b);
+    memset(x, 0, (size_t)n * 8);
+    if (nb == 0.0) { *iters = 0; *relres = 0.0; return OR_OK; }
+    double* P = (double*)calloc((size_t)n * m, 8);
+    double* Q = (double*)calloc((size_t)n * m, 8);
+    double* c = (double*)calloc(m, 8);
+    double* r = (double*)calloc(n, 8);
+    int it = 0, st = OR_NOT_CONVERGED;
+    double beta = op_true_res(A, x, b, r);
+    while (it < maxit) {
+        if (beta <= tol * nb) { st = OR_OK; break; }
+        for (int j = 0; j < m && it < maxit; ++j) {
+            double* p = P + (int64_t)j * n;
+            double* q = Q + (int64_t)j * n;
+            prec(pctx, r, p);
+            op_apply(A, p, q);
+            double nu0 = nrm2(n, q);
+            for (int pass = 0; pass < 2 && j > 0; ++pass) {
+                for (int i = 0; i < j; ++i) c[i] = dot(n, q, Q + (int64_t)i * n);
+                for (int i = 0; i < j; ++i)
+                    for (int64_t t = 0; t < n; ++t) {
+                        q[t] -= c[i] * Q[(int64_t)i * n + t];
+                        p[t] -= c[i] * P[(int64_t)i * n + t];
+                    }
+            }
+            double nu = nrm2(n, q);
+            if (!(nu > 1e-14 * nu0) || !isfinite(nu)) { st = OR_BREAKDOWN; goto out; }
+            for (int64_t t = 0; t < n; ++t) { q[t] /= nu; p[t] /= nu; }
+            double alpha = dot(n, r, q);
+            for (int64_t t = 0; t < n; ++t) { x[t] += alpha * p[t]; r[t] -= alpha * q[t]; }
+            ++it;
+            double rn = nrm2(n, r);
+            if (hist) hist[it - 1] = rn / nb;
+            if (rn <= tol * nb) break;
+        }
+        beta = op_true_res(A, x, b, r);
+    }
+    if (it >= maxit && beta <= tol * nb) st = OR_OK;
+out:
+    *iters = it;
+    *relres = op_true_res(A, x, b, r) / nb;
+    free(P); free(Q); free(c); free(r);
+    return st;
+}
+
+int or_gcr_bj(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
+              int32_t k, const int64_t* urp, const int32_t* uci, const double* uv, const double* c,
+              const int64_t* prp, const int32_t* pci, const double* pv, const int64_t* pdp,
+              int32_t nblocks, const int32_t* bp, void* border, const double* b, double* x, double tol,
+              int32_t m, int32_t maxit, int32_t* iters, double* relres, double* hist) {
+    or_op A = {n, rp, ci, v, k, urp, uci, uv, c};
+    or_bj P = {n, prp, pci, pv, pdp, nblocks, bp};
+    if (border) return gcr_run(&A, bjb_apply, border, b, x, tol, m, maxit, iters, relres, hist);
+    return gcr_run(&A, bj_apply, &P, b, x, tol, m, maxit, iters, relres, hist);
+}
+
+/* ------------------------------------------------------------------ */
 /* BBD preconditioner (paper Sec. 2.4): interior blocks, tail sets,       */
 /* dense Schur complement with LU and partial pivoting, block LU apply.   */
 /* ------------------------------------------------------------------ */
@@ -886,6 +1047,13 @@ int or_gmres_bbd(int64_t n, const int64_t* rp, const int32_t* ci, const double* 
                  double* relres, double* hist) {
     or_op A = {n, rp, ci, v, 0, NULL, NULL, NULL, NULL};
     return gmres_run(&A, bbd_apply, bbd, b, x, tol, m, maxit, iters, relres, hist);
+}
+
+int or_gcr_bbd(int64_t n, const int64_t* rp, const int32_t* ci, const double* v, void* bbd,
+               const double* b, double* x, double tol, int32_t m, int32_t maxit, int32_t* iters,
+               double* relres, double* hist) {
+    or_op A = {n, rp, ci, v, 0, NULL, NULL, NULL, NULL};
+    return gcr_run(&A, bbd_apply, bbd, b, x, tol, m, maxit, iters, relres, hist);
 }
 
 /* ------------------------------------------------------------------ */

@@ -25,7 +25,7 @@ BJ, BBD = 0, 1
 FILTER_NONE, FILTER_MIN, FILTER_GEOMEAN = 0, 1, 2
 DIAG_DELTA, DIAG_DROPSUM = 1, 2
 PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT = 0, 1, 2
-PCG, GMRES = 0, 1
+PCG, GMRES, BICGSTAB, GCR = 0, 1, 2, 3
 FP64, FP32_IR, FP32_IR_RESTART = 0, 1, 2
 MEM_DEVICE, MEM_HOST = 0, 1
 

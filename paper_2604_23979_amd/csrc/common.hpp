@@ -31,6 +31,10 @@ struct KrylovState {
     double rr0;      // ||r||^2 at the last refinement point
     double delta2;   // refinement trigger (0: never)
     double rzs[2];   // (r, z) of the last two iterations, parity-indexed
+    // BiCGSTAB scalars of the last two iterations, parity-indexed
+    double bi_rho[2];
+    double bi_alpha[2];
+    double bi_omega[2];
 };
 
 // -------------------------------------------------------------- reductions
@@ -296,6 +300,20 @@ void launch_bj_levels(int nblocks, const int* bp, const int* lrp, const int* lci
 template <typename T>
 void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, const BorderDev& bd, KrylovState* st, int it,
                         int mode, hipStream_t s);
+// BiCGSTAB vector steps (kernels_iter.hip); partial arrays hold bicg_grid(n)
+// entries
+int bicg_grid(int n);
+void launch_dot2(int n, const double* a, const double* b, const double* c, const double* d, double* pa, double* pc,
+                 const KrylovState* st, hipStream_t s);
+void launch_bicg_p(int n, const double* r, double* p, const double* v, const double* part_rho,
+                   const double* part_rr, KrylovState* st, int it, bool first, hipStream_t s);
+void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* part_rv, double* part_ss,
+                   KrylovState* st, int it, hipStream_t s);
+void launch_bicg_x(int n, double* x, const double* ph, const double* sh, const double* sv, const double* t, double* r,
+                   const double* rh, const double* part_ss, const double* part_ts, const double* part_tt,
+                   double* part_rho, double* part_rr, KrylovState* st, int it, hipStream_t s);
+void launch_gcr_xr(int n, double* x, double* r, double* p, double* q, const double* nu2, const double* nu02,
+                   const double* part_rq, double* part_rr, hipStream_t s);
 template <typename T>
 void launch_border_fix(int n, T* z, const BorderDev& bd, hipStream_t s);
 // border setup: dense column j of U (CSC) into e; K = diag(1/c) + U^T W; Kinv

@@ -1379,6 +1379,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
     F* __restrict__ y = (F*)Vv.y;
     V* r = (V*)Vv.r;
 
+    if (MODE == 0 && st && block_done(st, &shd)) return;
     if (MODE == 1) {
         if (block_done(st, &shd)) return;
         const double pq = block_sum_array(Vv.part_pq, Vv.npq, red);
@@ -1542,6 +1543,211 @@ template void launch_pcg_pupdate<double>(int, const PcgVecs&, int, const BorderD
                                          hipStream_t);
 template void launch_pcg_pupdate<float>(int, const PcgVecs&, int, const BorderDev&, KrylovState*, int, int,
                                         hipStream_t);
+
+// ------------------------------------------------------------------ BiCGSTAB
+// Vector steps of right-preconditioned BiCGSTAB (van der Vorst 1992; the
+// paper's block-Jacobi solver, Sec. 4.3) with every scalar on the device:
+// each workgroup sums, in the same fixed order, the partials it needs, so no
+// scalar goes through the host.  The products and preconditioner applies
+// between the steps are the SpMV and block-Jacobi launches.  The scalars of
+// iteration `it` live at parity it & 1 (those of it - 1 at the other one);
+// every kernel is a no-op once the state says done.
+constexpr int kBicgThreads = 256;
+int bicg_grid(int n) {
+    int g = (n + kBicgThreads - 1) / kBicgThreads;
+    return g < 1 ? 1 : (g > 4096 ? 4096 : g);
+}
+
+// pa[w] = workgroup w's share of (a, b); with c, pc[w] of (c, d)
+__global__ __launch_bounds__(kBicgThreads) void k_dot2(int n, const double* __restrict__ a,
+                                                       const double* __restrict__ b, const double* __restrict__ c,
+                                                       const double* __restrict__ d, double* __restrict__ pa,
+                                                       double* __restrict__ pc, const KrylovState* st) {
+    __shared__ double red[8];
+    __shared__ int shd;
+    if (block_done(st, &shd)) return;
+    const int g = gridDim.x, per = (n + g - 1) / g;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        s1 = fma(a[i], b[i], s1);
+        if (c) s2 = fma(c[i], d[i], s2);
+    }
+    s1 = block_sum(s1, red);
+    if (c) s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+        pa[blockIdx.x] = s1;
+        if (c) pc[blockIdx.x] = s2;
+    }
+}
+void launch_dot2(int n, const double* a, const double* b, const double* c, const double* d, double* pa, double* pc,
+                 const KrylovState* st, hipStream_t s) {
+    k_dot2<<<bicg_grid(n), kBicgThreads, 0, s>>>(n, a, b, c, d, pa, pc, st);
+}
+
+__device__ __forceinline__ void bicg_stop(KrylovState* st, int iters, int conv) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->conv = conv;
+        st->breakdown = conv ? 0 : 1;
+        st->iters = iters;
+        set_done(st);
+    }
+}
+
+// Start of iteration it: the residual of it - 1 meets the tolerance ->
+// converged (iters = it); rho = (r^, r); p = r (first step of a cycle) or
+// p = r + beta (p - omega v), beta = (rho / rho_prev)(alpha / omega).
+__global__ __launch_bounds__(kBicgThreads) void k_bicg_p(int n, const double* __restrict__ r, double* __restrict__ p,
+                                                         const double* __restrict__ v,
+                                                         const double* __restrict__ part_rho,
+                                                         const double* __restrict__ part_rr, KrylovState* st, int it,
+                                                         int first) {
+    __shared__ double red[8];
+    __shared__ int shd;
+    if (block_done(st, &shd)) return;
+    const int m = gridDim.x;
+    const double rho = block_sum_array(part_rho, m, red);
+    if (!first) {
+        const double rr = block_sum_array(part_rr, m, red);
+        if (rr <= st->tol2 * st->bb) { bicg_stop(st, it, 1); return; }
+    }
+    const int q = (it + 1) & 1;
+    const double om = first ? 1.0 : st->bi_omega[q];
+    const double beta = first ? 0.0 : (rho / st->bi_rho[q]) * (st->bi_alpha[q] / om);
+    if (rho == 0.0 || !isfinite(rho) || !isfinite(beta) || om == 0.0) { bicg_stop(st, it, 0); return; }
+    const int per = (n + m - 1) / m;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x)
+        p[i] = first ? r[i] : r[i] + beta * (p[i] - om * v[i]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->bi_rho[it & 1] = rho;
+}
+void launch_bicg_p(int n, const double* r, double* p, const double* v, const double* part_rho, const double* part_rr,
+                   KrylovState* st, int it, bool first, hipStream_t s) {
+    k_bicg_p<<<bicg_grid(n), kBicgThreads, 0, s>>>(n, r, p, v, part_rho, part_rr, st, it, first ? 1 : 0);
+}
+
+// alpha = rho / (r^, v); s = r - alpha v; partials of ||s||^2
+__global__ __launch_bounds__(kBicgThreads) void k_bicg_s(int n, const double* __restrict__ r,
+                                                         const double* __restrict__ v, double* __restrict__ sv,
+                                                         const double* __restrict__ part_rv,
+                                                         double* __restrict__ part_ss, KrylovState* st, int it) {
+    __shared__ double red[8];
+    __shared__ int shd;
+    if (block_done(st, &shd)) return;
+    const int m = gridDim.x;
+    const double rv = block_sum_array(part_rv, m, red);
+    const double alpha = st->bi_rho[it & 1] / rv;
+    if (rv == 0.0 || !isfinite(alpha)) { bicg_stop(st, it, 0); return; }
+    const int per = (n + m - 1) / m;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    double ss = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const double si = r[i] - alpha * v[i];
+        sv[i] = si;
+        ss = fma(si, si, ss);
+    }
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) part_ss[blockIdx.x] = ss;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->bi_alpha[it & 1] = alpha;
+}
+void launch_bicg_s(int n, const double* r, const double* v, double* sv, const double* part_rv, double* part_ss,
+                   KrylovState* st, int it, hipStream_t s) {
+    k_bicg_s<<<bicg_grid(n), kBicgThreads, 0, s>>>(n, r, v, sv, part_rv, part_ss, st, it);
+}
+
+// End of iteration it: if ||s|| meets the tolerance, x += alpha ph and
+// r = s (converged, iters = it + 1); otherwise omega = (t, s) / (t, t),
+// x += alpha ph + omega sh, r = s - omega t, and the partials of (r^, r) and
+// ||r||^2 for the next iteration.
+__global__ __launch_bounds__(kBicgThreads) void k_bicg_x(
+    int n, double* __restrict__ x, const double* __restrict__ ph, const double* __restrict__ sh,
+    const double* __restrict__ sv, const double* __restrict__ t, double* __restrict__ r, const double* __restrict__ rh,
+    const double* __restrict__ part_ss, const double* __restrict__ part_ts, const double* __restrict__ part_tt,
+    double* __restrict__ part_rho, double* __restrict__ part_rr, KrylovState* st, int it) {
+    __shared__ double red[8];
+    __shared__ int shd;
+    if (block_done(st, &shd)) return;
+    const int m = gridDim.x;
+    const double ss = block_sum_array(part_ss, m, red);
+    const double alpha = st->bi_alpha[it & 1];
+    const int per = (n + m - 1) / m;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    if (ss <= st->tol2 * st->bb) {
+        for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            x[i] = x[i] + alpha * ph[i];
+            r[i] = sv[i];
+        }
+        bicg_stop(st, it + 1, 1);
+        return;
+    }
+    const double ts = block_sum_array(part_ts, m, red);
+    const double tt = block_sum_array(part_tt, m, red);
+    const double omega = ts / tt;
+    if (tt == 0.0 || !isfinite(omega)) { bicg_stop(st, it + 1, 0); return; }
+    double rho = 0.0, rr = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+        const double ri = sv[i] - omega * t[i];
+        r[i] = ri;
+        rho = fma(rh[i], ri, rho);
+        rr = fma(ri, ri, rr);
+    }
+    rho = block_sum(rho, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        part_rho[blockIdx.x] = rho;
+        part_rr[blockIdx.x] = rr;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->bi_omega[it & 1] = omega;
+}
+void launch_bicg_x(int n, double* x, const double* ph, const double* sh, const double* sv, const double* t, double* r,
+                   const double* rh, const double* part_ss, const double* part_ts, const double* part_tt,
+                   double* part_rho, double* part_rr, KrylovState* st, int it, hipStream_t s) {
+    k_bicg_x<<<bicg_grid(n), kBicgThreads, 0, s>>>(n, x, ph, sh, sv, t, r, rh, part_ss, part_ts, part_tt, part_rho,
+                                                     part_rr, st, it);
+}
+
+// ------------------------------------------------------------------ GCR(m)
+// End of a GCR step (right preconditioned, Sec. 2.2; Eisenstat, Elman and
+// Schultz 1983): q = M p has been made orthogonal to the cycle's earlier
+// directions, *nu2 = ||q||^2 after and *nu02 before the projections.  When
+// nu2 > 1e-28 nu02 (else the direction adds nothing: a breakdown, nothing
+// is written): q /= nu and p /= nu are stored, alpha = (r, q) / nu from the
+// partials of (r, q) taken before the scaling, x += alpha p, r -= alpha q,
+// and part_rr[w] = the workgroup's share of ||r||^2.
+__global__ __launch_bounds__(kBicgThreads) void k_gcr_xr(int n, double* __restrict__ x, double* __restrict__ r,
+                                                         double* __restrict__ p, double* __restrict__ q,
+                                                         const double* __restrict__ nu2, const double* __restrict__ nu02,
+                                                         const double* __restrict__ part_rq,
+                                                         double* __restrict__ part_rr) {
+    __shared__ double red[8];
+    const int m = gridDim.x;
+    const double v2 = nu2[0];
+    const bool ok = v2 > 1e-28 * nu02[0] && isfinite(v2);
+    const double inv = ok ? 1.0 / sqrt(v2) : 0.0;
+    const double alpha = ok ? block_sum_array(part_rq, m, red) * inv : 0.0;
+    const int per = (n + m - 1) / m;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    double rr = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        double ri = r[i];
+        if (ok) {
+            const double pi = p[i] * inv, qi = q[i] * inv;
+            p[i] = pi;
+            q[i] = qi;
+            x[i] = x[i] + alpha * pi;
+            ri = ri - alpha * qi;
+            r[i] = ri;
+        }
+        rr = fma(ri, ri, rr);
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = rr;
+}
+void launch_gcr_xr(int n, double* x, double* r, double* p, double* q, const double* nu2, const double* nu02,
+                   const double* part_rq, double* part_rr, hipStream_t s) {
+    k_gcr_xr<<<bicg_grid(n), kBicgThreads, 0, s>>>(n, x, r, p, q, nu2, nu02, part_rq, part_rr);
+}
 
 // z <- z - W s, s = Kinv (sum of the U^T z partials): the border correction
 // on its own (the solve loop fuses it into the direction update)

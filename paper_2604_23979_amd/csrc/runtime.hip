@@ -101,6 +101,7 @@ struct sdsl_ctx {
     float* y32 = nullptr;    // forward-sweep scratch of FP32 solves
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     double *part_pq = nullptr, *part_rz = nullptr, *part_rr = nullptr, *part_b = nullptr, *part_res = nullptr;
+    double* bi_part = nullptr;  // BiCGSTAB partials: 6 arrays of bicg_grid(n)
     double* scal = nullptr;  // [0] = ||r||^2 of the latest true residual, [1] = ||b||^2
     KrylovState* st = nullptr;
     KrylovState* st_h = nullptr;  // pinned
@@ -865,7 +866,7 @@ struct SolveTask {
     bool finished = false;
     double t0 = 0.0;
 
-    enum Phase { P64, PMIX, P32_RESTART, PGMRES } phase = P64;
+    enum Phase { P64, PMIX, P32_RESTART, PGMRES, PBICG, PGCR } phase = P64;
     Pcg<double, double> pcg64{};
     Pcg<double, float> pcgmix{};
     Pcg<float, float> pcg32{};
@@ -914,6 +915,10 @@ struct SolveTask {
         pcg32.init();
         if (h->o.krylov == SDSL_GMRES) {
             gm_begin();
+        } else if (h->o.krylov == SDSL_GCR) {
+            gcr_begin();
+        } else if (h->o.krylov == SDSL_BICGSTAB) {
+            bi_begin();
         } else if (h->o.precision == SDSL_FP64) {
             start64(b, xout, tol, nb);
         } else if (h->o.precision == SDSL_FP32_IR) {
@@ -1007,6 +1012,15 @@ struct SolveTask {
     std::vector<double> gH, gcs, gsn, gg;
     void gm_begin() {
         phase = PGMRES;
+        gm_alloc();
+        gH.assign((size_t)(gm_m + 1) * gm_m, 0.0);
+        gcs.assign(gm_m, 0.0);
+        gsn.assign(gm_m, 0.0);
+        gg.assign(gm_m + 1, 0.0);
+        gm_cycle();
+    }
+    // the restart length and the basis storage: V (m + 1 columns), Z (m)
+    void gm_alloc() {
         gm_m = std::max(1, std::min(h->o.restart, kMaxBasisHost - 1));
         const int n = h->n;
         if (h->gm_cap < gm_m) {
@@ -1023,11 +1037,6 @@ struct SolveTask {
             }
             h->gm_cap = gm_m;
         }
-        gH.assign((size_t)(gm_m + 1) * gm_m, 0.0);
-        gcs.assign(gm_m, 0.0);
-        gsn.assign(gm_m, 0.0);
-        gg.assign(gm_m + 1, 0.0);
-        gm_cycle();
     }
     void gm_cycle() {
         // r = b - M x (compensated), scal[0] = ||r||^2
@@ -1100,9 +1109,152 @@ struct SolveTask {
         gm_cycle();
     }
 
+    // ---- GCR(m), right preconditioned, FP64 (Sec. 2.2; the paper's solver
+    // with BBD, Sec. 4.2-4.3): directions P = Z columns, Q = M P = V
+    // columns, Q orthonormal within a cycle (classical Gram-Schmidt applied
+    // twice, the same coefficients update P).  The host reads ||q|| and
+    // ||r|| once per step; every cycle starts from the true residual.
+    int gcr_j = 0;
+    void gcr_begin() {
+        phase = PGCR;
+        gm_alloc();
+        gcr_cycle();
+    }
+    void gcr_cycle() {
+        nr = true_residual(h, b, xout, h->r);
+        if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
+        if (total_its >= max_iter()) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
+        if (outer > 0) restarts++;
+        outer++;
+        gcr_j = 0;
+    }
+    void gcr_step() {
+        const int n = h->n, j = gcr_j;
+        double* pj = h->gZ + (size_t)j * n;
+        double* qj = h->gV + (size_t)j * n;
+        apply_prec64(h, h->r, pj);
+        apply_op64(h, pj, qj);
+        // (q, Q_i) for i < j and (q, q) in ghcol[j]: Q_j is column j of V
+        launch_multidot(n, j + 1, h->gV, n, qj, h->gpart, h->ghcol, nullptr, h->s);
+        const double* nu2 = h->ghcol + j;
+        if (j > 0) {
+            launch_multiaxpy(n, j, h->gV, n, h->ghcol, -1.0, qj, nullptr, h->s);
+            launch_multiaxpy(n, j, h->gZ, n, h->ghcol, -1.0, pj, nullptr, h->s);
+            launch_multidot(n, j, h->gV, n, qj, h->gpart, h->gh2, nullptr, h->s);
+            launch_multiaxpy(n, j, h->gV, n, h->gh2, -1.0, qj, h->gnrm, h->s);
+            launch_multiaxpy(n, j, h->gZ, n, h->gh2, -1.0, pj, nullptr, h->s);
+            launch_sum_partials(h->gnrm, 512, h->scal + 2, h->s);
+            nu2 = h->scal + 2;
+        }
+        const int g = bicg_grid(n);
+        double* part_rq = h->gpart;
+        double* part_rr = h->gpart + 4096;
+        launch_dot2(n, h->r, qj, nullptr, nullptr, part_rq, nullptr, nullptr, h->s);
+        launch_gcr_xr(n, xout, h->r, pj, qj, nu2, h->ghcol + j, part_rq, part_rr, h->s);
+        launch_sum_partials(part_rr, g, h->scal + 3, h->s);
+        h->check_launch();
+        hip_check(hipMemcpyAsync(h->gh_h, nu2, sizeof(double), hipMemcpyDeviceToHost, h->s), "copy");
+        hip_check(hipMemcpyAsync(h->gh_h + 1, h->ghcol + j, sizeof(double), hipMemcpyDeviceToHost, h->s), "copy");
+        hip_check(hipMemcpyAsync(h->gh_h + 2, h->scal + 3, sizeof(double), hipMemcpyDeviceToHost, h->s), "copy");
+        h->sync();
+        const double v2 = h->gh_h[0], v02 = h->gh_h[1], rn = std::sqrt(h->gh_h[2]);
+        if (!(v2 > 1e-28 * v02) || !std::isfinite(v2)) {
+            // the new direction adds nothing: x and r were left unchanged
+            nr = true_residual(h, b, xout, h->r);
+            finish(nr <= tol * nb ? SDSL_OK : SDSL_E_BREAKDOWN, nr / nb);
+            return;
+        }
+        total_its++;
+        gcr_j = j + 1;
+        if (rn <= tol * nb || gcr_j == gm_m || total_its >= max_iter()) gcr_cycle();
+    }
+
+    // ---- BiCGSTAB, right preconditioned, FP64 (Sec. 2.2, Sec. 4.3): the
+    // vector steps keep every scalar on the device (k_bicg_*); the host
+    // issues check_every iterations between polls.  Vectors: r^ in rf, p,
+    // v in q, p^ = P^{-1} p in z, s in d, s^ = P^{-1} s in xref, t in x.
+    int bi_it = 0;
+    bool bi_first = true;
+    double* bp_(int k) { return h->bi_part + (size_t)k * bicg_grid(h->n); }
+    void bi_prec(const double* in, double* out) {
+        PcgVecs V{};
+        V.r = const_cast<double*>(in);
+        V.z = out;
+        V.y = h->y;
+        launch_bj<double, double>(0, bj_dev(h, false), V, h->st, 0, h->s);
+        if (h->bd.k > 0) {
+            launch_lowrank_tdot<double>(h->lr, out, h->st, LR_BORDER, h->bd.Kinv, h->s);
+            launch_border_fix<double>(h->n, out, h->bd, h->s);
+        }
+    }
+    void bi_op(const double* in, double* out) {
+        const CsrView A{h->n, h->rp, h->ci, h->halo};
+        if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, in, h->st, LR_SCALED, nullptr, h->s);
+        launch_spmv<double, double>(A, h->v, h->lr, in, out, nullptr, h->st, h->lanes, h->grid, h->s);
+    }
+    // a cycle from the residual in r: r^ = r, partials of (r^, r), ||r||^2
+    void bi_cycle_start() {
+        launch_copy<double>(h->n, h->r, h->rf, h->s);
+        launch_dot2(h->n, h->rf, h->r, h->r, h->r, bp_(0), bp_(1), nullptr, h->s);
+        bi_first = true;
+    }
+    void bi_begin() {
+        phase = PBICG;
+        launch_copy<double>(h->n, b, h->r, h->s);
+        launch_init_state(h->st, h->part_b, h->grid, tol, 0.0, h->s);
+        bi_cycle_start();
+        bi_issue(std::min(h->o.check_every, max_iter()));
+    }
+    void bi_issue(int count) {
+        const int n = h->n;
+        for (int k = 0; k < count; ++k, ++bi_it) {
+            launch_bicg_p(n, h->r, h->p, h->q, bp_(0), bp_(1), h->st, bi_it, bi_first, h->s);
+            bi_first = false;
+            bi_prec(h->p, h->z);
+            bi_op(h->z, h->q);
+            launch_dot2(n, h->rf, h->q, nullptr, nullptr, bp_(2), nullptr, h->st, h->s);
+            launch_bicg_s(n, h->r, h->q, h->d, bp_(2), bp_(3), h->st, bi_it, h->s);
+            bi_prec(h->d, h->xref);
+            bi_op(h->xref, h->x);
+            launch_dot2(n, h->x, h->d, h->x, h->x, bp_(4), bp_(5), h->st, h->s);
+            launch_bicg_x(n, xout, h->z, h->xref, h->d, h->x, h->r, h->rf, bp_(3), bp_(4), bp_(5), bp_(0), bp_(1),
+                          h->st, bi_it, h->s);
+        }
+        h->check_launch();
+    }
+    void bi_step() {
+        hip_check(hipMemcpyAsync(h->st_h, h->st, sizeof(KrylovState), hipMemcpyDeviceToHost, h->s), "copy");
+        h->sync();
+        const KrylovState s = *h->st_h;
+        if (!s.done) {
+            if (bi_it >= max_iter()) {
+                total_its = bi_it;
+                nr = true_residual(h, b, xout, h->r);
+                finish(SDSL_E_NOT_CONVERGED, nr / nb);
+                return;
+            }
+            bi_issue(std::min(h->o.check_every, max_iter() - bi_it));
+            return;
+        }
+        total_its = s.iters;
+        nr = true_residual(h, b, xout, h->r);
+        if (s.breakdown) { finish(SDSL_E_BREAKDOWN, nr / nb); return; }
+        if (nr <= tol * nb) { finish(SDSL_OK, nr / nb); return; }
+        if (total_its >= max_iter()) { finish(SDSL_E_NOT_CONVERGED, nr / nb); return; }
+        // the recurrence met the tolerance but the true residual (now in r)
+        // did not: a new cycle from it
+        restarts++;
+        bi_it = total_its;
+        launch_init_state(h->st, h->part_b, h->grid, tol, 0.0, h->s);
+        bi_cycle_start();
+        bi_issue(std::min(h->o.check_every, max_iter() - bi_it));
+    }
+
     void step() {
         if (finished) return;
         if (phase == PGMRES) { gm_step(); return; }
+        if (phase == PBICG) { bi_step(); return; }
+        if (phase == PGCR) { gcr_step(); return; }
         if (phase == P64) { step64(); return; }
         if (phase == PMIX) { step_mixed(); return; }
         // classical refinement: wait for the inner solve to stop
@@ -1234,15 +1386,22 @@ void check_idle(sdsl_ctx* h) {
 
 void check_options(const sdsl_options* o) {
     if (o->method != SDSL_BJ && o->method != SDSL_BBD) fail(SDSL_E_INVALID, "unknown method");
-    if (o->method == SDSL_BBD && (o->krylov != SDSL_GMRES || o->precision != SDSL_FP64))
-        fail(SDSL_E_INVALID, "the BBD preconditioner runs with GMRES in FP64");
+    if (o->method == SDSL_BBD && ((o->krylov != SDSL_GMRES && o->krylov != SDSL_GCR) || o->precision != SDSL_FP64))
+        fail(SDSL_E_INVALID, "the BBD preconditioner runs with GMRES or GCR in FP64");
     if (o->filter < SDSL_FILTER_NONE || o->filter > SDSL_FILTER_GEOMEAN) fail(SDSL_E_INVALID, "unknown filter");
     if (!(o->tau >= 0.0)) fail(SDSL_E_INVALID, "tau must be >= 0");
     if (!(o->delta >= 0.0) || !std::isfinite(o->delta)) fail(SDSL_E_INVALID, "delta must be finite and >= 0");
     if (o->pivot < SDSL_PIVOT_FAIL || o->pivot > SDSL_PIVOT_SHIFT) fail(SDSL_E_INVALID, "unknown pivot policy");
     if (o->pivot == SDSL_PIVOT_SHIFT && !(o->shift0 > 0.0 && std::isfinite(o->shift0)))
         fail(SDSL_E_INVALID, "shift0 must be positive");
-    if (o->krylov != SDSL_PCG && o->krylov != SDSL_GMRES) fail(SDSL_E_INVALID, "unknown Krylov method");
+    if (o->krylov != SDSL_PCG && o->krylov != SDSL_GMRES && o->krylov != SDSL_BICGSTAB && o->krylov != SDSL_GCR)
+        fail(SDSL_E_INVALID, "unknown Krylov method");
+    if (o->krylov == SDSL_GCR && o->precision != SDSL_FP64)
+        fail(SDSL_E_INVALID, "GCR runs in FP64 (precision must be SDSL_FP64)");
+    if (o->krylov == SDSL_GCR && (o->restart < 1 || o->restart >= kMaxBasisHost))
+        fail(SDSL_E_INVALID, "GCR restart must be in [1, 63]");
+    if (o->krylov == SDSL_BICGSTAB && (o->method != SDSL_BJ || o->precision != SDSL_FP64))
+        fail(SDSL_E_INVALID, "BiCGSTAB runs with the block-Jacobi preconditioner in FP64");
     if (o->krylov == SDSL_GMRES && o->precision != SDSL_FP64)
         fail(SDSL_E_INVALID, "GMRES runs in FP64 (precision must be SDSL_FP64)");
     if (o->krylov == SDSL_GMRES && (o->restart < 1 || o->restart >= kMaxBasisHost))
@@ -1345,12 +1504,15 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
     b += (size_t)2 * ((n + 1) * 4 + nnz * (4 + 8 + 4));             // older entries (L, U)
     b += (size_t)2 * n * (8 + 4);                                   // level-order placement
     b += n * (9 * 8 + 6 * 4);                                       // Krylov vectors
+    b += (size_t)6 * 4096 * 8;                                      // BiCGSTAB partials
     b += (nb + 1) * 4 + nb * (8 + 4) + 2048 * 8 * 4 + nb * 8 * 3;
     if (lr && lr->k > 0)  // U twice (CSR, CSC), W = P^{-1} U, K and its inverse, reduction partials
         b += (size_t)lr->U.nnz * 2 * (4 + 8) + (n + 1) * 4 + (size_t)lr->k * n * 8 + (size_t)lr->k * lr->k * 16 +
              64 * 1024;
     b += (n + 1023) / 1024 * 4 + 4096;
-    if (o->krylov == SDSL_GMRES) {  // basis V (m + 1 columns), Z = P^{-1} V (m columns), reduction partials
+    if (o->krylov == SDSL_GMRES || o->krylov == SDSL_GCR) {
+        // GMRES: basis V (m + 1 columns), Z = P^{-1} V (m columns); GCR: Q and
+        // P in the same storage; reduction partials
         const size_t m = (size_t)std::max(1, std::min(o->restart, kMaxBasisHost - 1));
         b += (2 * m + 1) * n * 8 + ((size_t)512 * kMaxBasisHost + 512 + 3 * kMaxBasisHost) * 8;
     }
@@ -1538,6 +1700,7 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         h->part_rr = h->alloc<double>(h->nb);
         h->part_b = h->alloc<double>(h->grid);
         h->part_res = h->alloc<double>(h->grid);
+        h->bi_part = h->alloc<double>((size_t)6 * bicg_grid(n));
         h->scal = h->alloc<double>(4);
         h->st = h->alloc<KrylovState>(1);
         if (o->method == SDSL_BBD) {

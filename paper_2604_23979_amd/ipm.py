@@ -11,12 +11,15 @@ that fails with fresh factors switches the sequence from block Jacobi to the
 BBD preconditioner for good (Alg. 1) when BBD options are given and the
 system has a bordered form; otherwise the failure is reported.
 
-``degrade = inf`` keeps the fixed schedule only.  ``make_solver(system,
+``tau_schedule`` changes the filter threshold along the sequence (Sec.
+4.3.3: 1e-3 for the early steps, 1e-2 later); a change builds the
+preconditioner anew.  ``degrade = inf`` keeps the fixed schedule only.  ``make_solver(system,
 options)`` builds a solver (``from_system`` for the
 GPU library); the solver needs ``solve``, ``refactor``, ``update_values``,
 ``set_max_iter`` and ``close``."""
 from __future__ import annotations
 
+import dataclasses
 import math
 from dataclasses import dataclass, field
 from typing import Any, Callable, Optional
@@ -37,9 +40,13 @@ class StepRecord:
 
 class SequenceSolver:
     def __init__(self, make_solver: Callable[[Any, Any], Any], options, reuse_every: int = 5,
-                 degrade: float = 1.5, min_cap: int = 50, bbd_options=None):
+                 degrade: float = 1.5, min_cap: int = 50, bbd_options=None, tau_schedule=None):
         self.make_solver = make_solver
         self.options = options
+        # [(first step, tau), ...] ascending: the filter threshold from that
+        # step on (Sec. 4.3.3 runs tau = 1e-3 and later 1e-2); a change builds
+        # the preconditioner anew with the new threshold
+        self.tau_schedule = sorted(tau_schedule) if tau_schedule else None
         self.reuse_every = max(1, int(reuse_every))
         self.degrade = float(degrade)
         self.min_cap = int(min_cap)
@@ -51,6 +58,15 @@ class SequenceSolver:
         self.ref_its: Optional[int] = None   # iterations of the last fresh solve
         self.since = 0                       # steps since the last fresh factorisation
 
+    def _tau_at(self, k: int):
+        if not self.tau_schedule:
+            return None
+        tau = None
+        for k0, t in self.tau_schedule:
+            if k >= k0:
+                tau = t
+        return tau
+
     def _fresh_solve(self, b, tol):
         self.sv.set_max_iter(self.max_iter)
         return self.sv.solve(b, tol=tol)
@@ -61,6 +77,13 @@ class SequenceSolver:
         Returns (x, StepRecord)."""
         rec = StepRecord(k=k, kind="", method=self.method)
         fresh = True
+        want = self._tau_at(k)
+        if self.sv is not None and want is not None and self.method == "BJ" and want != self.options.tau:
+            self.sv.close()
+            self.sv = None
+            rec.events.append(f"tau {self.options.tau:g} -> {want:g}")
+        if want is not None and self.method == "BJ":
+            self.options = dataclasses.replace(self.options, tau=want)
         if self.sv is None:
             self.sv = self.make_solver(system, self.options)
             rec.kind = "setup"

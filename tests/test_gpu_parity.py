@@ -183,11 +183,41 @@ def test_pcg_fp64_matches_oracle(case):
     assert true_rr <= 1e-8
     assert abs(rr - true_rr) <= 1e-3 * true_rr + 1e-15
     assert abs(its - its_o) <= max(1, 0.10 * its_o)
-    # error against the oracle's solution in the M-norm, bounded by both residuals
-    M = s.scipy()
-    e = x - xo
-    rel_m = np.sqrt(abs(e @ (M @ e))) / np.sqrt(abs(xo @ (M @ xo)))
-    print(f"{name}: ||x - x_oracle||_M / ||x_oracle||_M = {rel_m:.2e}, 2-norm {np.linalg.norm(e) / np.linalg.norm(xo):.2e}")
+    check_solution_gate(name, s, x, xo)
+
+
+def smallest_eigenvalue(s):
+    """A lower bound for lambda_min of the explicit sparse part of M (itself
+    a lower bound for the operator's when a positive semidefinite low-rank
+    term is added): Gershgorin's when it is positive (diagonally dominant
+    matrices), else the eigenvalue itself by shift-invert Lanczos (small IPM
+    systems only: a sparse LU of a large random pattern would not finish)."""
+    import scipy.sparse.linalg as sla
+    M = s.scipy().tocsr()
+    d = M.diagonal()
+    gersh = float(np.min(d - (np.asarray(abs(M).sum(axis=1)).ravel() - np.abs(d))))
+    if gersh > 0:
+        return gersh
+    assert s.n <= 8000, "no cheap lambda_min bound for this system"
+    return float(sla.eigsh(M.tocsc(), k=1, sigma=0, which="LM", return_eigenvectors=False)[0])
+
+
+def check_solution_gate(name, s, x, xo):
+    """Solution parity (the 1e-6 gate where it is attainable).  Two
+    solutions with residuals r and r_o differ by M^{-1}(r_o - r), so
+    ||x - x_o|| <= (||r|| + ||r_o||) / lambda_min(M): the difference must
+    respect that bound, and must be below 1e-6 relative wherever the bound
+    itself is."""
+    _, nr = O.residual(s.row_ptr, s.col, s.val, x, s.b, s.lowrank)
+    _, nro = O.residual(s.row_ptr, s.col, s.val, xo, s.b, s.lowrank)
+    lam = smallest_eigenvalue(s)
+    bound = (nr + nro) / lam / np.linalg.norm(xo)
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"{name}: ||x - x_oracle|| / ||x_oracle|| = {rel:.2e}; residual bound {bound:.2e} "
+          f"(lambda_min {lam:.2e}); 1e-6 gate {'applies' if bound <= 1e-6 else 'not attainable'}")
+    assert rel <= 1.01 * bound + 1e-15
+    if bound <= 1e-6:
+        assert rel <= 1e-6
 
 
 @pytest.mark.parametrize("prec", ["refine", "restart"])
@@ -217,12 +247,9 @@ def test_fp32_inner_refinement(case, prec):
             # FP32 sums in a different order than the oracle's perturb the
             # recurrence; the counts stay within 10% plus a few iterations
             assert abs(its - inner_o) <= max(4, 0.10 * inner_o)
-        x64, _, _, _ = solver.solve(tdev(s.b), tol=1e-8)
-        M = s.scipy()
-        e = x.cpu().numpy() - x64.cpu().numpy()
-        x64 = x64.cpu().numpy()
-        print(f"{name}: FP32 {prec} vs FP64 solution M-norm rel diff "
-              f"{np.sqrt(abs(e @ (M @ e))) / np.sqrt(abs(x64 @ (M @ x64))):.2e}")
+        # the error against the FP64 oracle's solution, stated and bounded
+        check_solution_gate(f"{name} FP32 {prec}", s, x.cpu().numpy(),
+                            O.pcg_bj(s, P, tol=1e-8, maxit=50_000)[0])
     finally:
         sv.close()
 
@@ -303,16 +330,28 @@ def test_full_c2_solves(c2_full):
     print(f"  {k} iterations: GPU relres {rr:.9e}, oracle {rr_o:.9e}, |x - x_oracle| / |x_oracle| = {dx:.2e}")
     assert st == sd.E_NOT_CONVERGED and its == its_o == k
     assert abs(rr - rr_o) <= 1e-9 * rr_o and dx <= 1e-9
+    # the oracle's complete solves on this system (tests/golden/c2_full_counts.json,
+    # written by make_c2_counts.py: minutes of oracle time, so stored)
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c2_full_counts.json")) as f:
+        gold = json.load(f)
+    assert gold["n"] == s.n and gold["nnz"] == s.nnz and gold["nnz_kept"] == solver.info()["nnz_kept"]
     x, its, rr, st = solver.solve(b, tol=1e-8)
     true_rr = O.relres(s, x.cpu().numpy())
-    print(f"  FP64: {its} iterations, relres {true_rr:.2e}")
+    print(f"  FP64: {its} iterations (oracle {gold['fp64']['iterations']}), relres {true_rr:.2e}")
     assert st == sd.OK and true_rr <= 1e-8 and abs(rr - true_rr) <= 1e-3 * true_rr
+    assert abs(its - gold["fp64"]["iterations"]) <= 0.10 * gold["fp64"]["iterations"]
     sv = sd.from_system(s, sd.Options(**{**o.__dict__, "precision": sd.FP32_IR}))
     try:
         x, its32, rr, st = sv.solve(b, tol=1e-8)
         true_rr = O.relres(s, x.cpu().numpy())
-        print(f"  FP32-inner: {its32} iterations, relres {true_rr:.2e}")
+        inf = sv.info()
+        mx = gold["fp32_mixed"]
+        print(f"  FP32-inner: {its32} iterations, {inf['outer_iters']} points, {inf['fp64_fallbacks']} FP64 solves "
+              f"(oracle {mx['iterations']}, {mx['points']}, {mx['fp64_solves']}), relres {true_rr:.2e}")
         assert st == sd.OK and true_rr <= 1e-8 and abs(rr - true_rr) <= 1e-3 * true_rr
+        O.replay_refine(sv.rf_history(), 0, inf["rf_nb"], 1e-8, o.max_iter)
     finally:
         sv.close()
 
@@ -551,6 +590,134 @@ def test_gmres_bj_matches_oracle(which):
     sv.close()
 
 
+@pytest.mark.parametrize("which", ["nonsym", "nonsym-7blocks"])
+def test_bicgstab_matches_oracle(which):
+    """Right-preconditioned BiCGSTAB (the paper's block-Jacobi solver, Sec.
+    4.3) on nonsymmetric systems whose count does not move under one-ulp
+    changes of b (oracle: 6 iterations for each of 6 draws): true relres <=
+    1e-8, iterations within 10% (or 2) of the oracle's, solution within
+    1e-6."""
+    print(f"[bicgstab {which}]", flush=True)
+    s = nonsym_system() if which == "nonsym" else nonsym_system(n=9000, nblocks=7, seed=4)
+    o = opts(krylov=sd.BICGSTAB, spd=False)
+    sv = sd.from_system(s, o)
+    try:
+        P = O.BJ(s, **oracle_opts(o))
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        x_o, its_o, rr_o, st_o, _ = O.bicgstab_bj(s, P, tol=1e-8, maxit=20_000)
+        x = x.cpu().numpy()
+        true_rr = O.relres(s, x)
+        print(f"  GPU its {its} relres {true_rr:.2e}; oracle its {its_o} relres {rr_o:.2e}")
+        assert st == sd.OK and st_o == O.OK
+        assert true_rr <= 1e-8 and abs(rr - true_rr) <= 1e-3 * true_rr + 1e-15
+        assert abs(its - its_o) <= max(2, 0.1 * its_o)
+        assert np.linalg.norm(x - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    finally:
+        sv.close()
+
+
+def test_bicgstab_c1_and_low_rank_against_oracle():
+    """C1 (SPD, D spread 1e8) and C2 x 0.004 (low-rank term eliminated as a
+    border): the first iterations follow the oracle's (true residual after
+    10 iterations within 1e-6 relative), which exercises the product with
+    the low-rank term and the bordered apply.  On C1 the complete solve
+    meets 1e-8 with a count inside 10% of the range the oracle spans when
+    one entry of b moves by one ulp (8 draws; BiCGSTAB there is as sensitive
+    to rounding as GMRES)."""
+    for name, s, o in (("C1", gen.c1(), opts(krylov=sd.BICGSTAB)),
+                       ("C2x0.004", gen.c2(0.004), opts(krylov=sd.BICGSTAB, filter=sd.FILTER_GEOMEAN, tau=1e-3,
+                                                        diag_flags=sd.DIAG_DROPSUM))):
+        sv = sd.from_system(s, o)
+        try:
+            P = O.BJ(s, **oracle_opts(o))
+            sv.set_max_iter(10)
+            _, its, rr, st = sv.solve(tdev(s.b), tol=1e-30)
+            _, its_o, rr_o, _, _ = O.bicgstab_bj(s, P, tol=1e-30, maxit=10)
+            print(f"  {name} after 10: GPU relres {rr:.12e}, oracle {rr_o:.12e}")
+            assert its == its_o == 10 and abs(rr - rr_o) <= 1e-6 * rr_o
+            if name != "C1":
+                continue
+            sv.set_max_iter(20_000)
+            x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+            b0 = s.b.copy()
+            rng = np.random.default_rng(3)
+            counts = [O.bicgstab_bj(s, P, tol=1e-8, maxit=20_000)[1]]
+            for _ in range(8):
+                bb = b0.copy()
+                i = rng.integers(0, s.n)
+                bb[i] = np.nextafter(bb[i], np.inf)
+                s.b = bb
+                counts.append(O.bicgstab_bj(s, P, tol=1e-8, maxit=20_000)[1])
+            s.b = b0
+            true_rr = O.relres(s, x.cpu().numpy())
+            print(f"  C1 BiCGSTAB: GPU its {its} relres {true_rr:.2e}; oracle {counts[0]}, one-ulp range "
+                  f"{min(counts)}-{max(counts)}")
+            assert st == sd.OK and true_rr <= 1e-8
+            assert 0.9 * min(counts) <= its <= 1.1 * max(counts)
+        finally:
+            sv.close()
+
+
+@pytest.mark.parametrize("which", ["nonsym", "nonsym-7blocks"])
+def test_gcr_matches_oracle(which):
+    """Right-preconditioned restarted GCR(30) (the paper's solver with BBD and
+    on single nodes, Sec. 4.2-4.3) with block Jacobi: true relres <= 1e-8,
+    iterations within 10% (or 2) of the oracle's, solution within 1e-6; the
+    first 10 steps follow the oracle's residual within 1e-8 relative."""
+    print(f"[gcr {which}]", flush=True)
+    s = nonsym_system() if which == "nonsym" else nonsym_system(n=9000, nblocks=7, seed=4)
+    o = opts(krylov=sd.GCR, spd=False)
+    sv = sd.from_system(s, o)
+    try:
+        P = O.BJ(s, **oracle_opts(o))
+        sv.set_max_iter(10)
+        _, its, rr, st = sv.solve(tdev(s.b), tol=1e-30)
+        _, its_o, rr_o, _, _ = O.gcr_bj(s, P, tol=1e-30, m=30, maxit=10)
+        print(f"  after 10: GPU relres {rr:.12e}, oracle {rr_o:.12e}")
+        assert its == its_o == 10 and abs(rr - rr_o) <= 1e-8 * rr_o
+        sv.set_max_iter(20_000)
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        x_o, its_o, rr_o, st_o, _ = O.gcr_bj(s, P, tol=1e-8, m=30, maxit=20_000)
+        x = x.cpu().numpy()
+        true_rr = O.relres(s, x)
+        print(f"  GPU its {its} relres {true_rr:.2e}; oracle its {its_o} relres {rr_o:.2e}")
+        assert st == sd.OK and st_o == O.OK
+        assert true_rr <= 1e-8 and abs(rr - true_rr) <= 1e-3 * true_rr + 1e-15
+        assert abs(its - its_o) <= max(2, 0.1 * its_o)
+        assert np.linalg.norm(x - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    finally:
+        sv.close()
+
+
+def test_gcr_exact_preconditioner_and_breakdown():
+    """A tridiagonal single block (ILU(0) exact) converges in one GCR step; a
+    2 x 2 system whose residual is orthogonal to M P^-1 r repeats its first
+    direction, which adds nothing: SDSL_E_BREAKDOWN after one step with x
+    unchanged (the oracle says the same)."""
+    rng = np.random.default_rng(5)
+    n = 4000
+    lo, up = rng.standard_normal(n - 1), rng.standard_normal(n - 1)
+    dg = np.abs(np.r_[lo, 0]) + np.abs(np.r_[0, up]) + 1.0
+    a = sp.diags([lo, dg, up], [-1, 0, 1]).tocsr()
+    a.sort_indices()
+    s = gen.System("tri-ns", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data,
+                   rng.standard_normal(n), np.array([0, n], dtype=np.int32))
+    sv = sd.from_system(s, opts(krylov=sd.GCR, spd=False))
+    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-12)
+    assert st == sd.OK and its == 1 and O.relres(s, x.cpu().numpy()) <= 1e-12
+    sv.close()
+    m = sp.csr_matrix(np.array([[1.0, 3.0], [-1.0, 1.0]]))
+    bd = gen.System("bd", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, np.array([1.0, -1.0]),
+                    np.array([0, 1, 2], dtype=np.int32))
+    o = opts(krylov=sd.GCR, spd=False, pivot=sd.PIVOT_FAIL)
+    sv = sd.from_system(bd, o)
+    x, its, rr, st = sv.solve(tdev(bd.b), tol=1e-12)
+    _, its_o, _, st_o, _ = O.gcr_bj(bd, O.BJ(bd, **oracle_opts(o)), tol=1e-12, maxit=10)
+    assert st == sd.E_BREAKDOWN and st_o == O.BREAKDOWN and its == its_o == 1
+    assert np.all(x.cpu().numpy() == 0.0)
+    sv.close()
+
+
 def _row_scaled_system(seed, n=400):
     """Nonsymmetric, weakly dominant, rows scaled over 1e-5..1e5: GMRES(60)
     makes slow progress, which keeps a long run of cycles meaningful."""
@@ -583,21 +750,40 @@ def test_gmres_long_run_on_row_scaled_system(seed):
     sv.close()
 
 
-def test_gmres_c1_reaches_tolerance():
-    """C1 with GMRES(30): restarted GMRES on this SPD system with a 1e8
-    spread of D stagnates between restarts, and its iteration count moves by
-    tens of percent with rounding alone (the oracle needs 3821 iterations
-    with modified and 4632 with twice-applied classical Gram-Schmidt), so
-    only the true residual is gated here; the counts are printed."""
+def test_gmres_c1_matches_oracle_within_rounding_spread():
+    """C1 with GMRES(30).  Restarted GMRES on this SPD system (D spread 1e8)
+    stagnates between restarts, and rounding alone moves its count: in the
+    oracle, one ulp of one entry of b takes the 4,632 iterations to anywhere
+    in 3,029-3,899 (12 draws, tests/golden/c1_gmres_ensemble.json, written by
+    make_c1_gmres_ensemble.py), while the residual histories agree to 1e-12
+    for the first 300 iterations and separate only after 1,200.  Gates: the
+    true residual after 30 and 300 iterations equals the oracle's (1e-6
+    relative), the solve meets 1e-8, and its count lies within 10% of the
+    range the oracle spans under one-ulp changes of b."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_gmres_ensemble.json")) as f:
+        ens = json.load(f)
     s = gen.c1()
     o = opts(krylov=sd.GMRES, max_iter=20_000)
     sv = sd.from_system(s, o)
-    x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
-    true_rr = O.relres(s, x.cpu().numpy())
-    _, its_o, rr_o, st_o, _ = O.gmres_bj(s, O.BJ(s), tol=1e-8, m=30, maxit=20_000)
-    print(f"  C1 GMRES: GPU its {its} relres {true_rr:.2e}; oracle its {its_o}")
-    assert st == sd.OK and true_rr <= 1e-8
-    sv.close()
+    try:
+        b = tdev(s.b)
+        for k in (30, 300):
+            sv.set_max_iter(k)
+            _, its, rr, st = sv.solve(b, tol=1e-30)
+            ref = ens[f"relres_after_{k}"]
+            print(f"  after {k}: GPU relres {rr:.12e}, oracle {ref:.12e}")
+            assert its == k and abs(rr - ref) <= 1e-6 * ref
+        sv.set_max_iter(o.max_iter)
+        x, its, rr, st = sv.solve(b, tol=1e-8)
+        true_rr = O.relres(s, x.cpu().numpy())
+        lo, hi = min(ens["one_ulp_counts"] + [ens["iterations"]]), max(ens["one_ulp_counts"] + [ens["iterations"]])
+        print(f"  C1 GMRES: GPU its {its} relres {true_rr:.2e}; oracle {ens['iterations']}, one-ulp range {lo}-{hi}")
+        assert st == sd.OK and true_rr <= 1e-8
+        assert 0.9 * lo <= its <= 1.1 * hi
+    finally:
+        sv.close()
 
 
 def test_gmres_exact_preconditioner_one_step():
@@ -671,6 +857,106 @@ def test_bbd_gmres_matches_oracle(bbd_case):
     assert st == sd.OK and st_o == O.OK and true_rr <= 1e-8
     assert abs(its - its_o) <= max(2, 0.1 * its_o)
     assert np.linalg.norm(x.cpu().numpy() - x_o) <= 1e-6 * np.linalg.norm(x_o)
+
+
+def test_bbd_gcr_matches_oracle(bbd_case):
+    """GCR(30) with the BBD preconditioner, the pairing of the paper's
+    ill-conditioned runs (Sec. 4.3): iterations within 10% (or 2) of the
+    oracle's, true relres <= 1e-8, solution within 1e-6."""
+    name, s, _, P = bbd_case
+    sv = sd.from_system(s, opts(**dict(BBD_OPTS, krylov=sd.GCR)))
+    try:
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        x_o, its_o, rr_o, st_o, _ = O.gcr_bbd(s, P, tol=1e-8, m=30)
+        true_rr = O.relres(s, x.cpu().numpy())
+        print(f"  {name} GCR: GPU its {its} relres {true_rr:.2e}; oracle its {its_o} relres {rr_o:.2e}")
+        assert st == sd.OK and st_o == O.OK and true_rr <= 1e-8
+        assert abs(its - its_o) <= max(2, 0.1 * its_o)
+        assert np.linalg.norm(x.cpu().numpy() - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    finally:
+        sv.close()
+
+
+def test_full_c3_bbd_matches_oracle_samples():
+    """C3 at full size (1,500,096 rows, 32 blocks, 4,096-row border): the
+    Schur LU takes the oracle's pivots, sampled LU entries and sampled
+    entries of one preconditioner apply agree within 1e-10 of the largest
+    magnitude, GMRES(30) takes the oracle's iteration count within 10%, and
+    the solution meets 1e-8 (oracle residual) and agrees with the oracle's
+    sampled entries within 1e-6 of its largest.  The oracle's numbers take it
+    a minute, so they are stored: tests/golden/c3_full_samples.json, written
+    by make_c3_full.py."""
+    import json
+    import os
+    print("\n[C3 at full size]", flush=True)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_full_samples.json")) as f:
+        gold = json.load(f)
+    s = gen.c3(1.0)
+    assert s.n == gold["n"] and s.n_border == gold["n_border"]
+    sv = sd.from_system(s, opts(**BBD_OPTS))
+    try:
+        lu, piv, _ = sv.schur()
+        assert np.array_equal(piv, np.asarray(gold["pivots"]))
+        smp = np.asarray(gold["lu_samples"])
+        ii, jj = smp[:, 0].astype(np.int64), smp[:, 1].astype(np.int64)
+        d = np.max(np.abs(lu[ii, jj] - smp[:, 2]))
+        print(f"  Schur LU: pivots equal, sampled max diff {d:.2e} (max |LU| {gold['lu_max_abs']:.2e})")
+        assert d <= 1e-10 * gold["lu_max_abs"]
+        del lu
+        r = np.random.default_rng(gold["apply_rhs_seed"]).standard_normal(s.n)
+        z = sv.precond_apply(tdev(r)).cpu().numpy()
+        smp = np.asarray(gold["apply_samples"])
+        d = np.max(np.abs(z[smp[:, 0].astype(np.int64)] - smp[:, 1]))
+        print(f"  apply: sampled max diff {d:.2e} (max |z| {gold['apply_max_abs']:.2e})")
+        assert d <= 1e-10 * gold["apply_max_abs"]
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        x = x.cpu().numpy()
+        g = gold["gmres"]
+        true_rr = O.relres(s, x)
+        smp = np.asarray(g["x_samples"])
+        d = np.max(np.abs(x[smp[:, 0].astype(np.int64)] - smp[:, 1]))
+        print(f"  GMRES: {its} iterations (oracle {g['iterations']}), relres {true_rr:.2e}, sampled solution "
+              f"max diff {d:.2e} (max |x| {g['x_max_abs']:.2e})")
+        assert st == sd.OK and true_rr <= 1e-8
+        assert abs(its - g["iterations"]) <= max(1, 0.10 * g["iterations"])
+        assert d <= 1e-6 * g["x_max_abs"]
+    finally:
+        sv.close()
+
+
+def test_alg1_switch_through_the_library():
+    """Alg. 1 through the library: on a bordered system whose border couples
+    strongly to its blocks (gen.strong_border_system), block-Jacobi GMRES
+    fails with fresh factors, the sequence driver switches to BBD for good,
+    and BBD GMRES converges with the oracle's count (10% or 2); the oracle's
+    block-Jacobi GMRES fails on the system too.  The next two systems of the
+    sequence (scaled values) stay on BBD and reuse its factors."""
+    from paper_2604_23979_amd.ipm import SequenceSolver
+    s = gen.strong_border_system(20.0)
+    bj = gen.as_block_jacobi(s)
+    _, its_j, rr_j, st_j, _ = O.gmres_bj(bj, O.BJ(bj, spd=False), tol=1e-8, m=30, maxit=300)
+    _, its_b, rr_b, st_b, _ = O.gmres_bbd(s, O.BBD(s), tol=1e-8, m=30, maxit=300)
+    print(f"\n  oracle: BJ {its_j} its relres {rr_j:.2e} (status {st_j}); BBD {its_b} its relres {rr_b:.2e}")
+    assert st_j == O.NOT_CONVERGED and st_b == O.OK
+    o_bj = opts(krylov=sd.GMRES, spd=False, max_iter=300)
+    o_bbd = opts(method=sd.BBD, krylov=sd.GMRES, spd=False, max_iter=300)
+    make = lambda sys_, o: sd.from_system(gen.as_block_jacobi(sys_) if o.method == sd.BJ else sys_, o)
+    seq = SequenceSolver(make, o_bj, bbd_options=o_bbd)
+    try:
+        for k in range(3):
+            vals = s.val * (1.0 + 0.25 * k)
+            sk = gen.System(f"sb{k}", s.row_ptr, s.col, vals, s.b, s.block_ptr, n_border=s.n_border)
+            x, rec = seq.step(k, sk, tdev(vals), tdev(s.b), tol=1e-8)
+            true_rr = O.relres(sk, x.cpu().numpy())
+            print(f"  step {k}: {rec.kind} {rec.method} {rec.iterations} its, status {rec.status}, relres {true_rr:.2e}")
+            assert rec.status == sd.OK and true_rr <= 1e-8 and rec.method == "BBD"
+            if k == 0:
+                assert rec.kind == "setup+bbd" and seq.switched
+                assert abs((rec.iterations - 300) - its_b) <= max(2, 0.1 * its_b)
+            else:
+                assert rec.kind == "reuse"
+    finally:
+        seq.close()
 
 
 def test_bbd_exact_blocks_one_step():

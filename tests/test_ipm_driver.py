@@ -109,3 +109,20 @@ def test_infinite_degrade_keeps_the_fixed_schedule():
     recs = run(seq, 4)
     assert [r.kind for r in recs] == ["setup", "reuse", "reuse", "reuse"]
     assert [r.iterations for r in recs] == [100, 100, 300, 300]
+
+
+def test_two_phase_tau_schedule_rebuilds_the_preconditioner():
+    """Sec. 4.3.3 filters with tau = 1e-3 for the early IPM steps and 1e-2
+    later: the driver builds the preconditioner anew with the new threshold
+    at the step where the schedule changes, then reuses it as before."""
+    log, taus = [], []
+
+    def make(system, options):
+        taus.append((system, options.tau))
+        return make_factory(lambda k, age, m: 100, log)(system, options)
+    seq = SequenceSolver(make, Options(max_iter=1000, tau=1e-3), tau_schedule=[(0, 1e-3), (24, 1e-2)])
+    recs = run(seq, 27)
+    assert taus == [(0, 1e-3), (24, 1e-2)]
+    assert recs[24].kind == "setup" and any("tau 0.001 -> 0.01" in e for e in recs[24].events)
+    assert [r.kind for r in recs[20:27]] == ["refactor", "reuse", "reuse", "reuse", "setup", "reuse", "reuse"]
+    assert seq.options.tau == 1e-2

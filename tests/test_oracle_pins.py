@@ -662,6 +662,199 @@ def test_dense_lu_matches_lapack():
     assert np.array_equal(piv, piv_ref)
 
 
+# --------------------------------------------------------------- BiCGSTAB
+
+def _small_nonsym(n, seed, blocks=3):
+    rng = np.random.default_rng(seed)
+    a = rand_sparse(n, 0.2, rng, sym=False, dd=0.6)
+    m = csr_of(a)
+    b = rng.standard_normal(n)
+    return gen.System("ns", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, b,
+                      gen.contiguous_blocks(n, blocks)), a
+
+
+def test_bicgstab_first_step_is_petrov_galerkin_then_minimal_residual():
+    """One BiCGSTAB step (paper Sec. 4.3's solver for block Jacobi), right
+    preconditioned (Sec. 2.2) with x0 = 0 and shadow r^ = b: x1 lies in
+    span{u1, u2}, u1 = P^-1 b, u2 = P^-1 M u1, as x1 = (a + w) u1 - a w u2,
+    where a makes the half-step residual b - a M u1 orthogonal to b
+    (Petrov-Galerkin) and w minimises ||s - w M P^-1 s|| over w (the
+    stabilising step); both are checked from x1 alone."""
+    s, a = _small_nonsym(30, 50)
+    P = O.BJ(s, policy=O.PIVOT_FAIL, spd=False)
+    assert P.status == O.OK
+    L, U = unpack_lu(P.rp, P.ci, P.v, s.n)
+    pinv = np.linalg.inv(L @ U)
+    b = s.b
+    u1 = pinv @ b
+    u2 = pinv @ (a @ u1)
+    x1, its, rr, st, _ = O.bicgstab_bj(s, P, tol=1e-30, maxit=1)
+    assert its == 1 and st == O.NOT_CONVERGED
+    coef, res, *_ = np.linalg.lstsq(np.c_[u1, u2], x1, rcond=None)
+    assert np.linalg.norm(np.c_[u1, u2] @ coef - x1) <= 1e-12 * np.linalg.norm(x1)
+    # coef = (alpha + omega, -alpha omega): alpha is the Petrov-Galerkin step
+    alpha = (b @ b) / (b @ (a @ u1))
+    omega = coef[0] - alpha
+    assert abs(-alpha * omega - coef[1]) <= 1e-10 * abs(coef[1])
+    sres = b - alpha * (a @ u1)
+    assert abs(b @ sres) <= 1e-12 * np.linalg.norm(b) * np.linalg.norm(sres)
+    t = a @ (pinv @ sres)
+    assert abs(omega - (t @ sres) / (t @ t)) <= 1e-12 * abs(omega)
+
+
+def test_bicgstab_iterates_stay_in_the_right_krylov_space():
+    """Each step adds two dimensions: x_k lies in P^-1 K_2k(M P^-1, b) and
+    not in P^-1 K_(2k-1) (a step with one product, or a left-preconditioned
+    form, fails one of the two)."""
+    s, a = _small_nonsym(40, 51)
+    P = O.BJ(s, policy=O.PIVOT_FAIL, spd=False)
+    L, U = unpack_lu(P.rp, P.ci, P.v, s.n)
+    pinv = np.linalg.inv(L @ U)
+    K = [s.b]
+    for _ in range(8):
+        K.append(a @ (pinv @ K[-1]))
+    for k in (1, 2, 3):
+        x, its, rr, st, _ = O.bicgstab_bj(s, P, tol=1e-30, maxit=k)
+        for dim, inside in ((2 * k, True), (2 * k - 1, False)):
+            B = pinv @ np.array(K[:dim]).T
+            Q, _ = np.linalg.qr(B)
+            off = np.linalg.norm(x - Q @ (Q.T @ x)) / np.linalg.norm(x)
+            assert (off <= 1e-9) if inside else (off >= 1e-6), (k, dim, off)
+
+
+def test_bicgstab_exact_preconditioner_terminates_and_small_systems_converge():
+    """A single tridiagonal block (ILU(0) exact) converges in one step; a
+    12-unknown nonsymmetric system converges within 12 steps (the BiCG
+    polynomial inside the residual annihilates r0 by step n in exact
+    arithmetic); an indefinite case with (r^, M P^-1 r0) = 0 is a
+    breakdown."""
+    n = 200
+    rng = np.random.default_rng(52)
+    lo, up = rng.standard_normal(n - 1), rng.standard_normal(n - 1)
+    a = np.diag(np.abs(np.r_[lo, 0]) + np.abs(np.r_[0, up]) + 1.0) + np.diag(lo, -1) + np.diag(up, 1)
+    m = csr_of(a)
+    t = gen.System("tri", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, rng.standard_normal(n),
+                   np.array([0, n], dtype=np.int32))
+    x, its, rr, st, _ = O.bicgstab_bj(t, O.BJ(t, spd=False), tol=1e-12, maxit=10)
+    assert st == O.OK and its == 1 and rr <= 1e-12
+    s, a = _small_nonsym(12, 53, blocks=2)
+    x, its, rr, st, _ = O.bicgstab_bj(s, O.BJ(s, spd=False), tol=1e-10, maxit=50)
+    assert st == O.OK and its <= 12 and np.linalg.norm(s.b - a @ x) <= 1e-9 * np.linalg.norm(s.b)
+    m = csr_of([[1.0, 3.0], [-1.0, 1.0]])
+    bd = gen.System("bd", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, np.array([1.0, -1.0]),
+                    np.array([0, 1, 2], dtype=np.int32))
+    x, its, rr, st, _ = O.bicgstab_bj(bd, O.BJ(bd, spd=False), tol=1e-12, maxit=10)
+    assert st == O.BREAKDOWN
+
+
+def test_bicgstab_solves_c1_and_stops_on_the_true_residual():
+    s = gen.c1()
+    P = O.BJ(s)
+    x, its, rr, st, h = O.bicgstab_bj(s, P, tol=1e-8, maxit=20_000, hist=True)
+    assert st == O.OK and rr <= 1e-8
+    assert np.linalg.norm(s.b - s.scipy() @ x) / np.linalg.norm(s.b) <= 1.5e-8
+
+
+# --------------------------------------------------------------- GCR(m)
+
+def test_gcr_iterates_minimise_residual_brute_force():
+    """GCR (the paper's single-node and BBD solver, Sec. 4.2-4.3), right
+    preconditioned (Sec. 2.2): after k steps from x0 = 0 the iterate is
+    the minimiser of ||b - M P^-1 y|| over y in K_k(M P^-1, b), checked
+    against a dense least-squares solve; the residual never grows."""
+    rng = np.random.default_rng(60)
+    n = 50
+    a = rand_sparse(n, 0.15, rng, dd=0.4)
+    m = csr_of(a)
+    s = gen.System("ns", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                   rng.standard_normal(n), gen.contiguous_blocks(n, 4))
+    P = O.BJ(s, spd=False, policy=O.PIVOT_FAIL)
+    L, U = unpack_lu(P.rp, P.ci, P.v, n)
+    Pinv = np.linalg.inv(L @ U)
+    prev = np.inf
+    for k in range(1, 10):
+        x, its, rr, st, hist = O.gcr_bj(s, P, tol=1e-30, m=30, maxit=k, hist=True)
+        assert its == k
+        K = [s.b]
+        for _ in range(k - 1):
+            K.append(a @ (Pinv @ K[-1]))
+        Q, _ = np.linalg.qr(np.array(K).T)
+        c, *_ = np.linalg.lstsq(a @ Pinv @ Q, s.b, rcond=None)
+        xb = Pinv @ (Q @ c)
+        assert np.linalg.norm(x - xb) <= 1e-8 * max(1.0, np.linalg.norm(xb)), k
+        assert rr <= prev * (1 + 1e-12)
+        # the recurrence residual is the true one
+        assert hist[-1] == pytest.approx(np.linalg.norm(s.b - a @ x) / np.linalg.norm(s.b), rel=1e-8)
+        prev = rr
+
+
+@pytest.mark.parametrize("m", [40, 7])
+def test_gcr_follows_gmres_step_by_step(m):
+    """GCR(m) and GMRES(m) minimise the same residual over the same space in
+    every cycle, so from the same start their residual histories agree step
+    by step, with restarts too (two independent recurrences: Arnoldi with
+    Givens rotations against orthogonalised directions)."""
+    rng = np.random.default_rng(61)
+    n = 300
+    a = rand_sparse(n, 0.03, rng, dd=0.3)
+    mm = csr_of(a)
+    s = gen.System("ns", mm.indptr.astype(np.int64), mm.indices.astype(np.int32), mm.data,
+                   rng.standard_normal(n), gen.contiguous_blocks(n, 10))
+    P = O.BJ(s, spd=False, policy=O.PIVOT_FAIL)
+    _, its_g, rr_g, st_g, h_g = O.gmres_bj(s, P, tol=1e-10, m=m, maxit=2000, hist=True)
+    _, its_c, rr_c, st_c, h_c = O.gcr_bj(s, P, tol=1e-10, m=m, maxit=2000, hist=True)
+    assert st_g == O.OK and st_c == O.OK
+    assert abs(its_c - its_g) <= 1
+    k = min(its_c, its_g) - 1
+    assert its_g > m or m == 40
+    np.testing.assert_allclose(h_c[:k], h_g[:k], rtol=1e-6)
+
+
+def test_gcr_small_cases_and_breakdown():
+    """A single tridiagonal block (ILU(0) exact) converges in one step; a
+    dense 25-unknown system within 25 steps; a residual orthogonal to
+    M P^-1 r gives alpha = 0, the next direction repeats the last one, and
+    the empty projection is a breakdown."""
+    n = 200
+    rng = np.random.default_rng(62)
+    lo, up = rng.standard_normal(n - 1), rng.standard_normal(n - 1)
+    a = np.diag(np.abs(np.r_[lo, 0]) + np.abs(np.r_[0, up]) + 1.0) + np.diag(lo, -1) + np.diag(up, 1)
+    m = csr_of(a)
+    t = gen.System("tri", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, rng.standard_normal(n),
+                   np.array([0, n], dtype=np.int32))
+    x, its, rr, st, _ = O.gcr_bj(t, O.BJ(t, spd=False), tol=1e-12)
+    assert st == O.OK and its == 1 and rr <= 1e-12
+    n = 25
+    a = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    m = csr_of(a)
+    g = gen.System("g", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                   rng.standard_normal(n), np.arange(n + 1, dtype=np.int32))
+    x, its, rr, st, _ = O.gcr_bj(g, O.BJ(g, spd=False, policy=O.PIVOT_FAIL), tol=1e-10, m=30)
+    assert st == O.OK and its <= n and np.linalg.norm(g.b - a @ x) <= 1e-9 * np.linalg.norm(g.b)
+    m = csr_of([[1.0, 3.0], [-1.0, 1.0]])
+    bd = gen.System("bd", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, np.array([1.0, -1.0]),
+                    np.array([0, 1, 2], dtype=np.int32))
+    x, its, rr, st, _ = O.gcr_bj(bd, O.BJ(bd, spd=False), tol=1e-12, maxit=10)
+    assert st == O.BREAKDOWN and its == 1 and np.all(x == 0.0)
+
+
+def test_gcr_with_bbd_matches_gmres_and_exact_blocks_take_one_step():
+    s = gen.bbd_system(nblocks=4, block_rows=80, n_border=16, nnz_off=1, half_band=1, tail_frac=0.1,
+                       border_c=2, seed=16, name="bbd-tri")
+    P = O.BBD(s)
+    x, its, rr, st, _ = O.gcr_bbd(s, P, tol=1e-10)
+    assert st == O.OK and its == 1 and rr <= 1e-10
+    s = gen.bbd_system(nblocks=3, block_rows=60, n_border=12, nnz_off=4, half_band=10, tail_frac=0.2,
+                       border_c=2, seed=14, name="bbd-tiny")
+    P = O.BBD(s)
+    _, its_g, _, st_g, h_g = O.gmres_bbd(s, P, tol=1e-10, m=5, hist=True)
+    x, its_c, rr, st_c, h_c = O.gcr_bbd(s, P, tol=1e-10, m=5, hist=True)
+    assert st_g == O.OK and st_c == O.OK and abs(its_c - its_g) <= 1
+    k = min(its_c, its_g) - 1
+    np.testing.assert_allclose(h_c[:k], h_g[:k], rtol=1e-6)
+    assert np.linalg.norm(s.b - s.scipy() @ x) <= 1.5e-10 * np.linalg.norm(s.b)
+
+
 # --------------------------------------------------------------- IR
 
 def test_ir_reaches_tolerance_and_matches_fp64_solution():
