@@ -302,6 +302,50 @@ sdsl_status sdsl_solve_begin(sdsl_handle h, const double* b, double* x, double t
 sdsl_status sdsl_solve_step(sdsl_handle h, int32_t* done);
 sdsl_status sdsl_solve_end(sdsl_handle h, int32_t* iters, double* relres);
 
+/* ---- shared launches for served solves --------------------------------
+ * A group advances the running solves of several handles on ONE stream with
+ * shared launches: each PCG iteration of all of them is one SpMV launch, one
+ * block-Jacobi launch and one p-update launch, whose workgroups are the
+ * handles' own grids laid end to end (per precision form and SpMV lane
+ * count), so that small solves fill the device together.  Every handle's
+ * workgroups compute exactly what its own launches compute, so each result
+ * is bitwise the one sdsl_solve gives on the same handle.  Applies to PCG
+ * iterations (FP64 and both FP32 modes) of handles without a low-rank term;
+ * everything else a solve does (true residuals, refinement points, the
+ * GMRES/BiCGSTAB/GCR methods, low-rank handles) runs as in sdsl_solve_step.
+ *
+ * sdsl_group_create: hip_stream is the stream every member handle was set up
+ * on (NULL: the default stream); use_graphs = 1 records the iterations of
+ * each shape of a step (member set, counts, grids) once as a HIP graph and
+ * replays it (the kernels read the member table from device memory, so a
+ * replay needs only the table copy); al as for sdsl_setup (NULL: hipMalloc)
+ * provides the table.  The group keeps a device table, pinned staging and
+ * up to 16 graphs until sdsl_group_destroy.
+ * sdsl_group_begin: as sdsl_solve_begin, but the first iterations wait for
+ * the group's next step, where they share its launches.
+ * sdsl_group_step: for each of the k handles (HOST array, each at most once,
+ * each with a solve begun by sdsl_solve_begin or sdsl_group_begin on this
+ * group's stream): waits for its last iterations, takes its next step, and
+ * sets done[i] = 1 once its solve has finished (then call sdsl_solve_end);
+ * then launches every collected iteration.  Handles whose solve finished
+ * are skipped.  SDSL_E_INVALID for a handle on another stream, SDSL_E_STATE
+ * for one without a running solve; the other handles still advance, and the
+ * first non-OK status is returned.  A handle must not be destroyed while its
+ * solve runs.  Calls on one group must not overlap. */
+typedef struct sdsl_group_s* sdsl_group;
+typedef struct {
+    int64_t flushes;         /* shared issues (one per step and kernel form)    */
+    int64_t slot_issues;     /* handle issues they merged                        */
+    int64_t launches;        /* kernel launches they made (3 per iteration)      */
+    int64_t graph_launches;  /* issues replayed from a graph                     */
+    int64_t captures;        /* graphs recorded                                  */
+} sdsl_group_stats;
+sdsl_status sdsl_group_create(void* hip_stream, int32_t use_graphs, const sdsl_allocator* al, sdsl_group* out);
+sdsl_status sdsl_group_begin(sdsl_group g, sdsl_handle h, const double* b, double* x, double tol);
+sdsl_status sdsl_group_step(sdsl_group g, int32_t k, const sdsl_handle* hs, int32_t* done);
+sdsl_status sdsl_group_get_stats(sdsl_group g, sdsl_group_stats* out);
+void sdsl_group_destroy(sdsl_group g);
+
 sdsl_status sdsl_get_info(sdsl_handle h, sdsl_info* out);
 
 /* Last error message of h (or of the calling thread when h is NULL). */

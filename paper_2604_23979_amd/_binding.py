@@ -119,6 +119,11 @@ def torch_allocator() -> Allocator:
     return _TORCH_ALLOC
 
 
+class CGroupStats(C.Structure):
+    _fields_ = [("flushes", C.c_int64), ("slot_issues", C.c_int64), ("launches", C.c_int64),
+                ("graph_launches", C.c_int64), ("captures", C.c_int64)]
+
+
 # every symbol the header declares, with its ctypes signature
 H = C.c_void_p
 P = C.c_void_p
@@ -145,6 +150,11 @@ SIGNATURES = {
     "sdsl_solve_begin": (C.c_int, [H, P, P, C.c_double]),
     "sdsl_solve_step": (C.c_int, [H, P]),
     "sdsl_solve_end": (C.c_int, [H, P, P]),
+    "sdsl_group_create": (C.c_int, [P, C.c_int32, C.POINTER(Allocator), C.POINTER(H)]),
+    "sdsl_group_begin": (C.c_int, [H, H, P, P, C.c_double]),
+    "sdsl_group_step": (C.c_int, [H, C.c_int32, P, P]),
+    "sdsl_group_get_stats": (C.c_int, [H, C.POINTER(CGroupStats)]),
+    "sdsl_group_destroy": (None, [H]),
 }
 
 _lib = None
@@ -407,6 +417,65 @@ class Solver:
         if getattr(self, "h", None):
             lib().sdsl_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group:
+    """Shared launches for the running solves of several Solvers set up on
+    one stream (sdsl_group_*): each PCG iteration of all of them is one
+    launch per kernel, optionally replayed from a HIP graph.  Each solve's
+    result is bitwise the one Solver.solve gives."""
+
+    def __init__(self, stream=None, graphs: bool = True, torch_memory: bool = True):
+        self.stream = stream
+        self._alloc = torch_allocator() if torch_memory else None
+        g = C.c_void_p()
+        st = lib().sdsl_group_create(_stream_ptr(stream), int(graphs),
+                                     C.byref(self._alloc) if self._alloc is not None else None, C.byref(g))
+        if st != OK:
+            msg = lib().sdsl_last_error(None)
+            raise SdslError(st, msg.decode() if msg else "")
+        self.g = g
+        _LIVE.add(self)
+
+    def begin(self, solver: "Solver", b, x, tol: float = 1e-8):
+        """Start M x = b on solver; its first iterations go out with the next
+        step.  b and x (CUDA float64) must stay alive until solve_end."""
+        import torch
+        assert b.is_cuda and b.dtype == torch.float64 and b.numel() == solver.n and x.numel() == solver.n
+        solver._order()
+        solver._async = (b, x)
+        _check(solver.h, lib().sdsl_group_begin(self.g, solver.h, _dptr(b), _dptr(x), tol))
+
+    def step(self, solvers) -> list:
+        """Advance every listed solve once (waiting for its last iterations)
+        and launch the collected iterations together; True where done."""
+        k = len(solvers)
+        hs = (C.c_void_p * max(k, 1))(*[s.h for s in solvers])
+        done = np.zeros(max(k, 1), dtype=np.int32)
+        st = lib().sdsl_group_step(self.g, k, hs, done.ctypes.data_as(C.c_void_p))
+        if st != OK:
+            for s in solvers:
+                msg = lib().sdsl_last_error(s.h)
+                if msg:
+                    raise SdslError(st, msg.decode())
+            _check(None, st)
+        return [bool(d) for d in done[:k]]
+
+    def stats(self) -> dict:
+        s = CGroupStats()
+        _check(None, lib().sdsl_group_get_stats(self.g, C.byref(s)))
+        return {f: int(getattr(s, f)) for f, _ in CGroupStats._fields_}
+
+    def close(self):
+        if getattr(self, "g", None):
+            lib().sdsl_group_destroy(self.g)
+            self.g = None
 
     def __del__(self):
         try:

@@ -241,6 +241,52 @@ struct BorderDev {
     const double* Kinv = nullptr;  // k x k, row-major
 };
 
+// ---------------------------------------------------------- shared launches
+// Several handles' PCG iterations in one launch per kernel: each handle (a
+// slot) keeps the workgroup grid, arguments and therefore the arithmetic of
+// its own launches; a launch's workgroups are the slots' grids laid end to
+// end (prefix sums in *_pre, ns + 1 entries, each slot's range starting at a
+// multiple of 8 so that the XCD mapping of its workgroups is unchanged).
+// The iteration index of slot s at offset k of a shared issue is it0 + k.
+struct SpmvSlot {
+    int n, halo, rows, grid;
+    const int* rp;
+    const int* ci;
+    const void* v;
+    const void* x;
+    void* y;
+    double* part_dot;
+    const KrylovState* st;
+};
+struct BjSlot {
+    BJDev P;
+    PcgVecs Vv;
+    KrylovState* st;
+    int it0;
+};
+struct PupdSlot {
+    int n, nb, grid, it0;
+    void* p;
+    const void* z;
+    const double* part_rz;
+    const double* part_rr;
+    KrylovState* st;
+};
+struct SlotTable {
+    const int* spmv_pre;
+    const SpmvSlot* spmv;
+    const int* bj_pre;
+    const BjSlot* bj;
+    const int* pu_pre;
+    const PupdSlot* pu;
+};
+// One PCG iteration (SpMV with the (p, q) partials, block-Jacobi apply with
+// the r/x update, p update) of the first ns slots at offset k; wg[3] = the
+// workgroup totals of the three launches, shm = the largest SpMV window.
+template <typename V, typename F>
+void launch_slots_iteration(const SlotTable& t, int ns, int k, int lanes, const int* wg, size_t shm, hipStream_t s);
+int pupdate_grid(int n);
+
 // pupdate modes
 enum { PUPD_STEP = 0, PUPD_START = 1, PUPD_REAPPLY = 2 };
 template <typename V, typename F>

@@ -264,11 +264,10 @@ __device__ __forceinline__ T dpp_sum(T s) {
 template <int G> struct SumLane { static constexpr int value = G <= 16 ? 0 : (G == 32 ? 16 : 48); };
 
 template <typename V, typename F, int G, int U, bool LR>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restrict__ rp,
-                                                       const int* __restrict__ ci, const F* __restrict__ v,
-                                                       const V* __restrict__ x, V* __restrict__ y,
-                                                       double* __restrict__ part_dot, const KrylovState* st,
-                                                       LowRankDev lr, int halo, int rows) {
+__device__ __forceinline__ void spmv_body(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                          const F* __restrict__ v, const V* __restrict__ x, V* __restrict__ y,
+                                          double* __restrict__ part_dot, const KrylovState* st, LowRankDev lr,
+                                          int halo, int rows, int bid, int gdim) {
     extern __shared__ double xwin_lds[];
     __shared__ double red[16];
     __shared__ double tk[kMaxRank];
@@ -277,8 +276,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
     if (LR) {
         for (int j = threadIdx.x; j < lr.k; j += blockDim.x) tk[j] = lr.fold[j];
     }
-    const int g = gridDim.x;
-    const int lw = xcd_swizzle(blockIdx.x, g);
+    const int g = gdim;
+    const int lw = xcd_swizzle(bid, g);
     const int r0 = min(n, lw * rows), r1 = min(n, r0 + rows);
     F* xs = reinterpret_cast<F*>(xwin_lds);
     const int wlo = halo > 0 ? max(0, r0 - halo) : 0;
@@ -395,9 +394,18 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restr
     }
     if (part_dot) {
         const double tot = block_sum(dacc, red);
-        if (threadIdx.x == 0) part_dot[blockIdx.x] = tot;
+        if (threadIdx.x == 0) part_dot[bid] = tot;
     }
 }
+template <typename V, typename F, int G, int U, bool LR>
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, const F* __restrict__ v,
+                                                       const V* __restrict__ x, V* __restrict__ y,
+                                                       double* __restrict__ part_dot, const KrylovState* st,
+                                                       LowRankDev lr, int halo, int rows) {
+    spmv_body<V, F, G, U, LR>(n, rp, ci, v, x, y, part_dot, st, lr, halo, rows, blockIdx.x, gridDim.x);
+}
+
 
 // Entries of the SpMV workgroups' rows whose column lies in the near window
 // [r0 - halo, r1 + halo): count[0] += their number.
@@ -1353,7 +1361,7 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
 }
 
 template <typename V, typename F, int MODE>
-__global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovState* st, int it) {
+__device__ __forceinline__ void bj_body(const BJDev& P, const PcgVecs& Vv, KrylovState* st, int it, int bid) {
     using Bits = typename Sentinel<F>::Bits;
     constexpr int RING = BjRing<F>::size;
     __shared__ Bits ring[RING + 1];
@@ -1366,7 +1374,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
     __shared__ int shd;
     __shared__ int lnl[kTab];
     __shared__ int unl[kTab];
-    const int b = blockIdx.x, t = threadIdx.x;
+    const int b = bid, t = threadIdx.x;
     const int nb = P.nblocks;
     const int lo = P.bp[b], hi = P.bp[b + 1];
     for (int q = t; q < kTab && q <= hi - lo; q += kBjThreads) {
@@ -1437,6 +1445,11 @@ __global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovSt
         if (t == 0) Vv.part_rz[(it & 1) * nb + b] = rz;
     }
 }
+template <typename V, typename F, int MODE>
+__global__ __launch_bounds__(kBjThreads) void k_bj(BJDev P, PcgVecs Vv, KrylovState* st, int it) {
+    bj_body<V, F, MODE>(P, Vv, st, it, blockIdx.x);
+}
+
 
 template <typename V, typename F>
 void launch_bj(int mode, const BJDev& P, const PcgVecs& v, KrylovState* st, int it, hipStream_t s) {
@@ -1462,10 +1475,10 @@ template void launch_bj<float, float>(int, const BJDev&, const PcgVecs&, KrylovS
 // (r, z') = (r, z) - t.s, which holds because the block factors of a
 // symmetric matrix give a symmetric P.  (r, z') is published in rzs[it & 1].
 template <typename T, bool BORDER>
-__global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, const T* __restrict__ z,
-                                                     const double* __restrict__ part_rz,
-                                                     const double* __restrict__ part_rr, int nb, BorderDev bd,
-                                                     KrylovState* st, int it, int mode) {
+__device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* __restrict__ z,
+                                             const double* __restrict__ part_rz, const double* __restrict__ part_rr,
+                                             int nb, const BorderDev& bd, KrylovState* st, int it, int mode, int bid,
+                                             int gdim) {
     __shared__ double red[8];
     __shared__ double ts[64];
     __shared__ double ss[64];
@@ -1477,7 +1490,7 @@ __global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, c
         const bool upd = rr < st->delta2 * st->rr0 ||
                          (st->refine_every > 0 && it + 1 - st->it_refine >= st->refine_every);
         if (conv || upd) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (bid == 0 && threadIdx.x == 0) {
                 st->conv = conv ? 1 : 0;
                 st->update = upd ? 1 : 0;
                 st->iters = it + 1;
@@ -1501,7 +1514,7 @@ __global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, c
     double beta = 0.0;
     if (mode != PUPD_START) beta = rz / st->rzs[(it + 1) & 1];
     if (!isfinite(beta) || !isfinite(rz)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bid == 0 && threadIdx.x == 0) {
             st->breakdown = 1;
             st->iters = it + 1;
             set_done(st);
@@ -1509,9 +1522,9 @@ __global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, c
         return;
     }
     const T bt = (T)beta;
-    const int g = gridDim.x;
+    const int g = gdim;
     const int per = (n + g - 1) / g;
-    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    const int r0 = bid * per, r1 = min(n, r0 + per);
     const double* W = bd.W;
     for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         T zi = z[i];
@@ -1522,16 +1535,28 @@ __global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, c
         }
         p[i] = (mode == PUPD_START) ? zi : zi + bt * p[i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->rzs[it & 1] = rz;
+    if (bid == 0 && threadIdx.x == 0) st->rzs[it & 1] = rz;
+}
+template <typename T, bool BORDER>
+__global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, const T* __restrict__ z,
+                                                     const double* __restrict__ part_rz,
+                                                     const double* __restrict__ part_rr, int nb, BorderDev bd,
+                                                     KrylovState* st, int it, int mode) {
+    pupdate_body<T, BORDER>(n, p, z, part_rz, part_rr, nb, bd, st, it, mode, blockIdx.x, gridDim.x);
+}
+
+
+// one row per thread (every workgroup resident at once up to ~1M rows)
+int pupdate_grid(int n) {
+    int g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    return g < 1 ? 1 : g;
 }
 
 template <typename T>
 void launch_pcg_pupdate(int n, const PcgVecs& v, int nblocks, const BorderDev& bd, KrylovState* st, int it,
                         int mode, hipStream_t s) {
-    // one row per thread (every workgroup resident at once up to ~1M rows)
-    int g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
-    if (g < 1) g = 1;
+    const int g = pupdate_grid(n);
     if (bd.k > 0)
         k_pcg_pupdate<T, true><<<g, 256, 0, s>>>(n, (T*)v.p, (const T*)v.z, v.part_rz, v.part_rr, nblocks, bd, st,
                                                  it, mode);
@@ -1543,6 +1568,71 @@ template void launch_pcg_pupdate<double>(int, const PcgVecs&, int, const BorderD
                                          hipStream_t);
 template void launch_pcg_pupdate<float>(int, const PcgVecs&, int, const BorderDev&, KrylovState*, int, int,
                                         hipStream_t);
+
+// ------------------------------------------------------------------ shared launches
+// The slot that owns workgroup w (slots in launch order; ns is small, and
+// the table sits in the scalar cache after the first workgroups).
+__device__ __forceinline__ int slot_of(const int* __restrict__ pre, int ns, int w) {
+    int s = 0;
+    while (s + 1 < ns && pre[s + 1] <= w) ++s;
+    return s;
+}
+
+template <typename V, typename F, int G>
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv_slots(const int* __restrict__ pre,
+                                                             const SpmvSlot* __restrict__ tab, int ns) {
+    const int s = slot_of(pre, ns, blockIdx.x);
+    const SpmvSlot d = tab[s];
+    const int w = blockIdx.x - pre[s];
+    if (w >= d.grid) return;  // padding to the next multiple of 8
+    const LowRankDev none{};
+    spmv_body<V, F, G, 4, false>(d.n, d.rp, d.ci, (const F*)d.v, (const V*)d.x, (V*)d.y, d.part_dot, d.st, none,
+                                 d.halo, d.rows, w, d.grid);
+}
+
+template <typename V, typename F>
+__global__ __launch_bounds__(kBjThreads) void k_bj_slots(const int* __restrict__ pre, const BjSlot* __restrict__ tab,
+                                                         int ns, int k) {
+    const int s = slot_of(pre, ns, blockIdx.x);
+    const int w = blockIdx.x - pre[s];
+    const BjSlot& d = tab[s];
+    if (w >= d.P.nblocks) return;
+    bj_body<V, F, 1>(d.P, d.Vv, d.st, d.it0 + k, w);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pupdate_slots(const int* __restrict__ pre, const PupdSlot* __restrict__ tab,
+                                                       int ns, int k) {
+    const int s = slot_of(pre, ns, blockIdx.x);
+    const PupdSlot d = tab[s];
+    const int w = blockIdx.x - pre[s];
+    if (w >= d.grid) return;
+    const BorderDev none{};
+    pupdate_body<T, false>(d.n, (T*)d.p, (const T*)d.z, d.part_rz, d.part_rr, d.nb, none, d.st, d.it0 + k,
+                           PUPD_STEP, w, d.grid);
+}
+
+template <typename V, typename F>
+void launch_slots_iteration(const SlotTable& t, int ns, int k, int lanes, const int* wg, size_t shm,
+                            hipStream_t s) {
+    if (ns <= 0) return;
+    constexpr int T = kSpmvThreads;
+    switch (lanes) {
+        case 64: k_spmv_slots<V, F, 64><<<wg[0], T, shm, s>>>(t.spmv_pre, t.spmv, ns); break;
+        case 32: k_spmv_slots<V, F, 32><<<wg[0], T, shm, s>>>(t.spmv_pre, t.spmv, ns); break;
+        case 16: k_spmv_slots<V, F, 16><<<wg[0], T, shm, s>>>(t.spmv_pre, t.spmv, ns); break;
+        case 8: k_spmv_slots<V, F, 8><<<wg[0], T, shm, s>>>(t.spmv_pre, t.spmv, ns); break;
+        default: k_spmv_slots<V, F, 4><<<wg[0], T, shm, s>>>(t.spmv_pre, t.spmv, ns); break;
+    }
+    k_bj_slots<V, F><<<wg[1], kBjThreads, 0, s>>>(t.bj_pre, t.bj, ns, k);
+    k_pupdate_slots<V><<<wg[2], 256, 0, s>>>(t.pu_pre, t.pu, ns, k);
+}
+template void launch_slots_iteration<double, double>(const SlotTable&, int, int, int, const int*, size_t,
+                                                     hipStream_t);
+template void launch_slots_iteration<double, float>(const SlotTable&, int, int, int, const int*, size_t,
+                                                    hipStream_t);
+template void launch_slots_iteration<float, float>(const SlotTable&, int, int, int, const int*, size_t,
+                                                   hipStream_t);
 
 // ------------------------------------------------------------------ BiCGSTAB
 // Vector steps of right-preconditioned BiCGSTAB (van der Vorst 1992; the

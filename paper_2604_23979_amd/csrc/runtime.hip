@@ -46,9 +46,14 @@ struct SolveTask;
 void delete_task(SolveTask* t);
 }  // namespace
 
+struct sdsl_group_s;
+
 struct sdsl_ctx {
     hipStream_t s = nullptr;
     SolveTask* task = nullptr;  // solve started by sdsl_solve_begin
+    sdsl_group_s* defer = nullptr;  // set while a group step collects this handle's iterations
+    bool unflushed = false;         // iterations collected by a group and not yet launched
+    sdsl_group_s* holder = nullptr; // the group holding them
     sdsl_options o{};
     int n = 0, n_int = 0, nbd = 0, nb = 0;
     int64_t nnz = 0;
@@ -709,6 +714,10 @@ struct Pcg {
     // = the batch position of the k-th timed iteration
     std::vector<int> sampled;
     void issue(int count) {
+        if (h->defer && h->lr.k == 0 && h->bd.k == 0) {
+            defer_issue(count);
+            return;
+        }
         const CsrView A{h->n, h->rp, h->ci, h->halo};
         const int period = h->o.kernel_timing;
         batch_start = it;
@@ -737,6 +746,8 @@ struct Pcg {
         }
         h->check_launch();
     }
+    // the same iterations, collected for the shared launches of a group
+    void defer_issue(int count);
     const KrylovState& poll() {
         hip_check(hipMemcpyAsync(h->st_h, h->st, sizeof(KrylovState), hipMemcpyDeviceToHost, h->s), "copy");
         h->sync();
@@ -760,6 +771,260 @@ struct Pcg {
         return *h->st_h;
     }
 };
+
+}  // namespace
+
+// ------------------------------------------------------- shared launches
+// Iterations that handles on one stream asked for during a group step; the
+// flush lays every handle's SpMV, block-Jacobi and p-update grids end to end
+// in one launch per kernel (per vector/factor type and SpMV lane count), so
+// small solves fill the device together and pay one launch per kernel.  Each
+// handle's workgroups see the grid, arguments and iteration index of its own
+// launch, so its arithmetic, and its result, are those of a solve alone.
+struct IssueRec {
+    sdsl_ctx* h;
+    int type;   // 0: FP64 vectors and factors, 1: FP64 vectors / FP32 factors, 2: FP32
+    int lanes;
+    int count;
+    size_t shm;
+    SpmvSlot sp;
+    BjSlot bj;
+    PupdSlot pu;
+};
+
+struct sdsl_group_s {
+    hipStream_t s = nullptr;
+    hipStream_t cap = nullptr;  // capture stream of the iteration graphs (nothing runs on it)
+    bool graphs = false;
+    sdsl_allocator al{};
+    std::vector<IssueRec> recs;
+    char* dev = nullptr;
+    size_t dev_cap = 0;
+    char* stage = nullptr;  // pinned
+    size_t stage_cap = 0;
+    hipEvent_t copied = nullptr;  // the last table copy has read the staging buffer
+    bool copy_pending = false;
+    struct Graph {
+        std::vector<int64_t> key;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    std::vector<Graph> cache;
+    uint64_t tick = 0;
+    sdsl_group_stats stats{};
+
+    ~sdsl_group_s() {
+        if (s) (void)hipStreamSynchronize(s);
+        for (auto& g : cache) (void)hipGraphExecDestroy(g.exec);
+        if (dev) {
+            if (al.alloc) al.free(dev, dev_cap, (void*)s, al.ctx);
+            else (void)hipFree(dev);
+        }
+        if (stage) (void)hipHostFree(stage);
+        if (copied) (void)hipEventDestroy(copied);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+    void drop_graphs() {
+        for (auto& g : cache) (void)hipGraphExecDestroy(g.exec);
+        cache.clear();
+    }
+    void reserve(size_t bytes) {
+        if (copy_pending) {
+            hip_check(hipEventSynchronize(copied), "event synchronize");
+            copy_pending = false;
+        }
+        if (bytes > stage_cap) {
+            if (stage) (void)hipHostFree(stage);
+            stage = nullptr;
+            const size_t c = std::max<size_t>(bytes, 64 << 10);
+            hip_check(hipHostMalloc((void**)&stage, c, hipHostMallocDefault), "pinned alloc");
+            stage_cap = c;
+        }
+        if (bytes > dev_cap) {
+            // graphs hold table addresses: rebuilt on the new table
+            hip_check(hipStreamSynchronize(s), "stream synchronize");
+            drop_graphs();
+            if (dev) {
+                if (al.alloc) al.free(dev, dev_cap, (void*)s, al.ctx);
+                else (void)hipFree(dev);
+            }
+            dev = nullptr;
+            const size_t c = std::max<size_t>(bytes, 64 << 10);
+            void* ptr = nullptr;
+            if (al.alloc) ptr = al.alloc(c, (void*)s, al.ctx);
+            else if (hipMalloc(&ptr, c) != hipSuccess) {
+                (void)hipGetLastError();
+                ptr = nullptr;
+            }
+            if (!ptr) fail(SDSL_E_NOMEM, "device allocation of the slot table failed");
+            dev = (char*)ptr;
+            dev_cap = c;
+        }
+    }
+    static void launch(int type, const SlotTable& t, int ns, int k, int lanes, const int* wg, size_t shm,
+                       hipStream_t st) {
+        if (type == 0) launch_slots_iteration<double, double>(t, ns, k, lanes, wg, shm, st);
+        else if (type == 1) launch_slots_iteration<double, float>(t, ns, k, lanes, wg, shm, st);
+        else launch_slots_iteration<float, float>(t, ns, k, lanes, wg, shm, st);
+    }
+    void flush();
+};
+
+namespace {
+template <typename V, typename F>
+void Pcg<V, F>::defer_issue(int count) {
+    IssueRec rec{};
+    rec.h = h;
+    rec.type = sizeof(V) == 4 ? 2 : (sizeof(F) == 4 ? 1 : 0);
+    rec.lanes = h->lanes;
+    rec.count = count;
+    const int rows = spmv_rows(h->n, h->grid);
+    rec.shm = h->halo > 0 ? (size_t)(rows + 2 * h->halo) * sizeof(F) : 0;
+    rec.sp = SpmvSlot{h->n, h->halo, rows, h->grid, h->rp, h->ci, v, p, q, h->part_pq, h->st};
+    rec.bj.P = P;
+    rec.bj.Vv = Vv;
+    rec.bj.st = h->st;
+    rec.bj.it0 = it;
+    rec.pu = PupdSlot{h->n, h->nb, pupdate_grid(h->n), it, p, z, h->part_rz, h->part_rr, h->st};
+    h->defer->recs.push_back(rec);
+    h->unflushed = true;
+    h->holder = h->defer;
+    batch_start = it;
+    batch_count = count;
+    sampled.clear();
+    it += count;
+}
+}  // namespace
+
+void sdsl_group_s::flush() {
+    if (recs.empty()) return;
+    // groups of one kernel instantiation, in first-appearance order; in a
+    // group the slots go by decreasing iteration count, so that the slots
+    // still iterating at offset k are a prefix of the table
+    std::vector<std::vector<int>> parts;
+    for (int i = 0; i < (int)recs.size(); ++i) {
+        bool put = false;
+        for (auto& g : parts)
+            if (recs[g[0]].type == recs[i].type && recs[g[0]].lanes == recs[i].lanes) {
+                g.push_back(i);
+                put = true;
+                break;
+            }
+        if (!put) parts.push_back({i});
+    }
+    for (auto& g : parts)
+        std::stable_sort(g.begin(), g.end(), [&](int a, int b) { return recs[a].count > recs[b].count; });
+    auto up = [](size_t x) { return (x + 63) / 64 * 64; };
+    size_t bytes = 0;
+    std::vector<size_t> base(parts.size());
+    for (size_t gi = 0; gi < parts.size(); ++gi) {
+        const size_t ns = parts[gi].size();
+        base[gi] = bytes;
+        bytes += up(3 * (ns + 1) * sizeof(int)) + up(ns * sizeof(SpmvSlot)) + up(ns * sizeof(BjSlot)) +
+                 up(ns * sizeof(PupdSlot));
+    }
+    reserve(bytes);
+    std::vector<SlotTable> tabs(parts.size());
+    std::vector<std::vector<int>> pres(parts.size());
+    for (size_t gi = 0; gi < parts.size(); ++gi) {
+        const auto& g = parts[gi];
+        const int ns = (int)g.size();
+        char* hb = stage + base[gi];
+        char* db = dev + base[gi];
+        int* pre = (int*)hb;  // spmv_pre | bj_pre | pu_pre
+        pre[0] = pre[ns + 1] = pre[2 * (ns + 1)] = 0;
+        for (int i = 0; i < ns; ++i) {
+            const IssueRec& r = recs[g[i]];
+            pre[i + 1] = pre[i] + (r.sp.grid + 7) / 8 * 8;
+            pre[ns + 1 + i + 1] = pre[ns + 1 + i] + r.bj.P.nblocks;
+            pre[2 * (ns + 1) + i + 1] = pre[2 * (ns + 1) + i] + r.pu.grid;
+        }
+        size_t off = up(3 * (ns + 1) * sizeof(int));
+        SpmvSlot* sp = (SpmvSlot*)(hb + off);
+        const size_t o_sp = off;
+        off += up(ns * sizeof(SpmvSlot));
+        BjSlot* bj = (BjSlot*)(hb + off);
+        const size_t o_bj = off;
+        off += up(ns * sizeof(BjSlot));
+        PupdSlot* pu = (PupdSlot*)(hb + off);
+        const size_t o_pu = off;
+        for (int i = 0; i < ns; ++i) {
+            sp[i] = recs[g[i]].sp;
+            bj[i] = recs[g[i]].bj;
+            pu[i] = recs[g[i]].pu;
+        }
+        tabs[gi] = SlotTable{(const int*)db, (const SpmvSlot*)(db + o_sp), (const int*)db + (ns + 1),
+                             (const BjSlot*)(db + o_bj), (const int*)db + 2 * (ns + 1), (const PupdSlot*)(db + o_pu)};
+        pres[gi].assign(pre, pre + 3 * (ns + 1));
+    }
+    hip_check(hipMemcpyAsync(dev, stage, bytes, hipMemcpyHostToDevice, s), "copy");
+    hip_check(hipEventRecord(copied, s), "event record");
+    copy_pending = true;
+    for (size_t gi = 0; gi < parts.size(); ++gi) {
+        const auto& g = parts[gi];
+        const int ns = (int)g.size();
+        const IssueRec& r0 = recs[g[0]];
+        size_t shm = 0;
+        for (int i : g) shm = std::max(shm, recs[i].shm);
+        const int* pre = pres[gi].data();
+        auto issue_all = [&](hipStream_t st) {
+            int live = ns;
+            for (int k = 0; k < r0.count; ++k) {
+                while (live > 0 && recs[g[live - 1]].count <= k) --live;
+                const int wg[3] = {pre[live], pre[ns + 1 + live], pre[2 * (ns + 1) + live]};
+                launch(r0.type, tabs[gi], live, k, r0.lanes, wg, shm, st);
+            }
+        };
+        stats.flushes += 1;
+        stats.slot_issues += ns;
+        stats.launches += 3 * (int64_t)r0.count;
+        if (!graphs) {
+            issue_all(s);
+            hip_check(hipGetLastError(), "kernel launch");
+            continue;
+        }
+        // the graph of this shape: the kernels read the table, so only the
+        // layout (types, counts, grids, window, table address) is its key
+        std::vector<int64_t> key{r0.type, r0.lanes, ns, (int64_t)shm, (int64_t)(intptr_t)(dev + base[gi])};
+        for (int i : g) key.push_back(recs[i].count);
+        for (int q = 0; q < 3 * (ns + 1); ++q) key.push_back(pre[q]);
+        Graph* hit = nullptr;
+        for (auto& c : cache)
+            if (c.key == key) hit = &c;
+        if (!hit) {
+            if (cache.size() >= 16) {
+                auto lru = std::min_element(cache.begin(), cache.end(),
+                                            [](const Graph& a, const Graph& b) { return a.used < b.used; });
+                (void)hipGraphExecDestroy(lru->exec);
+                cache.erase(lru);
+            }
+            hipGraph_t graph = nullptr;
+            hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
+            issue_all(cap);
+            const hipError_t le = hipGetLastError();
+            const hipError_t ce = hipStreamEndCapture(cap, &graph);
+            hip_check(le, "kernel launch under capture");
+            hip_check(ce, "end capture");
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            hip_check(ie, "graph instantiate");
+            cache.push_back(Graph{key, exec, 0});
+            hit = &cache.back();
+            stats.captures += 1;
+        }
+        hit->used = ++tick;
+        hip_check(hipGraphLaunch(hit->exec, s), "graph launch");
+        stats.graph_launches += 1;
+    }
+    for (auto& r : recs) {
+        r.h->unflushed = false;
+        r.h->holder = nullptr;
+    }
+    recs.clear();
+}
+
+namespace {
 
 // sum of a device partial array into scal[idx], then copied to the host
 double reduce_to_host(sdsl_ctx* h, const double* part, int m, int idx) {
@@ -1797,6 +2062,7 @@ sdsl_status sdsl_solve_step(sdsl_handle h, int32_t* done) {
     *done = 0;
     return guard(h, [&] {
         if (!h->task) fail(SDSL_E_STATE, "no solve was begun on this handle");
+        if (h->unflushed) fail(SDSL_E_STATE, "the solve's first iterations wait for its group's next step");
         SolveTask& t = *h->task;
         if (!t.finished) {
             const hipError_t q = hipStreamQuery(h->s);
@@ -1863,6 +2129,94 @@ sdsl_status sdsl_solve_batch(int32_t k, const sdsl_handle* hs, const double* con
     return first;
 }
 
+sdsl_status sdsl_group_create(void* hip_stream, int32_t use_graphs, const sdsl_allocator* al, sdsl_group* out) {
+    if (!out) return SDSL_E_INVALID;
+    *out = nullptr;
+    if (al && (!al->alloc) != (!al->free)) return SDSL_E_INVALID;
+    sdsl_group g = nullptr;
+    sdsl_status st = guard(nullptr, [&] {
+        g = new sdsl_group_s();
+        g->s = (hipStream_t)hip_stream;
+        g->graphs = use_graphs != 0;
+        if (al) g->al = *al;
+        hip_check(hipEventCreateWithFlags(&g->copied, hipEventDisableTiming), "event create");
+        if (g->graphs) hip_check(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking), "stream create");
+    });
+    if (st != SDSL_OK) {
+        delete g;
+        return st;
+    }
+    *out = g;
+    return SDSL_OK;
+}
+
+sdsl_status sdsl_group_begin(sdsl_group g, sdsl_handle h, const double* b, double* x, double tol) {
+    if (!g || !h) return SDSL_E_INVALID;
+    return guard(h, [&] {
+        if (!b || !x) fail(SDSL_E_INVALID, "null vector");
+        if (!(tol > 0.0)) fail(SDSL_E_INVALID, "tol must be positive");
+        if (h->s != g->s) fail(SDSL_E_INVALID, "the handle runs on another stream than the group");
+        check_idle(h);
+        if (h->task) delete_task(h->task);
+        h->task = new SolveTask();
+        h->defer = g;
+        try {
+            h->task->begin(h, b, x, tol);
+        } catch (...) {
+            h->defer = nullptr;
+            throw;
+        }
+        h->defer = nullptr;
+    });
+}
+
+sdsl_status sdsl_group_step(sdsl_group g, int32_t k, const sdsl_handle* hs, int32_t* done) {
+    if (!g || k < 0 || (k > 0 && (!hs || !done))) return SDSL_E_INVALID;
+    sdsl_status first = SDSL_OK;
+    for (int i = 0; i < k; ++i) {
+        done[i] = 0;
+        sdsl_handle h = hs[i];
+        if (!h) {
+            if (first == SDSL_OK) first = SDSL_E_INVALID;
+            continue;
+        }
+        const sdsl_status st = guard(h, [&] {
+            for (int j = 0; j < i; ++j)
+                if (hs[j] == h) fail(SDSL_E_STATE, "the same handle appears twice in one group step");
+            if (h->s != g->s) fail(SDSL_E_INVALID, "the handle runs on another stream than the group");
+            if (!h->task) fail(SDSL_E_STATE, "no solve was begun on this handle");
+            SolveTask& t = *h->task;
+            // iterations collected by sdsl_group_begin go out with this step's
+            if (!t.finished && !h->unflushed) {
+                h->defer = g;
+                try {
+                    t.step();
+                } catch (...) {
+                    h->defer = nullptr;
+                    throw;
+                }
+                h->defer = nullptr;
+            }
+            done[i] = t.finished ? 1 : 0;
+        });
+        if (st != SDSL_OK && first == SDSL_OK) first = st;
+    }
+    const sdsl_status fs = guard(nullptr, [&] { g->flush(); });
+    return first != SDSL_OK ? first : fs;
+}
+
+sdsl_status sdsl_group_get_stats(sdsl_group g, sdsl_group_stats* out) {
+    if (!g || !out) return SDSL_E_INVALID;
+    *out = g->stats;
+    return SDSL_OK;
+}
+
+void sdsl_group_destroy(sdsl_group g) {
+    if (!g) return;
+    (void)guard(nullptr, [&] { g->flush(); });
+    delete g;
+}
+
 sdsl_status sdsl_get_info(sdsl_handle h, sdsl_info* out) {
     if (!h || !out) return SDSL_E_INVALID;
     *out = h->info;
@@ -1872,7 +2226,15 @@ sdsl_status sdsl_get_info(sdsl_handle h, sdsl_info* out) {
 
 const char* sdsl_last_error(sdsl_handle h) { return h ? h->err.c_str() : g_thread_err.c_str(); }
 
-void sdsl_destroy(sdsl_handle h) { delete h; }
+void sdsl_destroy(sdsl_handle h) {
+    if (!h) return;
+    if (h->unflushed && h->holder) {
+        // iterations a group still holds for this handle are dropped
+        auto& v = h->holder->recs;
+        v.erase(std::remove_if(v.begin(), v.end(), [&](const IssueRec& r) { return r.h == h; }), v.end());
+    }
+    delete h;
+}
 
 sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y) {
     if (!h) return SDSL_E_INVALID;

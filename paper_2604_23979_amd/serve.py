@@ -2,12 +2,17 @@
 
 Continuous batching: a request is admitted as soon as it has arrived, a slot
 is free and its predicted device footprint (``sdsl_footprint_bytes``) fits
-the free HBM (or an artificial budget); every admitted request gets its own
-HIP stream and resident preconditioner, and the loop advances all of them
-with the non-blocking ``sdsl_solve_step``, so their kernels overlap on the
-device and new requests join while others are still iterating.  A finished
-request releases its slot and memory at once.  Latency counts from arrival
-to completion (queueing, setup and solve)."""
+the free HBM (or an artificial budget); every admitted request gets a
+resident preconditioner, and new requests join while others are still
+iterating.  A finished request releases its slot and memory at once.
+
+Shared mode (the default): every request's handle lives on one stream and a
+``Group`` advances them together, so each PCG iteration of all running
+requests is one launch per kernel (replayed from a HIP graph once a shape
+repeats); each result is bitwise the one a solve alone gives.  Stream mode:
+one stream per request, advanced with the non-blocking ``sdsl_solve_step``,
+so the requests' kernels overlap only as far as the hardware queues allow.
+Latency counts from arrival to completion (queueing, setup and solve)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -64,10 +69,14 @@ class Server:
     """Runs a list of requests to completion; ``stats()`` summarises."""
 
     def __init__(self, options: Optional[B.Options] = None, tol: float = 1e-8, max_active: int = 8,
-                 budget_bytes: Optional[int] = None, reserve_bytes: int = 1 << 30):
+                 budget_bytes: Optional[int] = None, reserve_bytes: int = 1 << 30, shared: bool = True,
+                 graphs: bool = True):
         self.options = options or B.Options(precision=B.FP32_IR)
         self.tol = tol
         self.max_active = max_active
+        self.shared = shared
+        self.graphs = graphs
+        self.group_stats = None
         self.budget = budget_bytes
         self.reserve = reserve_bytes
         self.done: list[Request] = []
@@ -85,6 +94,74 @@ class Server:
         return avail
 
     def run(self, requests: list[Request]) -> list[Request]:
+        if self.shared:
+            return self._run_shared(requests)
+        return self._run_streams(requests)
+
+    def _admit(self, pending, active, used, now):
+        """Requests that may start now (arrived, a slot and memory free)."""
+        out = []
+        while pending and pending[0].arrival <= now and len(active) + len(out) < self.max_active:
+            req = pending[0]
+            need = footprint(req.system, self.options)
+            if need > self._free_bytes(used):
+                if active or out:
+                    self.waited_for_memory += 1
+                    break          # wait until a running request frees memory
+                raise MemoryError(f"request {req.tag} needs {need} bytes, more than the device can give")
+            pending.popleft()
+            out.append((req, need))
+            used += need
+        return out, used
+
+    def _run_shared(self, requests: list[Request]) -> list[Request]:
+        import torch
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        stream = torch.cuda.Stream()
+        group = B.Group(stream, graphs=self.graphs)
+        active = []      # (request, solver, b, bytes)
+        used = 0
+        self.t_start = time.perf_counter()
+        try:
+            while pending or active:
+                now = time.perf_counter() - self.t_start
+                admit, used = self._admit(pending, active, used, now)
+                for req, need in admit:
+                    with torch.cuda.stream(stream):
+                        b = torch.as_tensor(np.ascontiguousarray(req.system.b), device="cuda:0")
+                        x = torch.empty_like(b)
+                    solver = B.Solver(req.system.row_ptr, req.system.col, req.system.val, req.system.block_ptr,
+                                      n_border=getattr(req.system, "n_border", 0),
+                                      lowrank=getattr(req.system, "lowrank", None), options=self.options,
+                                      stream=stream)
+                    group.begin(solver, b, x, self.tol)
+                    req.admitted = time.perf_counter() - self.t_start
+                    active.append((req, solver, b, need))
+                    self.max_concurrency = max(self.max_concurrency, len(active))
+                if active:
+                    done = group.step([a[1] for a in active])
+                    still = []
+                    for item, d in zip(active, done):
+                        req, solver, b, need = item
+                        if d:
+                            req.x, req.iters, req.relres, req.status = solver.solve_end()
+                            req.finished = time.perf_counter() - self.t_start
+                            solver.close()
+                            used -= need
+                            self.done.append(req)
+                        else:
+                            still.append(item)
+                    active = still
+                elif pending and pending[0].arrival > now:
+                    time.sleep(min(0.001, pending[0].arrival - now))
+            stream.synchronize()
+        finally:
+            self.group_stats = group.stats()
+            group.close()
+        self.t_end = time.perf_counter() - self.t_start
+        return self.done
+
+    def _run_streams(self, requests: list[Request]) -> list[Request]:
         import torch
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         active = []      # (request, solver, stream, b, bytes)
@@ -142,4 +219,6 @@ class Server:
                 "solves_per_s": len(self.done) / self.t_end if self.t_end > 0 else 0.0,
                 "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
                 "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
-                "max_concurrency": self.max_concurrency, "waited_for_memory": self.waited_for_memory}
+                "max_concurrency": self.max_concurrency, "waited_for_memory": self.waited_for_memory,
+                "shared_launches": self.shared, "graphs": self.shared and self.graphs,
+                "group": self.group_stats}

@@ -1023,10 +1023,12 @@ def test_bbd_rejects_block_coupling(row, col):
 
 # ------------------------------------------------------------------ serving
 
-def test_serving_mix_equals_alone():
+@pytest.mark.parametrize("mode", ["shared-graphs", "shared", "streams"])
+def test_serving_mix_equals_alone(mode):
     """Continuous batching: requests of different sizes admitted while
-    others run, each on its own stream; every result is bitwise the one the
-    same request gets when solved alone."""
+    others run (shared launches on one stream, with or without graph replay,
+    or one stream per request); every result is bitwise the one the same
+    request gets when solved alone."""
     from paper_2604_23979_amd.serve import Request, Server
     reqs = gen.c5_requests(count=6, seed=3, m_lo=3000, m_hi=30000)
     systems = [gen.c5_system(r) for r in reqs]
@@ -1037,16 +1039,113 @@ def test_serving_mix_equals_alone():
         x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
         alone.append((x.cpu().numpy(), its, st))
         sv.close()
-    srv = Server(options=o, tol=1e-8, max_active=4)
+    srv = Server(options=o, tol=1e-8, max_active=4, shared=mode != "streams", graphs=mode == "shared-graphs")
     done = srv.run([Request(s, arrival=0.002 * i, tag=i) for i, s in enumerate(systems)])
     stats = srv.stats()
-    print(f"  serving: {stats}")
+    print(f"  serving ({mode}): {stats}")
     assert stats["requests"] == len(systems) and stats["max_concurrency"] >= 2
+    if mode != "streams":
+        g = stats["group"]
+        assert g["slot_issues"] > g["flushes"] > 0           # launches were shared
+        assert (g["graph_launches"] > g["captures"] > 0) == (mode == "shared-graphs")
     for r in done:
         xa, its_a, st_a = alone[r.tag]
         assert r.status == st_a == sd.OK and r.iters == its_a
         assert np.array_equal(r.x.cpu().numpy(), xa)
         assert O.relres(systems[r.tag], xa) <= 1e-8
+
+
+@pytest.mark.parametrize("graphs", [True, False], ids=["graphs", "launches"])
+def test_group_steps_equal_solo_solves(graphs):
+    """A group advancing handles of every kind on one stream: FP64 PCG,
+    FP32-inner PCG, classical refinement (their PCG iterations share
+    launches), a low-rank handle and a GMRES handle (stepped on their own);
+    solves begin at different steps and end at different steps.  Every
+    result (solution, iterations, residual) is bitwise that of a solve alone."""
+    geo = dict(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    cases = [
+        ("c1-fp64", gen.c1(), opts()),
+        ("ragged-fp64", ragged_system(), opts()),
+        ("c2-fp32ir", gen.c2(0.004, dense_cols=0), opts(precision=sd.FP32_IR, **geo)),
+        ("c1-restart", gen.c1(), opts(precision=sd.FP32_IR_RESTART)),
+        ("ragged2-fp32ir", ragged_system(n=5000, nblocks=9, seed=7), opts(precision=sd.FP32_IR)),
+        ("c2-lowrank", gen.c2(0.004), opts(**geo)),
+        ("gmres", nonsym_system(), opts(krylov=sd.GMRES, spd=False)),
+    ]
+    solo = {}
+    for name, s, o in cases:
+        sv = sd.from_system(s, o)
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        solo[name] = (x.cpu(), its, rr, st)
+        sv.close()
+    stream = torch.cuda.Stream()
+    grp = sd.Group(stream, graphs=graphs)
+    svs, bufs = {}, {}
+    for name, s, o in cases:
+        svs[name] = sd.from_system(s, o, stream=stream)
+        with torch.cuda.stream(stream):
+            bufs[name] = (tdev(s.b), torch.empty(s.n, dtype=torch.float64, device=DEV))
+    running, results, steps = [], {}, 0
+    late = {name: 3 * i for i, (name, _, _) in enumerate(cases)}   # staggered joins
+    while len(results) < len(cases):
+        for name in [n for n, at in late.items() if at == steps]:
+            b, x = bufs[name]
+            if steps % 2:
+                grp.begin(svs[name], b, x, 1e-8)
+            else:
+                svs[name].solve_begin(b, x, 1e-8)
+            running.append(name)
+        if running:
+            done = grp.step([svs[n] for n in running])
+            for n, d in zip(list(running), done):
+                if d:
+                    results[n] = svs[n].solve_end()
+                    running.remove(n)
+        steps += 1
+        assert steps < 100_000
+    stream.synchronize()
+    st_g = grp.stats()
+    print(f"  group stats ({'graphs' if graphs else 'launches'}): {st_g}")
+    for name, _, _ in cases:
+        x, its, rr, st = results[name]
+        xs, its_s, rr_s, st_s = solo[name]
+        assert st == st_s == sd.OK and its == its_s and rr == rr_s, name
+        assert torch.equal(x.cpu(), xs), name
+    assert st_g["slot_issues"] > st_g["flushes"] > 0
+    assert (st_g["graph_launches"] > 0) == graphs
+    for sv in svs.values():
+        sv.close()
+    grp.close()
+
+
+def test_group_refuses_misuse():
+    """A handle on another stream and a handle with no running solve are
+    refused (the others in the step still advance); a solve begun in a group
+    cannot be stepped alone before the group's next step."""
+    s = gen.c1()
+    stream = torch.cuda.Stream()
+    grp = sd.Group(stream)
+    a = sd.from_system(s, stream=stream)
+    other = sd.from_system(s)                     # default stream
+    b = tdev(s.b)
+    x = torch.empty_like(b)
+    with pytest.raises(sd.SdslError) as e:
+        grp.begin(other, b, x)
+    assert e.value.status == sd.E_INVALID
+    with pytest.raises(sd.SdslError) as e:
+        grp.step([a])                             # nothing begun
+    assert e.value.status == sd.E_STATE
+    grp.begin(a, b, x)
+    with pytest.raises(sd.SdslError) as e:
+        a.solve_step()
+    assert e.value.status == sd.E_STATE
+    while not grp.step([a])[0]:
+        pass
+    _, its, rr, st = a.solve_end()
+    assert st == sd.OK and rr <= 1e-8
+    for h in (a, other):
+        h.close()
+    grp.close()
 
 
 def test_async_solve_equals_solve():
