@@ -161,6 +161,21 @@ typedef struct {
     int32_t refine_every;  /* FP32_IR: iterations after which a refinement
                               point is taken regardless of the reduction;
                               FP32_IR_RESTART: cap of one inner solve        */
+    int32_t mc64;          /* 1: MC64 matching and scaling first (Sec. 3.3,
+                              Alg. 3): the handle holds A' = Q Dr A Dc, whose
+                              matched entries (largest diagonal product) sit
+                              on the diagonal with magnitude 1 and no entry
+                              is larger; filter, correction and factors are
+                              built from A'; a solve takes b' = Q Dr b and
+                              returns x = Dc y (relres and the tolerance are
+                              those of A' y = b').  spd = 1: the matching of
+                              an SPD matrix is the identity and the symmetric
+                              scaling is 1 / sqrt(a_ii) (no permutation).
+                              Block Jacobi without a low-rank term only; the
+                              matrix must be readable on the host (a device
+                              matrix is copied); refactor / update_values
+                              take values of A and reuse the matching.
+                              spmv, precond_apply and residual act on A'.    */
 } sdsl_options;
 
 typedef struct {
@@ -206,13 +221,14 @@ typedef struct {
     int32_t rf_act[64];
     int32_t rf_flag[64];
     double rf_nb;
+    int32_t mc64_moved;     /* MC64: rows matched to another column than their own */
 } sdsl_info;
 #define SDSL_RF_HISTORY 64
 
 /* Fills *o with defaults: BJ, no filter, no correction, SHIFT(1e-2), SPD,
  * PCG, restart 30, max_iter 100000, FP64, inner_tol 1e-4, max_outer 30,
  * check_every 16, kernel_timing 0, border 1, refine_delta 0.1,
- * refine_every 500. */
+ * refine_every 500, mc64 0. */
 void sdsl_default_options(sdsl_options* o);
 
 /* Device-memory provider of a handle (PyTorch's caching allocator in the
@@ -389,6 +405,12 @@ sdsl_status sdsl_residual_noalloc(sdsl_handle h, const double* b, const double* 
  * shifts[nblocks] (relative shift used per block). */
 sdsl_status sdsl_get_factors(sdsl_handle h, int64_t* row_ptr, int32_t* col, double* corrected,
                              double* lu, double* shifts);
+
+/* MC64 data of a handle set up with mc64 = 1 (HOST arrays of n entries):
+ * row_of[k] = the row of A at row k of A' (Q), row_scale = dr (per row of
+ * A), col_scale = dc (per column).  Any pointer may be NULL.  SDSL_E_STATE
+ * when the handle has no MC64 transform. */
+sdsl_status sdsl_get_mc64(sdsl_handle h, int32_t* row_of, double* row_scale, double* col_scale);
 
 /* BBD only (Sec. 2.4): copies the dense border Schur complement's LU
  * factors with partial pivoting (row-major n_border x n_border, strict

@@ -89,6 +89,8 @@ def _declare(L):
     L.or_gcr_bj.restype = C.c_int
     L.or_gcr_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
     L.or_gcr_bbd.restype = C.c_int
+    L.or_mc64.argtypes = [I64, P, P, P, P, P, P]
+    L.or_mc64.restype = C.c_int
     L.or_gmres_bbd.argtypes = [I64, P, P, P, P, P, P, D, I32, I32, P, P, P]
     L.or_gmres_bbd.restype = C.c_int
     L.or_ir_pcg_bj.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, P, I32, P, P, P, P, D, D, I32, I32,
@@ -502,3 +504,46 @@ def dense_lu_solve(lu, piv, b):
     b = np.ascontiguousarray(b, dtype=np.float64).copy()
     lib().or_dense_lu_solve(lu.shape[0], _p(np.ascontiguousarray(lu)), _p(piv), _p(b))
     return b
+
+
+def mc64(sys_):
+    """MC64 maximum-product matching and scaling (Sec. 3.3, Alg. 3 step 1).
+    Returns (match, dr, dc, status): row i is matched to column match[i];
+    |dr_i a_ij dc_j| <= 1 with equality on the matching."""
+    rp, ci, v = _csr(sys_.row_ptr, sys_.col, sys_.val)
+    n = sys_.n
+    match = np.empty(n, dtype=np.int32)
+    dr = np.empty(n)
+    dc = np.empty(n)
+    st = lib().or_mc64(n, _p(rp), _p(ci), _p(v), _p(match), _p(dr), _p(dc))
+    return match, dr, dc, st
+
+
+def mc64_transform(sys_, match, dr, dc, spd=False):
+    """The system Alg. 3 hands to the preconditioner and the Krylov method:
+    A' = Q Dr A Dc, row i moved to position match[i], with right-hand side
+    b' = Q Dr b and x = Dc y.  spd: the symmetric form S A S with
+    s = sqrt(dr dc) (the matching of a symmetric positive definite matrix is
+    the identity), b' = S b and x = S y.  Returns (System A', x_of_y)."""
+    import scipy.sparse as sp
+    M = sp.csr_matrix((np.asarray(sys_.val, dtype=np.float64), np.asarray(sys_.col),
+                       np.asarray(sys_.row_ptr)), shape=(sys_.n, sys_.n))
+    b = np.asarray(sys_.b, dtype=np.float64)
+    if spd:
+        if not np.array_equal(match, np.arange(sys_.n)):
+            raise ValueError("a symmetric positive definite matrix matches every row to its own column")
+        s = np.sqrt(dr * dc)
+        A2 = (sp.diags(s) @ M @ sp.diags(s)).tocsr()
+        b2 = s * b
+        x_of = (lambda y, s=s: s * np.asarray(y))
+    else:
+        Q = sp.csr_matrix((np.ones(sys_.n), (match, np.arange(sys_.n))), shape=(sys_.n, sys_.n))
+        A2 = (Q @ sp.diags(dr) @ M @ sp.diags(dc)).tocsr()
+        b2 = np.empty(sys_.n)
+        b2[match] = dr * b
+        x_of = (lambda y, dc=dc: dc * np.asarray(y))
+    A2.sort_indices()
+    out = type(sys_)(sys_.name + "-mc64", A2.indptr.astype(np.int64), A2.indices.astype(np.int32), A2.data, b2,
+                     sys_.block_ptr, n_border=getattr(sys_, "n_border", 0))
+    return out, x_of
+

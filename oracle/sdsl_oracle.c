@@ -1479,3 +1479,78 @@ done:
     free(r); free(z); free(p); free(q); free(xs); free(zs); free(S.v); free(S.pv); free(xr);
     return st;
 }
+
+/* ------------------------------------------------------------------ */
+/* MC64 matching and scaling (paper Sec. 3.3, Alg. 3 step 1; Duff and  */
+/* Koster, SIAM J. Matrix Anal. Appl. 22 (2001) 973, the maximum-product */
+/* option): a row-to-column matching sigma that maximises the product of */
+/* |a_{i,sigma(i)}|, found as the minimum-cost assignment with costs      */
+/* c_ij = log(max_k |a_kj|) - log|a_ij| on the nonzeros (absent entries   */
+/* cost "infinity").  The assignment's dual variables u (rows), v         */
+/* (columns), with c_ij - u_i - v_j >= 0 and equality on the matching,    */
+/* give the scalings dr_i = exp(u_i), dc_j = exp(v_j) / max_k |a_kj|:    */
+/* every |dr_i a_ij dc_j| <= 1 and the matched ones equal 1.              */
+/* The assignment here is the dense O(n^3) Hungarian method with row and  */
+/* column potentials (Kuhn; the shortest-augmenting-path form), adding    */
+/* rows one at a time; it is meant for the small test systems.            */
+/* Returns 0, or OR_STRUCTURE when no matching uses nonzeros only.        */
+/* ------------------------------------------------------------------ */
+int or_mc64(int64_t n, const int64_t* rp, const int32_t* ci, const double* v, int32_t* match, double* dr,
+            double* dc) {
+    const double BIG = 1e100;
+    double* colmax = calloc(n, 8);
+    double* c = malloc((size_t)n * n * 8);   /* c[i*n + j] */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (fabs(v[p]) > colmax[ci[p]]) colmax[ci[p]] = fabs(v[p]);
+    for (int64_t q = 0; q < n * n; ++q) c[q] = BIG;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (v[p] != 0.0) c[i * n + ci[p]] = log(colmax[ci[p]]) - log(fabs(v[p]));
+    /* potentials u (rows 1..n), w (columns 1..n); owner[j] = row matched to
+       column j (0: none); index 0 is the virtual start column */
+    double* u = calloc(n + 1, 8);
+    double* w = calloc(n + 1, 8);
+    double* mins = malloc((n + 1) * 8);
+    int64_t* owner = calloc(n + 1, 8);
+    int64_t* from = calloc(n + 1, 8);
+    char* used = malloc(n + 1);
+    for (int64_t i = 1; i <= n; ++i) {
+        owner[0] = i;
+        int64_t j0 = 0;
+        for (int64_t j = 0; j <= n; ++j) { mins[j] = INFINITY; used[j] = 0; }
+        do {
+            used[j0] = 1;
+            const int64_t i0 = owner[j0];
+            double delta = INFINITY;
+            int64_t j1 = 0;
+            for (int64_t j = 1; j <= n; ++j) {
+                if (used[j]) continue;
+                const double cur = c[(i0 - 1) * n + (j - 1)] - u[i0] - w[j];
+                if (cur < mins[j]) { mins[j] = cur; from[j] = j0; }
+                if (mins[j] < delta) { delta = mins[j]; j1 = j; }
+            }
+            for (int64_t j = 0; j <= n; ++j) {
+                if (used[j]) { u[owner[j]] += delta; w[j] -= delta; }
+                else mins[j] -= delta;
+            }
+            j0 = j1;
+        } while (owner[j0] != 0);
+        do {  /* flip the augmenting path */
+            const int64_t j1 = from[j0];
+            owner[j0] = owner[j1];
+            j0 = j1;
+        } while (j0);
+    }
+    int st = OR_OK;
+    for (int64_t j = 1; j <= n; ++j) {
+        const int64_t i = owner[j] - 1;
+        match[i] = (int32_t)(j - 1);
+        if (c[i * n + (j - 1)] >= BIG / 2) st = OR_STRUCTURE;
+    }
+    for (int64_t i = 0; i < n; ++i) dr[i] = exp(u[i + 1]);
+    for (int64_t j = 0; j < n; ++j) dc[j] = colmax[j] > 0.0 ? exp(w[j + 1]) / colmax[j] : 1.0;
+    free(colmax); free(c); free(u); free(w); free(mins); free(owner); free(from); free(used);
+    return st;
+}
+

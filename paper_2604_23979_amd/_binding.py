@@ -55,7 +55,7 @@ class COptions(C.Structure):
                 ("krylov", C.c_int), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("kernel_timing", C.c_int32), ("border", C.c_int32), ("refine_delta", C.c_double),
-                ("refine_every", C.c_int32)]
+                ("refine_every", C.c_int32), ("mc64", C.c_int32)]
 
 
 class CInfo(C.Structure):
@@ -67,7 +67,7 @@ class CInfo(C.Structure):
                 ("spmv_launches", C.c_int64 * 2), ("bj_ms", C.c_double * 2), ("bj_launches", C.c_int64 * 2),
                 ("spmv_bytes", C.c_int64 * 2), ("bj_bytes", C.c_int64 * 2), ("rf_count", C.c_int32),
                 ("rf_it", C.c_int32 * 64), ("rf_nr", C.c_double * 64), ("rf_act", C.c_int32 * 64),
-                ("rf_flag", C.c_int32 * 64), ("rf_nb", C.c_double)]
+                ("rf_flag", C.c_int32 * 64), ("rf_nb", C.c_double), ("mc64_moved", C.c_int32)]
 
 
 class Allocator(C.Structure):
@@ -147,6 +147,7 @@ SIGNATURES = {
     "sdsl_residual_noalloc": (C.c_int, [H, P, P, P, C.POINTER(C.c_double)]),
     "sdsl_get_factors": (C.c_int, [H, P, P, P, P, P]),
     "sdsl_get_schur": (C.c_int, [H, P, P, P]),
+    "sdsl_get_mc64": (C.c_int, [H, P, P, P]),
     "sdsl_solve_begin": (C.c_int, [H, P, P, C.c_double]),
     "sdsl_solve_step": (C.c_int, [H, P]),
     "sdsl_solve_end": (C.c_int, [H, P, P]),
@@ -196,6 +197,7 @@ class Options:
     border: bool = True
     refine_delta: float = 0.1
     refine_every: int = 500
+    mc64: bool = False
 
     def c(self) -> COptions:
         o = COptions()
@@ -394,6 +396,17 @@ class Solver:
         _check(self.h, lib().sdsl_get_schur(self.h, lu.ctypes.data_as(C.c_void_p), piv.ctypes.data_as(C.c_void_p),
                                             inv.ctypes.data_as(C.c_void_p)))
         return lu, piv, inv
+
+    def mc64(self):
+        """(row_of, row_scale, col_scale) of a handle set up with mc64: row k
+        of A' is row row_of[k] of A, scaled by row_scale of that row; column
+        j is scaled by col_scale[j]."""
+        row_of = np.empty(self.n, dtype=np.int32)
+        dr = np.empty(self.n)
+        dc = np.empty(self.n)
+        _check(self.h, lib().sdsl_get_mc64(self.h, row_of.ctypes.data_as(C.c_void_p), dr.ctypes.data_as(C.c_void_p),
+                                           dc.ctypes.data_as(C.c_void_p)))
+        return row_of, dr, dc
 
     def info(self) -> dict:
         inf = CInfo()

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdsl.so")
-SOURCES = ["kernels_setup.hip", "kernels_iter.hip", "kernels_bbd.hip", "runtime.hip"]
+SOURCES = ["kernels_setup.hip", "kernels_iter.hip", "kernels_bbd.hip", "runtime.hip", "mc64.cpp"]
 
 
 def hipcc() -> str:

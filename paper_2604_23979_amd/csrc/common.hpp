@@ -3,6 +3,7 @@
 // are compiled with -ffp-contract=off: every fused multiply-add is written as
 // fma(), so the arithmetic is exactly what the source says.
 #pragma once
+#include <vector>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -286,6 +287,15 @@ struct SlotTable {
 template <typename V, typename F>
 void launch_slots_iteration(const SlotTable& t, int ns, int k, int lanes, const int* wg, size_t shm, hipStream_t s);
 int pupdate_grid(int n);
+// MC64 transform (Alg. 3): A' values, b' = Q Dr b, x = Dc y
+void launch_mc64_values(int64_t nnz, const int* emap, const double* escale, const double* a, double* out,
+                        hipStream_t s);
+void launch_mc64_rhs(int n, const int* rowof, const double* rs, const double* b, double* out, hipStream_t s);
+void launch_mc64_sol(int n, const double* cs, const double* y, double* x, hipStream_t s);
+// host: maximum-product matching (row i -> column match[i]) and the scalings
+// dr, dc from its duals; false when no matching uses nonzeros only
+bool mc64_match(int n, const int64_t* rp, const int* ci, const double* v, std::vector<int>& match,
+                std::vector<double>& dr, std::vector<double>& dc);
 
 // pupdate modes
 enum { PUPD_STEP = 0, PUPD_START = 1, PUPD_REAPPLY = 2 };

@@ -543,6 +543,39 @@ void launch_residual(const CsrView& A, const double* v, const LowRankDev& lr, co
 #undef RES_CASE
 }
 
+// ------------------------------------------------------------------ MC64 transform
+// Alg. 3 (Sec. 3.3) on the device, with the matching and scalings found at
+// setup: values of A' = Q Dr A Dc from new values of A (entry p of A goes to
+// position emap[p] of A', times escale[p] = dr_row * dc_col), the
+// right-hand side b' = Q Dr b (b'_k = rs_k b_{rowof_k}) and the solution
+// x = Dc y.
+__global__ void k_mc64_values(int64_t nnz, const int* __restrict__ emap, const double* __restrict__ escale,
+                              const double* __restrict__ a, double* __restrict__ out) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        out[emap[p]] = escale[p] * a[p];
+}
+void launch_mc64_values(int64_t nnz, const int* emap, const double* escale, const double* a, double* out,
+                        hipStream_t s) {
+    const int64_t g = (nnz + 255) / 256;
+    if (nnz > 0) k_mc64_values<<<(int)(g < 4096 ? g : 4096), 256, 0, s>>>(nnz, emap, escale, a, out);
+}
+__global__ void k_mc64_rhs(int n, const int* __restrict__ rowof, const double* __restrict__ rs,
+                           const double* __restrict__ b, double* __restrict__ out) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) out[k] = rs[k] * b[rowof[k]];
+}
+void launch_mc64_rhs(int n, const int* rowof, const double* rs, const double* b, double* out, hipStream_t s) {
+    const int g = std::min(4096, (n + 255) / 256);
+    if (n > 0) k_mc64_rhs<<<g, 256, 0, s>>>(n, rowof, rs, b, out);
+}
+__global__ void k_mc64_sol(int n, const double* __restrict__ cs, const double* __restrict__ y,
+                           double* __restrict__ x) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) x[j] = cs[j] * y[j];
+}
+void launch_mc64_sol(int n, const double* cs, const double* y, double* x, hipStream_t s) {
+    const int g = std::min(4096, (n + 255) / 256);
+    if (n > 0) k_mc64_sol<<<g, 256, 0, s>>>(n, cs, y, x);
+}
+
 // ------------------------------------------------------------------ reductions
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ part, int m, double* out) {
     __shared__ double red[16];

@@ -136,6 +136,12 @@ struct sdsl_ctx {
     double *gV = nullptr, *gZ = nullptr, *gpart = nullptr, *gnrm = nullptr;
     double *ghcol = nullptr, *gh2 = nullptr, *gy = nullptr;
     double* gh_h = nullptr;  // pinned, kMaxBasisHost + 2 doubles
+    // MC64 transform (Alg. 3): the handle holds A' = Q Dr A Dc
+    bool mc64 = false;
+    std::vector<int> m_rowof_h;          // row of A at each row of A'
+    std::vector<double> m_dr_h, m_dc_h;  // dr per row of A, dc per column
+    int *m_rowof = nullptr, *m_emap = nullptr;
+    double *m_rs = nullptr, *m_cs = nullptr, *m_escale = nullptr, *m_b = nullptr, *m_y = nullptr;
 
     template <typename T>
     T* alloc(size_t count) {
@@ -200,6 +206,85 @@ void validate_values(sdsl_ctx* h, const int64_t* rp64_dev) {
 }
 
 // new operator values must be finite (same pattern, so nothing else changes)
+// new operator values (device, in the order of A): copied, or mapped to A'
+void take_values(sdsl_ctx* h, const double* vals) {
+    if (h->mc64) launch_mc64_values(h->nnz, h->m_emap, h->m_escale, vals, h->v, h->s);
+    else hip_check(hipMemcpyAsync(h->v, vals, h->nnz * sizeof(double), hipMemcpyDeviceToDevice, h->s), "copy");
+    h->check_launch();
+}
+
+// Alg. 3 step 1 on the host: matching and scalings (or, for SPD, the
+// identity with 1 / sqrt(a_ii)), then A' = Q Dr A Dc in CSR with, per entry
+// of A, its position in A' and its factor dr_row dc_col; rs = dr of the row
+// of A at each row of A'
+void mc64_transform(const sdsl_csr* A, bool spd, sdsl_ctx* h, std::vector<int64_t>& rp2, std::vector<int>& ci2,
+                    std::vector<double>& v2, std::vector<int>& emap, std::vector<double>& escale,
+                    std::vector<double>& rs) {
+    const int n = A->n;
+    const int64_t nnz = A->nnz;
+    if (nnz >= (int64_t(1) << 31)) fail(SDSL_E_INVALID, "MC64 limited to 2^31 entries");
+    std::vector<int64_t> rp(n + 1);
+    std::vector<int> ci(nnz);
+    std::vector<double> v(nnz);
+    const hipMemcpyKind k = A->mem == SDSL_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+    if (!A->row_ptr || !A->col || !A->val) fail(SDSL_E_INVALID, "null CSR arrays");
+    hip_check(hipMemcpy(rp.data(), A->row_ptr, (n + 1) * sizeof(int64_t), k), "copy");
+    hip_check(hipMemcpy(ci.data(), A->col, nnz * sizeof(int), k), "copy");
+    hip_check(hipMemcpy(v.data(), A->val, nnz * sizeof(double), k), "copy");
+    if (rp[0] != 0 || rp[n] != nnz) fail(SDSL_E_INVALID, "row_ptr must run from 0 to nnz");
+    for (int i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) fail(SDSL_E_INVALID, "row_ptr must not decrease");
+    for (int64_t q = 0; q < nnz; ++q) {
+        if (ci[q] < 0 || ci[q] >= n) fail(SDSL_E_INVALID, "column index out of range");
+        if (!std::isfinite(v[q])) fail(SDSL_E_INVALID, "non-finite matrix values");
+    }
+    std::vector<int> match;
+    if (spd) {
+        // |a_ij| <= sqrt(a_ii a_jj) makes the identity the best matching;
+        // the symmetric scaling sqrt(dr dc) is then 1 / sqrt(a_ii)
+        match.resize(n);
+        h->m_dr_h.assign(n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            match[i] = i;
+            double d = 0.0;
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+                if (ci[q] == i) d = v[q];
+            if (!(d > 0.0)) fail(SDSL_E_INVALID, "SPD mode needs a positive diagonal");
+            h->m_dr_h[i] = 1.0 / std::sqrt(d);
+        }
+        h->m_dc_h = h->m_dr_h;
+    } else if (!mc64_match(n, rp.data(), ci.data(), v.data(), match, h->m_dr_h, h->m_dc_h)) {
+        fail(SDSL_E_STRUCTURE, "MC64: the matrix has no matching of nonzeros (structurally singular)");
+    }
+    h->mc64 = true;
+    h->m_rowof_h.assign(n, 0);
+    int moved = 0;
+    for (int i = 0; i < n; ++i) {
+        h->m_rowof_h[match[i]] = i;
+        moved += match[i] != i;
+    }
+    h->info.mc64_moved = moved;
+    rp2.assign(n + 1, 0);
+    ci2.resize(nnz);
+    v2.resize(nnz);
+    emap.resize(nnz);
+    escale.resize(nnz);
+    rs.resize(n);
+    for (int kk = 0; kk < n; ++kk) {
+        const int r = h->m_rowof_h[kk];
+        rs[kk] = h->m_dr_h[r];
+        rp2[kk + 1] = rp2[kk] + (rp[r + 1] - rp[r]);
+        int64_t out = rp2[kk];
+        for (int64_t q = rp[r]; q < rp[r + 1]; ++q, ++out) {
+            const double f = h->m_dr_h[r] * h->m_dc_h[ci[q]];
+            ci2[out] = ci[q];
+            v2[out] = f * v[q];
+            emap[q] = (int)out;
+            escale[q] = f;
+        }
+    }
+}
+
 void check_values(sdsl_ctx* h, const double* vals) {
     launch_count_nonfinite(h->nnz, vals, h->vout, h->s);
     h->check_launch();
@@ -1122,6 +1207,7 @@ int fb_decide(double nr, double tol_nb, sdsl_status st64, int nsolves) {
 struct SolveTask {
     sdsl_ctx* h = nullptr;
     const double* b = nullptr;
+    double* user_x = nullptr;  // MC64: the caller's x = Dc y, written at the end
     double* xout = nullptr;
     double tol = 1e-8;
     double nb = 0.0;
@@ -1160,6 +1246,14 @@ struct SolveTask {
 
     void begin(sdsl_ctx* hh, const double* bb, double* xx, double tt) {
         h = hh; b = bb; xout = xx; tol = tt;
+        if (h->mc64) {
+            // Alg. 3: the Krylov method solves A' y = Q Dr b
+            launch_mc64_rhs(h->n, h->m_rowof, h->m_rs, bb, h->m_b, h->s);
+            h->check_launch();
+            b = h->m_b;
+            user_x = xx;
+            xout = h->m_y;
+        }
         t0 = now_ms();
         for (int p = 0; p < 2; ++p) {
             h->info.spmv_ms[p] = h->info.bj_ms[p] = 0.0;
@@ -1208,6 +1302,11 @@ struct SolveTask {
         status = s;
         relres = rr;
         finished = true;
+        if (user_x) {
+            launch_mc64_sol(h->n, h->m_cs, xout, user_x, h->s);  // x = Dc y
+            h->check_launch();
+            h->sync();
+        }
         h->info.solve_ms = now_ms() - t0;
         h->info.relres = rr;
         h->info.inner_iters = total_its;
@@ -1672,6 +1771,8 @@ void check_options(const sdsl_options* o) {
     if (o->krylov == SDSL_GMRES && (o->restart < 1 || o->restart >= kMaxBasisHost))
         fail(SDSL_E_INVALID, "GMRES restart must be in [1, 63]");
     if (o->max_iter < 1 || o->check_every < 1) fail(SDSL_E_INVALID, "max_iter and check_every must be >= 1");
+    if (o->mc64 != 0 && o->mc64 != 1) fail(SDSL_E_INVALID, "mc64 must be 0 or 1");
+    if (o->mc64 && o->method != SDSL_BJ) fail(SDSL_E_INVALID, "MC64 applies to the block-Jacobi method");
     if (o->precision < SDSL_FP64 || o->precision > SDSL_FP32_IR_RESTART) fail(SDSL_E_INVALID, "unknown precision");
     if (o->precision == SDSL_FP32_IR_RESTART && (!(o->inner_tol > 0.0 && o->inner_tol < 1.0) || o->max_outer < 1))
         fail(SDSL_E_INVALID, "inner_tol must be in (0,1) and max_outer >= 1");
@@ -1761,6 +1862,7 @@ size_t sdsl_footprint_bytes(const sdsl_csr* A, const sdsl_partition* p, const sd
     const size_t n = (size_t)A->n, nnz = (size_t)A->nnz, nb = (size_t)std::max(p->nblocks, 1);
     size_t b = 0;
     b += (n + 1) * (8 + 4) + nnz * (4 + 8 + 4) + n * 8;            // operator + FP32 copy + diag
+    if (o->mc64) b += nnz * (4 + 8) + n * (4 + 4 * 8);              // MC64 maps, scalings, b', y
     b += (n + 1) * 4 + nnz * (4 + 8 + 8) + n * (4 + 4 + 4 + 8);     // filtered pattern, values, factors
     // split factors (L and U each sized for every entry) + FP32 copies, the
     // U diagonal, chunk tables, levels
@@ -1835,6 +1937,18 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
         std::unique_ptr<sdsl_ctx> hp(new sdsl_ctx());
         h = hp.get();
         const double t0 = now_ms();
+        // Alg. 3 step 1: MC64 on the host; the rest of the setup sees A'
+        sdsl_csr Am{};
+        std::vector<int64_t> m_rp;
+        std::vector<int> m_ci, m_emap;
+        std::vector<double> m_val, m_escale, m_rs;
+        if (o->mc64) {
+            if (lr && lr->k > 0) fail(SDSL_E_INVALID, "MC64 takes no low-rank term");
+            if (p->n_border != 0) fail(SDSL_E_INVALID, "MC64 takes no border");
+            mc64_transform(A, o->spd != 0, h, m_rp, m_ci, m_val, m_emap, m_escale, m_rs);
+            Am = sdsl_csr{A->n, A->nnz, m_rp.data(), m_ci.data(), m_val.data(), SDSL_MEM_HOST};
+            A = &Am;
+        }
         if (al) h->al = *al;
         h->s = (hipStream_t)hip_stream;
         h->o = *o;
@@ -1978,6 +2092,21 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
             hip_check(hipMemcpy(cih.data(), A->col, nnz * sizeof(int), dk), "copy");
             setup_bbd(h, rph, cih);
         }
+        if (h->mc64) {
+            h->m_rowof = h->alloc<int>(n);
+            h->m_emap = h->alloc<int>(nnz);
+            h->m_rs = h->alloc<double>(n);
+            h->m_cs = h->alloc<double>(n);
+            h->m_escale = h->alloc<double>(nnz);
+            h->m_b = h->alloc<double>(n);
+            h->m_y = h->alloc<double>(n);
+            const hipMemcpyKind hd = hipMemcpyHostToDevice;
+            hip_check(hipMemcpyAsync(h->m_rowof, h->m_rowof_h.data(), n * sizeof(int), hd, h->s), "copy");
+            hip_check(hipMemcpyAsync(h->m_emap, m_emap.data(), nnz * sizeof(int), hd, h->s), "copy");
+            hip_check(hipMemcpyAsync(h->m_rs, m_rs.data(), n * sizeof(double), hd, h->s), "copy");
+            hip_check(hipMemcpyAsync(h->m_cs, h->m_dc_h.data(), n * sizeof(double), hd, h->s), "copy");
+            hip_check(hipMemcpyAsync(h->m_escale, m_escale.data(), nnz * sizeof(double), hd, h->s), "copy");
+        }
         build_precond(h);
         h->sync();
         h->release(rp64);
@@ -1996,7 +2125,7 @@ sdsl_status sdsl_refactor(sdsl_handle h, const double* new_val) {
         check_idle(h);
         const double t0 = now_ms();
         check_values(h, new_val);
-        hip_check(hipMemcpyAsync(h->v, new_val, h->nnz * sizeof(double), hipMemcpyDeviceToDevice, h->s), "copy");
+        take_values(h, new_val);
         launch_cast_f32(h->nnz, h->v, h->v32, h->s);
         h->check_launch();
         build_precond(h);
@@ -2010,7 +2139,7 @@ sdsl_status sdsl_update_values(sdsl_handle h, const double* new_val) {
         if (!new_val) fail(SDSL_E_INVALID, "null values");
         check_idle(h);
         check_values(h, new_val);
-        hip_check(hipMemcpyAsync(h->v, new_val, h->nnz * sizeof(double), hipMemcpyDeviceToDevice, h->s), "copy");
+        take_values(h, new_val);
         launch_cast_f32(h->nnz, h->v, h->v32, h->s);
         h->check_launch();
         h->sync();
@@ -2330,6 +2459,17 @@ sdsl_status sdsl_get_factors(sdsl_handle h, int64_t* row_ptr, int32_t* col, doub
         if (corrected) hip_check(hipMemcpy(corrected, h->pv_corr, m * sizeof(double), hipMemcpyDeviceToHost), "copy");
         if (lu) hip_check(hipMemcpy(lu, h->pv, m * sizeof(double), hipMemcpyDeviceToHost), "copy");
         if (shifts) hip_check(hipMemcpy(shifts, h->shifts, h->nb * sizeof(double), hipMemcpyDeviceToHost), "copy");
+    });
+}
+
+sdsl_status sdsl_get_mc64(sdsl_handle h, int32_t* row_of, double* row_scale, double* col_scale) {
+    if (!h) return SDSL_E_INVALID;
+    return guard(h, [&] {
+        if (!h->mc64) fail(SDSL_E_STATE, "the handle was set up without MC64");
+        const size_t n = (size_t)h->n;
+        if (row_of) std::copy(h->m_rowof_h.begin(), h->m_rowof_h.end(), row_of);
+        if (row_scale) std::copy(h->m_dr_h.begin(), h->m_dr_h.begin() + n, row_scale);
+        if (col_scale) std::copy(h->m_dc_h.begin(), h->m_dc_h.begin() + n, col_scale);
     });
 }
 

@@ -718,6 +718,128 @@ def test_gcr_exact_preconditioner_and_breakdown():
     sv.close()
 
 
+def scrambled_system(n=1200, nblocks=6, seed=8):
+    """The banded nonsymmetric system with its rows randomly permuted and
+    rows / columns scaled over 1e-4..1e4: its diagonal is mostly empty, so
+    block Jacobi cannot run on it as it stands; MC64 (Alg. 3) recovers a
+    permutation with a heavy unit diagonal."""
+    s = nonsym_system(n=n, nblocks=nblocks, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    a = s.scipy()
+    a = sp.diags(10.0 ** rng.uniform(-4, 4, n)) @ a[rng.permutation(n)] @ sp.diags(10.0 ** rng.uniform(-2, 2, n))
+    a = a.tocsr()
+    a.sort_indices()
+    return gen.System("scrambled", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data,
+                      rng.standard_normal(n), s.block_ptr)
+
+
+def test_mc64_matching_scaling_and_solve_match_oracle():
+    """MC64 on the host of the library (sparse shortest augmenting paths)
+    against the oracle's dense Hungarian method: the same matching (unique
+    for these random values), scalings that bound every scaled entry by 1
+    with the matched ones equal to 1, and block-Jacobi GMRES through Alg. 3
+    (A' y = Q Dr b, x = Dc y) that solves the original system like the
+    oracle: iterations within 10% (or 2), solution within 1e-6."""
+    print("[mc64 nonsymmetric]", flush=True)
+    s = scrambled_system()
+    o = opts(krylov=sd.GMRES, spd=False, pivot=sd.PIVOT_FAIL, mc64=True)
+    sv = sd.from_system(s, o)
+    try:
+        row_of, dr, dc = sv.mc64()
+        match_o, dr_o, dc_o, st_o = O.mc64(s)
+        assert st_o == O.OK
+        inv = np.empty_like(match_o)
+        inv[match_o] = np.arange(s.n, dtype=match_o.dtype)
+        assert np.array_equal(row_of, inv)
+        a = s.scipy().tocoo()
+        sc = np.abs(dr[a.row] * a.data * dc[a.col])
+        assert sc.max() <= 1.0 + 1e-12
+        matched = a.col == match_o[a.row]
+        np.testing.assert_allclose(sc[matched], 1.0, rtol=1e-12)
+        assert sv.info()["mc64_moved"] == int(np.count_nonzero(match_o != np.arange(s.n)))
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-10)
+        s2, x_of = O.mc64_transform(s, match_o, dr_o, dc_o)
+        P = O.BJ(s2, **oracle_opts(o))
+        y_o, its_o, rr_o, st2, _ = O.gmres_bj(s2, P, tol=1e-10, m=30, maxit=5000)
+        x_o = x_of(y_o)
+        x = x.cpu().numpy()
+        print(f"  GPU its {its} relres(A') {rr:.2e}; oracle its {its_o} relres(A') {rr_o:.2e}; "
+              f"moved rows {sv.info()['mc64_moved']}")
+        assert st == sd.OK and st2 == O.OK
+        assert abs(its - its_o) <= max(2, 0.1 * its_o)
+        assert np.linalg.norm(x - x_o) <= 1e-6 * np.linalg.norm(x_o)
+        # the tolerance is that of A' y = b'; on A x = b the residual is the
+        # oracle's (rows of A are scaled over 1e-4..1e4, so ||Dr^-1|| ||Dr||
+        # bounds the ratio of the two relative residuals)
+        rr_a, rr_ao = O.relres(s, x), O.relres(s, x_o)
+        print(f"  relres on A x = b: GPU {rr_a:.2e}, oracle {rr_ao:.2e}")
+        assert rr_a <= 2.0 * rr_ao + 1e-14
+        assert rr_a <= 1e-10 * (dr.max() / dr.min())
+    finally:
+        sv.close()
+
+
+def test_mc64_spd_is_jacobi_scaling_and_refactor_reuses_it():
+    """SPD mode: the identity matching with 1/sqrt(a_ii) on both sides (the
+    oracle's Hungarian method finds the identity and sqrt(dr dc) equals it);
+    PCG on S A S matches the oracle on its transformed system; refactor with
+    new values maps them through the same transform (the result equals a
+    fresh handle on the new values scaled by the old diagonal)."""
+    s = gen.c1()
+    o = opts(mc64=True)
+    sv = sd.from_system(s, o)
+    try:
+        row_of, dr, dc = sv.mc64()
+        d = s.scipy().diagonal()
+        assert np.array_equal(row_of, np.arange(s.n))
+        np.testing.assert_allclose(dr, 1.0 / np.sqrt(d), rtol=1e-15)
+        assert np.array_equal(dr, dc)
+        match_o, dr_o, dc_o, _ = O.mc64(s)
+        assert np.array_equal(match_o, np.arange(s.n))
+        np.testing.assert_allclose(np.sqrt(dr_o * dc_o), dr, rtol=1e-10)
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+        s2, x_of = O.mc64_transform(s, match_o, dr_o, dc_o, spd=True)
+        y_o, its_o, rr_o, st_o, _ = O.pcg_bj(s2, O.BJ(s2, **oracle_opts(o)), tol=1e-8)
+        x = x.cpu().numpy()
+        print(f"  C1 MC64 (SPD): GPU its {its}, oracle its {its_o}")
+        assert st == sd.OK and st_o == O.OK and abs(its - its_o) <= max(2, 0.1 * its_o)
+        assert np.linalg.norm(x - x_of(y_o)) <= 1e-6 * np.linalg.norm(x_of(y_o))
+        # refactor: new values (the diagonal raised by half the row's
+        # magnitude sum), mapped through the transform of the old ones
+        M = s.scipy()
+        rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+        v2 = s.val.copy()
+        on_diag = s.col == rows
+        v2[on_diag] += 0.5 * np.asarray(abs(M).sum(axis=1)).ravel()[rows[on_diag]]
+        sv.refactor(tdev(v2))
+        x2, its2, rr2, st2 = sv.solve(tdev(s.b), tol=1e-8)
+        s3 = gen.System("c1-new", s.row_ptr, s.col, v2, s.b, s.block_ptr)
+        s_old = 1.0 / np.sqrt(d)
+        s3b, x_of3 = O.mc64_transform(s3, np.arange(s.n, dtype=np.int32), s_old, s_old, spd=False)
+        y3, its3, _, st3, _ = O.pcg_bj(s3b, O.BJ(s3b, **oracle_opts(o)), tol=1e-8)
+        print(f"  after refactor: GPU its {its2}, oracle on the old transform its {its3}")
+        assert st2 == sd.OK and st3 == O.OK and abs(its2 - its3) <= max(2, 0.1 * its3)
+        assert np.linalg.norm(x2.cpu().numpy() - x_of3(y3)) <= 1e-6 * np.linalg.norm(x_of3(y3))
+    finally:
+        sv.close()
+
+
+def test_mc64_rejects_what_it_cannot_transform():
+    """A structurally singular matrix (no matching of nonzeros) is
+    SDSL_E_STRUCTURE; a low-rank term or a BBD border is SDSL_E_INVALID."""
+    a = sp.csr_matrix(np.array([[1.0, 0.0, 2.0], [3.0, 0.0, 1.0], [0.0, 0.0, 4.0]]))
+    a = (a + sp.csr_matrix((np.array([0.0]), (np.array([1]), np.array([1]))), shape=(3, 3))).tocsr()
+    a.sort_indices()
+    bad = gen.System("sing", a.indptr.astype(np.int64), a.indices.astype(np.int32), a.data, np.ones(3),
+                     np.array([0, 3], dtype=np.int32))
+    with pytest.raises(sd.SdslError) as e:
+        sd.from_system(bad, opts(krylov=sd.GMRES, spd=False, mc64=True))
+    assert e.value.status == sd.E_STRUCTURE
+    with pytest.raises(sd.SdslError) as e:
+        sd.from_system(gen.c2(0.004), opts(mc64=True))
+    assert e.value.status == sd.E_INVALID
+
+
 def _row_scaled_system(seed, n=400):
     """Nonsymmetric, weakly dominant, rows scaled over 1e-5..1e5: GMRES(60)
     makes slow progress, which keeps a long run of cycles meaningful."""

@@ -855,6 +855,114 @@ def test_gcr_with_bbd_matches_gmres_and_exact_blocks_take_one_step():
     assert np.linalg.norm(s.b - s.scipy() @ x) <= 1.5e-10 * np.linalg.norm(s.b)
 
 
+# --------------------------------------------------------------- MC64 (Alg. 3 step 1)
+
+def _scrambled(n, seed, density=0.15):
+    """Nonsymmetric sparse matrix whose large entries sit off the diagonal:
+    a random permutation of rows of a diagonally heavy matrix, with entry
+    magnitudes spread over 1e-4..1e4 by row and column scalings."""
+    rng = np.random.default_rng(seed)
+    a = rand_sparse(n, density, rng, dd=0.8)
+    a = a[rng.permutation(n)]
+    a = np.diag(10.0 ** rng.uniform(-4, 4, n)) @ a @ np.diag(10.0 ** rng.uniform(-2, 2, n))
+    m = csr_of(a)
+    return gen.System("scr", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data,
+                      rng.standard_normal(n), gen.contiguous_blocks(n, 3)), a
+
+
+@pytest.mark.parametrize("seed", [70, 71, 72])
+def test_mc64_matching_maximises_the_diagonal_product(seed):
+    """The matching maximises prod |a_{i,sigma(i)}| (Duff-Koster maximum
+    product): its log-sum equals the optimum of SciPy's assignment solver on
+    -log|a| (an independent algorithm), and it uses nonzeros only."""
+    from scipy.optimize import linear_sum_assignment
+    s, a = _scrambled(60, seed)
+    match, dr, dc, st = O.mc64(s)
+    assert st == O.OK
+    assert np.all(a[np.arange(60), match] != 0.0)
+    cost = np.where(a != 0.0, -np.log(np.abs(np.where(a != 0.0, a, 1.0))), 1e6)
+    r, c = linear_sum_assignment(cost)
+    best = -cost[r, c].sum()
+    assert np.sum(np.log(np.abs(a[np.arange(60), match]))) == pytest.approx(best, abs=1e-9)
+
+
+def test_mc64_brute_force_on_seven_unknowns():
+    import itertools
+    rng = np.random.default_rng(73)
+    a = rng.standard_normal((7, 7)) * 10.0 ** rng.uniform(-3, 3, (7, 7))
+    a[rng.random((7, 7)) < 0.3] = 0.0
+    np.fill_diagonal(a, 0.0)
+    a[np.arange(7), (np.arange(7) + 1) % 7] = 1.0   # keeps one nonzero matching
+    m = csr_of(a)
+    s = gen.System("bf", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, np.ones(7),
+                   np.array([0, 7], dtype=np.int32))
+    match, dr, dc, st = O.mc64(s)
+    best, arg = -np.inf, None
+    for perm in itertools.permutations(range(7)):
+        vals = np.abs(a[np.arange(7), perm])
+        if np.all(vals > 0):
+            lv = np.sum(np.log(vals))
+            if lv > best:
+                best, arg = lv, perm
+    assert st == O.OK and tuple(match) == arg
+
+
+@pytest.mark.parametrize("seed", [74, 75])
+def test_mc64_scaling_is_dual_feasible(seed):
+    """The scalings from the assignment's duals make every scaled entry at
+    most 1 in magnitude and every matched one exactly 1 (MC64's scaling);
+    then the transformed system A' = Q Dr A Dc has a unit diagonal with no
+    larger entry, b' = Q Dr b, and x = Dc y solves A x = b."""
+    s, a = _scrambled(80, seed)
+    match, dr, dc, st = O.mc64(s)
+    sc = np.abs(dr[:, None] * a * dc[None, :])
+    assert np.max(sc[a != 0.0]) <= 1.0 + 1e-12
+    np.testing.assert_allclose(sc[np.arange(80), match], 1.0, rtol=1e-12)
+    s2, x_of = O.mc64_transform(s, match, dr, dc)
+    A2 = s2.scipy().toarray()
+    np.testing.assert_allclose(np.abs(np.diag(A2)), 1.0, rtol=1e-12)
+    assert np.max(np.abs(A2)) <= 1.0 + 1e-12
+    y = np.linalg.solve(A2, s2.b)
+    x = x_of(y)
+    assert np.linalg.norm(a @ x - s.b) <= 1e-9 * np.linalg.norm(s.b) * np.linalg.cond(A2)
+
+
+def test_mc64_of_spd_matrix_is_the_identity_with_jacobi_scaling():
+    """|a_ij| <= sqrt(a_ii a_jj) for SPD matrices, so the identity has the
+    largest diagonal product; the symmetric scaling sqrt(dr dc) is then
+    1/sqrt(a_ii), the unit-diagonal scaling under which Eq. (filter) is the
+    GEOMEAN rule."""
+    s = gen.c1()
+    match, dr, dc, st = O.mc64(s)
+    assert st == O.OK and np.array_equal(match, np.arange(s.n))
+    d = s.scipy().diagonal()
+    np.testing.assert_allclose(np.sqrt(dr * dc), 1.0 / np.sqrt(d), rtol=1e-10)
+    s2, x_of = O.mc64_transform(s, match, dr, dc, spd=True)
+    np.testing.assert_allclose(s2.scipy().diagonal(), 1.0, rtol=1e-10)
+
+
+def test_mc64_structurally_singular_and_transformed_solve():
+    """An empty column has no matching (STRUCTURE).  A row-permuted, badly
+    scaled system whose diagonal is mostly empty (so block Jacobi cannot
+    factor it as it stands) is solved through Alg. 3: block-Jacobi GMRES on
+    A', then x = Dc y."""
+    a = np.array([[1.0, 0.0, 2.0], [3.0, 0.0, 1.0], [0.0, 0.0, 4.0]])
+    m = csr_of(a)
+    bad = gen.System("sing", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, np.ones(3),
+                     np.array([0, 3], dtype=np.int32))
+    assert O.mc64(bad)[3] == O.STRUCTURE
+    s, a = _scrambled(600, 76, density=0.02)
+    match, dr, dc, st = O.mc64(s)
+    s2, x_of = O.mc64_transform(s, match, dr, dc)
+    s.block_ptr = s2.block_ptr = gen.contiguous_blocks(600, 20)
+    P2 = O.BJ(s2, spd=False, policy=O.PIVOT_FAIL)
+    y, its2, rr2, st2, _ = O.gmres_bj(s2, P2, tol=1e-10, m=60, maxit=3000)
+    assert st2 == O.OK
+    x = x_of(y)
+    assert np.linalg.norm(a @ x - s.b) <= 1e-8 * np.linalg.norm(s.b) * 1e4
+    assert np.count_nonzero(np.diag(a)) < 600 // 4
+
+
 # --------------------------------------------------------------- IR
 
 def test_ir_reaches_tolerance_and_matches_fp64_solution():
