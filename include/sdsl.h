@@ -98,6 +98,19 @@ typedef enum { SDSL_PCG = 0, SDSL_GMRES = 1, SDSL_BICGSTAB = 2, SDSL_GCR = 3 } s
  * solved in FP64. */
 typedef enum { SDSL_FP64 = 0, SDSL_FP32_IR = 1, SDSL_FP32_IR_RESTART = 2 } sdsl_precision;
 
+/* Factorisation of each filtered, corrected block (Sec. 3.1: ILU(0) for
+ * block Jacobi, complete LU for BBD; Sec. 3.2 Alg. 2: a complete
+ * factorisation of the filtered matrix).  COMPLETE: LU without pivoting of
+ * the whole block, i.e. elimination over the block's symbolic fill pattern
+ * (found on the host, rows merged in natural order; no fill-reducing
+ * ordering), numerically by the same in-block elimination as ILU(0); in
+ * SPD mode its U is D L^T, the LU form of the complete Cholesky factor.
+ * The breakdown policy applies as for ILU(0).  nnz_kept then counts the
+ * factor's entries (fill included); the fill is symbolic analysis of the
+ * filtered pattern, repeated by refactor, and it is not part of
+ * sdsl_footprint_bytes. */
+typedef enum { SDSL_FACT_ILU0 = 0, SDSL_FACT_COMPLETE = 1 } sdsl_factor;
+
 typedef enum { SDSL_MEM_DEVICE = 0, SDSL_MEM_HOST = 1 } sdsl_mem;
 
 /* Square sparse matrix in CSR: row_ptr[n+1] (int64), col[nnz] (int32,
@@ -176,6 +189,7 @@ typedef struct {
                               matrix is copied); refactor / update_values
                               take values of A and reuse the matching.
                               spmv, precond_apply and residual act on A'.    */
+    sdsl_factor factor;    /* ILU0 (default) or COMPLETE                     */
 } sdsl_options;
 
 typedef struct {
@@ -228,7 +242,7 @@ typedef struct {
 /* Fills *o with defaults: BJ, no filter, no correction, SHIFT(1e-2), SPD,
  * PCG, restart 30, max_iter 100000, FP64, inner_tol 1e-4, max_outer 30,
  * check_every 16, kernel_timing 0, border 1, refine_delta 0.1,
- * refine_every 500, mc64 0. */
+ * refine_every 500, mc64 0, factor ILU0. */
 void sdsl_default_options(sdsl_options* o);
 
 /* Device-memory provider of a handle (PyTorch's caching allocator in the

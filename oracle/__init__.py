@@ -74,7 +74,7 @@ def _declare(L):
     L.or_dense_lu.argtypes = [I64, P, P]
     L.or_dense_lu.restype = C.c_int
     L.or_dense_lu_solve.argtypes = [I64, P, P, P]
-    L.or_bbd_setup.argtypes = [I64, P, P, P, I32, P, I64, I32, D, C.c_uint32, D, I32, P, P]
+    L.or_bbd_setup.argtypes = [I64, P, P, P, I32, P, I64, I32, D, C.c_uint32, D, I32, I32, P, P]
     L.or_bbd_setup.restype = P
     L.or_bbd_free.argtypes = [P]
     L.or_bbd_apply.argtypes = [P, P, P]
@@ -207,12 +207,16 @@ class BJ:
     block's diagonal by a relative amount starting at ``shift0``)."""
 
     def __init__(self, sys_, mode=FILTER_NONE, tau=0.0, flags=0, delta=0.0, spd=True,
-                 policy=PIVOT_SHIFT, shift0=1e-2, border=False):
+                 policy=PIVOT_SHIFT, shift0=1e-2, border=False, complete=False):
         self.rp, self.ci, v0, self.dropsum = filter_correct(sys_.row_ptr, sys_.col, sys_.val,
                                                             sys_.block_ptr, mode, tau, flags, delta)
-        self.corrected = v0
         n = self.rp.shape[0] - 1
         bp = np.ascontiguousarray(sys_.block_ptr, dtype=np.int32)
+        if complete:
+            # complete LU without pivoting of each block (Sec. 3.1, Alg. 2):
+            # the same elimination over the block's full (dense) pattern
+            self.rp, self.ci, v0 = _dense_blocks(self.rp, self.ci, v0, bp)
+        self.corrected = v0
         self.bp, self.nb = bp, bp.shape[0] - 1
         self.v = np.empty_like(v0)
         self.dp = np.empty(max(n, 1), dtype=np.int64)
@@ -250,6 +254,26 @@ class BJ:
                 self.border = None
         except Exception:
             pass  # interpreter shutdown
+
+
+def _dense_blocks(rp, ci, v, bp):
+    """Every block of a block-diagonal CSR matrix stored densely (all
+    columns of the block in every row, zeros where the matrix has none)."""
+    n = rp.shape[0] - 1
+    sizes = np.zeros(n, dtype=np.int64)
+    for b in range(bp.shape[0] - 1):
+        sizes[bp[b]:bp[b + 1]] = bp[b + 1] - bp[b]
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    rp2[1:] = np.cumsum(sizes)
+    ci2 = np.empty(int(rp2[-1]), dtype=np.int32)
+    v2 = np.zeros(int(rp2[-1]))
+    for b in range(bp.shape[0] - 1):
+        lo, hi = int(bp[b]), int(bp[b + 1])
+        for i in range(lo, hi):
+            ci2[rp2[i]:rp2[i + 1]] = np.arange(lo, hi, dtype=np.int32)
+            q = slice(int(rp[i]), int(rp[i + 1]))
+            v2[rp2[i] + ci[q].astype(np.int64) - lo] = v[q]
+    return rp2, ci2, v2
 
 
 def _lr_args(lowrank):
@@ -424,7 +448,7 @@ def gmres_bj(sys_, P: BJ, tol=1e-8, m=30, maxit=10_000, hist=False):
 class BBD:
     """Bordered-block-diagonal preconditioner of paper Sec. 2.4."""
 
-    def __init__(self, sys_, mode=FILTER_NONE, tau=0.0, flags=0, delta=0.0, pivot_fix=False):
+    def __init__(self, sys_, mode=FILTER_NONE, tau=0.0, flags=0, delta=0.0, pivot_fix=False, complete=False):
         self.rp, self.ci, self.v = _csr(sys_.row_ptr, sys_.col, sys_.val)
         self.bp = np.ascontiguousarray(sys_.block_ptr, dtype=np.int32)
         self.n = sys_.n
@@ -433,7 +457,7 @@ class BBD:
         info = np.zeros(3, dtype=np.int64)
         self.ctx = lib().or_bbd_setup(self.n, _p(self.rp), _p(self.ci), _p(self.v),
                                       self.bp.shape[0] - 1, _p(self.bp), self.n_border, mode, tau,
-                                      flags, delta, int(pivot_fix), C.byref(st), _p(info))
+                                      flags, delta, int(pivot_fix), int(complete), C.byref(st), _p(info))
         self.status = st.value
         self.kept, self.nfix, self.bad_row = (int(t) for t in info)
 

@@ -891,7 +891,8 @@ static int64_t* tail_starts(int64_t n_int, const int64_t* rp, const int32_t* ci,
  * info[0] = kept entries, info[1] = pivot fixes, info[2] = bad row. */
 void* or_bbd_setup(int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                    int32_t nblocks, const int32_t* bp, int64_t n_border, int32_t mode, double tau,
-                   uint32_t flags, double delta, int32_t pivot_fix, int32_t* status, int64_t* info) {
+                   uint32_t flags, double delta, int32_t pivot_fix, int32_t complete, int32_t* status,
+                   int64_t* info) {
     int64_t n_int = n - n_border;
     *status = OR_OK;
     if (bp[0] != 0 || bp[nblocks] != n_int) { *status = OR_STRUCTURE; return NULL; }
@@ -912,6 +913,26 @@ void* or_bbd_setup(int64_t n, const int64_t* rp, const int32_t* ci, const double
     free(ds);
     info[0] = kept;
     if (kept < 0) { *status = OR_STRUCTURE; return B; }
+    if (complete) {
+        /* complete LU of each interior block (Sec. 3.1: BBD uses complete LU):
+         * the same elimination over the block's full pattern */
+        int64_t tot = 0;
+        for (int32_t b = 0; b < nblocks; ++b) tot += (int64_t)(bp[b + 1] - bp[b]) * (bp[b + 1] - bp[b]);
+        int64_t* rp2 = malloc((size_t)(n_int + 1) * 8);
+        int32_t* ci2 = malloc((size_t)tot * 4 + 4);
+        double* v2 = calloc((size_t)tot + 1, 8);
+        rp2[0] = 0;
+        for (int32_t b = 0; b < nblocks; ++b) {
+            const int64_t lo = bp[b], hi = bp[b + 1];
+            for (int64_t i = lo; i < hi; ++i) {
+                rp2[i + 1] = rp2[i] + (hi - lo);
+                for (int64_t j = lo; j < hi; ++j) ci2[rp2[i] + j - lo] = (int32_t)j;
+                for (int64_t p = B->lrp[i]; p < B->lrp[i + 1]; ++p) v2[rp2[i] + B->lci[p] - lo] = B->lv[p];
+            }
+        }
+        free(B->lrp); free(B->lci); free(B->lv);
+        B->lrp = rp2; B->lci = ci2; B->lv = v2;
+    }
     int32_t nfix = 0; int64_t brow = -1;
     int st = or_ilu0(n_int, B->lrp, B->lci, B->lv, 0, pivot_fix, B->ldp, &nfix, &brow);
     info[1] = nfix; info[2] = brow;

@@ -4,7 +4,7 @@ preconditioned CG in FP64 or FP32-inner / FP64-refined form, GMRES(m),
 BiCGSTAB, GCR(m), and the
 bordered-block-diagonal preconditioner with a dense Schur complement, behind
 the C ABI of include/sdsl.h.  This package is the binding of that library."""
-from ._binding import (BBD, BICGSTAB, BJ, GCR, Group, DIAG_DELTA, DIAG_DROPSUM, E_BREAKDOWN, E_DEVICE, E_INVALID, E_NOMEM,
+from ._binding import (BBD, BICGSTAB, BJ, FACT_COMPLETE, FACT_ILU0, GCR, Group, DIAG_DELTA, DIAG_DROPSUM, E_BREAKDOWN, E_DEVICE, E_INVALID, E_NOMEM,
                        E_NOT_CONVERGED, E_STATE, E_STRUCTURE, FILTER_GEOMEAN, FILTER_MIN, FILTER_NONE, FP32_IR,
                        FP32_IR_RESTART,
                        FP64, GMRES, OK, PCG, PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT, SIGNATURES, LIB_PATH, Options,

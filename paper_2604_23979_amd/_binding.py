@@ -26,6 +26,7 @@ FILTER_NONE, FILTER_MIN, FILTER_GEOMEAN = 0, 1, 2
 DIAG_DELTA, DIAG_DROPSUM = 1, 2
 PIVOT_FAIL, PIVOT_REPLACE, PIVOT_SHIFT = 0, 1, 2
 PCG, GMRES, BICGSTAB, GCR = 0, 1, 2, 3
+FACT_ILU0, FACT_COMPLETE = 0, 1
 FP64, FP32_IR, FP32_IR_RESTART = 0, 1, 2
 MEM_DEVICE, MEM_HOST = 0, 1
 
@@ -55,7 +56,7 @@ class COptions(C.Structure):
                 ("krylov", C.c_int), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("kernel_timing", C.c_int32), ("border", C.c_int32), ("refine_delta", C.c_double),
-                ("refine_every", C.c_int32), ("mc64", C.c_int32)]
+                ("refine_every", C.c_int32), ("mc64", C.c_int32), ("factor", C.c_int)]
 
 
 class CInfo(C.Structure):
@@ -198,6 +199,7 @@ class Options:
     refine_delta: float = 0.1
     refine_every: int = 500
     mc64: bool = False
+    factor: int = 0  # FACT_ILU0 or FACT_COMPLETE
 
     def c(self) -> COptions:
         o = COptions()

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <queue>
 #include <vector>
 
 #include "common.hpp"
@@ -94,6 +95,7 @@ struct sdsl_ctx {
     double *lov = nullptr, *uov = nullptr;
     float *lov32 = nullptr, *uov32 = nullptr;
     int p_nnz = 0;
+    int64_t pcap = 0;  // capacity of the filtered / factor entry arrays
     // border correction of the low-rank term (W = P^{-1} U, K^{-1})
     double* W64 = nullptr;
     double *Kmat = nullptr, *Kinv = nullptr;
@@ -605,6 +607,90 @@ void build_bbd(sdsl_ctx* h) {
     h->sync();
 }
 
+// Symbolic fill of LU without pivoting, one block [lo, hi) of the filtered
+// pattern (columns inside the block, sorted, diagonal present): row i's
+// pattern is its own entries plus, for every k < i in it (taken in
+// increasing order, fill included), the entries of row k's U part right of
+// k.  Appends the rows to rp / ci (global row offsets in rp).
+void lu_fill_block(int lo, int hi, const std::vector<int>& prp, const std::vector<int>& pci, std::vector<int64_t>& rp,
+                   std::vector<int>& ci) {
+    const int m = hi - lo;
+    std::vector<std::vector<int>> upat(m);  // U part (columns > row) of processed rows, local indices
+    std::vector<int> mark(m, -1);
+    std::vector<int> row;
+    std::priority_queue<int, std::vector<int>, std::greater<int>> lower;
+    for (int i = 0; i < m; ++i) {
+        row.clear();
+        for (int q = prp[lo + i]; q < prp[lo + i + 1]; ++q) {
+            const int c = pci[q] - lo;
+            mark[c] = i;
+            row.push_back(c);
+            if (c < i) lower.push(c);
+        }
+        while (!lower.empty()) {
+            const int k = lower.top();
+            lower.pop();
+            for (int c : upat[k])
+                if (mark[c] != i) {
+                    mark[c] = i;
+                    row.push_back(c);
+                    if (c < i) lower.push(c);
+                }
+        }
+        std::sort(row.begin(), row.end());
+        for (int c : row)
+            if (c > i) upat[i].push_back(c);
+        for (int c : row) ci.push_back(c + lo);
+        rp.push_back((int64_t)ci.size());
+    }
+}
+
+// COMPLETE factorisation: the filtered, corrected pattern grows by its
+// symbolic fill (values 0 at the new positions) before the elimination
+void complete_fill(sdsl_ctx* h) {
+    const int ni = h->n_int;
+    h->sync();
+    std::vector<int> prp(ni + 1), pd(ni);
+    hip_check(hipMemcpy(prp.data(), h->prp, (ni + 1) * sizeof(int), hipMemcpyDeviceToHost), "copy");
+    const int kept = prp[ni];
+    std::vector<int> pci(kept);
+    std::vector<double> pv(kept);
+    hip_check(hipMemcpy(pci.data(), h->pci, kept * sizeof(int), hipMemcpyDeviceToHost), "copy");
+    hip_check(hipMemcpy(pv.data(), h->pv_corr, kept * sizeof(double), hipMemcpyDeviceToHost), "copy");
+    std::vector<int64_t> rp{0};
+    std::vector<int> ci;
+    ci.reserve(kept);
+    for (int b = 0; b < h->nb; ++b) lu_fill_block(h->bp_h[b], h->bp_h[b + 1], prp, pci, rp, ci);
+    const int64_t F = rp[ni];
+    if (F >= (int64_t(1) << 31)) fail(SDSL_E_NOMEM, "complete factor limited to 2^31 entries");
+    std::vector<int> rp32(ni + 1);
+    std::vector<double> v(F, 0.0);
+    for (int i = 0; i < ni; ++i) {
+        rp32[i] = (int)rp[i];
+        int64_t q = prp[i];
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (q < prp[i + 1] && pci[q] == ci[e]) v[e] = pv[q++];
+            if (ci[e] == i) pd[i] = (int)e;
+        }
+    }
+    rp32[ni] = (int)F;
+    if (F > h->pcap) {
+        // every array sized by the factor's entries grows (no launch reads them now)
+        auto grow_i = [&](int*& a) { h->release(a); a = h->alloc<int>(F); };
+        auto grow_d = [&](double*& a) { h->release(a); a = h->alloc<double>(F); };
+        auto grow_f = [&](float*& a) { h->release(a); a = h->alloc<float>(F); };
+        grow_i(h->pci); grow_i(h->lci); grow_i(h->uci); grow_i(h->loci); grow_i(h->uoci);
+        grow_d(h->pv_corr); grow_d(h->pv); grow_d(h->lval); grow_d(h->uval); grow_d(h->lov); grow_d(h->uov);
+        grow_f(h->lval32); grow_f(h->uval32); grow_f(h->lov32); grow_f(h->uov32);
+        h->pcap = F;
+    }
+    hip_check(hipMemcpyAsync(h->prp, rp32.data(), (ni + 1) * sizeof(int), hipMemcpyHostToDevice, h->s), "copy");
+    hip_check(hipMemcpyAsync(h->pci, ci.data(), F * sizeof(int), hipMemcpyHostToDevice, h->s), "copy");
+    hip_check(hipMemcpyAsync(h->pv_corr, v.data(), F * sizeof(double), hipMemcpyHostToDevice, h->s), "copy");
+    hip_check(hipMemcpyAsync(h->pdiag, pd.data(), ni * sizeof(int), hipMemcpyHostToDevice, h->s), "copy");
+    h->sync();  // the host vectors go out of scope
+}
+
 void build_precond(sdsl_ctx* h) {
     const double t0 = now_ms();
     hipStream_t s = h->s;
@@ -614,6 +700,7 @@ void build_precond(sdsl_ctx* h) {
     launch_scan(h->n_int, h->cnt, h->prp, h->scan_tmp, s);
     launch_filter_compact(h->n_int, h->rp, h->ci, h->v, h->diag, h->bp, h->nb, mode, h->o.tau, h->o.diag_flags,
                           h->o.delta, h->dropsum, h->prp, h->pci, h->pv_corr, h->pdiag, s);
+    if (h->o.factor == SDSL_FACT_COMPLETE) complete_fill(h);
     hip_check(hipMemsetAsync(h->nfix, 0, sizeof(int), s), "memset");
     hip_check(hipMemsetAsync(h->spin_err, 0, sizeof(int), s), "memset");
     launch_ilu0(h->nb, h->bp, h->prp, h->pci, h->pv_corr, h->pv, h->pdiag, h->o.spd, h->o.pivot, h->o.shift0,
@@ -1773,6 +1860,7 @@ void check_options(const sdsl_options* o) {
     if (o->max_iter < 1 || o->check_every < 1) fail(SDSL_E_INVALID, "max_iter and check_every must be >= 1");
     if (o->mc64 != 0 && o->mc64 != 1) fail(SDSL_E_INVALID, "mc64 must be 0 or 1");
     if (o->mc64 && o->method != SDSL_BJ) fail(SDSL_E_INVALID, "MC64 applies to the block-Jacobi method");
+    if (o->factor != SDSL_FACT_ILU0 && o->factor != SDSL_FACT_COMPLETE) fail(SDSL_E_INVALID, "unknown factorisation");
     if (o->precision < SDSL_FP64 || o->precision > SDSL_FP32_IR_RESTART) fail(SDSL_E_INVALID, "unknown precision");
     if (o->precision == SDSL_FP32_IR_RESTART && (!(o->inner_tol > 0.0 && o->inner_tol < 1.0) || o->max_outer < 1))
         fail(SDSL_E_INVALID, "inner_tol must be in (0,1) and max_outer >= 1");
@@ -2013,6 +2101,7 @@ sdsl_status sdsl_setup(const sdsl_csr* A, const sdsl_partition* p, const sdsl_op
             fail(SDSL_E_INVALID, "block-Jacobi part limited to 2^31 / " + std::to_string(kBjEllWidth) + " rows");
         h->prp = h->alloc<int>(ni + 1);
         h->pci = h->alloc<int>(nnz);
+        h->pcap = nnz;
         h->pv_corr = h->alloc<double>(nnz);
         h->pv = h->alloc<double>(nnz);
         h->pdiag = h->alloc<int>(ni);

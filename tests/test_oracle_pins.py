@@ -631,6 +631,22 @@ def test_bbd_exact_blocks_gmres_one_step():
     assert st == O.OK and its == 1 and rr <= 1e-10
 
 
+def test_bbd_with_complete_blocks_is_exact():
+    """With complete LU blocks and no filter the BBD preconditioner is M
+    itself for any blocks (the Schur complement is exact for M_BBD), so
+    right-preconditioned GMRES and GCR converge in one step, and the apply
+    inverts M."""
+    s = gen.bbd_system(nblocks=3, block_rows=60, n_border=12, nnz_off=4, half_band=10, tail_frac=0.2,
+                       border_c=2, seed=14, name="bbd-tiny")
+    P = O.BBD(s, complete=True)
+    assert P.status == O.OK
+    r = np.random.default_rng(19).standard_normal(s.n)
+    np.testing.assert_allclose(s.scipy() @ P.apply(r), r, atol=1e-10 * np.abs(r).max())
+    for fn in (O.gmres_bbd, O.gcr_bbd):
+        x, its, rr, st, _ = fn(s, P, tol=1e-10)
+        assert st == O.OK and its == 1 and rr <= 1e-10
+
+
 @pytest.mark.parametrize("row,col", [(0, 45), (29, 30), (30, 29)],
                          ids=["inside", "next-block-first-column", "previous-block-last-column"])
 def test_bbd_rejects_block_coupling(row, col):
@@ -853,6 +869,60 @@ def test_gcr_with_bbd_matches_gmres_and_exact_blocks_take_one_step():
     k = min(its_c, its_g) - 1
     np.testing.assert_allclose(h_c[:k], h_g[:k], rtol=1e-6)
     assert np.linalg.norm(s.b - s.scipy() @ x) <= 1.5e-10 * np.linalg.norm(s.b)
+
+
+# --------------------------------------------------------------- complete factorisation
+
+def test_complete_lu_reproduces_the_filtered_block_and_lapack():
+    """COMPLETE (Sec. 3.1 complete LU, Alg. 2 complete factorisation of the
+    filtered matrix): per block, L U equals the filtered, corrected block to
+    rounding, and L, U equal SciPy's LU (LAPACK) where partial pivoting keeps
+    the diagonal (a diagonally dominant block)."""
+    s = gen.c2(0.004, dense_cols=0)
+    P = O.BJ(s, O.FILTER_GEOMEAN, 1e-3, O.DIAG_DROPSUM, policy=O.PIVOT_FAIL, complete=True)
+    F = O.BJ(s, O.FILTER_GEOMEAN, 1e-3, O.DIAG_DROPSUM, policy=O.PIVOT_FAIL)
+    assert P.status == O.OK
+    L, U = unpack_lu(P.rp, P.ci, P.v, s.n)
+    Ph = sp.csr_matrix((F.corrected, F.ci, F.rp), shape=(s.n, s.n)).toarray()
+    for b in range(s.nblocks):
+        lo, hi = s.block_ptr[b], s.block_ptr[b + 1]
+        blk = Ph[lo:hi, lo:hi]
+        Lb, Ub = L[lo:hi, lo:hi], U[lo:hi, lo:hi]
+        assert np.abs(Lb @ Ub - blk).max() <= 1e-12 * np.abs(blk).max()
+    rng = np.random.default_rng(80)
+    a = rand_sparse(150, 0.05, rng, dd=2.5)
+    m = csr_of(a)
+    t = gen.System("dd", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, rng.standard_normal(150),
+                   np.array([0, 150], dtype=np.int32))
+    Q = O.BJ(t, spd=False, policy=O.PIVOT_FAIL, complete=True)
+    L, U = unpack_lu(Q.rp, Q.ci, Q.v, 150)
+    p_, l_ref, u_ref = sl.lu(a)
+    assert np.array_equal(p_, np.eye(150))
+    np.testing.assert_allclose(L, l_ref, atol=1e-13)
+    np.testing.assert_allclose(U, u_ref, atol=1e-12 * np.abs(u_ref).max())
+
+
+def test_complete_lu_without_filter_is_exact_and_filtered_beats_ilu0():
+    """Without a filter each block's complete LU is the block itself, so on
+    one block PCG and GMRES converge in one step; with the filter and 4
+    blocks it takes fewer PCG steps than ILU(0) of the same filtered
+    blocks."""
+    s = gen.c1()
+    one = gen.System("c1-one", s.row_ptr, s.col, s.val, s.b, np.array([0, s.n], dtype=np.int32))
+    x, its, rr, st, _ = O.pcg_bj(one, O.BJ(one, complete=True), tol=1e-8)
+    assert st == O.OK and its == 1
+    rng = np.random.default_rng(81)
+    a = rand_sparse(300, 0.03, rng, dd=0.3)
+    m = csr_of(a)
+    g = gen.System("ns", m.indptr.astype(np.int64), m.indices.astype(np.int32), m.data, rng.standard_normal(300),
+                   np.array([0, 300], dtype=np.int32))
+    x, its, rr, st, _ = O.gmres_bj(g, O.BJ(g, spd=False, policy=O.PIVOT_FAIL, complete=True), tol=1e-10)
+    assert st == O.OK and its == 1
+    s2 = gen.c2(0.004, dense_cols=0)
+    kw = dict(mode=O.FILTER_GEOMEAN, tau=1e-3, flags=O.DIAG_DROPSUM)
+    _, its_c, _, st_c, _ = O.pcg_bj(s2, O.BJ(s2, complete=True, **kw), tol=1e-8)
+    _, its_i, _, st_i, _ = O.pcg_bj(s2, O.BJ(s2, **kw), tol=1e-8)
+    assert st_c == st_i == O.OK and its_c < its_i
 
 
 # --------------------------------------------------------------- MC64 (Alg. 3 step 1)
