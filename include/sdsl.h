@@ -236,6 +236,10 @@ typedef struct {
     int32_t rf_flag[64];
     double rf_nb;
     int32_t mc64_moved;     /* MC64: rows matched to another column than their own */
+    /* dependency levels of the triangular sweeps (forward + backward, summed
+     * over a block's row chunks): the largest over the blocks and the mean */
+    int32_t sweep_levels_max;
+    double sweep_levels_mean;
 } sdsl_info;
 #define SDSL_RF_HISTORY 64
 

@@ -68,7 +68,8 @@ class CInfo(C.Structure):
                 ("spmv_launches", C.c_int64 * 2), ("bj_ms", C.c_double * 2), ("bj_launches", C.c_int64 * 2),
                 ("spmv_bytes", C.c_int64 * 2), ("bj_bytes", C.c_int64 * 2), ("rf_count", C.c_int32),
                 ("rf_it", C.c_int32 * 64), ("rf_nr", C.c_double * 64), ("rf_act", C.c_int32 * 64),
-                ("rf_flag", C.c_int32 * 64), ("rf_nb", C.c_double), ("mc64_moved", C.c_int32)]
+                ("rf_flag", C.c_int32 * 64), ("rf_nb", C.c_double), ("mc64_moved", C.c_int32),
+                ("sweep_levels_max", C.c_int32), ("sweep_levels_mean", C.c_double)]
 
 
 class Allocator(C.Structure):

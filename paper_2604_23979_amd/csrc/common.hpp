@@ -344,6 +344,7 @@ constexpr int kLuPanel = 64;
 constexpr int kLuSub = 16;    // columns factored by one workgroup inside a panel
 void launch_bj_ell(int nblocks, const int* bp, const int* rp, const int* ci, const double* val, const int* pos,
                    bool fwd, int* ec, double* ev64, float* ev32, hipStream_t s);
+constexpr int kBjThreads = 512;  // threads (and rows per chunk) of a triangular-sweep workgroup
 constexpr int kBjEllWidth = 24;  // entries per row in the interleaved copies
 void launch_bj_old(int n, const int* rp, const int* ci, const double* val, int* cnt, int* tmp, int* orp, int* oci,
                    double* ov64, float* ov32, hipStream_t s);

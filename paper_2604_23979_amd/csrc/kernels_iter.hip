@@ -826,7 +826,6 @@ void launch_scale_inv_norm(int n, const double* nrm2, const double* w, double* v
 // (forward: ascending columns, backward: descending), each with a separate
 // product and difference.  The solve runs in the factor type F (FP32
 // factors: FP32 arithmetic); vectors have type V.
-constexpr int kBjThreads = 512;
 constexpr int kEll = kBjEllWidth;
 constexpr int kHeld = 8;                   // newest slots kept in registers through the levels
 constexpr int kPark = kEll - kHeld;        // the others, parked in LDS

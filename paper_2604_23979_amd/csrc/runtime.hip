@@ -729,7 +729,25 @@ void build_precond(sdsl_ctx* h) {
     std::vector<double> sh(h->nb);
     hip_check(hipMemcpyAsync(bst.data(), h->bstatus, h->nb * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     hip_check(hipMemcpyAsync(sh.data(), h->shifts, h->nb * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    std::vector<int> lnl(h->n_int + h->nb), unl(h->n_int + h->nb);
+    hip_check(hipMemcpyAsync(lnl.data(), h->lnl, lnl.size() * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+    hip_check(hipMemcpyAsync(unl.data(), h->unl, unl.size() * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     h->sync();
+    {
+        // dependency depth of each block's two sweeps (chunk-table indexing)
+        int64_t tot = 0;
+        int mx = 0;
+        for (int b = 0; b < h->nb; ++b) {
+            const int lo = h->bp_h[b], hi = h->bp_h[b + 1];
+            const int nch = (hi - lo + kBjThreads - 1) / kBjThreads;
+            int lv = 0;
+            for (int q = 0; q < nch; ++q) lv += lnl[lo + b + q] + unl[lo + b + q];
+            tot += lv;
+            mx = std::max(mx, lv);
+        }
+        h->info.sweep_levels_max = mx;
+        h->info.sweep_levels_mean = h->nb > 0 ? (double)tot / h->nb : 0.0;
+    }
     h->p_nnz = kept;
     launch_cast_f32(nl, h->lval, h->lval32, s);
     launch_cast_f32(nu, h->uval, h->uval32, s);

@@ -309,6 +309,34 @@ def test_full_c2_setup_spmv_apply_residual(c2_full):
     test_spmv_parity(c2_full)
     test_precond_apply_parity(c2_full)
     test_residual_parity(c2_full)
+    # sdsl_info's sweep depth: levels of 512-row chunks (forward chunks from
+    # each block's top, backward ones from its bottom), recounted here from
+    # the factor pattern
+    name, s, o, solver, P = c2_full
+    f = solver.factors()
+    rp, ci = f["row_ptr"], f["col"]
+    per_block = []
+    for b in range(s.nblocks):
+        lo, hi = int(s.block_ptr[b]), int(s.block_ptr[b + 1])
+        total = 0
+        for fwd in (True, False):
+            m = 0
+            while (lo + m * 512 < hi) if fwd else (hi - m * 512 > lo):
+                a, e = (lo + m * 512, min(hi, lo + (m + 1) * 512)) if fwd else (max(lo, hi - (m + 1) * 512),
+                                                                              hi - m * 512)
+                lev = {}
+                rows = range(a, e) if fwd else range(e - 1, a - 1, -1)
+                for i in rows:
+                    cols = ci[rp[i]:rp[i + 1]]
+                    dep = cols[(cols >= a) & (cols < i)] if fwd else cols[(cols > i) & (cols < e)]
+                    lev[i] = 1 + max(lev[j] for j in dep) if dep.size else 0
+                total += 1 + max(lev.values())
+                m += 1
+        per_block.append(total)
+    inf = solver.info()
+    print(f"  sweep levels per block: max {inf['sweep_levels_max']}, mean {inf['sweep_levels_mean']:.1f}")
+    assert inf["sweep_levels_max"] == max(per_block)
+    assert inf["sweep_levels_mean"] == pytest.approx(np.mean(per_block), rel=1e-12)
 
 
 def test_full_c2_solves(c2_full):
