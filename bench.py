@@ -446,10 +446,11 @@ def main():
     ap.add_argument("--serve", type=int, default=48,
                     help="served C5 requests (closed loop, then Poisson at 0.8x that rate; 0: skip)")
     ap.add_argument("--serve-active", type=int, default=32)
-    ap.add_argument("--serve-modes", default="fp32ir",
+    ap.add_argument("--serve-modes", default="fp32ir,fp64",
                     help="precisions of the served stream (the first also gets the Poisson run)")
     ap.add_argument("--gen-workers", type=int, default=8,
-                    help="processes that build the C4 and C5 inputs while the GPU runs C2")
+                    help="processes that build the C4 and C5 inputs while the GPU runs C2 (0: build them in this "
+                         "process, after C2)")
     ap.add_argument("--c4", type=int, default=0,
                     help="also run the IPM sequence (this many systems, refactor every 5) at --c4-rows rows")
     ap.add_argument("--c4-rows", type=int, default=520_000)
@@ -460,7 +461,7 @@ def main():
     ap.add_argument("--c3", type=int, default=0,
                     help="also run the BBD / GMRES(30) system C3 (setup, then this many solves)")
     ap.add_argument("--c4-kernels", type=int, default=300,
-                    help="PCG iterations timed on the full-size C4 system (0: skip)")
+                    help="PCG iterations timed on the full-size C4 system (0: skip; also run by --profile-iters)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="profiling run: first copy a buffer of this many bytes three times (counter scale)")
     args = ap.parse_args()
@@ -477,8 +478,8 @@ def main():
     fut_c5 = []
     want_c4 = args.c4_kernels > 0 and args.scale == 1.0 and args.profile_iters == 0
     want_c5 = args.serve > 0 and args.profile_iters == 0
-    if want_c4 or want_c5:
-        pool = ProcessPoolExecutor(max_workers=max(1, args.gen_workers))
+    if (want_c4 or want_c5) and args.gen_workers > 0:
+        pool = ProcessPoolExecutor(max_workers=args.gen_workers)
         if want_c4:
             fut_c4 = pool.submit(build_c4)
         if want_c5:
@@ -519,6 +520,8 @@ def main():
             torch.cuda.synchronize()
             log(f"profile {m}: {its} iterations, status {st}, relres {rr:.2e}")
             sv.close()
+        if args.c4_kernels > 0 and args.scale == 1.0:
+            run_c4_kernels(sd, torch, build_c4(), args.c4_kernels)
         if args.c1 > 0:
             run_c1(sd, torch, gen, args.c1)
         if args.c3 > 0:
@@ -563,6 +566,10 @@ def main():
         c5_sys = [f.result() for f in fut_c5]
         pool.shutdown()
         log(f"  background inputs ready (waited {time.time() - t_wait:.1f} s)")
+    elif want_c4 or want_c5:
+        # --gen-workers 0 (for instance under a profiler): built here
+        c4_sys = build_c4() if want_c4 else None
+        c5_sys = [build_c5(r) for r in gen.c5_requests()[:args.serve]] if want_c5 else None
     cpu = None
     if not args.no_cpu_baseline:
         model, avail, threads = host_cpu()
