@@ -134,6 +134,13 @@ def run_serving(sd, torch, gen, systems, active, modes):
     completion (queueing, setup and solve)."""
     from paper_2604_23979_amd.serve import Request, Server
     count = len(systems)
+
+    def progress(tag):
+        def done(req):
+            k = done.count = getattr(done, "count", 0) + 1
+            if k % 10 == 0 or k == count:
+                log(f"    {tag}: {k}/{count} requests done")
+        return done
     prec = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR}
     out = {"workload": f"C5: first {count} requests of the seeded stream (rows log-uniform 1e4..5e5, 6-10 per "
                        f"column, D spread 1e8, 8-128 blocks; {sum(s.n for s in systems)} rows in all), "
@@ -143,7 +150,7 @@ def run_serving(sd, torch, gen, systems, active, modes):
     for mode in modes:
         o = sd.Options(precision=prec[mode], filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
                        pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
-        srv = Server(options=o, max_active=active)
+        srv = Server(options=o, max_active=active, on_done=progress(f"closed loop {mode}"))
         srv.run([Request(s, 0.0, i) for i, s in enumerate(systems)])
         st = srv.stats()
         st["iterations"] = int(sum(r.iters for r in srv.done))
@@ -152,7 +159,7 @@ def run_serving(sd, torch, gen, systems, active, modes):
         if mode == modes[0]:
             mu = st["solves_per_s"]
             arr = gen.poisson_arrivals(count, 0.8 * mu)
-            srv2 = Server(options=o, max_active=active)
+            srv2 = Server(options=o, max_active=active, on_done=progress(f"Poisson {mode}"))
             srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
             out["poisson_0.8mu"] = dict(srv2.stats(), mode=mode, rate_per_s=0.8 * mu)
             log(f"  Poisson at 0.8 mu ({mode}): {out['poisson_0.8mu']}")
@@ -172,6 +179,8 @@ def run_serving(sd, torch, gen, systems, active, modes):
         lat.append(1e3 * (time.perf_counter() - t0))
         its_tot += its
         ok += st == sd.OK
+        if len(lat) % 10 == 0:
+            log(f"    plain FP64: {len(lat)}/{count} requests done")
     span = time.perf_counter() - t0
     out["plain_fp64"] = dict(requests=count, ok=ok, makespan_s=round(span, 3), solves_per_s=round(count / span, 4),
                              p50_ms=round(float(np.percentile(lat, 50)), 1),

@@ -190,6 +190,14 @@ typedef struct {
                               take values of A and reuse the matching.
                               spmv, precond_apply and residual act on A'.    */
     sdsl_factor factor;    /* ILU0 (default) or COMPLETE                     */
+    int32_t graphs;        /* 1: sdsl_solve issues the PCG iterations of each
+                              check interval through the shared-launch kernels
+                              with a one-handle table, recorded once as a HIP
+                              graph and replayed (a launch per interval instead
+                              of three per iteration); handles without a
+                              low-rank term; results are bitwise those of
+                              graphs = 0; kernel_timing does not time these
+                              iterations                                      */
 } sdsl_options;
 
 typedef struct {
@@ -246,7 +254,7 @@ typedef struct {
 /* Fills *o with defaults: BJ, no filter, no correction, SHIFT(1e-2), SPD,
  * PCG, restart 30, max_iter 100000, FP64, inner_tol 1e-4, max_outer 30,
  * check_every 16, kernel_timing 0, border 1, refine_delta 0.1,
- * refine_every 500, mc64 0, factor ILU0. */
+ * refine_every 500, mc64 0, factor ILU0, graphs 0. */
 void sdsl_default_options(sdsl_options* o);
 
 /* Device-memory provider of a handle (PyTorch's caching allocator in the

@@ -56,7 +56,7 @@ class COptions(C.Structure):
                 ("krylov", C.c_int), ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("check_every", C.c_int32),
                 ("kernel_timing", C.c_int32), ("border", C.c_int32), ("refine_delta", C.c_double),
-                ("refine_every", C.c_int32), ("mc64", C.c_int32), ("factor", C.c_int)]
+                ("refine_every", C.c_int32), ("mc64", C.c_int32), ("factor", C.c_int), ("graphs", C.c_int32)]
 
 
 class CInfo(C.Structure):
@@ -201,6 +201,7 @@ class Options:
     refine_every: int = 500
     mc64: bool = False
     factor: int = 0  # FACT_ILU0 or FACT_COMPLETE
+    graphs: bool = False
 
     def c(self) -> COptions:
         o = COptions()

@@ -46,6 +46,8 @@ namespace {
 struct SolveTask;
 void delete_task(SolveTask* t);
 }  // namespace
+struct sdsl_group_s;
+void delete_group(sdsl_group_s* g);
 
 struct sdsl_group_s;
 
@@ -55,6 +57,7 @@ struct sdsl_ctx {
     sdsl_group_s* defer = nullptr;  // set while a group step collects this handle's iterations
     bool unflushed = false;         // iterations collected by a group and not yet launched
     sdsl_group_s* holder = nullptr; // the group holding them
+    sdsl_group_s* own = nullptr;    // graphs = 1: the one-handle group of sdsl_solve
     sdsl_options o{};
     int n = 0, n_int = 0, nbd = 0, nb = 0;
     int64_t nnz = 0;
@@ -177,6 +180,7 @@ struct sdsl_ctx {
     ~sdsl_ctx() {
         if (s) (void)hipStreamSynchronize(s);
         if (task) delete_task(task);
+        if (own) delete_group(own);
         for (auto& a : allocs) give_back(a.first, a.second);
         if (st_h) (void)hipHostFree(st_h);
         if (scal_h) (void)hipHostFree(scal_h);
@@ -1214,6 +1218,19 @@ void sdsl_group_s::flush() {
     recs.clear();
 }
 
+void delete_group(sdsl_group_s* g) { delete g; }
+
+// the one-handle group of a graphs = 1 handle: its stream and allocator
+sdsl_group_s* make_own_group(sdsl_ctx* h) {
+    std::unique_ptr<sdsl_group_s> g(new sdsl_group_s());
+    g->s = h->s;
+    g->graphs = true;
+    g->al = h->al;
+    hip_check(hipEventCreateWithFlags(&g->copied, hipEventDisableTiming), "event create");
+    hip_check(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking), "stream create");
+    return g.release();
+}
+
 namespace {
 
 // sum of a device partial array into scal[idx], then copied to the host
@@ -1879,6 +1896,7 @@ void check_options(const sdsl_options* o) {
     if (o->mc64 != 0 && o->mc64 != 1) fail(SDSL_E_INVALID, "mc64 must be 0 or 1");
     if (o->mc64 && o->method != SDSL_BJ) fail(SDSL_E_INVALID, "MC64 applies to the block-Jacobi method");
     if (o->factor != SDSL_FACT_ILU0 && o->factor != SDSL_FACT_COMPLETE) fail(SDSL_E_INVALID, "unknown factorisation");
+    if (o->graphs != 0 && o->graphs != 1) fail(SDSL_E_INVALID, "graphs must be 0 or 1");
     if (o->precision < SDSL_FP64 || o->precision > SDSL_FP32_IR_RESTART) fail(SDSL_E_INVALID, "unknown precision");
     if (o->precision == SDSL_FP32_IR_RESTART && (!(o->inner_tol > 0.0 && o->inner_tol < 1.0) || o->max_outer < 1))
         fail(SDSL_E_INVALID, "inner_tol must be in (0,1) and max_outer >= 1");
@@ -2270,8 +2288,29 @@ sdsl_status sdsl_solve(sdsl_handle h, const double* b, double* x, double tol, in
         if (!(tol > 0.0)) fail(SDSL_E_INVALID, "tol must be positive");
         check_idle(h);
         SolveTask t;
-        t.begin(h, b, x, tol);
-        while (!t.finished) t.step();
+        if (h->o.graphs && h->lr.k == 0 && h->bd.k == 0) {
+            // iterations through the shared-launch kernels, replayed from a graph
+            if (!h->own) h->own = make_own_group(h);
+            struct Clear {  // also on an error: nothing of this solve stays queued
+                sdsl_ctx* h;
+                ~Clear() {
+                    h->defer = nullptr;
+                    h->own->recs.clear();
+                    h->unflushed = false;
+                    h->holder = nullptr;
+                }
+            } clear{h};
+            h->defer = h->own;
+            t.begin(h, b, x, tol);
+            h->own->flush();
+            while (!t.finished) {
+                t.step();
+                h->own->flush();
+            }
+        } else {
+            t.begin(h, b, x, tol);
+            while (!t.finished) t.step();
+        }
         if (iters) *iters = t.total_its;
         if (relres) *relres = t.relres;
         result = t.status;

@@ -70,12 +70,13 @@ class Server:
 
     def __init__(self, options: Optional[B.Options] = None, tol: float = 1e-8, max_active: int = 8,
                  budget_bytes: Optional[int] = None, reserve_bytes: int = 1 << 30, shared: bool = True,
-                 graphs: bool = True):
+                 graphs: bool = True, on_done=None):
         self.options = options or B.Options(precision=B.FP32_IR)
         self.tol = tol
         self.max_active = max_active
         self.shared = shared
         self.graphs = graphs
+        self.on_done = on_done      # called with each finished Request
         self.group_stats = None
         self.budget = budget_bytes
         self.reserve = reserve_bytes
@@ -149,6 +150,8 @@ class Server:
                             solver.close()
                             used -= need
                             self.done.append(req)
+                            if self.on_done:
+                                self.on_done(req)
                         else:
                             still.append(item)
                     active = still
@@ -204,6 +207,8 @@ class Server:
                     solver.close()
                     used -= need
                     self.done.append(req)
+                    if self.on_done:
+                        self.on_done(req)
                 else:
                     still.append(item)
             active = still

@@ -108,3 +108,13 @@ def test_setup_rejects_bad_arguments_without_touching_the_device():
                                C.byref(h)) == sd.E_INVALID
     assert b"allocator" in sd.lib().sdsl_last_error(None)
     assert not h.value
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; --gpus N > 1 exits with a message
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""

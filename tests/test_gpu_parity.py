@@ -1379,6 +1379,29 @@ def test_group_steps_equal_solo_solves(graphs):
     grp.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32ir", "restart"])
+def test_graph_replayed_solve_equals_plain_solve(prec):
+    """graphs = 1: sdsl_solve issues each check interval's PCG iterations as
+    one replayed HIP graph of the shared-launch kernels; the solution,
+    iterations and residual are bitwise those of the plain launches (C1 and
+    a ragged system, every precision form)."""
+    mode = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR, "restart": sd.FP32_IR_RESTART}[prec]
+    for s in (gen.c1(), ragged_system()):
+        res = []
+        for graphs in (False, True):
+            sv = sd.from_system(s, opts(precision=mode, graphs=graphs))
+            try:
+                x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8)
+                x2, its2, rr2, st2 = sv.solve(tdev(s.b), tol=1e-8)   # the cached graphs again
+                assert (its2, rr2, st2) == (its, rr, st) and torch.equal(x, x2)
+                res.append((x.cpu(), its, rr, st))
+            finally:
+                sv.close()
+        (xa, ia, ra, sa), (xb, ib, rb, sb) = res
+        print(f"  {s.name} {prec}: its {ia}, graphs {ib}")
+        assert sa == sb == sd.OK and ia == ib and ra == rb and torch.equal(xa, xb)
+
+
 def test_group_refuses_misuse():
     """A handle on another stream and a handle with no running solve are
     refused (the others in the step still advance); a solve begun in a group
