@@ -150,6 +150,8 @@ def run_serving(sd, torch, gen, systems, active, modes):
     for mode in modes:
         o = sd.Options(precision=prec[mode], filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM,
                        pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()   # each leg starts from the same free HBM
         srv = Server(options=o, max_active=active, on_done=progress(f"closed loop {mode}"))
         srv.run([Request(s, 0.0, i) for i, s in enumerate(systems)])
         st = srv.stats()
@@ -159,6 +161,8 @@ def run_serving(sd, torch, gen, systems, active, modes):
         if mode == modes[0]:
             mu = st["solves_per_s"]
             arr = gen.poisson_arrivals(count, 0.8 * mu)
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
             srv2 = Server(options=o, max_active=active, on_done=progress(f"Poisson {mode}"))
             srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
             out["poisson_0.8mu"] = dict(srv2.stats(), mode=mode, rate_per_s=0.8 * mu)

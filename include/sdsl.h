@@ -6,14 +6,17 @@
  * Solvers for Large-Scale Interior Point Methods" (arXiv 2604.23979): at every
  * IPM iteration a sparse system M x = b (Sec. 2.1, Eq. (schur); the system of
  * each interior-point iteration is the input of Alg. 1) is solved by a
- * preconditioned Krylov method (Sec. 2.2, right preconditioning) with either
+ * preconditioned Krylov method (Sec. 2.2, right preconditioning: PCG,
+ * GMRES(m), BiCGSTAB, GCR(m)) with either
  *   - a block-Jacobi preconditioner (Sec. 2.3): contiguous row blocks, each
  *     diagonal block filtered (Sec. 3.2, Eq. (filter)), diagonally corrected
- *     (Sec. 3.3, Eq. (diagcorr)) and ILU(0) factored; or
+ *     (Sec. 3.3, Eq. (diagcorr)) and ILU(0) or completely LU factored
+ *     (Sec. 3.1), optionally after MC64 matching and scaling (Alg. 3); or
  *   - a bordered-block-diagonal (BBD) preconditioner (Sec. 2.4): factored
  *     interior blocks coupled through a dense Schur complement of the border.
  * Preconditioners stay resident between calls so that consecutive IPM systems
- * reuse them (Sec. 3.4).
+ * reuse them (Sec. 3.4).  Several handles on one stream can share kernel
+ * launches (sdsl_group_*).
  *
  * All arrays named "device" live in GPU memory of the current HIP device;
  * "host" arrays live in CPU memory.  Every call returns an sdsl_status and
@@ -32,7 +35,7 @@
 extern "C" {
 #endif
 
-#define SDSL_ABI_VERSION 1
+#define SDSL_ABI_VERSION 2
 
 typedef struct sdsl_ctx* sdsl_handle;
 

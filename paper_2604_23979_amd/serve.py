@@ -89,6 +89,9 @@ class Server:
     def _free_bytes(self, used: int) -> int:
         import torch
         free, _ = torch.cuda.mem_get_info()
+        # handles come from torch's caching allocator: blocks it has cached
+        # but not handed out are free for the next handle too
+        free += torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
         avail = free - self.reserve
         if self.budget is not None:
             avail = min(avail, self.budget - used)
