@@ -240,6 +240,13 @@ struct BorderDev {
     const double* fold = nullptr;  // t = U^T z and K^{-1} t (LR_BORDER layout)
     const double* W = nullptr;     // n x k, column-major
     const double* Kinv = nullptr;  // k x k, row-major
+    // U^T p of the new direction without a pass over U: U^T z' = t - G s
+    // with G = U^T W, so U^T p = t - G s + beta U^T p_old (FP64 vectors
+    // only; up = nullptr: not kept).  ufold = c_j (U^T p)_j for the product.
+    const double* G = nullptr;  // k x k, row-major
+    const double* c = nullptr;  // k scales of the low-rank term
+    double* up = nullptr;       // k: U^T p of the current direction
+    double* ufold = nullptr;    // k: c_j (U^T p)_j
 };
 
 // ---------------------------------------------------------- shared launches
@@ -377,7 +384,7 @@ void launch_border_fix(int n, T* z, const BorderDev& bd, hipStream_t s);
 void launch_scatter_column(int n, const int* ucp, const int* uri, const double* ucv, int j, double* e,
                            hipStream_t s);
 void launch_border_k(int n, int k, const int* ucp, const int* uri, const double* ucv, const double* c,
-                     const double* W, double* K, hipStream_t s);
+                     const double* W, double* K, double* G, hipStream_t s);
 void launch_small_inverse(int k, const double* K, double* Kinv, int* status, hipStream_t s);
 
 // vector helpers

@@ -1553,6 +1553,16 @@ __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* 
         }
         return;
     }
+    if (BORDER && bd.up && bid == 0) {
+        // the next product's low-rank coefficients: U^T p = t - G s + beta U^T p_old
+        for (int j = threadIdx.x; j < bd.k; j += blockDim.x) {
+            double u = ts[j];
+            for (int i = 0; i < bd.k; ++i) u = fma(-bd.G[j * bd.k + i], ss[i], u);
+            if (mode != PUPD_START) u = fma(beta, bd.up[j], u);
+            bd.up[j] = u;
+            bd.ufold[j] = bd.c[j] * u;
+        }
+    }
     const T bt = (T)beta;
     const int g = gdim;
     const int per = (n + g - 1) / g;
@@ -1916,17 +1926,20 @@ void launch_scatter_column(int n, const int* ucp, const int* uri, const double* 
 __global__ __launch_bounds__(256) void k_border_k(int n, int k, const int* __restrict__ ucp,
                                                   const int* __restrict__ uri, const double* __restrict__ ucv,
                                                   const double* __restrict__ c, const double* __restrict__ W,
-                                                  double* __restrict__ K) {
+                                                  double* __restrict__ K, double* __restrict__ G) {
     __shared__ double red[8];
     const int a = blockIdx.x / k, b = blockIdx.x % k;
     double s = 0.0;
     for (int p = ucp[a] + threadIdx.x; p < ucp[a + 1]; p += blockDim.x) s = fma(ucv[p], W[(size_t)b * n + uri[p]], s);
     s = block_sum(s, red);
-    if (threadIdx.x == 0) K[a * k + b] = s + (a == b ? 1.0 / c[a] : 0.0);
+    if (threadIdx.x == 0) {
+        K[a * k + b] = s + (a == b ? 1.0 / c[a] : 0.0);
+        G[a * k + b] = s;  // (U^T W)_ab
+    }
 }
 void launch_border_k(int n, int k, const int* ucp, const int* uri, const double* ucv, const double* c,
-                     const double* W, double* K, hipStream_t s) {
-    k_border_k<<<k * k, 256, 0, s>>>(n, k, ucp, uri, ucv, c, W, K);
+                     const double* W, double* K, double* G, hipStream_t s) {
+    k_border_k<<<k * k, 256, 0, s>>>(n, k, ucp, uri, ucv, c, W, K, G);
 }
 
 // Kinv = K^{-1} for k <= 64 by Gauss-Jordan elimination with partial

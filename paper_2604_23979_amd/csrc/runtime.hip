@@ -101,7 +101,7 @@ struct sdsl_ctx {
     int64_t pcap = 0;  // capacity of the filtered / factor entry arrays
     // border correction of the low-rank term (W = P^{-1} U, K^{-1})
     double* W64 = nullptr;
-    double *Kmat = nullptr, *Kinv = nullptr;
+    double *Kmat = nullptr, *Kinv = nullptr, *Gmat = nullptr, *lr_up = nullptr, *lr_ufold = nullptr;
     int* kstat = nullptr;
     BorderDev bd{};
     // Krylov workspace
@@ -341,6 +341,9 @@ void build_border(sdsl_ctx* h) {
         h->W64 = h->alloc<double>((size_t)k * n);
         h->Kmat = h->alloc<double>((size_t)k * k);
         h->Kinv = h->alloc<double>((size_t)k * k);
+        h->Gmat = h->alloc<double>((size_t)k * k);
+        h->lr_up = h->alloc<double>(k);
+        h->lr_ufold = h->alloc<double>(kMaxRank);
         h->kstat = h->alloc<int>(1);
     }
     PcgVecs V{};
@@ -352,14 +355,15 @@ void build_border(sdsl_ctx* h) {
         launch_bj<double, double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
     }
     launch_border_k(n, k, h->lr.ucp, h->lr.uri, (const double*)h->lr.ucv, (const double*)h->lr.c, h->W64, h->Kmat,
-                    h->s);
+                    h->Gmat, h->s);
     launch_small_inverse(k, h->Kmat, h->Kinv, h->kstat, h->s);
     h->check_launch();
     int bad = 0;
     hip_check(hipMemcpyAsync(&bad, h->kstat, sizeof(int), hipMemcpyDeviceToHost, h->s), "copy");
     h->sync();
     if (bad) fail(SDSL_E_BREAKDOWN, "border Schur complement K = C^-1 + U^T P^-1 U is singular");
-    h->bd = BorderDev{k, h->lr.slices, h->lr.fold, h->W64, h->Kinv};
+    h->bd = BorderDev{k, h->lr.slices, h->lr.fold, h->W64, h->Kinv, h->Gmat, (const double*)h->lr.c, h->lr_up,
+                      h->lr_ufold};
 }
 
 // ---------------------------------------------------------------- BBD
@@ -888,11 +892,24 @@ struct Pcg {
         Vv.part_rr = h->part_rr;
     }
     void set_x(V* xx) { x = xx; Vv.x = xx; }
+    // FP64 directions with a border keep U^T p by its recurrence (the p
+    // update writes the product's coefficients): no U^T p pass per iteration
+    bool lr_rec() const { return sizeof(V) == 8 && h->bd.k > 0 && h->bd.up; }
+    BorderDev border() const {
+        BorderDev B = h->bd;
+        if (!lr_rec()) B.up = nullptr;
+        return B;
+    }
+    LowRankDev spmv_lr() const {
+        LowRankDev L = h->lr;
+        if (lr_rec()) L.fold = h->bd.ufold;
+        return L;
+    }
     void precondition(int j, int mode) {
         launch_bj<V, F>(2, P, Vv, h->st, j, h->s);
         if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
-        launch_pcg_pupdate<V>(h->n, Vv, h->nb, h->bd, h->st, j, mode, h->s);
-        if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
+        launch_pcg_pupdate<V>(h->n, Vv, h->nb, border(), h->st, j, mode, h->s);
+        if (h->lr.k > 0 && !lr_rec()) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
         h->check_launch();
     }
     void start(int it0) {
@@ -914,6 +931,9 @@ struct Pcg {
         }
         const CsrView A{h->n, h->rp, h->ci, h->halo};
         const int period = h->o.kernel_timing;
+        const LowRankDev lr_s = spmv_lr();
+        const BorderDev bd_ = border();
+        const bool rec = lr_rec();
         batch_start = it;
         batch_count = count;
         sampled.clear();
@@ -930,13 +950,13 @@ struct Pcg {
                 sampled.push_back(k);
             }
             if (timed) hip_check(hipEventRecord(h->ev[e], h->s), "event record");
-            launch_spmv<V, F>(A, v, h->lr, p, q, h->part_pq, h->st, h->lanes, h->grid, h->s);
+            launch_spmv<V, F>(A, v, lr_s, p, q, h->part_pq, h->st, h->lanes, h->grid, h->s);
             if (timed) hip_check(hipEventRecord(h->ev[e + 1], h->s), "event record");
             launch_bj<V, F>(1, P, Vv, h->st, it, h->s);
             if (timed) hip_check(hipEventRecord(h->ev[e + 2], h->s), "event record");
             if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, h->st, LR_BORDER, h->bd.Kinv, h->s);
-            launch_pcg_pupdate<V>(h->n, Vv, h->nb, h->bd, h->st, it, PUPD_STEP, h->s);
-            if (h->lr.k > 0) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
+            launch_pcg_pupdate<V>(h->n, Vv, h->nb, bd_, h->st, it, PUPD_STEP, h->s);
+            if (h->lr.k > 0 && !rec) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
         }
         h->check_launch();
     }
