@@ -64,7 +64,7 @@ def build_c4():
     return gen.IPMSequence(steps=30).system(0)
 
 
-def run_mode(sd, torch, system, opts, steps, warmup, tol):
+def run_mode(sd, torch, system, opts, steps, warmup, tol, log=None):
     t0 = time.time()
     solver = sd.from_system(system, opts)
     torch.cuda.synchronize()
@@ -83,7 +83,7 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol):
     t_start = time.perf_counter()
     for k in range(steps):
         t1 = time.perf_counter()
-        _, its, rr, st = solver.solve(b, x, tol)
+        _, its, rr, st = solver.solve(b, x, tol, log=log, extra={"config": system.name, "step": k})
         lat.append((time.perf_counter() - t1) * 1e3)
         its_all.append(its)
         rr_all.append(rr)
@@ -123,7 +123,7 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol):
     return res
 
 
-def run_serving(sd, torch, gen, systems, active, modes):
+def run_serving(sd, torch, gen, systems, active, modes, log=None):
     """Served C5 stream: the first len(systems) requests of the seeded
     stream (built before timing), solved to 1e-8 with the C2 filter in each
     of `modes`, by the serving loop with shared launches (one stream, one
@@ -152,7 +152,7 @@ def run_serving(sd, torch, gen, systems, active, modes):
                        pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
         torch.cuda.synchronize()
         torch.cuda.empty_cache()   # each leg starts from the same free HBM
-        srv = Server(options=o, max_active=active, on_done=progress(f"closed loop {mode}"))
+        srv = Server(options=o, max_active=active, on_done=progress(f"closed loop {mode}"), log=log)
         srv.run([Request(s, 0.0, i) for i, s in enumerate(systems)])
         st = srv.stats()
         st["iterations"] = int(sum(r.iters for r in srv.done))
@@ -163,7 +163,7 @@ def run_serving(sd, torch, gen, systems, active, modes):
             arr = gen.poisson_arrivals(count, 0.8 * mu)
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
-            srv2 = Server(options=o, max_active=active, on_done=progress(f"Poisson {mode}"))
+            srv2 = Server(options=o, max_active=active, on_done=progress(f"Poisson {mode}"), log=log)
             srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
             out["poisson_0.8mu"] = dict(srv2.stats(), mode=mode, rate_per_s=0.8 * mu)
             log(f"  Poisson at 0.8 mu ({mode}): {out['poisson_0.8mu']}")
@@ -461,6 +461,8 @@ def main():
     ap.add_argument("--serve-active", type=int, default=32)
     ap.add_argument("--serve-modes", default="fp32ir,fp64",
                     help="precisions of the served stream (the first also gets the Poisson run)")
+    ap.add_argument("--log", default=None,
+                    help="append one JSON record per solve (C2 solves and served requests) to this JSONL file")
     ap.add_argument("--gen-workers", type=int, default=8,
                     help="processes that build the C4 and C5 inputs while the GPU runs C2 (0: build them in this "
                          "process, after C2)")
@@ -540,13 +542,17 @@ def main():
         if args.c3 > 0:
             run_bbd(sd, torch, gen, args.c3)
         return
+    solve_log = None
+    if args.log:
+        from paper_2604_23979_amd.solvelog import JsonlLog
+        solve_log = JsonlLog(args.log)
     modes = {}
     mode_list = args.modes.split(",")
     for i, m in enumerate(mode_list):
         prec = {"fp64": sd.FP64, "fp32ir": sd.FP32_IR, "fp32restart": sd.FP32_IR_RESTART}[m]
         steps, warmup = (args.steps, args.warmup) if i == 0 else (args.extra_steps, 1)
         log(f"mode {m} ({steps} timed solves{', the JSON value' if i == 0 else ''}):")
-        modes[m] = run_mode(sd, torch, system, sd.Options(precision=prec, **common), steps, warmup, 1e-8)
+        modes[m] = run_mode(sd, torch, system, sd.Options(precision=prec, **common), steps, warmup, 1e-8, solve_log)
         modes[m]["timed_solves"] = steps
         log(f"  {m}: {modes[m]['solves_per_s']:.3f} solves/s, SpMV {modes[m].get('spmv_gbps', 0):.0f} GB/s, "
             f"BJ {modes[m].get('bj_gbps', 0):.0f} GB/s")
@@ -598,7 +604,7 @@ def main():
     log(f"  bandwidth ceilings: {ceiling}")
     c4k = run_c4_kernels(sd, torch, c4_sys, args.c4_kernels) if c4_sys is not None else None
     del c4_sys
-    serving = (run_serving(sd, torch, gen, c5_sys, args.serve_active, args.serve_modes.split(","))
+    serving = (run_serving(sd, torch, gen, c5_sys, args.serve_active, args.serve_modes.split(","), solve_log)
                if c5_sys else None)
     ipm_seq = (run_ipm_sequence(sd, torch, gen, args.c4, args.c4_rows, args.c4_policy, args.c4_precision)
                if args.c4 > 0 else None)

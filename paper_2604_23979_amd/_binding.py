@@ -290,8 +290,10 @@ class Solver:
         _LIVE.add(self)
 
     # -- solves
-    def solve(self, b, x=None, tol: float = 1e-8, check: bool = True):
-        """Solve M x = b (b: CUDA float64 tensor).  Returns (x, iters, relres, status)."""
+    def solve(self, b, x=None, tol: float = 1e-8, check: bool = True, log=None, extra: Optional[dict] = None):
+        """Solve M x = b (b: CUDA float64 tensor).  Returns (x, iters, relres, status).
+        With ``log`` (a solvelog.JsonlLog) one record of the solve is written,
+        with ``extra`` fields added."""
         import torch
         assert b.is_cuda and b.dtype == torch.float64 and b.numel() == self.n
         b = b.contiguous()
@@ -303,6 +305,9 @@ class Solver:
         st = lib().sdsl_solve(self.h, _dptr(b), _dptr(x), tol, C.byref(its), C.byref(rr))
         if check and st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN):
             _check(self.h, st)
+        if log is not None:
+            from .solvelog import record
+            log.write(record(self, st, dict(extra or {}, tol=tol)))
         return x, its.value, rr.value, st
 
     # -- asynchronous solve (serving loops)

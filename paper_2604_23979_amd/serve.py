@@ -70,13 +70,14 @@ class Server:
 
     def __init__(self, options: Optional[B.Options] = None, tol: float = 1e-8, max_active: int = 8,
                  budget_bytes: Optional[int] = None, reserve_bytes: int = 1 << 30, shared: bool = True,
-                 graphs: bool = True, on_done=None):
+                 graphs: bool = True, on_done=None, log=None):
         self.options = options or B.Options(precision=B.FP32_IR)
         self.tol = tol
         self.max_active = max_active
         self.shared = shared
         self.graphs = graphs
         self.on_done = on_done      # called with each finished Request
+        self.log = log              # solvelog.JsonlLog: one record per finished request
         self.group_stats = None
         self.budget = budget_bytes
         self.reserve = reserve_bytes
@@ -96,6 +97,15 @@ class Server:
         if self.budget is not None:
             avail = min(avail, self.budget - used)
         return avail
+
+    def _log(self, req: Request, solver) -> None:
+        if self.log is None:
+            return
+        from .solvelog import record
+        self.log.write(record(solver, req.status, {"request": req.tag, "arrival_s": req.arrival,
+                                                   "admitted_s": req.admitted, "finished_s": req.finished,
+                                                   "latency_s": req.latency, "tol": self.tol,
+                                                   "shared_launches": self.shared}))
 
     def run(self, requests: list[Request]) -> list[Request]:
         if self.shared:
@@ -150,6 +160,7 @@ class Server:
                         if d:
                             req.x, req.iters, req.relres, req.status = solver.solve_end()
                             req.finished = time.perf_counter() - self.t_start
+                            self._log(req, solver)
                             solver.close()
                             used -= need
                             self.done.append(req)
@@ -207,6 +218,7 @@ class Server:
                     req.x, req.iters, req.relres, req.status = solver.solve_end()
                     stream.synchronize()
                     req.finished = time.perf_counter() - self.t_start
+                    self._log(req, solver)
                     solver.close()
                     used -= need
                     self.done.append(req)

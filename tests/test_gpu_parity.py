@@ -1432,6 +1432,28 @@ def test_group_refuses_misuse():
     grp.close()
 
 
+def test_solve_writes_a_jsonl_record(tmp_path):
+    """One JSON line per solve with what the library reports, and one per
+    served request with its arrival, admission and completion times."""
+    from paper_2604_23979_amd.serve import Request, Server
+    from paper_2604_23979_amd.solvelog import JsonlLog, read
+    s = gen.c1()
+    path = str(tmp_path / "solves.jsonl")
+    with JsonlLog(path) as log:
+        sv = sd.from_system(s)
+        x, its, rr, st = sv.solve(tdev(s.b), tol=1e-8, log=log, extra={"config": "C1"})
+        sv.close()
+        srv = Server(options=sd.Options(), max_active=2, log=log)
+        srv.run([Request(s, 0.0, "a"), Request(s, 0.0, "b")])
+    recs = read(path)
+    assert len(recs) == 3
+    r = recs[0]
+    assert r["config"] == "C1" and r["status"] == "OK" and r["iterations"] == its and r["relres"] == rr
+    assert r["n"] == s.n and r["nnz"] == s.nnz and r["gbps"] > 0 and r["tol"] == 1e-8
+    for q in recs[1:]:
+        assert q["request"] in ("a", "b") and q["iterations"] == its and q["finished_s"] >= q["admitted_s"] >= 0
+
+
 def test_async_solve_equals_solve():
     s = gen.c1()
     sv = sd.from_system(s)
