@@ -339,6 +339,69 @@ def test_full_c2_setup_spmv_apply_residual(c2_full):
     assert inf["sweep_levels_mean"] == pytest.approx(np.mean(per_block), rel=1e-12)
 
 
+def test_full_c4_samples_match_oracle():
+    """C4's first system at its full size (5.2M rows, 256 blocks, the bench's
+    filter and breakdown policy), on outputs the oracle computes piece by
+    piece: the FP64 SpMV at 2,000 sampled rows (each row a plain dot
+    product), and for five sampled blocks (one of them shifted by the
+    breakdown policy, where there is one) the filtered pattern (bitwise),
+    corrected values (bitwise), factors (1e-12) and shifts, and those
+    blocks' part of one preconditioner apply (1e-12 of the block's largest
+    entry).  The blocks are independent in the preconditioner, so each is
+    factored by the oracle on its own."""
+    print("\n[C4 at full size]", flush=True)
+    s = gen.IPMSequence(steps=30).system(0)
+    assert s.n == 5_200_000 and s.nblocks == 256
+    o = opts(filter=sd.FILTER_GEOMEAN, tau=1e-3, diag_flags=sd.DIAG_DROPSUM)
+    sv = sd.from_system(s, o)
+    try:
+        rng = np.random.default_rng(40)
+        x = rng.standard_normal(s.n)
+        y = sv.spmv(tdev(x)).cpu().numpy()
+        rows = rng.choice(s.n, 2000, replace=False)
+        for i in rows:
+            a, e = s.row_ptr[i], s.row_ptr[i + 1]
+            ref = float(np.dot(s.val[a:e], x[s.col[a:e]]))
+            scale = float(np.dot(np.abs(s.val[a:e]), np.abs(x[s.col[a:e]])))
+            assert abs(y[i] - ref) <= 64 * U64 * scale, i
+        r = rng.standard_normal(s.n)
+        z = sv.precond_apply(tdev(r)).cpu().numpy()
+        f = sv.factors()
+        # also the first block the library had to shift (SHIFT policy), if any
+        shifted = [int(q) for q in np.flatnonzero(f["shifts"] > 0)[:1]]
+        for b in [0, 77, 160, 255] + shifted:
+            lo, hi = int(s.block_ptr[b]), int(s.block_ptr[b + 1])
+            blk = s_sub(s, lo, hi)
+            sub = gen.System(f"C4-block{b}", blk.indptr.astype(np.int64), blk.indices.astype(np.int32), blk.data,
+                             r[lo:hi], np.array([0, hi - lo], dtype=np.int32))
+            P = O.BJ(sub, **oracle_opts(o))
+            assert P.status == O.OK
+            a0, a1 = int(f["row_ptr"][lo]), int(f["row_ptr"][hi])
+            assert np.array_equal(f["row_ptr"][lo:hi + 1] - a0, P.rp), b
+            assert np.array_equal(f["col"][a0:a1] - lo, P.ci), b
+            assert np.array_equal(f["corrected"][a0:a1], P.corrected), b
+            rel = np.abs(f["lu"][a0:a1] - P.v) / np.maximum(np.abs(P.v), 1e-300)
+            assert rel.max() <= 1e-12, (b, rel.max())
+            assert f["shifts"][b] == P.shifts[0], b
+            zo = P.apply(r[lo:hi])
+            assert np.max(np.abs(z[lo:hi] - zo)) <= 1e-12 * np.max(np.abs(zo)), b
+            print(f"  block {b}: {hi - lo} rows, kept {P.rp[-1]}, shift {P.shifts[0]}", flush=True)
+    finally:
+        sv.close()
+
+
+def s_sub(s, lo, hi):
+    """Rows and columns [lo, hi) of the system's matrix (CSR, sorted)."""
+    a, e = int(s.row_ptr[lo]), int(s.row_ptr[hi])
+    rp = s.row_ptr[lo:hi + 1] - a
+    ci, v = s.col[a:e], s.val[a:e]
+    keep = (ci >= lo) & (ci < hi)
+    cnt = np.add.reduceat(keep.astype(np.int64), rp[:-1]) if hi > lo else np.zeros(0, np.int64)
+    cnt[np.diff(rp) == 0] = 0
+    rp2 = np.concatenate([[0], np.cumsum(cnt)])
+    return sp.csr_matrix((v[keep], ci[keep] - lo, rp2), shape=(hi - lo, hi - lo))
+
+
 def test_full_c2_solves(c2_full):
     """The first PCG iterations against the oracle's (a full oracle solve
     takes minutes), then complete FP64 and FP32-inner solves, whose true
