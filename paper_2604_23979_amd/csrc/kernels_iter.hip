@@ -827,17 +827,30 @@ void launch_scale_inv_norm(int n, const double* nrm2, const double* w, double* v
 // product and difference.  The solve runs in the factor type F (FP32
 // factors: FP32 arithmetic); vectors have type V.
 constexpr int kEll = kBjEllWidth;
+static_assert(kEll % 4 == 0, "the straight pass reads ELL slots four at a time");
 constexpr int kHeld = 8;                   // newest slots kept in registers through the levels
 constexpr int kPark = kEll - kHeld;        // the others, parked in LDS
 constexpr int kStageOld = 2 * kBjThreads;  // older entries of a chunk staged in LDS
-constexpr int kOldLevel = 4;               // level at which the next chunk's older entries load
-constexpr int kTab = 128;                  // per-chunk level counts cached in LDS
 // solution values kept in LDS per block (FP64 solves leave room for the
 // parked FP64 weights)
 template <typename F>
 struct BjRing {
     static constexpr int size = sizeof(F) == 8 ? 4096 : 8192;
 };
+
+// Reads typed by address space.  A value that comes from LDS on one path and
+// from global memory on another is otherwise read by one merged flat load,
+// and waiting for a flat load waits for every load in flight (the next
+// chunk's, issued ahead on purpose); loads of different address spaces are
+// never merged.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ T lload(const T* p) {
+    return *(const __attribute__((address_space(3))) T*)p;
+}
 
 template <typename T>
 __device__ __forceinline__ T from_bits(typename Sentinel<T>::Bits b) {
@@ -1087,7 +1100,8 @@ struct BjRow {
     int o0;        // first older entry (older CSR)
     int obase;     // first older entry of the chunk
     int ocnt;      // older entries of the chunk
-    F a0;          // r_i (forward) or y_i (backward)
+    V ar;          // r_i (forward), converted only when the chunk starts
+    F a0;          // y_i (backward)
     F dg;          // u_ii (backward)
     V rr;          // r_i for (r, z) (backward, MODE 1/2)
     int lev;       // level inside the chunk
@@ -1104,10 +1118,11 @@ __device__ __forceinline__ int2 bj_row(const BJDev& P, int lo, int hi, int m, in
 }
 
 // Issue the loads of thread t's row il = {i, entries} of chunk m; only the
-// occupied ELL slots are read.
+// occupied ELL slots are read.  orng = the chunk's older entries [first, end),
+// read earlier.
 template <bool FWD, int MODE, typename V, typename F>
 __device__ __forceinline__ void bj_load(BjRow<V, F>& R, const BJDev& P, const V* rin, const F* y, int lo, int hi,
-                                        int m, int t, int2 il) {
+                                        int m, int t, int2 il, int2 orng) {
     int ca, cb;
     bj_chunk<FWD>(lo, hi, m, ca, cb);
     const int nrows = cb - ca;
@@ -1116,8 +1131,8 @@ __device__ __forceinline__ void bj_load(BjRow<V, F>& R, const BJDev& P, const V*
     const int* __restrict__ orp = FWD ? P.lorp : P.uorp;
     const int* __restrict__ ec = FWD ? P.lell_c : P.uell_c;
     const F* __restrict__ ev = (const F*)(FWD ? P.lell_v : P.uell_v);
-    R.obase = orp[ca];
-    R.ocnt = orp[cb] - R.obase;
+    R.obase = orng.x;
+    R.ocnt = orng.y - orng.x;
     if (t < nrows) {
         R.len = il.y;
         R.o0 = orp[i];
@@ -1135,7 +1150,7 @@ __device__ __forceinline__ void bj_load(BjRow<V, F>& R, const BJDev& P, const V*
         }
         R.lev = FWD ? P.llev[i] : P.ulev[i];
         if (FWD) {
-            R.a0 = (F)rin[i];
+            R.ar = rin[i];
         } else {
             R.a0 = y[i];
             R.dg = ((const F*)P.udiag)[i];
@@ -1152,14 +1167,14 @@ __device__ __forceinline__ void bj_load(BjRow<V, F>& R, const BJDev& P, const V*
 // from memory (forward: y; backward: z).
 template <bool FWD, int RING, typename V, typename F, typename Bits>
 __device__ __forceinline__ F bj_value(int j, bool inring, const Bits* ring, int lo, const F* y, const V* z) {
-    if (inring) return from_bits<F>(ring[(j - lo) & (RING - 1)]);
-    return FWD ? y[j] : (F)z[j];
+    if (inring) return from_bits<F>(lload(ring + ((j - lo) & (RING - 1))));
+    return FWD ? gload(y + j) : (F)gload(z + j);
 }
 
 template <bool FWD, int MODE, typename V, typename F>
 __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* z, int lo, int hi, int t,
                                          typename Sentinel<F>::Bits* ring, int* pka, F* pkw, int* soc, F* sov,
-                                         F* spr, const int* nltab, const int* nlg, double& rz, int& bad) {
+                                         F* spr, const int* nlg, double& rz, int& bad) {
     using Bits = typename Sentinel<F>::Bits;
     constexpr Bits SENT = Sentinel<F>::bits;
     constexpr int RING = BjRing<F>::size;
@@ -1167,13 +1182,26 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
     const int nch = (hi - lo + kBjThreads - 1) / kBjThreads;
     const int* __restrict__ oci = FWD ? P.loci : P.uoci;
     const F* __restrict__ oval = (const F*)(FWD ? P.lov : P.uov);
+    const int* __restrict__ oorp = FWD ? P.lorp : P.uorp;
     const char* rbase = (const char*)ring;
     auto rd = [&](unsigned off) { return from_bits<F>(*(const Bits*)(rbase + off)); };
     BjRow<V, F> nx, cu;
     int sc[kStageOld / kBjThreads];
     F sv[kStageOld / kBjThreads];
-    // row indices run one chunk ahead of the row loads
-    bj_load<FWD, MODE>(nx, P, rin, y, lo, hi, 0, t, bj_row<FWD>(P, lo, hi, 0, t));
+    // the older-entry range of chunk m: {orp[first row], orp[end row]}
+    auto orange = [&](int m) {
+        int ca, cb;
+        bj_chunk<FWD>(lo, hi, m, ca, cb);
+        return make_int2(gload(oorp + ca), gload(oorp + cb));
+    };
+    // row indices run one chunk ahead of the row loads, and the older-entry
+    // ranges two chunks ahead, so that the stage of the next chunk's older
+    // entries never waits for that chunk's row loads
+    bj_load<FWD, MODE>(nx, P, rin, y, lo, hi, 0, t, bj_row<FWD>(P, lo, hi, 0, t), orange(0));
+    int2 orng1 = orange(min(1, nch - 1));
+    // levels of chunk m, read a chunk ahead
+    auto levels_of = [&](int m) { return gload(nlg + m); };
+    int cnl1 = levels_of(0);
     int2 inext = bj_row<FWD>(P, lo, hi, min(1, nch - 1), t);
     auto stage_load = [&]() {
 #pragma unroll
@@ -1190,6 +1218,7 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
         cu = nx;
         int ca, cb;
         bj_chunk<FWD>(lo, hi, m, ca, cb);
+        const int cnl = cnl1;
         const bool live = t < cb - ca;
         const int i = cu.i;
         // rows whose values are in the ring: forward [cb - RING, cb),
@@ -1217,7 +1246,8 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
         }
         if (live) ring[(i - lo) & (RING - 1)] = SENT;
         __syncthreads();
-        F acc = cu.a0;
+        const F a0 = FWD ? (F)cu.ar : cu.a0;
+        F acc = a0;
         const int nold = max(0, cu.len - kEll);
         const int first = kEll - min(cu.len, kEll);  // first occupied ELL slot
         int opos = 0;                                 // older entries taken
@@ -1226,11 +1256,11 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
         auto old_at = [&](int k, int& j, F& w) {
             const int s = cu.o0 - cu.obase + k;
             if (s < kStageOld) {
-                j = soc[s];
-                w = sov[s];
+                j = lload(soc + s);
+                w = lload(sov + s);
             } else {
-                j = oci[cu.o0 + k];
-                w = oval[cu.o0 + k];
+                j = gload(oci + cu.o0 + k);
+                w = gload(oval + cu.o0 + k);
             }
         };
         if (live) {
@@ -1297,12 +1327,23 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
                         next = tk ? u + 1 : next;
                     }
                 } else {
+                    // four slots at a time: their values first (the reads
+                    // in flight together), then the terms in slot order
 #pragma unroll
-                    for (int u = 0; u < kEll; ++u) {
-                        if (u >= first && earlier(cu.ec[u])) {
-                            acc = acc - cu.ev[u] * bj_value<FWD, RING, V, F>(cu.ec[u], in_ring(cu.ec[u]), ring, lo,
-                                                                              y, z);
-                            next = u + 1;
+                    for (int u0 = 0; u0 < kEll; u0 += 4) {
+                        F vv[4];
+#pragma unroll
+                        for (int u = u0; u < u0 + 4; ++u) {
+                            vv[u - u0] = F(0);
+                            if (u >= first && earlier(cu.ec[u]))
+                                vv[u - u0] = bj_value<FWD, RING, V, F>(cu.ec[u], in_ring(cu.ec[u]), ring, lo, y, z);
+                        }
+#pragma unroll
+                        for (int u = u0; u < u0 + 4; ++u) {
+                            if (u >= first && earlier(cu.ec[u])) {
+                                acc = acc - cu.ev[u] * vv[u - u0];
+                                next = u + 1;
+                            }
                         }
                     }
                 }
@@ -1342,20 +1383,23 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
         // share); the last chunk loads itself again, so that the loads, and
         // the registers they fill, are unconditional
         __builtin_amdgcn_sched_barrier(0);
-        bj_load<FWD, MODE>(nx, P, rin, y, lo, hi, min(m + 1, nch - 1), t, inext);
+        bj_load<FWD, MODE>(nx, P, rin, y, lo, hi, min(m + 1, nch - 1), t, inext, orng1);
         inext = bj_row<FWD>(P, lo, hi, min(m + 2, nch - 1), t);
-        const int cnl = m < kTab ? nltab[m] : nlg[m];
         auto level = [&](int lv) {
             if (live && cu.lev == lv) {
-                // older entries left (only when an older entry is on this chunk)
-                for (; opos < nold; ++opos) {
-                    int j;
-                    F w;
-                    old_at(opos, j, w);
+                // older entries left (only when an older entry is on this
+                // chunk): the staged ones, then any past the stage, in two
+                // loops so that waiting for a load from memory never also
+                // waits for the staged path (and the next chunk's loads)
+                auto older = [&](int j, F w) {
                     const Bits vb = ring[(j - lo) & (RING - 1)];
                     bad |= vb == SENT;
                     acc = acc - w * from_bits<F>(vb);
-                }
+                };
+                const int sb = cu.o0 - cu.obase;
+                for (; opos < nold && sb + opos < kStageOld; ++opos)
+                    older(lload(soc + sb + opos), lload(sov + sb + opos));
+                for (; opos < nold; ++opos) older(gload(oci + cu.o0 + opos), gload(oval + cu.o0 + opos));
                 for (int k = 0; k < npad; k += 4) {
                     unsigned oo[4];
                     F ww[4];
@@ -1371,7 +1415,7 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
                 for (int h = 0; h < kHeld; ++h) acc = acc - hw[h] * rd(hoff[h]);
                 const F out = FWD ? acc : acc / cu.dg;
                 // a sentinel read turns the row into NaN
-                bad |= (out != out) && (cu.a0 == cu.a0);
+                bad |= (out != out) && (a0 == a0);
                 ring[(i - lo) & (RING - 1)] = to_bits<F>(out);
                 if (FWD) {
                     y[i] = out;
@@ -1383,12 +1427,15 @@ __device__ __forceinline__ void bj_sweep(const BJDev& P, const V* rin, F* y, V* 
             }
             __syncthreads();
         };
-        // the next chunk's older entries load after a few levels, once the
-        // chunk's range has arrived
-        const int l1 = min(kOldLevel, cnl);
-        for (int lv = 0; lv < l1; ++lv) level(lv);
+        // the next chunk's older entries load with its rows (their range
+        // was read a chunk earlier), and the range of the chunk after it
+        // last (waited for at the end of this chunk, with the row loads)
         stage_load();
-        for (int lv = l1; lv < cnl; ++lv) level(lv);
+        const int2 orng2 = orange(min(m + 2, nch - 1));
+        const int cnl2 = levels_of(min(m + 1, nch - 1));
+        for (int lv = 0; lv < cnl; ++lv) level(lv);
+        orng1 = orng2;
+        cnl1 = cnl2;
     }
 }
 
@@ -1404,15 +1451,9 @@ __device__ __forceinline__ void bj_body(const BJDev& P, const PcgVecs& Vv, Krylo
     __shared__ F spr[kStageOld];
     __shared__ double red[16];
     __shared__ int shd;
-    __shared__ int lnl[kTab];
-    __shared__ int unl[kTab];
     const int b = bid, t = threadIdx.x;
     const int nb = P.nblocks;
     const int lo = P.bp[b], hi = P.bp[b + 1];
-    for (int q = t; q < kTab && q <= hi - lo; q += kBjThreads) {
-        lnl[q] = P.lnl[lo + b + q];
-        unl[q] = P.unl[lo + b + q];
-    }
     if (t == 0) ring[RING] = to_bits<F>(F(0));
     __syncthreads();
     V* __restrict__ z = (V*)Vv.z;
@@ -1468,9 +1509,9 @@ __device__ __forceinline__ void bj_body(const BJDev& P, const PcgVecs& Vv, Krylo
     int bad = 0;
     double rz = 0.0;
     // forward substitution y_i = r_i - sum_{j<i} l_ij y_j (MODE 4: y given)
-    if (MODE != 4 && lo < hi) bj_sweep<true, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, spr, lnl, P.lnl + lo + b, rz, bad);
+    if (MODE != 4 && lo < hi) bj_sweep<true, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, spr, P.lnl + lo + b, rz, bad);
     // backward substitution z_i = (y_i - sum_{j>i} u_ij z_j) / u_ii (MODE 3: not done)
-    if (MODE != 3 && lo < hi) bj_sweep<false, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, spr, unl, P.unl + lo + b, rz, bad);
+    if (MODE != 3 && lo < hi) bj_sweep<false, MODE, V, F>(P, r, y, z, lo, hi, t, ring, pka, pkw, soc, sov, spr, P.unl + lo + b, rz, bad);
     if (bad && st) atomicExch(&st->spin_err, 1);
     if (MODE == 1 || MODE == 2) {
         rz = block_sum(rz, red);
