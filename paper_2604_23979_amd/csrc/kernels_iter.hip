@@ -8,6 +8,20 @@ namespace sdsl {
 
 
 // ------------------------------------------------------------------ helpers
+// Reads typed by address space.  A value that comes from LDS on one path and
+// from global memory on another is otherwise read by one merged flat load,
+// and waiting for a flat load waits for every load in flight (those issued
+// ahead on purpose); loads of different address spaces are
+// never merged.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ T lload(const T* p) {
+    return *(const __attribute__((address_space(3))) T*)p;
+}
+
 __device__ __forceinline__ bool krylov_done(const KrylovState* st) {
     return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
@@ -296,7 +310,11 @@ __device__ __forceinline__ void spmv_body(int n, const int* __restrict__ rp, con
         }
     }
     __syncthreads();
-    auto gather = [&](int c) -> F { return (c >= wlo && c <= whi) ? xs[c - wlo] : (F)x[c]; };
+    // x_c comes from the window (LDS) or from memory, each read in its own
+    // address space (one merged flat read would wait for every load in
+    // flight); a round's terms are added window terms first, then memory
+    // terms, each in slot order
+    auto in_win = [&](int c) { return c >= wlo && c <= whi; };
 
     constexpr int RPS = kWave / G;
     const int RW = rows / (kSpmvThreads / kWave);  // rows per wave (at most 64)
@@ -339,6 +357,7 @@ __device__ __forceinline__ void spmv_body(int n, const int* __restrict__ rp, con
         double lw = 0.0, nlw = 0.0;
         int lc = 0, nlc = 0;
         lr_load(0, lw, lc);
+
         for (int j = 0; j < nrow; j += RPS) {
             // next step's entries in flight while this one gathers
             const int jn = j + RPS;
@@ -354,14 +373,31 @@ __device__ __forceinline__ void spmv_body(int n, const int* __restrict__ rp, con
             }
             lr_load(jn, nlw, nlc);
             F s = F(0);
+            {
+                V m[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) s = fma(vv[u], gather(cc[u]), s);
-            // rows longer than one round
+                for (int u = 0; u < U; ++u) {
+                    m[u] = V(0);
+                    if (!in_win(cc[u])) m[u] = gload(x + cc[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (in_win(cc[u])) s = fma(vv[u], lload(xs + (cc[u] - wlo)), s);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (!in_win(cc[u])) s = fma(vv[u], (F)m[u], s);
+            }
+            // rows longer than one round, entry by entry
             for (int p0 = a + gl + U * G; p0 < e; p0 += U * G) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int p = p0 + u * G;
-                    if (p < e) s = fma(v[p], gather(ci[p]), s);
+                    if (p < e) {
+                        const int c = ci[p];
+                        const F w = in_win(c) ? lload(xs + (c - wlo)) : F(0);
+                        const V m = in_win(c) ? V(0) : gload(x + c);
+                        s = fma(v[p], in_win(c) ? w : (F)m, s);
+                    }
                 }
             }
             // low-rank term of the step's rows, FP64, one entry per lane
@@ -379,7 +415,7 @@ __device__ __forceinline__ void spmv_body(int n, const int* __restrict__ rp, con
             if (gl == SumLane<G>::value && row < nrow) {
                 const V out = LR ? (V)((double)s + t) : (V)s;
                 y[base + row] = out;
-                if (part_dot) dacc += (double)x[base + row] * (double)out;
+                if (part_dot) dacc += (double)gload(x + base + row) * (double)out;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -398,7 +434,7 @@ __device__ __forceinline__ void spmv_body(int n, const int* __restrict__ rp, con
     }
 }
 template <typename V, typename F, int G, int U, bool LR>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv(int n, const int* __restrict__ rp,
+__global__ __launch_bounds__(kSpmvThreads, 8) void k_spmv(int n, const int* __restrict__ rp,
                                                        const int* __restrict__ ci, const F* __restrict__ v,
                                                        const V* __restrict__ x, V* __restrict__ y,
                                                        double* __restrict__ part_dot, const KrylovState* st,
@@ -837,20 +873,6 @@ template <typename F>
 struct BjRing {
     static constexpr int size = sizeof(F) == 8 ? 4096 : 8192;
 };
-
-// Reads typed by address space.  A value that comes from LDS on one path and
-// from global memory on another is otherwise read by one merged flat load,
-// and waiting for a flat load waits for every load in flight (the next
-// chunk's, issued ahead on purpose); loads of different address spaces are
-// never merged.
-template <typename T>
-__device__ __forceinline__ T gload(const T* p) {
-    return *(const __attribute__((address_space(1))) T*)p;
-}
-template <typename T>
-__device__ __forceinline__ T lload(const T* p) {
-    return *(const __attribute__((address_space(3))) T*)p;
-}
 
 template <typename T>
 __device__ __forceinline__ T from_bits(typename Sentinel<T>::Bits b) {
