@@ -211,7 +211,7 @@ struct BJDev {
     const int* uorp;     // the same for U rows
     const int* uoci;
     const void* uov;
-    const int2* lperm;   // {row, entries} solved by each thread of a forward chunk (level order)
+    const int2* lperm;   // {row, entries} solved by each thread of a forward chunk (ELL group, then level order)
     const int2* uperm;   // the same for backward chunks
 };
 

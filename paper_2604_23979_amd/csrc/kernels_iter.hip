@@ -928,11 +928,12 @@ void launch_bj_chunks(int nblocks, const int* bp, const int* lrp, const int* urp
 // number of levels per chunk (same indexing as the chunk tables).  Computed
 // in rounds: a row gets its level once all its same-chunk dependencies have
 // one; a chain of r rows needs r rounds and at most nrows rounds are run.
-// The sweeps give the rows of a chunk to threads in level order, so that
-// the rows of one level share as few wavefronts as possible: lperm/uperm
-// hold, at the chunk's first row + p, {the row solved by thread p, its
-// number of entries}, and lpos/upos the inverse (inside a level, rows keep
-// their chunk order).
+// The sweeps give the rows of a chunk to threads grouped by how many ELL
+// slots they occupy and in level order inside a group, so that the rows of
+// one level share a few wavefronts and the cache lines of a slot mostly
+// serve rows that occupy it: lperm/uperm hold, at the chunk's first row + p,
+// {the row solved by thread p, its number of entries}, and lpos/upos the
+// inverse.
 __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict__ bp, const int* __restrict__ lrp,
                                                           const int* __restrict__ lci, const int* __restrict__ urp,
                                                           const int* __restrict__ uci, const int2* __restrict__ lch,
@@ -942,7 +943,7 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
                                                           int2* __restrict__ uperm, int* __restrict__ lpos,
                                                           int* __restrict__ upos) {
     __shared__ int slev[kBjThreads];
-    __shared__ int hist[kBjThreads];
+    __shared__ int slen[kBjThreads];
     __shared__ int smax;
     const int b = blockIdx.x, t = threadIdx.x;
     const int lo = bp[b], hi = bp[b + 1];
@@ -999,31 +1000,26 @@ __global__ __launch_bounds__(kBjThreads) void k_bj_levels(const int* __restrict_
                 }
                 if (__syncthreads_count(mine < 0) == 0) break;
             }
-            hist[t] = 0;
-            __syncthreads();
+            slen[t] = min(rlen, kEll);  // occupied ELL slots
             if (live) {
                 lev[i] = mine;
                 atomicMax(&smax, mine + 1);
-                atomicAdd(&hist[mine], 1);
             }
             __syncthreads();
-            if (t == 0) {
-                nl[m] = smax;
-                int run = 0;
-                for (int l = 0; l < smax; ++l) {
-                    const int c = hist[l];
-                    hist[l] = run;
-                    run += c;
-                }
-            }
-            __syncthreads();
+            if (t == 0) nl[m] = smax;
             if (live) {
-                // rank inside the level: the threads before this one with
-                // the same level (a stable order, the same in every setup)
-                int rank = 0;
-                for (int q = 0; q < t; ++q) rank += slev[q] == mine ? 1 : 0;
+                // place in the chunk: rows by occupied ELL slots in groups
+                // of eight (17-24 first, then 9-16, 1-8, none), each group in
+                // level order, then row order (the same in every setup): a
+                // level's rows share a few runs of threads, and a cache line
+                // of an ELL slot mostly serves rows that all occupy it
+                const int mc = (slen[t] + 7) / 8;
+                int p = 0;
+                for (int q = 0; q < nrows; ++q) {
+                    const int qc = (slen[q] + 7) / 8;
+                    p += qc > mc || (qc == mc && (slev[q] < mine || (slev[q] == mine && q < t))) ? 1 : 0;
+                }
                 const int first = dir == 0 ? a : e;  // lowest row of the chunk
-                const int p = hist[mine] + rank;
                 perm[first + p] = make_int2(i, rlen);
                 pos[i] = p;
             }

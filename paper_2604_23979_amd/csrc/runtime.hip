@@ -93,7 +93,7 @@ struct sdsl_ctx {
     float *lell_v32 = nullptr, *uell_v32 = nullptr;
     // older entries of the longer factor rows (CSR per triangle)
     int *lorp = nullptr, *loci = nullptr, *uorp = nullptr, *uoci = nullptr;
-    int2 *lperm = nullptr, *uperm = nullptr;  // level-order row placement
+    int2 *lperm = nullptr, *uperm = nullptr;  // row placement on the sweep threads
     int *lpos = nullptr, *upos = nullptr;
     double *lov = nullptr, *uov = nullptr;
     float *lov32 = nullptr, *uov32 = nullptr;
