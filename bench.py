@@ -64,7 +64,7 @@ def build_c4():
     return gen.IPMSequence(steps=30).system(0)
 
 
-def run_mode(sd, torch, system, opts, steps, warmup, tol, log=None):
+def run_mode(sd, torch, system, opts, steps, warmup, tol, solve_log=None):
     t0 = time.time()
     solver = sd.from_system(system, opts)
     torch.cuda.synchronize()
@@ -83,7 +83,7 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol, log=None):
     t_start = time.perf_counter()
     for k in range(steps):
         t1 = time.perf_counter()
-        _, its, rr, st = solver.solve(b, x, tol, log=log, extra={"config": system.name, "step": k})
+        _, its, rr, st = solver.solve(b, x, tol, log=solve_log, extra={"config": system.name, "step": k})
         lat.append((time.perf_counter() - t1) * 1e3)
         its_all.append(its)
         rr_all.append(rr)
@@ -123,7 +123,7 @@ def run_mode(sd, torch, system, opts, steps, warmup, tol, log=None):
     return res
 
 
-def run_serving(sd, torch, gen, systems, active, modes, log=None):
+def run_serving(sd, torch, gen, systems, active, modes, solve_log=None):
     """Served C5 stream: the first len(systems) requests of the seeded
     stream (built before timing), solved to 1e-8 with the C2 filter in each
     of `modes`, by the serving loop with shared launches (one stream, one
@@ -152,7 +152,7 @@ def run_serving(sd, torch, gen, systems, active, modes, log=None):
                        pivot=sd.PIVOT_SHIFT, shift0=1e-2, max_iter=60_000, refine_delta=0.3)
         torch.cuda.synchronize()
         torch.cuda.empty_cache()   # each leg starts from the same free HBM
-        srv = Server(options=o, max_active=active, on_done=progress(f"closed loop {mode}"), log=log)
+        srv = Server(options=o, max_active=active, on_done=progress(f"closed loop {mode}"), log=solve_log)
         srv.run([Request(s, 0.0, i) for i, s in enumerate(systems)])
         st = srv.stats()
         st["iterations"] = int(sum(r.iters for r in srv.done))
@@ -163,7 +163,7 @@ def run_serving(sd, torch, gen, systems, active, modes, log=None):
             arr = gen.poisson_arrivals(count, 0.8 * mu)
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
-            srv2 = Server(options=o, max_active=active, on_done=progress(f"Poisson {mode}"), log=log)
+            srv2 = Server(options=o, max_active=active, on_done=progress(f"Poisson {mode}"), log=solve_log)
             srv2.run([Request(s, float(arr[i]), i) for i, s in enumerate(systems)])
             out["poisson_0.8mu"] = dict(srv2.stats(), mode=mode, rate_per_s=0.8 * mu)
             log(f"  Poisson at 0.8 mu ({mode}): {out['poisson_0.8mu']}")
