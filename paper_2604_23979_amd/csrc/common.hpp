@@ -156,9 +156,11 @@ struct LowRankDev {
     unsigned* counter = nullptr;  // arrival count of the folding reduction (self-resetting)
 };
 
-// What the last workgroup of a U^T x reduction leaves in fold[]:
-// LR_SCALED: fold[j] = c_j (U^T x)_j (the operator's low-rank term);
-// LR_BORDER: fold[j] = t_j = (U^T x)_j and fold[kMaxRank + j] = (K^{-1} t)_j.
+// LR_SCALED: the last workgroup of a U^T x reduction leaves
+// fold[j] = c_j (U^T x)_j (the operator's low-rank term) in fold[];
+// LR_BORDER: only the slice partials, which the next kernel (the direction
+// update, the border correction) folds into t = U^T x and K^{-1} t itself,
+// so that the reduction needs no arrival count and no device-wide fence.
 enum LrFold { LR_NONE = 0, LR_SCALED = 1, LR_BORDER = 2 };
 constexpr int kMaxRank = 64;
 
@@ -237,7 +239,7 @@ struct PcgVecs {
 struct BorderDev {
     int k = 0;                  // 0: no border
     int slices = 0;
-    const double* fold = nullptr;  // t = U^T z and K^{-1} t (LR_BORDER layout)
+    const double* part = nullptr;  // slice partials of U^T z (LR_BORDER), [k * slices]
     const double* W = nullptr;     // n x k, column-major
     const double* Kinv = nullptr;  // k x k, row-major
     // U^T p of the new direction without a pass over U: U^T z' = t - G s

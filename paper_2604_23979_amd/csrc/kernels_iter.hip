@@ -180,9 +180,8 @@ __global__ __launch_bounds__(256) void k_lowrank_tdot(LowRankDev lr, const T* __
         const double tot = block_sum(sum, red);
         if (threadIdx.x == 0) part[j * slices + s] = tot;
     }
-    if (FOLD != LR_NONE) {
+    if (FOLD == LR_SCALED) {
         __shared__ double sp[kMaxRank * kMaxRank];
-        __shared__ double ts[kMaxRank];
         __shared__ int last;
         if (threadIdx.x == 0) {
             __threadfence();  // publish this workgroup's partial
@@ -198,19 +197,7 @@ __global__ __launch_bounds__(256) void k_lowrank_tdot(LowRankDev lr, const T* __
         for (int jj = threadIdx.x; jj < k; jj += blockDim.x) {
             double t = 0.0;
             for (int q = 0; q < slices; ++q) t += sp[jj * slices + q];
-            ts[jj] = t;
-            if (FOLD == LR_SCALED) lr.fold[jj] = ((const double*)lr.c)[jj] * t;
-            else lr.fold[jj] = t;
-        }
-        if (FOLD == LR_BORDER) {
-            __syncthreads();
-            for (int q = threadIdx.x; q < k * k; q += blockDim.x) sp[q] = Kinv[q];
-            __syncthreads();
-            for (int jj = threadIdx.x; jj < k; jj += blockDim.x) {
-                double t = 0.0;
-                for (int i = 0; i < k; ++i) t = fma(sp[jj * k + i], ts[i], t);
-                lr.fold[kMaxRank + jj] = t;
-            }
+            lr.fold[jj] = ((const double*)lr.c)[jj] * t;
         }
     }
 }
@@ -1565,6 +1552,26 @@ template void launch_bj<float, float>(int, const BJDev&, const PcgVecs&, KrylovS
 // preconditioned residual is z' = z - W s, s = Kinv (U^T z), and
 // (r, z') = (r, z) - t.s, which holds because the block factors of a
 // symmetric matrix give a symmetric P.  (r, z') is published in rzs[it & 1].
+// The border's t = U^T z and s = K^{-1} t from the projection's slice
+// partials (each column's slices added in slice order, then K^{-1} t row by
+// row), into the shared arrays ts and ss; every workgroup of the consumer
+// folds for itself.  Reached by all threads of the workgroup.
+__device__ __forceinline__ void border_fold(const BorderDev& bd, double* ts, double* ss) {
+    const int k = bd.k, sl = bd.slices;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        double t = 0.0;
+        for (int q = 0; q < sl; ++q) t += bd.part[j * sl + q];
+        ts[j] = t;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        double t = 0.0;
+        for (int i = 0; i < k; ++i) t = fma(bd.Kinv[j * k + i], ts[i], t);
+        ss[j] = t;
+    }
+    __syncthreads();
+}
+
 template <typename T, bool BORDER>
 __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* __restrict__ z,
                                              const double* __restrict__ part_rz, const double* __restrict__ part_rr,
@@ -1593,11 +1600,7 @@ __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* 
     double rz = block_sum_array(part_rz + (it & 1) * nb, nb, red);
     if (BORDER) {
         const int k = bd.k;
-        for (int j = threadIdx.x; j < k; j += blockDim.x) {
-            ts[j] = bd.fold[j];
-            ss[j] = bd.fold[kMaxRank + j];
-        }
-        __syncthreads();
+        border_fold(bd, ts, ss);
         double ts_dot = 0.0;
         for (int j = 0; j < k; ++j) ts_dot = fma(ts[j], ss[j], ts_dot);
         rz -= ts_dot;
@@ -1944,10 +1947,10 @@ void launch_gcr_xr(int n, double* x, double* r, double* p, double* q, const doub
 // on its own (the solve loop fuses it into the direction update)
 template <typename T>
 __global__ __launch_bounds__(256) void k_border_fix(int n, T* __restrict__ z, BorderDev bd) {
-    __shared__ double ss[64];
+    __shared__ double ts[kMaxRank];
+    __shared__ double ss[kMaxRank];
     const int k = bd.k;
-    for (int j = threadIdx.x; j < k; j += blockDim.x) ss[j] = bd.fold[kMaxRank + j];
-    __syncthreads();
+    border_fold(bd, ts, ss);
     const double* W = bd.W;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double c = 0.0;

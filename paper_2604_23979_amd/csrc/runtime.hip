@@ -362,7 +362,7 @@ void build_border(sdsl_ctx* h) {
     hip_check(hipMemcpyAsync(&bad, h->kstat, sizeof(int), hipMemcpyDeviceToHost, h->s), "copy");
     h->sync();
     if (bad) fail(SDSL_E_BREAKDOWN, "border Schur complement K = C^-1 + U^T P^-1 U is singular");
-    h->bd = BorderDev{k, h->lr.slices, h->lr.fold, h->W64, h->Kinv, h->Gmat, (const double*)h->lr.c, h->lr_up,
+    h->bd = BorderDev{k, h->lr.slices, h->lr.part, h->W64, h->Kinv, h->Gmat, (const double*)h->lr.c, h->lr_up,
                       h->lr_ufold};
 }
 
