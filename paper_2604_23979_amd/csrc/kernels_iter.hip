@@ -1580,15 +1580,55 @@ __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* 
     __shared__ double red[8];
     __shared__ double ts[64];
     __shared__ double ss[64];
+    __shared__ double fp[kMaxRank * 32];
     __shared__ int shd;
+    // The loads the workgroup needs are issued before any of them is used,
+    // so that their latencies overlap instead of adding up: the (r,r) and
+    // (r,z) partials, the border's slice partials and rows of K^{-1}, and
+    // this thread's first row (z, p and its border columns).  The
+    // arithmetic and its order are those of the plain sequence.
+    constexpr int kPre = 24;  // border columns held in registers
+    constexpr int kPart = 8;  // staged values (slice partials, then K^{-1}) per thread
+    const int t = threadIdx.x;
+    const int g = gdim;
+    const int per = (n + g - 1) / g;
+    const int r0 = bid * per, r1 = min(n, r0 + per);
+    const int i0 = r0 + t;
+    const bool has0 = i0 < r1;
+    const T z0 = has0 ? z[i0] : T(0);
+    const T p0 = has0 && mode != PUPD_START ? p[i0] : T(0);
+    const bool one = nb <= (int)blockDim.x;  // at most one partial per thread
+    const double prr = one && mode == PUPD_STEP && t < nb ? part_rr[t] : 0.0;
+    const double prz = one && t < nb ? part_rz[(it & 1) * nb + t] : 0.0;
+    const int k = BORDER ? bd.k : 0;
+    const int m = BORDER ? k * bd.slices : 0;  // slice partials; K^{-1} follows them in fp
+    const int mk = m + k * k;
+    const bool pre = BORDER && k <= kPre;
+    const bool stage = BORDER && mk <= kPart * (int)blockDim.x && mk <= kMaxRank * 32;
+    double wv[kPre], pv[kPart];
+    if (BORDER) {
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) wv[u] = pre && has0 && u < k ? bd.W[(size_t)u * n + i0] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kPart; ++u) {
+            const int q = t + u * (int)blockDim.x;
+            pv[u] = !stage || q >= mk ? 0.0 : (q < m ? bd.part[q] : bd.Kinv[q - m]);
+        }
+    }
+    auto sum_partials = [&](const double* a, double mine) {
+        if (!one) return block_sum_array(a, nb, red);
+        double s = 0.0;
+        if (t < nb) s += mine;
+        return block_sum(s, red);
+    };
     if (mode == PUPD_STEP) {
         if (block_done(st, &shd)) return;
-        const double rr = block_sum_array(part_rr, nb, red);
+        const double rr = sum_partials(part_rr, prr);
         const bool conv = rr <= st->tol2 * st->bb;
         const bool upd = rr < st->delta2 * st->rr0 ||
                          (st->refine_every > 0 && it + 1 - st->it_refine >= st->refine_every);
         if (conv || upd) {
-            if (bid == 0 && threadIdx.x == 0) {
+            if (bid == 0 && t == 0) {
                 st->conv = conv ? 1 : 0;
                 st->update = upd ? 1 : 0;
                 st->iters = it + 1;
@@ -1597,10 +1637,32 @@ __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* 
             return;
         }
     }
-    double rz = block_sum_array(part_rz + (it & 1) * nb, nb, red);
+    double rz = sum_partials(part_rz + (it & 1) * nb, prz);
     if (BORDER) {
-        const int k = bd.k;
-        border_fold(bd, ts, ss);
+        if (stage) {
+            // t = U^T z and s = K^{-1} t as border_fold computes them
+#pragma unroll
+            for (int u = 0; u < kPart; ++u) {
+                const int q = t + u * (int)blockDim.x;
+                if (q < mk) fp[q] = pv[u];
+            }
+            __syncthreads();
+            const int sl = bd.slices;
+            if (t < k) {
+                double a = 0.0;
+                for (int q = 0; q < sl; ++q) a += fp[t * sl + q];
+                ts[t] = a;
+            }
+            __syncthreads();
+            if (t < k) {
+                double a = 0.0;
+                for (int i = 0; i < k; ++i) a = fma(fp[m + t * k + i], ts[i], a);
+                ss[t] = a;
+            }
+            __syncthreads();
+        } else {
+            border_fold(bd, ts, ss);
+        }
         double ts_dot = 0.0;
         for (int j = 0; j < k; ++j) ts_dot = fma(ts[j], ss[j], ts_dot);
         rz -= ts_dot;
@@ -1608,7 +1670,7 @@ __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* 
     double beta = 0.0;
     if (mode != PUPD_START) beta = rz / st->rzs[(it + 1) & 1];
     if (!isfinite(beta) || !isfinite(rz)) {
-        if (bid == 0 && threadIdx.x == 0) {
+        if (bid == 0 && t == 0) {
             st->breakdown = 1;
             st->iters = it + 1;
             set_done(st);
@@ -1617,7 +1679,7 @@ __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* 
     }
     if (BORDER && bd.up && bid == 0) {
         // the next product's low-rank coefficients: U^T p = t - G s + beta U^T p_old
-        for (int j = threadIdx.x; j < bd.k; j += blockDim.x) {
+        for (int j = t; j < bd.k; j += blockDim.x) {
             double u = ts[j];
             for (int i = 0; i < bd.k; ++i) u = fma(-bd.G[j * bd.k + i], ss[i], u);
             if (mode != PUPD_START) u = fma(beta, bd.up[j], u);
@@ -1626,20 +1688,24 @@ __device__ __forceinline__ void pupdate_body(int n, T* __restrict__ p, const T* 
         }
     }
     const T bt = (T)beta;
-    const int g = gdim;
-    const int per = (n + g - 1) / g;
-    const int r0 = bid * per, r1 = min(n, r0 + per);
     const double* W = bd.W;
-    for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        T zi = z[i];
+    for (int i = i0; i < r1; i += blockDim.x) {
+        const bool first = i == i0;
+        T zi = first ? z0 : z[i];
         if (BORDER) {
             double c = 0.0;
-            for (int j = 0; j < bd.k; ++j) c = fma(W[(size_t)j * n + i], ss[j], c);
+            if (pre && first) {
+#pragma unroll
+                for (int j = 0; j < kPre; ++j)
+                    if (j < k) c = fma(wv[j], ss[j], c);
+            } else {
+                for (int j = 0; j < k; ++j) c = fma(W[(size_t)j * n + i], ss[j], c);
+            }
             zi = (T)((double)zi - c);
         }
-        p[i] = (mode == PUPD_START) ? zi : zi + bt * p[i];
+        p[i] = (mode == PUPD_START) ? zi : zi + bt * (first ? p0 : p[i]);
     }
-    if (bid == 0 && threadIdx.x == 0) st->rzs[it & 1] = rz;
+    if (bid == 0 && t == 0) st->rzs[it & 1] = rz;
 }
 template <typename T, bool BORDER>
 __global__ __launch_bounds__(256) void k_pcg_pupdate(int n, T* __restrict__ p, const T* __restrict__ z,
