@@ -175,8 +175,7 @@ constexpr int kSpmvHalo = 2176;  // near-window halo (FP64 window: 36-43 KB of L
 int spmv_lanes(double mean_row);
 
 template <typename T>
-void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, int fold, const double* Kinv,
-                         hipStream_t s);
+void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, int fold, hipStream_t s);
 template <typename V, typename F>
 void launch_spmv(const CsrView& A, const F* v, const LowRankDev& lr, const V* x, V* y, double* part_dot,
                  const KrylovState* st, int lanes, int grid, hipStream_t s);

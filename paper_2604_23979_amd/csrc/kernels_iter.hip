@@ -11,8 +11,7 @@ namespace sdsl {
 // Reads typed by address space.  A value that comes from LDS on one path and
 // from global memory on another is otherwise read by one merged flat load,
 // and waiting for a flat load waits for every load in flight (those issued
-// ahead on purpose); loads of different address spaces are
-// never merged.
+// ahead on purpose); loads of different address spaces are never merged.
 template <typename T>
 __device__ __forceinline__ T gload(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;
@@ -119,13 +118,14 @@ int spmv_lanes(double mean_row) {
 // ------------------------------------------------------------------ low rank
 // part[j * slices + s] = sum over slice s of column j of U^T x (FP64).  With
 // COMP the slice sums are compensated and their error terms go to
-// part[k * slices + j * slices + s].  With FOLD the last workgroup to finish
-// sums the slices of every column in slice order and writes the coefficients
-// that the consumers need into lr.fold (LrFold), so that they read k values
-// instead of k * slices.
+// part[k * slices + j * slices + s].  With FOLD = LR_SCALED the last
+// workgroup to finish sums the slices of every column in slice order and
+// writes c_j (U^T x)_j into lr.fold, so that the SpMV reads k values instead
+// of k * slices; with LR_BORDER the consumers fold the partials themselves
+// (LrFold).
 template <typename T, bool COMP, int FOLD>
 __global__ __launch_bounds__(256) void k_lowrank_tdot(LowRankDev lr, const T* __restrict__ x,
-                                                      const double* __restrict__ Kinv, const KrylovState* st) {
+                                                      const KrylovState* st) {
     __shared__ double red[8];
     __shared__ int shd;
     if (block_done(st, &shd)) return;
@@ -203,18 +203,15 @@ __global__ __launch_bounds__(256) void k_lowrank_tdot(LowRankDev lr, const T* __
 }
 
 template <typename T>
-void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, int fold, const double* Kinv,
-                         hipStream_t s) {
+void launch_lowrank_tdot(const LowRankDev& lr, const T* x, const KrylovState* st, int fold, hipStream_t s) {
     if (lr.k <= 0) return;
     const int g = lr.k * lr.slices;
-    if (fold == LR_SCALED) k_lowrank_tdot<T, false, LR_SCALED><<<g, 256, 0, s>>>(lr, x, Kinv, st);
-    else if (fold == LR_BORDER) k_lowrank_tdot<T, false, LR_BORDER><<<g, 256, 0, s>>>(lr, x, Kinv, st);
-    else k_lowrank_tdot<T, false, LR_NONE><<<g, 256, 0, s>>>(lr, x, Kinv, st);
+    if (fold == LR_SCALED) k_lowrank_tdot<T, false, LR_SCALED><<<g, 256, 0, s>>>(lr, x, st);
+    else if (fold == LR_BORDER) k_lowrank_tdot<T, false, LR_BORDER><<<g, 256, 0, s>>>(lr, x, st);
+    else k_lowrank_tdot<T, false, LR_NONE><<<g, 256, 0, s>>>(lr, x, st);
 }
-template void launch_lowrank_tdot<double>(const LowRankDev&, const double*, const KrylovState*, int, const double*,
-                                          hipStream_t);
-template void launch_lowrank_tdot<float>(const LowRankDev&, const float*, const KrylovState*, int, const double*,
-                                         hipStream_t);
+template void launch_lowrank_tdot<double>(const LowRankDev&, const double*, const KrylovState*, int, hipStream_t);
+template void launch_lowrank_tdot<float>(const LowRankDev&, const float*, const KrylovState*, int, hipStream_t);
 
 // ------------------------------------------------------------------ SpMV
 // y = M x (+ U diag(c) U^T x) with G lanes per row.  Values (type F) and
@@ -344,7 +341,6 @@ __device__ __forceinline__ void spmv_body(int n, const int* __restrict__ rp, con
         double lw = 0.0, nlw = 0.0;
         int lc = 0, nlc = 0;
         lr_load(0, lw, lc);
-
         for (int j = 0; j < nrow; j += RPS) {
             // next step's entries in flight while this one gathers
             const int jn = j + RPS;
@@ -549,7 +545,7 @@ __global__ __launch_bounds__(256) void k_residual(int n, const int* __restrict__
 void launch_residual(const CsrView& A, const double* v, const LowRankDev& lr, const double* b,
                      const double* x, double* r, double* part, int lanes, int grid, hipStream_t s) {
     if (lr.k > 0)
-        k_lowrank_tdot<double, true, LR_NONE><<<lr.k * lr.slices, 256, 0, s>>>(lr, x, nullptr, nullptr);
+        k_lowrank_tdot<double, true, LR_NONE><<<lr.k * lr.slices, 256, 0, s>>>(lr, x, nullptr);
 #define RES_CASE(G)                                                                                  \
     case G:                                                                                          \
         if (lr.k > 0) k_residual<G, true><<<grid, 256, 0, s>>>(A.n, A.rp, A.ci, v, b, x, r, part, lr); \

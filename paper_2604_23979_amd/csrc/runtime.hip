@@ -907,9 +907,9 @@ struct Pcg {
     }
     void precondition(int j, int mode) {
         launch_bj<V, F>(2, P, Vv, h->st, j, h->s);
-        if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
+        if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, nullptr, LR_BORDER, h->s);
         launch_pcg_pupdate<V>(h->n, Vv, h->nb, border(), h->st, j, mode, h->s);
-        if (h->lr.k > 0 && !lr_rec()) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
+        if (h->lr.k > 0 && !lr_rec()) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, h->s);
         h->check_launch();
     }
     void start(int it0) {
@@ -954,9 +954,9 @@ struct Pcg {
             if (timed) hip_check(hipEventRecord(h->ev[e + 1], h->s), "event record");
             launch_bj<V, F>(1, P, Vv, h->st, it, h->s);
             if (timed) hip_check(hipEventRecord(h->ev[e + 2], h->s), "event record");
-            if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, h->st, LR_BORDER, h->bd.Kinv, h->s);
+            if (h->bd.k > 0) launch_lowrank_tdot<V>(h->lr, z, h->st, LR_BORDER, h->s);
             launch_pcg_pupdate<V>(h->n, Vv, h->nb, bd_, h->st, it, PUPD_STEP, h->s);
-            if (h->lr.k > 0 && !rec) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, nullptr, h->s);
+            if (h->lr.k > 0 && !rec) launch_lowrank_tdot<V>(h->lr, p, h->st, LR_SCALED, h->s);
         }
         h->check_launch();
     }
@@ -1273,7 +1273,7 @@ double true_residual(sdsl_ctx* h, const double* b, const double* x, double* r) {
 // FP64 operator y = M x (+ U diag(c) U^T x)
 void apply_op64(sdsl_ctx* h, const double* x, double* y) {
     const CsrView A{h->n, h->rp, h->ci, h->halo};
-    if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, x, nullptr, LR_SCALED, nullptr, h->s);
+    if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, x, nullptr, LR_SCALED, h->s);
     launch_spmv<double, double>(A, h->v, h->lr, x, y, nullptr, nullptr, h->lanes, h->grid, h->s);
 }
 
@@ -1296,7 +1296,7 @@ void apply_prec64(sdsl_ctx* h, const double* r, double* z) {
     }
     launch_bj<double, double>(0, bj_dev(h, false), V, nullptr, 0, h->s);
     if (h->bd.k > 0) {
-        launch_lowrank_tdot<double>(h->lr, z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
+        launch_lowrank_tdot<double>(h->lr, z, nullptr, LR_BORDER, h->s);
         launch_border_fix<double>(h->n, z, h->bd, h->s);
     }
 }
@@ -1689,13 +1689,13 @@ struct SolveTask {
         V.y = h->y;
         launch_bj<double, double>(0, bj_dev(h, false), V, h->st, 0, h->s);
         if (h->bd.k > 0) {
-            launch_lowrank_tdot<double>(h->lr, out, h->st, LR_BORDER, h->bd.Kinv, h->s);
+            launch_lowrank_tdot<double>(h->lr, out, h->st, LR_BORDER, h->s);
             launch_border_fix<double>(h->n, out, h->bd, h->s);
         }
     }
     void bi_op(const double* in, double* out) {
         const CsrView A{h->n, h->rp, h->ci, h->halo};
-        if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, in, h->st, LR_SCALED, nullptr, h->s);
+        if (h->lr.k > 0) launch_lowrank_tdot<double>(h->lr, in, h->st, LR_SCALED, h->s);
         launch_spmv<double, double>(A, h->v, h->lr, in, out, nullptr, h->st, h->lanes, h->grid, h->s);
     }
     // a cycle from the residual in r: r^ = r, partials of (r^, r), ||r||^2
@@ -2540,7 +2540,7 @@ sdsl_status sdsl_spmv(sdsl_handle h, int32_t prec, const void* x, void* y) {
         if (prec == SDSL_FP64) {
             apply_op64(h, (const double*)x, (double*)y);
         } else {
-            if (h->lr.k > 0) launch_lowrank_tdot<float>(h->lr, (const float*)x, nullptr, LR_SCALED, nullptr, h->s);
+            if (h->lr.k > 0) launch_lowrank_tdot<float>(h->lr, (const float*)x, nullptr, LR_SCALED, h->s);
             launch_spmv<float, float>(A, h->v32, h->lr, (const float*)x, (float*)y, nullptr, nullptr, h->lanes,
                                       h->grid, h->s);
         }
@@ -2564,7 +2564,7 @@ sdsl_status sdsl_precond_apply(sdsl_handle h, int32_t prec, const void* r, void*
             V.y = h->y32;
             launch_bj<float, float>(0, bj_dev(h, true), V, nullptr, 0, h->s);
             if (h->bd.k > 0) {
-                launch_lowrank_tdot<float>(h->lr, (const float*)z, nullptr, LR_BORDER, h->bd.Kinv, h->s);
+                launch_lowrank_tdot<float>(h->lr, (const float*)z, nullptr, LR_BORDER, h->s);
                 launch_border_fix<float>(h->n, (float*)z, h->bd, h->s);
             }
         }
