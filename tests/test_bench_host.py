@@ -63,3 +63,22 @@ def test_run_mode_without_a_record_sink():
     system = SimpleNamespace(b=np.ones(4), name="tiny")
     res = bench.run_mode(sd, torch, system, SimpleNamespace(precision=sd.FP32_IR), steps=1, warmup=0, tol=1e-8)
     assert res["iterations"] == [12]
+
+
+def test_traffic_is_reported_only_while_the_sources_match(tmp_path, monkeypatch):
+    """roofline.traffic comes from a committed counter file that records a
+    hash of the kernel sources; a changed source turns it off (None)."""
+    import hashlib
+    import json
+    src = tmp_path / "k.hip"
+    src.write_text("kernel v1\n")
+    (tmp_path / "profiles").mkdir()
+    rec = {"hbm_bytes_per_launch": 123, "sources": ["k.hip"],
+           "sources_sha256": hashlib.sha256(b"kernel v1\n").hexdigest()}
+    (tmp_path / "profiles" / "traffic_k_bj_c2_fp64.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("bj", "fp64") == 123
+    assert bench.measured_traffic("spmv", "fp64") is None  # no counter file
+    src.write_text("kernel v2\n")
+    assert bench.measured_traffic("bj", "fp64") is None
+
